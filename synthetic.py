@@ -1,0 +1,94 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the
+benchmark.  Holds none of the method's arithmetic: only key, value and query
+generation.
+
+The paper's experiments use 64-bit integer keys (section 5).  Here every key
+set is the image of a counter under P, a keyed 4-round Feistel permutation of
+64-bit words (32-bit halves, a round function built from 31-bit odd
+multipliers).  P is a bijection whatever its round function, so
+
+* members      key_i = P(2 i)          for i < n       (all distinct),
+* non-members  neg_j = P(2 (n + j) + 1)                (distinct, disjoint),
+
+and values are the low b bits of a second Feistel stream.  Query batches mix
+members (drawn uniformly with replacement) and fresh non-members, each query
+choosing its kind from a third stream.
+
+All functions take and return int64 torch tensors holding the 64-bit patterns
+and run unchanged on the CPU or a GPU, so the same seed gives bit-identical
+inputs on both.  Every product is below 2^63, so no signed overflow occurs.
+"""
+from __future__ import annotations
+
+import torch
+
+M32 = 0xFFFFFFFF
+_C1 = 0x7FEB352D
+_C2 = 0x2C1B3C6D
+
+
+def _round_keys(key: int, rounds: int = 4) -> list[int]:
+    # round keys from a small LCG on the Python side (plain integers)
+    out, x = [], (key * 0x5851F42D4C957F2D + 0x14057B7EF767814F) & ((1 << 64) - 1)
+    for _ in range(rounds):
+        x = (x * 0x5851F42D4C957F2D + 0x14057B7EF767814F) & ((1 << 64) - 1)
+        out.append((x >> 33) & M32)
+    return out
+
+
+def _f(x: torch.Tensor, k: int) -> torch.Tensor:
+    y = ((x ^ k) * _C1) & M32
+    y = y ^ (y >> 15)
+    y = (y * _C2) & M32
+    return y ^ (y >> 13)
+
+
+def _join(hi: torch.Tensor, lo: torch.Tensor) -> torch.Tensor:
+    # (hi << 32) | lo as an int64 bit pattern, without overflow
+    hi_s = hi - ((hi >> 31) << 32)  # signed 32-bit reading of hi
+    return hi_s * (1 << 32) + lo
+
+
+def feistel(x: torch.Tensor, key: int) -> torch.Tensor:
+    """Keyed 4-round Feistel permutation of 64-bit words (int64 patterns)."""
+    lo = x & M32
+    hi = (x >> 32) & M32
+    for k in _round_keys(key):
+        hi, lo = lo, hi ^ _f(lo, k)
+    return _join(hi, lo)
+
+
+def member_keys(n: int, data_seed: int, device="cpu") -> torch.Tensor:
+    i = torch.arange(n, dtype=torch.int64, device=device)
+    return feistel(2 * i, data_seed)
+
+
+def negative_keys(n: int, count: int, data_seed: int, start: int = 0,
+                  device="cpu") -> torch.Tensor:
+    """count non-members P(2 (n + start + j) + 1)."""
+    j = torch.arange(count, dtype=torch.int64, device=device)
+    return feistel(2 * (n + start + j) + 1, data_seed)
+
+
+def values(n: int, b: int, data_seed: int, device="cpu") -> torch.Tensor:
+    """Uniform b-bit values (int64 patterns, b <= 64)."""
+    i = torch.arange(n, dtype=torch.int64, device=device)
+    v = feistel(i, data_seed ^ 0x5EED0001)
+    if b >= 64:
+        return v
+    return v & ((1 << b) - 1) if b < 63 else v & 0x7FFFFFFFFFFFFFFF
+
+
+def queries(keys: torch.Tensor, q: int, data_seed: int, member_share_per_256: int = 128):
+    """q queries: each is a member (uniform, with replacement) with
+    probability member_share_per_256 / 256, else a fresh non-member.
+    Returns (queries, is_member)."""
+    n = keys.numel()
+    device = keys.device
+    j = torch.arange(q, dtype=torch.int64, device=device)
+    r = feistel(j, data_seed ^ 0x0A5E7A11)
+    is_member = ((r >> 56) & 0xFF) < member_share_per_256
+    idx = ((r & M32) * n) >> 32  # uniform in [0, n)
+    neg = negative_keys(n, q, data_seed, start=0, device=device)
+    out = torch.where(is_member, keys[idx], neg)
+    return out, is_member

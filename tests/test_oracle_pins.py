@@ -1,0 +1,440 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints, published outputs of the hash it names, closed forms and
+identities, brute force on tiny systems, hand-worked hypergraphs, and
+statistical laws the paper relies on.  None of these tests needs a GPU.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                   "paper_examples.json")))
+M64 = (1 << 64) - 1
+
+
+# --------------------------------------------------------------- hashing
+
+def test_splitmix64_published_stream():
+    """The finalizer, run as the SplitMix64 generator from state 0, gives
+    the generator's published first outputs."""
+    want = [int(x, 16) for x in GOLD["splitmix64_seed0_first_outputs"]["outputs"]]
+    got = [int(x) for x in O.seed_words(0)]
+    assert got == want
+
+
+def _unmix64(z: int) -> int:
+    """Inverse of the SplitMix64 finalizer, derived independently: invert
+    each xorshift by iteration and each multiplication by the modular
+    inverse of the odd constant."""
+    def unxorshift(y, s):
+        x = y
+        for _ in range(64 // s + 1):
+            x = y ^ (x >> s)
+        return x & M64
+    z = unxorshift(z, 31)
+    z = (z * pow(0x94d049bb133111eb, -1, 1 << 64)) & M64
+    z = unxorshift(z, 27)
+    z = (z * pow(0xbf58476d1ce4e5b9, -1, 1 << 64)) & M64
+    return unxorshift(z, 30)
+
+
+def test_mix64_is_a_bijection():
+    """Distinct 64-bit keys never share a signature word (so duplicate
+    signatures, section 4.5, cannot arise from distinct uint64 keys)."""
+    rng = np.random.default_rng(1)
+    for x in list(rng.integers(0, 2**63, 2000, dtype=np.int64)) + [0, 1, M64, 1 << 63]:
+        x = int(x) & M64
+        assert _unmix64(O.mix64(x)) == x
+
+
+# -------------------------------------------------------- parameter math
+
+def test_lambert_w_against_library_and_identities():
+    from scipy.special import lambertw
+    assert O.lambert_w0(math.e) == pytest.approx(1.0, abs=1e-15)
+    assert O.lambert_w0(1.0) == pytest.approx(0.5671432904097838, abs=1e-15)
+    assert O.lambert_w0(-1 / math.e) == pytest.approx(-1.0, abs=1e-7)
+    assert O.lambert_w0(0.0) == 0.0
+    for x in np.concatenate([np.linspace(-0.36, 3, 50), np.geomspace(3, 1e15, 60)]):
+        w = O.lambert_w0(float(x))
+        assert w == pytest.approx(float(lambertw(x).real), rel=1e-12, abs=1e-12)
+        assert w * math.exp(w) == pytest.approx(float(x), rel=1e-12, abs=1e-14)
+
+
+def test_dupmwhc_worked_example():
+    """Section 4.1: 10^12 keys, c = 1.23, eta = 10^-3 -> 8192 shards."""
+    ex = GOLD["dupmwhc_worked_example"]
+    h = O.dupmwhc_bits(ex["n"], ex["c"], ex["eta"])
+    assert 1 << h == ex["shards"]
+
+
+def test_logdupfuse_two_printed_forms_agree_and_solve_the_inequality():
+    """eq. (logdupfuse) is lg of eq. (dupfuse), and both solve the
+    inequality they are derived from: with lg s(m) = alpha ln m ln ln m +
+    beta, the segment size at m = n / S must reach sqrt(-n/(2 c ln(1-eta)))."""
+    a, b = 0.41, -3.0
+    for n, c, eta in [(1e12, 1.105, 1e-3), (1e10, 1.105, 1e-3), (1e9, 1.12, 1e-2)]:
+        h = O.logdupfuse(n, c, eta, a, b)
+        assert h == pytest.approx(math.log2(O.dupfuse(n, c, eta, a, b)), abs=1e-9)
+        need = 0.5 * math.log2(-n / (2 * c * math.log1p(-eta)))
+
+        def lhs(hh):
+            m = n / 2.0 ** hh
+            return a * math.log(m) * math.log(math.log(m)) + b
+        lo_, hi_ = 0.0, math.log2(n) - 2
+        for _ in range(200):  # lhs decreases with h: bisection
+            mid = (lo_ + hi_) / 2
+            if lhs(mid) >= need:
+                lo_ = mid
+            else:
+                hi_ = mid
+        assert h == pytest.approx(lo_, abs=1e-6)
+
+
+def test_logdupfuse_paper_example_is_not_reproduced():
+    """Parity unpinned: the section 4.2 example claims 2048 shards at 10^12
+    keys; the printed formula gives about 2^8.59.  The oracle implements the
+    printed formula; this test records the discrepancy."""
+    ex = GOLD["logdupfuse_worked_example"]
+    h = O.logdupfuse(ex["n"], ex["c"], ex["eta"], ex["alpha"], ex["beta"])
+    assert 8.5 < h < 8.7
+    assert math.floor(h) != int(math.log2(ex["shards_claimed"]))
+
+
+def test_shard_bits_satisfy_the_balls_into_bins_inequality():
+    """eq. (logballsbins) must give S = 2^h with S ln S <= n eps^2 / 2
+    (the inequality of eq. (ballsbins), alpha = 1), and never more shards
+    than the exact-W bound of eq. (ballsbins)."""
+    for n in [1e5, 2**20, 2**27, 1e10, 1e12]:
+        for eps in [0.001, 0.01, 0.0175, 0.05]:
+            h = O.shard_bits_eps(n, eps)
+            x = n * eps * eps / 2
+            if x <= math.e:
+                assert h == 0
+                continue
+            Sh = 2.0 ** h
+            assert Sh * math.log(Sh) <= x * (1 + 1e-12)
+            assert h <= O.shard_bits_exact(n, eps) + 1e-12
+    assert O.shard_bits_eps(2**27, 0.0175) == 11
+
+
+def test_balls_into_bins_statistical():
+    """Raab-Steger (section 4): with h from eq. (logballsbins) the largest
+    shard is within (1 + eps) of the mean in nearly every trial."""
+    n, eps = 1 << 18, 0.06
+    h = O.shard_bits_eps(n, eps)
+    assert h >= 5
+    ok = 0
+    for seed in range(20):
+        keys = S.member_keys(n, 100 + seed).numpy()
+        g, counts = O.plan(keys, h, seed)
+        assert counts.sum() == n
+        ok += counts.max() <= (1 + eps) * n / (1 << h)
+    assert ok >= 19
+
+
+def test_geometry_rules():
+    g = O.geometry(66535, 11)
+    assert (g["c_num"], g["c_den"]) == (112, 100)
+    s = 1 << g["sigma"]
+    c = g["c_num"] / g["c_den"]
+    assert g["V"] == (g["l"] + 2) * s and g["V"] >= c * 66535
+    assert g["l"] == math.ceil(c * 66535 / s) - 2
+    # duplicate-edge rule: m / (2 c s^2) <= 1/8, and not with s / 2
+    assert 66535 / (2 * c * s * s) <= 1 / 8 < 66535 / (2 * c * (s / 2) ** 2)
+    g = O.geometry(10**6, 0)  # unsharded large graph: eq. (ln), c = 1.125
+    assert (g["c_num"], g["c_den"], g["sigma"]) == (1125, 1000, 13)
+    assert g["sigma"] == math.floor(math.log(10**6) / math.log(3.33) + 2.25)
+    g = O.geometry(10**7, 4)  # sharded large shards: eq. (nln), c = 1.105
+    lm = math.log(10**7)
+    assert (g["c_num"], g["c_den"]) == (1105, 1000)
+    assert g["sigma"] == math.floor(0.41 * lm * math.log(lm) - 3)
+    g = O.geometry(0, 3)
+    assert g["l"] == 1 and g["V"] == 3 << g["sigma"]
+
+
+def test_edge_fields():
+    """Fuse graph (section 4.2): one vertex in each of segments g, g+1, g+2
+    with g < ell; only the offsets depend on the local seed t."""
+    rng = np.random.default_rng(5)
+    h, l, sigma = 11, 144, 9
+    s = 1 << sigma
+    for _ in range(300):
+        hi, lo = (int(x) for x in rng.integers(0, 2**63, 2, dtype=np.int64))
+        hi |= int(rng.integers(0, 2)) << 63
+        v0 = O.edge(hi, lo, h, l, sigma, 0)
+        g = v0[0] // s
+        assert g < l and [v // s for v in v0] == [g, g + 1, g + 2]
+        F = ((hi << h) & M64) >> 32
+        assert g == (F * l) >> 32
+        assert [v % s for v in v0] == [(lo >> (i * sigma)) & (s - 1) for i in range(3)]
+        v1 = O.edge(hi, lo, h, l, sigma, 1)
+        assert [v // s for v in v1] == [g, g + 1, g + 2]
+
+
+# ---------------------------------------------------------------- peeling
+
+def test_peel_single_edge():
+    rnd, side, nr = O.peel(3, [[0, 1, 2]])
+    assert list(rnd) == [0] and list(side) == [0] and nr == 1
+    bad, w, core = O.solve(3, [[0, 1, 2]], [5])
+    assert (bad, core) == (0, 0) and list(w) == [5, 0, 0]
+
+
+def test_peel_hand_worked_two_rounds():
+    """e0={0,1,2}, e1={1,2,3}, e2={2,3,4}.  Round 0: vertices 0 and 4 have
+    degree one -> e0 (hinge side 0) and e2 (hinge side 2).  Round 1: e1 has
+    all degrees one -> hinge side 0.  Reverse assignment: w1 = r1, then
+    w0 = r0 ^ w1 ^ w2 and w4 = r2 ^ w2 ^ w3."""
+    E = [[0, 1, 2], [1, 2, 3], [2, 3, 4]]
+    rnd, side, nr = O.peel(5, E)
+    assert list(rnd) == [0, 1, 0] and list(side) == [0, 0, 2] and nr == 2
+    r = [3, 5, 6]
+    bad, w, core = O.solve(5, E, r)
+    assert bad == 0 and core == 0
+    assert list(w) == [r[0] ^ r[1], r[1], 0, 0, r[2]]
+
+
+def test_peel_chain_same_round_and_hinge_side():
+    """e0={0,1,2}, e1={2,3,4}: both peeled in round 0; e1's degree-one
+    vertices are 3 and 4, so its hinge is side 1 (vertex 3)."""
+    rnd, side, nr = O.peel(5, [[0, 1, 2], [2, 3, 4]])
+    assert list(rnd) == [0, 0] and list(side) == [0, 1] and nr == 1
+    bad, w, _ = O.solve(5, [[0, 1, 2], [2, 3, 4]], [9, 12])
+    assert list(w) == [9, 0, 0, 12, 0]
+
+
+def test_duplicate_edge_is_a_core():
+    """Two equal edges never peel (section 4.1: failures are duplicate
+    edges).  Equal right sides: consistent, pivot = highest variable, the
+    free variables are 0.  Different right sides: inconsistent."""
+    rnd, _, _ = O.peel(3, [[0, 1, 2], [0, 1, 2]])
+    assert list(rnd) == [-1, -1]
+    bad, w, core = O.solve(3, [[0, 1, 2], [0, 1, 2]], [7, 7])
+    assert (bad, core) == (0, 2) and list(w) == [0, 0, 7]
+    bad, _, _ = O.solve(3, [[0, 1, 2], [0, 1, 2]], [7, 6])
+    assert bad == 1
+
+
+def test_k4_core_hand_worked():
+    """All four triples of {0,1,2,3}: every vertex has degree 3, so nothing
+    peels.  (a) x0^x1^x2 = 1, (b) x0^x1^x3 = 2, (c) x0^x2^x3 = 4,
+    (d) x1^x2^x3 = 7.  (a)^(b): x2^x3 = 3; then (c) x0 = 7, (d) x1 = 4,
+    (a) x2 = 2, x3 = 1 -- the system has full rank, one solution."""
+    E = [[0, 1, 2], [0, 1, 3], [0, 2, 3], [1, 2, 3]]
+    bad, w, core = O.solve(4, E, [1, 2, 4, 7])
+    assert bad == 0 and core == 4
+    assert list(w) == [7, 4, 2, 1]
+
+
+def test_core_with_free_variable_hand_worked():
+    """{0,1,2} twice and {1,2,3} twice (equal right sides): a 2-core of rank
+    2 in 4 variables.  Pivots are the highest variables 2 and 3; x0 = x1 = 0
+    (free), x2 = r0, x3 = r1 ^ x2 ^ ... = r1 ^ r0."""
+    E = [[0, 1, 2], [0, 1, 2], [1, 2, 3], [1, 2, 3]]
+    bad, w, core = O.solve(4, E, [5, 5, 6, 6])
+    assert bad == 0 and core == 4
+    assert list(w) == [0, 0, 5, 6 ^ 5]
+
+
+# ------------------------------------------------------ core lexmin
+
+def _check(E, r, w):
+    return all((int(w[a]) ^ int(w[b]) ^ int(w[c])) == int(rr) for (a, b, c), rr in zip(E, r))
+
+
+def _brute_lexmin(nv, rows, rhs, bits):
+    """Lexicographically smallest solution (variable 0 most significant)
+    per bit plane by enumerating all 2^nv assignments; None if none."""
+    x = [0] * nv
+    for bit in range(bits):
+        best = None
+        for assign in itertools.product((0, 1), repeat=nv):  # lexicographic
+            if all((assign[a] ^ assign[b] ^ assign[c]) == ((rr >> bit) & 1)
+                   for (a, b, c), rr in zip(rows, rhs)):
+                best = assign
+                break
+        if best is None:
+            return None
+        for v in range(nv):
+            x[v] |= best[v] << bit
+    return x
+
+
+def test_core_lexmin_matches_brute_force():
+    rng = np.random.default_rng(7)
+    n_incons = 0
+    for trial in range(300):
+        nv = int(rng.integers(3, 12))
+        k = int(rng.integers(1, nv + 3))
+        rows = [sorted(rng.choice(nv, 3, replace=False).tolist()) for _ in range(k)]
+        rhs = [int(x) for x in rng.integers(0, 8, k)]
+        want = _brute_lexmin(nv, rows, rhs, bits=3)
+        bad, x = O.core_lexmin(nv, rows, rhs)
+        if want is None:
+            assert bad == 1
+            n_incons += 1
+        else:
+            assert bad == 0 and [int(v) for v in x] == want, (rows, rhs)
+    assert 10 < n_incons < 290  # both outcomes exercised
+
+
+def test_core_lexmin_independent_of_equation_order():
+    rng = np.random.default_rng(8)
+    nv, k = 400, 380
+    rows = np.sort(np.stack([rng.choice(nv, 3, replace=False) for _ in range(k)]), axis=1)
+    x_true = rng.integers(0, 2**63, nv, dtype=np.int64).view(np.uint64)
+    rhs = x_true[rows[:, 0]] ^ x_true[rows[:, 1]] ^ x_true[rows[:, 2]]
+    bad, x = O.core_lexmin(nv, rows, rhs)
+    assert bad == 0
+    assert np.array_equal(x[rows[:, 0]] ^ x[rows[:, 1]] ^ x[rows[:, 2]], rhs)
+    for _ in range(3):
+        p = rng.permutation(k)
+        bad2, x2 = O.core_lexmin(nv, rows[p], rhs[p])
+        assert bad2 == 0 and np.array_equal(x, x2)
+
+
+def test_solve_satisfies_every_equation_on_fuse_graphs():
+    rng = np.random.default_rng(9)
+    for trial in range(6):
+        sigma, l = 6, 30
+        s = 1 << sigma
+        m = int(1.12 ** -1 * (l + 2) * s)
+        g = rng.integers(0, l, m)
+        E = np.stack([(g + i) * s + rng.integers(0, s, m) for i in range(3)], 1)
+        r = rng.integers(0, 256, m).astype(np.uint64)
+        bad, w, core = O.solve((l + 2) * s, E, r)
+        if bad == 0:
+            assert np.array_equal(w[E[:, 0]] ^ w[E[:, 1]] ^ w[E[:, 2]], r)
+
+
+# ------------------------------------------------- whole construction
+
+def _keys(n, seed):
+    return S.member_keys(n, seed).numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("b,h", [(8, 0), (1, 0), (16, 2), (32, 3)])
+def test_vfunc_returns_every_value(b, h):
+    """Problem 1: f(x) for every x in S."""
+    n = 6000
+    keys = _keys(n, 11)
+    vals = S.values(n, b, 11).numpy().view(np.uint64)
+    B = O.build(keys, vals, b=b, is_filter=False, h=h, seed=3)
+    assert B.status == 0
+    assert np.array_equal(O.query(B, keys), vals)
+
+
+def test_vfilter_members_and_false_positive_rate():
+    """Problem 2 via a b-bit fingerprint: members always pass; negatives
+    pass with probability 2^-b (binomial, 5 sigma)."""
+    n, b = 40000, 4
+    keys = _keys(n, 12)
+    B = O.build(keys, b=b, is_filter=True, h=3, seed=4)
+    assert B.status == 0
+    assert O.query(B, keys).min() == 1
+    N = 400000
+    neg = S.negative_keys(n, N, 12).numpy().view(np.uint64)
+    fp = int(O.query(B, neg).sum())
+    p = 2.0 ** -b
+    assert abs(fp - N * p) <= 5 * math.sqrt(N * p * (1 - p))
+
+
+def test_space_is_shards_times_vertices_times_b():
+    """epsilon-cost sharding: S * V cells of b bits, V = (ell + 2) s >= c M,
+    and the relative overhead over n b bits is c (1 + eps_eff) up to the
+    segment rounding."""
+    n = 1 << 16
+    keys = _keys(n, 13)
+    g, counts = O.plan(keys, 4, 1)
+    Sh = 16
+    c = g.c_num / g.c_den
+    s = 1 << g.sigma
+    eps_eff = g.M / (n / Sh) - 1
+    cells = Sh * g.V
+    assert cells / n >= c * (1 + eps_eff) - 1e-9
+    assert cells / n <= c * (1 + eps_eff) + Sh * s / n
+
+
+def test_build_independent_of_key_order():
+    """The stored structure does not depend on the input order."""
+    n = 12000
+    keys = _keys(n, 14)
+    vals = S.values(n, 8, 14).numpy().view(np.uint64)
+    A = O.build(keys, vals, b=8, is_filter=False, h=1, seed=9)
+    p = np.random.default_rng(0).permutation(n)
+    B = O.build(keys[p], vals[p], b=8, is_filter=False, h=1, seed=9)
+    assert A.status == B.status == 0
+    assert np.array_equal(A.w, B.w) and np.array_equal(A.t, B.t)
+
+
+def test_conflicting_duplicate_key_fails_every_attempt():
+    """A VFunc key given twice with different values makes two identical
+    equations with different right sides: every local seed fails."""
+    n = 3000
+    keys = _keys(n, 15)
+    vals = S.values(n, 8, 15).numpy().view(np.uint64)
+    keys2 = np.concatenate([keys, keys[:1]])
+    vals2 = np.concatenate([vals, (vals[:1] ^ np.uint64(1))])
+    B = O.build(keys2, vals2, b=8, is_filter=False, h=0, seed=1, tmax=3)
+    assert B.status == 1 and list(B.t) == [3]
+    assert [f[:3] for f in B.failures] == [(0, 0, 1), (0, 1, 1), (0, 2, 1)]
+    # the same duplicate in a filter is harmless (equal fingerprints)
+    F = O.build(keys2, b=8, is_filter=True, h=0, seed=1, tmax=3)
+    assert F.status == 0 and O.query(F, keys).min() == 1
+
+
+def test_colliding_edge_pair_is_retried_with_next_local_seed():
+    """Two keys of one shard with the same edge at t = 0 (found by a
+    birthday search) and different fingerprints make the t = 0 core
+    inconsistent; the shard is rebuilt with t = 1 and the failure is
+    recorded."""
+    h, seed, b = 0, 5, 8
+    sw = O.seed_words(seed)
+    cand = _keys(4000, 16)
+    geo = O.geometry(40, h, sigma=2)
+    seen = {}
+    pair = None
+    for k in cand:
+        hi, lo = O.mix64(int(k) ^ int(sw[0])), O.mix64(int(k) ^ int(sw[1]))
+        e = O.edge(hi, lo, h, geo["l"], geo["sigma"], 0)
+        if e in seen and O.fingerprint(*seen[e][1:], seed, b) != O.fingerprint(hi, lo, seed, b):
+            pair = (seen[e][0], int(k))
+            break
+        seen[e] = (int(k), hi, lo)
+    assert pair is not None
+    others = [int(k) for k in cand[-38:] if int(k) not in pair]
+    keys = np.array(list(pair) + others, np.uint64)
+    B = O.build(keys, b=b, is_filter=True, h=h, seed=seed, sigma=2)
+    assert B.geom["sigma"] == 2
+    assert B.status == 0 and B.t[0] >= 1
+    assert B.failures[0][:3] == (0, 0, 1)
+    assert O.query(B, keys).min() == 1
+
+
+def test_mwhc_threshold_through_one_segment():
+    """With ell = 1 a fuse graph is the random 3-partite hypergraph of
+    MWHC (section 4.1); it peels above gamma_3 ~ 1.2217 and leaves a
+    2-core below it (section 3.1)."""
+    sigma = 13
+    s = 1 << sigma
+    rng = np.random.default_rng(21)
+    def core_frac(c, trials=6):
+        m = int(3 * s / c)
+        out = []
+        for _ in range(trials):
+            E = np.stack([i * s + rng.integers(0, s, m) for i in range(3)], 1)
+            rnd, _, _ = O.peel(3 * s, E)
+            out.append(float((rnd < 0).mean()))
+        return out
+    assert sum(f == 0.0 for f in core_frac(1.30)) >= 5
+    assert sum(f > 0.3 for f in core_frac(1.12)) >= 5

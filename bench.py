@@ -1,0 +1,182 @@
+"""Benchmark of the epsilon-cost sharded VFilter on one MI355X.
+
+Workload (one step = the whole hot path): build a VFilter with b = 8 over
+n = 2^27 distinct synthetic uint64 keys with h = 11 (2048 shards of about
+2^16 keys, eps = 0.0175 in eq. (logballsbins)), then answer 2^30 queries
+(half members drawn with replacement, half fresh non-members).  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "build Mkeys/s + query Gq/s (VFilter b=8, 2^27 keys); serve p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--log2n", type=int, default=27)
+    p.add_argument("--log2q", type=int, default=30)
+    p.add_argument("--b", type=int, default=8)
+    p.add_argument("--eps", type=float, default=0.0175)
+    p.add_argument("--seed", type=int, default=0)
+    p.add_argument("--data-seed", type=int, default=2027)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-shards", type=int, default=16)
+    return p.parse_args()
+
+
+def cpu_baseline(args) -> dict:
+    """The oracle (plain C, one thread) on a bounded sample of the same
+    workload: 16 shards of about 2^16 keys (h = 4), b = 8, same geometry
+    rule, then 2^21 queries of the same member/non-member mix."""
+    import numpy as np
+    import oracle as O
+    import synthetic as S
+    n_s = args.cpu_sample_shards << 16
+    h_s = (args.cpu_sample_shards - 1).bit_length()
+    keys = S.member_keys(n_s, args.data_seed)
+    q, _ = S.queries(keys, 1 << 21, args.data_seed)
+    k_np = keys.numpy().view(np.uint64)
+    q_np = q.numpy().view(np.uint64)
+    t0 = time.perf_counter()
+    built = O.build(k_np, b=args.b, is_filter=True, h=h_s, seed=args.seed)
+    t1 = time.perf_counter()
+    O.query(built, q_np)
+    t2 = time.perf_counter()
+    return {
+        "value": round(n_s / (t1 - t0) / 1e6, 4),
+        "unit": "Mkeys/s",
+        "query_value": round(q_np.size / (t2 - t1) / 1e9, 6),
+        "query_unit": "Gq/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{args.cpu_sample_shards} shards x ~2^16 keys (n={n_s}, h={h_s}, b={args.b}) "
+                  f"build; 2^21 mixed queries",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import synthetic as S
+    import paper_2503_18397_amd as vf
+
+    dev = torch.device("cuda:0")
+    n, Q = 1 << args.log2n, 1 << args.log2q
+    print(f"[bench] generating n=2^{args.log2n} keys, 2^{args.log2q} queries on {dev}",
+          file=sys.stderr, flush=True)
+    keys = S.member_keys(n, args.data_seed, device=dev)
+    queries, is_member = S.queries(keys, Q, args.data_seed)
+    n_neg = int((~is_member).sum().item())
+    out = torch.empty(Q, dtype=torch.uint8, device=dev)
+    opts = vf.vf_default_opts()
+    sz = vf.vf_plan(n, args.b, args.eps, True, opts)
+    ws = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=dev)
+    st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def step(timed: bool):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        rc, h = vf.vfilter_build(keys, args.b, args.eps, args.seed, opts, ws, st, stream)
+        e[1].record(stream)
+        vf.vfilter_contains(h, queries, out, stream)
+        e[2].record(stream)
+        e[2].synchronize()
+        info = vf.vf_info(h)
+        res = (rc, e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), info)
+        vf.vf_free(h)
+        return res
+
+    for i in range(args.warmup):
+        print(f"[bench] warmup {i}", file=sys.stderr, flush=True)
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = []
+    for i in range(args.steps):
+        recs.append(step(True))
+        print(f"[bench] step {i}: build {recs[-1][1]:.3f} ms, query {recs[-1][2]:.3f} ms",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    rc, _, _, info = recs[-1]
+    members_ok = bool(out[is_member].min().item() == 1)
+    fp = int(out[~is_member].sum().item())
+    build_ms = sum(r[1] for r in recs) / len(recs)
+    query_ms = sum(r[2] for r in recs) / len(recs)
+    k_build_ms = sum(r[3]["ms_build"] for r in recs) / len(recs)
+    k_count_ms = sum(r[3]["ms_count"] for r in recs) / len(recs)
+    k_scatter_ms = sum(r[3]["ms_scatter"] for r in recs) / len(recs)
+    S_, V, cb = info["S"], info["V"], info["cell_bytes"]
+
+    # algorithmic bytes per launch (measurement)
+    kern = {
+        "k_build": {"ms": k_build_ms, "bytes": 8 * n + S_ * V * cb + S_},
+        "k_query": {"ms": query_ms, "bytes": Q * (8 + 3 * cb + 1)},
+        "k_count+k_scan": {"ms": k_count_ms, "bytes": 8 * n},
+        "k_scatter": {"ms": k_scatter_ms, "bytes": 8 * n + 8 * n},
+    }
+    for k in kern.values():
+        k["GB/s"] = round(k["bytes"] / (k["ms"] * 1e-3) / 1e9, 2) if k["ms"] > 0 else None
+        k["frac"] = round(k["GB/s"] / HBM_PEAK_GBS, 5) if k["GB/s"] else None
+    dom = "k_build" if k_build_ms >= query_ms else "k_query"
+    achieved = kern[dom]["GB/s"]
+    res = {
+        "metric": METRIC,
+        "value": round(n / (build_ms * 1e-3) / 1e6, 3),
+        "unit": "Mkeys/s",
+        "query": {"value": round(Q / (query_ms * 1e-3) / 1e9, 4), "unit": "Gq/s"},
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "build_ms": round(build_ms, 3),
+        "query_ms": round(query_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "VFilter b=8, n=2^27 uint64 keys, h=11 (2048 shards of ~2^16 keys), "
+                               "2^30 queries (50% members)",
+                   "n": n, "queries": Q, "b": args.b, "eps": args.eps, "h": info["h"],
+                   "M": info["M"], "sigma": info["sigma"], "l": info["l"], "V": V,
+                   "c": f"{info['c_num']}/{info['c_den']}", "parallelism": "1 GPU"},
+        "check": {"rc": rc, "members_all_true": members_ok, "negatives": n_neg,
+                  "false_positives": fp, "fpr_x256": round(256 * fp / max(n_neg, 1), 4),
+                  "failed_attempts": info["n_failures"],
+                  "space_bits_per_key": round(info["space_bits"] / n, 4)},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5) if achieved else None,
+                     "traffic": None},
+        "kernels": kern,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * vf.h -- C ABI of the MI355X (gfx950) library for epsilon-cost sharded
+ * static functions (VFunc) and static filters (VFilter), after S. Vigna,
+ * "epsilon-Cost Sharding: Scaling Hypergraph-Based Static Functions and
+ * Filters to Trillions of Keys" (arXiv 2503.18397).
+ *
+ * Problems solved (section 3):
+ *   Problem 1 (static function): given n keys and a b-bit value per key,
+ *     store a structure that returns the value of every key; any value may
+ *     be returned for other keys.
+ *   Problem 2 (static filter): store a structure that answers "is x in the
+ *     set" with no false negatives and false-positive rate 2^-b; it is a
+ *     static function from each key to a b-bit fingerprint derived from its
+ *     signature (sections 3.1 and 4.5).
+ *
+ * Method (section 4): keys are hashed once to a signature; the h highest
+ * signature bits pick one of S = 2^h shards; every shard is a fuse
+ * 3-hypergraph sized by the largest shard (no offsets), is peeled, the
+ * unpeeled 2-core is solved by Gaussian elimination over GF(2), and values
+ * are assigned in reverse peel order.  A query xors three cells.
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: VF_OK (0) or a negative VF_E* code.  Nothing is thrown
+ *     across the ABI.  On error, outputs are left untouched unless stated.
+ *   - Keys are uint64 words in DEVICE memory (HBM).  Values, workspace,
+ *     structure and query outputs are DEVICE buffers too, allocated and
+ *     owned by the caller; the library only borrows them.
+ *   - All device work is enqueued on the caller's HIP stream `stream`.
+ *     vf_build/vfilter_build synchronize that stream twice (after shard
+ *     counting, and at the end to collect the failure record); queries do
+ *     not synchronize.
+ *   - Keys must be distinct for a VFunc unless equal keys carry equal
+ *     values; a filter accepts duplicate keys.
+ *   - A handle is a small host object that records pointers into the
+ *     caller's structure buffer: keep that buffer alive and unmodified for
+ *     as long as the handle is used.
+ */
+#ifndef VF_H
+#define VF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VF_OK 0
+#define VF_EINVAL (-1)    /* bad argument (null pointer, b, eps, sizes)   */
+#define VF_ENOSPC (-2)    /* workspace or structure buffer too small      */
+#define VF_EFAIL (-3)     /* some shard failed every local seed           */
+#define VF_EHIP (-4)      /* a HIP runtime call failed                    */
+#define VF_ECAPACITY (-5) /* a shard exceeded a fixed on-chip capacity of
+                             this implementation (elimination window or
+                             pivot log); the method itself did not fail    */
+
+/* Options.  vf_default_opts() fills the paper's defaults. */
+typedef struct vf_opts {
+  int32_t h;          /* shard bits; -1: from eps by eq. (logballsbins)   */
+  int32_t sigma;      /* lg of the segment size; -1: by the size rule     */
+  uint32_t c_num;     /* expansion factor c = c_num / c_den; 0: by rule   */
+  uint32_t c_den;
+  uint32_t tmax;      /* local seeds tried per shard, 1..255 (default 255) */
+  double alpha;       /* Raab-Steger constant of eq. (ballsbins) (1.0)    */
+} vf_opts;
+
+/* Sizes returned by vf_plan (upper bounds: the largest shard is known only
+ * after hashing). */
+typedef struct vf_sizes {
+  uint64_t structure_bytes; /* cells + per-shard seeds + header padding */
+  uint64_t workspace_bytes; /* scratch used only during the build       */
+  int32_t h;                /* shard bits that will be used             */
+  uint32_t shard_cap;       /* largest shard the sizes allow            */
+} vf_sizes;
+
+/* Read-only description of a built structure. */
+typedef struct vf_info_t {
+  int32_t is_filter, b, h;
+  uint32_t S;             /* shards                                      */
+  uint32_t M;             /* keys of the largest shard                   */
+  uint32_t c_num, c_den;  /* expansion factor                            */
+  int32_t sigma;          /* segment size 2^sigma                        */
+  uint32_t l;             /* start segments per shard                    */
+  uint64_t V;             /* vertices (cells) per shard = (l + 2) 2^sigma */
+  uint64_t n;             /* keys                                         */
+  uint64_t seed;
+  uint32_t cell_bytes;    /* bytes per cell in device memory: 1, 2, 4, 8 */
+  uint32_t failed_shards; /* shards with no successful local seed        */
+  uint32_t n_failures;    /* failed attempts recorded                    */
+  uint64_t space_bits;    /* S * V * b: the information the method stores */
+  const void *cells;      /* device: S * V cells of cell_bytes           */
+  const uint8_t *local_seeds; /* device: S bytes, 255 = shard failed     */
+  /* Durations of the build's device phases, measured with HIP events on
+   * the build stream: shard counting + scan, grouping keys by shard, and
+   * the per-shard construction kernel. */
+  float ms_count, ms_scatter, ms_build;
+} vf_info_t;
+
+/* One failed construction attempt of one shard. */
+typedef struct vf_failure {
+  uint32_t shard;
+  uint32_t attempt;    /* local seed t */
+  uint32_t kind;       /* 1 = the 2-core system was inconsistent */
+  uint32_t core_edges; /* edges left by peeling in that attempt  */
+} vf_failure;
+
+typedef struct vf_handle vf_handle;
+
+/* Paper defaults: h from eps with alpha = 1 (section 4), c and the segment
+ * size by the size rule (section 4.2), tmax = 255. */
+void vf_default_opts(vf_opts *o);
+
+/* Sizes of the caller-allocated buffers for n keys of b bits (section 4:
+ * S * V cells, V from the largest shard, bounded here by the Raab-Steger
+ * maximum load with a safety margin).  Pure host; o may be NULL.
+ * Errors: VF_EINVAL for b outside 1..64, eps <= 0 with o->h < 0, out NULL. */
+int vf_plan(uint64_t n, int32_t b, double eps, int32_t is_filter,
+            const vf_opts *o, vf_sizes *out);
+
+/* Build a static function (Problem 1).
+ *   keys      device, n uint64 keys
+ *   values    device, n uint64 words; the low b bits are stored, higher
+ *             bits must be zero (VF_EINVAL is not checked on device: higher
+ *             bits are masked off)
+ *   b         1..64 value bits; cells are 1, 2, 4 or 8 bytes wide
+ *   eps, o    sharding as in vf_plan; seed selects the hash functions
+ *   workspace device scratch of at least vf_plan().workspace_bytes
+ *   structure device buffer of at least vf_plan().structure_bytes
+ *   handle    receives a new handle (also on VF_EFAIL, for vf_failures)
+ * Errors: VF_EINVAL, VF_ENOSPC (buffers too small for the actual largest
+ * shard), VF_EFAIL, VF_ECAPACITY, VF_EHIP. */
+int vf_build(const uint64_t *keys, const uint64_t *values, uint64_t n,
+             int32_t b, double eps, uint64_t seed, const vf_opts *o,
+             void *workspace, uint64_t workspace_bytes, void *structure,
+             uint64_t structure_bytes, hipStream_t stream, vf_handle **handle);
+
+/* Query a static function (eq. (MWHC) with k = 3): out[i] = xor of the
+ * three cells of keys[i]'s edge; out has cell_bytes per key (device).
+ * Errors: VF_EINVAL (null handle/pointers, or a filter handle). */
+int vf_query(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
+             hipStream_t stream);
+
+/* Build a static filter (Problem 2) with b-bit fingerprints; arguments as
+ * vf_build without values. */
+int vfilter_build(const uint64_t *keys, uint64_t n, int32_t b, double eps,
+                  uint64_t seed, const vf_opts *o, void *workspace,
+                  uint64_t workspace_bytes, void *structure,
+                  uint64_t structure_bytes, hipStream_t stream,
+                  vf_handle **handle);
+
+/* Filter query: out[i] = 1 if keys[i] may be in the set, 0 if it is not
+ * (sections 3.1 and 4.5).  out is n bytes of device memory.
+ * Errors: VF_EINVAL (null handle/pointers, or a function handle). */
+int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n,
+                     uint8_t *out, hipStream_t stream);
+
+/* Describe a handle.  Errors: VF_EINVAL. */
+int vf_info(const vf_handle *h, vf_info_t *out);
+
+/* Copy up to cap failure records, sorted by (shard, attempt), into out
+ * (host memory); *count receives the total number recorded.  The record of
+ * the local seeds tried per shard (section 3.2: HEM keeps a local seed per
+ * shard; here every failed attempt is listed).  Errors: VF_EINVAL. */
+int vf_failures(const vf_handle *h, vf_failure *out, uint32_t cap,
+                uint32_t *count);
+
+/* Free the host-side handle only; the caller still owns every buffer. */
+void vf_free(vf_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -235,7 +235,7 @@ def plan(keys, h: int, seed: int, c: tuple | None = None, sigma: int = -1):
 
 
 def build(keys, values=None, *, b: int, is_filter: bool, h: int, seed: int,
-          tmax: int = 256, c: tuple | None = None, sigma: int = -1,
+          tmax: int = 255, c: tuple | None = None, sigma: int = -1,
           shards=None) -> Built:
     """Build the listed shards (all if None) of a VFunc / VFilter."""
     keys = _u64(keys)

@@ -1,0 +1,253 @@
+"""Python binding of libvf.so, the gfx950 library for epsilon-cost sharded
+static functions (VFunc) and static filters (VFilter), after S. Vigna,
+"epsilon-Cost Sharding: Scaling Hypergraph-Based Static Functions and
+Filters to Trillions of Keys" (arXiv 2503.18397).
+
+The functions below carry the names of the C ABI in ``include/vf.h`` and only
+marshal arguments: torch tensors provide device memory and the HIP stream,
+every step of construction and query runs in the library's kernels.  There is
+no CPU fallback: importing this module fails if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvf.so")
+
+VF_OK, VF_EINVAL, VF_ENOSPC, VF_EFAIL, VF_EHIP, VF_ECAPACITY = 0, -1, -2, -3, -4, -5
+_ERR = {VF_EINVAL: "VF_EINVAL", VF_ENOSPC: "VF_ENOSPC", VF_EFAIL: "VF_EFAIL",
+        VF_EHIP: "VF_EHIP", VF_ECAPACITY: "VF_ECAPACITY"}
+
+
+class VFError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {_ERR.get(code, code)}")
+        self.code = code
+
+
+class Opts(C.Structure):
+    _fields_ = [("h", C.c_int32), ("sigma", C.c_int32), ("c_num", C.c_uint32),
+                ("c_den", C.c_uint32), ("tmax", C.c_uint32), ("alpha", C.c_double)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("structure_bytes", C.c_uint64), ("workspace_bytes", C.c_uint64),
+                ("h", C.c_int32), ("shard_cap", C.c_uint32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("is_filter", C.c_int32), ("b", C.c_int32), ("h", C.c_int32),
+                ("S", C.c_uint32), ("M", C.c_uint32), ("c_num", C.c_uint32),
+                ("c_den", C.c_uint32), ("sigma", C.c_int32), ("l", C.c_uint32),
+                ("V", C.c_uint64), ("n", C.c_uint64), ("seed", C.c_uint64),
+                ("cell_bytes", C.c_uint32), ("failed_shards", C.c_uint32),
+                ("n_failures", C.c_uint32), ("space_bits", C.c_uint64),
+                ("cells", C.c_void_p), ("local_seeds", C.c_void_p),
+                ("ms_count", C.c_float), ("ms_scatter", C.c_float), ("ms_build", C.c_float)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Failure(C.Structure):
+    _fields_ = [("shard", C.c_uint32), ("attempt", C.c_uint32), ("kind", C.c_uint32),
+                ("core_edges", C.c_uint32)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2503_18397_amd.build` "
+        "(there is no CPU fallback)")
+
+_lib = C.CDLL(LIB_PATH)
+_vp, _u64, _i32, _dbl = C.c_void_p, C.c_uint64, C.c_int32, C.c_double
+_lib.vf_default_opts.argtypes = [C.POINTER(Opts)]
+_lib.vf_default_opts.restype = None
+_lib.vf_plan.argtypes = [_u64, _i32, _dbl, _i32, C.POINTER(Opts), C.POINTER(Sizes)]
+_lib.vf_build.argtypes = [_vp, _vp, _u64, _i32, _dbl, _u64, C.POINTER(Opts), _vp, _u64, _vp,
+                          _u64, _vp, C.POINTER(_vp)]
+_lib.vfilter_build.argtypes = [_vp, _u64, _i32, _dbl, _u64, C.POINTER(Opts), _vp, _u64, _vp,
+                               _u64, _vp, C.POINTER(_vp)]
+_lib.vf_query.argtypes = [_vp, _vp, _u64, _vp, _vp]
+_lib.vfilter_contains.argtypes = [_vp, _vp, _u64, _vp, _vp]
+_lib.vf_info.argtypes = [_vp, C.POINTER(Info)]
+_lib.vf_failures.argtypes = [_vp, C.POINTER(Failure), C.c_uint32, C.POINTER(C.c_uint32)]
+_lib.vf_free.argtypes = [_vp]
+_lib.vf_free.restype = None
+for _f in ("vf_plan", "vf_build", "vfilter_build", "vf_query", "vfilter_contains", "vf_info",
+           "vf_failures"):
+    getattr(_lib, _f).restype = C.c_int
+
+EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build",
+           "vfilter_contains", "vf_info", "vf_failures", "vf_free")
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != VF_OK:
+        raise VFError(rc, where)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev_ptr(t: torch.Tensor, name: str) -> int:
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous device tensor")
+    return t.data_ptr()
+
+
+def vf_default_opts(**overrides) -> Opts:
+    o = Opts()
+    _lib.vf_default_opts(C.byref(o))
+    for k, v in overrides.items():
+        if v is not None:
+            setattr(o, k, v)
+    return o
+
+
+def vf_plan(n: int, b: int, eps: float, is_filter: bool, opts: Opts | None = None) -> Sizes:
+    s = Sizes()
+    _check(_lib.vf_plan(n, b, eps, int(is_filter), C.byref(opts) if opts else None,
+                        C.byref(s)), "vf_plan")
+    return s
+
+
+def vf_build(keys, values, b, eps, seed, opts, workspace, structure, stream=None):
+    """Returns (rc, handle); rc is VF_OK or VF_EFAIL (the handle is valid for
+    the failure record); other codes raise."""
+    h = C.c_void_p()
+    rc = _lib.vf_build(_dev_ptr(keys, "keys"), _dev_ptr(values, "values"), keys.numel(), b,
+                       eps, seed, C.byref(opts) if opts else None,
+                       _dev_ptr(workspace, "workspace"), workspace.numel(),
+                       _dev_ptr(structure, "structure"), structure.numel(), _stream(stream),
+                       C.byref(h))
+    if rc not in (VF_OK, VF_EFAIL):
+        raise VFError(rc, "vf_build")
+    return rc, h
+
+
+def vfilter_build(keys, b, eps, seed, opts, workspace, structure, stream=None):
+    h = C.c_void_p()
+    rc = _lib.vfilter_build(_dev_ptr(keys, "keys"), keys.numel(), b, eps, seed,
+                            C.byref(opts) if opts else None, _dev_ptr(workspace, "workspace"),
+                            workspace.numel(), _dev_ptr(structure, "structure"),
+                            structure.numel(), _stream(stream), C.byref(h))
+    if rc not in (VF_OK, VF_EFAIL):
+        raise VFError(rc, "vfilter_build")
+    return rc, h
+
+
+def vf_query(handle, keys, out, stream=None) -> None:
+    _check(_lib.vf_query(handle, _dev_ptr(keys, "keys"), keys.numel(), _dev_ptr(out, "out"),
+                         _stream(stream)), "vf_query")
+
+
+def vfilter_contains(handle, keys, out, stream=None) -> None:
+    _check(_lib.vfilter_contains(handle, _dev_ptr(keys, "keys"), keys.numel(),
+                                 _dev_ptr(out, "out"), _stream(stream)), "vfilter_contains")
+
+
+def vf_info(handle) -> dict:
+    i = Info()
+    _check(_lib.vf_info(handle, C.byref(i)), "vf_info")
+    return i.as_dict()
+
+
+def vf_failures(handle) -> list:
+    cnt = C.c_uint32(0)
+    _check(_lib.vf_failures(handle, None, 0, C.byref(cnt)), "vf_failures")
+    buf = (Failure * max(cnt.value, 1))()
+    _check(_lib.vf_failures(handle, buf, cnt.value, C.byref(cnt)), "vf_failures")
+    return [(f.shard, f.attempt, f.kind, f.core_edges) for f in buf[: cnt.value]]
+
+
+def vf_free(handle) -> None:
+    _lib.vf_free(handle)
+
+
+_CELL_DTYPE = {1: torch.uint8, 2: torch.int16, 4: torch.int32, 8: torch.int64}
+
+
+@dataclass
+class Structure:
+    """A built VFunc or VFilter with the device buffers it lives in.
+
+    ``workspace`` is only needed during the build and may be dropped
+    (``release_workspace``); ``structure`` must stay alive with the handle."""
+    handle: C.c_void_p
+    rc: int
+    is_filter: bool
+    b: int
+    structure: torch.Tensor
+    workspace: torch.Tensor | None
+
+    @classmethod
+    def build(cls, keys: torch.Tensor, values: torch.Tensor | None = None, *, b: int,
+              eps: float = 0.0, seed: int = 0, h: int | None = None, sigma: int | None = None,
+              c: tuple | None = None, tmax: int | None = None, stream=None):
+        is_filter = values is None
+        opts = vf_default_opts(h=h, sigma=sigma, tmax=tmax)
+        if c is not None:
+            opts.c_num, opts.c_den = c
+        sz = vf_plan(keys.numel(), b, eps, is_filter, opts)
+        dev = keys.device
+        ws = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=dev)
+        st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
+        if is_filter:
+            rc, hd = vfilter_build(keys, b, eps, seed, opts, ws, st, stream)
+        else:
+            rc, hd = vf_build(keys, values, b, eps, seed, opts, ws, st, stream)
+        return cls(hd, rc, is_filter, b, st, ws)
+
+    def release_workspace(self) -> None:
+        self.workspace = None
+
+    @property
+    def info(self) -> dict:
+        return vf_info(self.handle)
+
+    @property
+    def failures(self) -> list:
+        return vf_failures(self.handle)
+
+    def cells(self) -> torch.Tensor:
+        """Device view of the S * V cells (cell_bytes each)."""
+        i = self.info
+        nbytes = i["S"] * i["V"] * i["cell_bytes"]
+        return self.structure[:nbytes].view(_CELL_DTYPE[i["cell_bytes"]]).view(i["S"], i["V"])
+
+    def local_seeds(self) -> torch.Tensor:
+        i = self.info
+        off = i["local_seeds"] - self.structure.data_ptr()
+        return self.structure[off: off + i["S"]]
+
+    def query(self, keys: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        if self.is_filter:
+            if out is None:
+                out = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+            vfilter_contains(self.handle, keys, out, stream)
+        else:
+            if out is None:
+                out = torch.empty(keys.numel(), dtype=_CELL_DTYPE[self.info["cell_bytes"]],
+                                  device=keys.device)
+            vf_query(self.handle, keys, out, stream)
+        return out
+
+    def free(self) -> None:
+        if self.handle:
+            vf_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,475 @@
+// Host orchestration behind the C ABI of include/vf.h: parameter math
+// (section 4: eq. (logballsbins) for the shard bits; section 4.2 for the
+// expansion factor and segment size), buffer carving, kernel launches and
+// the failure record.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "vf.h"
+#include "vf_launch.h"
+
+namespace {
+
+constexpr uint32_t kMagic = 0x56465531u;  // "VFU1"
+constexpr uint64_t kGoldenGamma = 0x9e3779b97f4a7c15ull;
+constexpr uint32_t kMaxShardBits = 24;
+constexpr uint64_t kMaxCells = (1ull << 21) - 1;  // packed edges hold 21-bit vertices
+
+uint64_t splitmix_finalize(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// The three seed words: consecutive SplitMix64 outputs from the user seed.
+void seed_words(uint64_t seed, uint64_t w[3]) {
+  uint64_t st = seed;
+  for (int i = 0; i < 3; i++) {
+    st += kGoldenGamma;
+    w[i] = splitmix_finalize(st);
+  }
+}
+
+// eq. (logballsbins): floor(lg x - lg ln x), x = n eps^2 / (2 alpha^2); no
+// sharding when x <= e.
+int32_t shard_bits_from_eps(uint64_t n, double eps, double alpha) {
+  double x = (double)n * eps * eps / (2.0 * alpha * alpha);
+  if (!(x > 2.718281828459045)) return 0;
+  double hb = std::floor(std::log2(x) - std::log2(std::log(x)));
+  if (hb < 0) hb = 0;
+  if (hb > kMaxShardBits) hb = kMaxShardBits;
+  return (int32_t)hb;
+}
+
+struct Geometry {
+  uint32_t M, c_num, c_den, l;
+  int32_t sigma;
+  uint64_t V;
+};
+
+// Section 4.2: c = 1.12 for shards below 800 000 keys (solved with Gaussian
+// elimination of the 2-core), c = 1.105 with lg s from eq. (nln) for larger
+// shards, c = 1.125 with lg s from eq. (ln) for a single large unsharded
+// graph.  Below 800 000 keys the segment size is the smallest power of two
+// with expected duplicate edges m / (2 c s^2) <= 1/8.  ell = max(1,
+// ceil(c M / s) - 2) start segments, V = (ell + 2) s cells per shard.
+Geometry geometry(uint32_t M, int32_t h, uint32_t cn, uint32_t cd, int32_t sigma_ovr) {
+  const bool large = M >= 800000u;
+  if (cn == 0 || cd == 0) {
+    if (!large) { cn = 112; cd = 100; }
+    else if (h > 0) { cn = 1105; cd = 1000; }
+    else { cn = 1125; cd = 1000; }
+  }
+  int32_t sg;
+  if (sigma_ovr >= 0) {
+    sg = sigma_ovr;
+  } else if (large && h > 0) {
+    const double lm = std::log((double)M);
+    sg = (int32_t)std::floor(0.41 * lm * std::log(lm) - 3.0);
+  } else if (large) {
+    sg = (int32_t)std::floor(std::log((double)M) / std::log(3.33) + 2.25);
+  } else {
+    sg = 0;
+    while (((uint64_t)cn << (2 * sg)) < 4ull * M * cd) sg++;
+  }
+  sg = std::min(std::max(sg, 0), 20);
+  const uint64_t den = (uint64_t)cd << sg;
+  const uint64_t q = ((uint64_t)cn * M + den - 1) / den;
+  Geometry g;
+  g.M = M;
+  g.c_num = cn;
+  g.c_den = cd;
+  g.sigma = sg;
+  g.l = q > 3 ? (uint32_t)(q - 2) : 1u;
+  g.V = ((uint64_t)g.l + 2) << sg;
+  return g;
+}
+
+uint32_t cell_bytes_for(int32_t b) { return b <= 8 ? 1 : b <= 16 ? 2 : b <= 32 ? 4 : 8; }
+
+// Upper bound on the largest shard used to size buffers before hashing:
+// mean + 1.5 * sqrt(2 mean ln S) + 64 (Raab-Steger maximum load, section 4).
+uint32_t shard_cap(uint64_t n, uint32_t S) {
+  if (S <= 1) return (uint32_t)std::min<uint64_t>(n, 0xFFFFFFFFull);
+  const double mean = (double)n / S;
+  double cap = std::ceil(mean + 1.5 * std::sqrt(2.0 * mean * std::log((double)S)) + 64.0);
+  return (uint32_t)std::min<double>(std::min<double>(cap, (double)n), 4.0e9);
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+int device_cus() {
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return ncu;
+}
+
+struct Layout {
+  int32_t h;
+  uint32_t S, cap;
+  Geometry gcap;
+  uint32_t cell_bytes;
+  uint32_t nwg;
+  uint32_t logcap;
+  uint64_t scratch_stride;
+  uint64_t ws_bytes, st_bytes;
+  uint64_t cells_bytes;
+  // workspace offsets
+  uint64_t o_counts, o_offsets, o_cursor, o_meta, o_work, o_fails, o_bkeys, o_bvals, o_scratch;
+  uint32_t fail_cap;
+};
+
+int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts &o,
+                int ncu, Layout *L) {
+  if (b < 1 || b > 64) return VF_EINVAL;
+  int32_t h = o.h;
+  if (h < 0) {
+    if (!(eps > 0)) return VF_EINVAL;
+    h = shard_bits_from_eps(n, eps, o.alpha > 0 ? o.alpha : 1.0);
+  }
+  if (h > (int32_t)kMaxShardBits) return VF_EINVAL;
+  if (o.tmax < 1 || o.tmax > 255) return VF_EINVAL;
+  if ((o.c_num == 0) != (o.c_den == 0)) return VF_EINVAL;
+  if (o.c_num && o.c_num < o.c_den) return VF_EINVAL;  // c >= 1
+  if (o.sigma > 20) return VF_EINVAL;
+  Layout l{};
+  l.h = h;
+  l.S = 1u << h;
+  l.cap = shard_cap(n, l.S);
+  l.gcap = geometry(l.cap, h, o.c_num, o.c_den, o.sigma);
+  // the rule for c and s changes at 800 000 keys: size buffers for the
+  // larger of the two sides, plus one spare segment
+  if (l.cap >= 800000u) {
+    Geometry below = geometry(799999u, h, o.c_num, o.c_den, o.sigma);
+    if (below.V > l.gcap.V) l.gcap.V = below.V;
+    if (below.l > l.gcap.l) l.gcap.l = below.l;
+  }
+  l.gcap.V += 1ull << l.gcap.sigma;
+  // smaller shards may use smaller segments and hence more of them: bound
+  // the segment count over all sizes up to the cap
+  for (uint32_t k = 1; k <= 64; k++) {
+    Geometry gk = geometry((uint32_t)((uint64_t)l.cap * k / 64), h, o.c_num, o.c_den, o.sigma);
+    if (gk.l > l.gcap.l) l.gcap.l = gk.l;
+  }
+  l.gcap.l += l.gcap.l / 8 + 8;
+  l.cell_bytes = cell_bytes_for(b);
+  l.nwg = (uint32_t)std::max(1, std::min<int>(ncu > 0 ? ncu : 256, (int)l.S));
+  l.logcap = 16u * l.cap + 4096u;
+  // scratch is sized for the largest shard the buffers allow, with the
+  // geometry of that size (the actual geometry is never larger)
+  l.scratch_stride =
+      align256(vfk::build_scratch_bytes(l.cap, l.gcap.V, l.gcap.l, l.logcap));
+  l.fail_cap = 4u * l.S + 1024u;
+  uint64_t o_ = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t at = o_;
+    o_ += align256(bytes);
+    return at;
+  };
+  l.o_counts = take(4ull * l.S);
+  l.o_offsets = take(8ull * (l.S + 1));
+  l.o_cursor = take(8ull * l.S);
+  l.o_meta = take(16);
+  l.o_work = take(4ull * vfk::kWorkWords);
+  l.o_fails = take(sizeof(vfk::FailRec) * (uint64_t)l.fail_cap);
+  l.o_bkeys = take(8ull * std::max<uint64_t>(n, 1));
+  l.o_bvals = is_filter ? 0 : take(8ull * std::max<uint64_t>(n, 1));
+  l.o_scratch = take(l.scratch_stride * l.nwg);
+  l.ws_bytes = o_;
+  l.cells_bytes = align256((uint64_t)l.S * l.gcap.V * l.cell_bytes);
+  l.st_bytes = l.cells_bytes + align256(l.S);
+  *L = l;
+  return VF_OK;
+}
+
+}  // namespace
+
+struct vf_handle {
+  uint32_t magic;
+  int32_t is_filter, b, h;
+  uint32_t S;
+  Geometry g;
+  uint64_t n, seed;
+  uint32_t cell_bytes;
+  vfk::Geo G;
+  void *cells;
+  uint8_t *tseed;
+  std::vector<vf_failure> fails;
+  uint32_t n_fail_total;
+  uint32_t failed_shards;
+  int ncu;
+  float ms[3];
+};
+
+namespace {
+// Events bracketing the device phases of one build (created per build).
+struct PhaseEvents {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool ok = true;
+  PhaseEvents() {
+    for (auto &e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+  }
+  ~PhaseEvents() {
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void record(int i, hipStream_t s) {
+    if (ok) ok = hipEventRecord(ev[i], s) == hipSuccess;
+  }
+  float between(int a, int b) const {
+    float ms = 0.f;
+    if (!ok || hipEventElapsedTime(&ms, ev[a], ev[b]) != hipSuccess) return -1.f;
+    return ms;
+  }
+};
+}  // namespace
+
+extern "C" {
+
+void vf_default_opts(vf_opts *o) {
+  if (!o) return;
+  o->h = -1;
+  o->sigma = -1;
+  o->c_num = 0;
+  o->c_den = 0;
+  o->tmax = 255;
+  o->alpha = 1.0;
+}
+
+int vf_plan(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts *o,
+            vf_sizes *out) {
+  if (!out) return VF_EINVAL;
+  vf_opts d;
+  vf_default_opts(&d);
+  Layout L;
+  int rc = make_layout(n, b, eps, is_filter, o ? *o : d, device_cus(), &L);
+  if (rc) return rc;
+  out->structure_bytes = L.st_bytes;
+  out->workspace_bytes = L.ws_bytes;
+  out->h = L.h;
+  out->shard_cap = L.cap;
+  return VF_OK;
+}
+
+static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n, int32_t b,
+                        double eps, uint64_t seed, const vf_opts *o, void *ws,
+                        uint64_t ws_bytes, void *st, uint64_t st_bytes, hipStream_t stream,
+                        vf_handle **handle, int32_t is_filter) {
+  if (!handle || !ws || !st || (n && !keys) || (!is_filter && n && !values)) return VF_EINVAL;
+  vf_opts d;
+  vf_default_opts(&d);
+  const vf_opts &op = o ? *o : d;
+  const int ncu = device_cus();
+  if (ncu <= 0) return VF_EHIP;
+  Layout L;
+  int rc = make_layout(n, b, eps, is_filter, op, ncu, &L);
+  if (rc) return rc;
+  if (ws_bytes < L.ws_bytes || st_bytes < L.st_bytes) return VF_ENOSPC;
+
+  uint8_t *W = (uint8_t *)ws;
+  uint32_t *counts = (uint32_t *)(W + L.o_counts);
+  uint64_t *offsets = (uint64_t *)(W + L.o_offsets);
+  uint64_t *cursor = (uint64_t *)(W + L.o_cursor);
+  uint32_t *meta = (uint32_t *)(W + L.o_meta);
+  uint32_t *work = (uint32_t *)(W + L.o_work);
+  vfk::FailRec *fails = (vfk::FailRec *)(W + L.o_fails);
+  uint64_t *bkeys = (uint64_t *)(W + L.o_bkeys);
+  uint64_t *bvals = is_filter ? nullptr : (uint64_t *)(W + L.o_bvals);
+  uint8_t *scratch = W + L.o_scratch;
+  uint8_t *cells = (uint8_t *)st;
+  uint8_t *tseed = cells + L.cells_bytes;
+
+  uint64_t sw[3];
+  seed_words(seed, sw);
+
+#define HIPCHK(x)                         \
+  do {                                    \
+    if ((x) != hipSuccess) return VF_EHIP; \
+  } while (0)
+
+  PhaseEvents pe;
+  // 1. keys per shard, largest shard
+  pe.record(0, stream);
+  HIPCHK(vfk::launch_fill_u32(counts, L.S, 0, stream));
+  HIPCHK(vfk::launch_fill_u32(meta, 4, 0, stream));
+  HIPCHK(vfk::launch_count(keys, n, sw[0], (uint32_t)L.h, L.S, counts, ncu, stream));
+  HIPCHK(vfk::launch_scan(counts, L.S, offsets, cursor, meta, stream));
+  pe.record(1, stream);
+  uint32_t hmeta[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(hmeta, meta, sizeof(hmeta), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const uint32_t M = hmeta[0];
+  if (M > L.cap) return VF_ENOSPC;
+  const Geometry g = geometry(M, L.h, op.c_num, op.c_den, op.sigma);
+  if (g.V > kMaxCells) return VF_ECAPACITY;
+  if ((uint64_t)L.S * g.V * L.cell_bytes > L.cells_bytes ||
+      vfk::build_scratch_bytes(M, g.V, g.l, L.logcap) > L.scratch_stride)
+    return VF_ENOSPC;
+
+  // 2. group keys by shard
+  HIPCHK(vfk::launch_scatter(keys, values, n, sw[0], (uint32_t)L.h, L.S, cursor, bkeys, bvals,
+                             ncu, stream));
+  pe.record(2, stream);
+
+  // 3. build every shard
+  vfk::BuildArgs A{};
+  A.G.khi = sw[0];
+  A.G.klo = sw[1];
+  A.G.kfp = sw[2];
+  A.G.V = g.V;
+  A.G.vmask = b >= 64 ? ~0ull : ((1ull << b) - 1);
+  A.G.h = (uint32_t)L.h;
+  A.G.S = L.S;
+  A.G.l = g.l;
+  A.G.sigma = (uint32_t)g.sigma;
+  A.G.b = (uint32_t)b;
+  A.G.is_filter = (uint32_t)is_filter;
+  A.bkeys = bkeys;
+  A.bvals = bvals;
+  A.offsets = offsets;
+  A.cells = cells;
+  A.tseed = tseed;
+  A.scratch = scratch;
+  A.scratch_stride = L.scratch_stride;
+  A.work = work;
+  A.fails = fails;
+  A.fail_cap = L.fail_cap;
+  A.M = M;
+  A.tmax = op.tmax;
+  A.lds_bytes = vfk::kLdsBudget - 1024;
+  A.wmax = vfk::window_slots((uint32_t)g.sigma, A.lds_bytes);
+  A.logcap = L.logcap;
+  A.cell_bytes = L.cell_bytes;
+  A.cells_in_lds = g.V * L.cell_bytes + 256 <= A.lds_bytes ? 1u : 0u;
+  HIPCHK(vfk::launch_fill_u32(work, vfk::kWorkWords, 0, stream));
+  HIPCHK(vfk::launch_build(A, (int)L.nwg, stream));
+  pe.record(3, stream);
+
+  // 4. failure record
+  uint32_t hwork[vfk::kWorkWords];
+  HIPCHK(hipMemcpyAsync(hwork, work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const uint32_t nf = std::min(hwork[vfk::kWorkFails], L.fail_cap);
+  std::vector<vfk::FailRec> fr(nf);
+  if (nf)
+    HIPCHK(hipMemcpyAsync(fr.data(), fails, nf * sizeof(vfk::FailRec), hipMemcpyDeviceToHost,
+                          stream));
+  std::vector<uint8_t> ts(L.S);
+  HIPCHK(hipMemcpyAsync(ts.data(), tseed, L.S, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+#undef HIPCHK
+
+  vf_handle *H = new (std::nothrow) vf_handle();
+  if (!H) return VF_EINVAL;
+  H->magic = kMagic;
+  H->is_filter = is_filter;
+  H->b = b;
+  H->h = L.h;
+  H->S = L.S;
+  H->g = g;
+  H->n = n;
+  H->seed = seed;
+  H->cell_bytes = L.cell_bytes;
+  H->G = A.G;
+  H->cells = cells;
+  H->tseed = tseed;
+  H->ncu = ncu;
+  H->n_fail_total = hwork[vfk::kWorkFails];
+  H->ms[0] = pe.between(0, 1);
+  H->ms[1] = pe.between(1, 2);
+  H->ms[2] = pe.between(2, 3);
+  for (const auto &f : fr) H->fails.push_back(vf_failure{f.shard, f.attempt, f.kind, f.core_edges});
+  std::sort(H->fails.begin(), H->fails.end(), [](const vf_failure &a, const vf_failure &c) {
+    return a.shard != c.shard ? a.shard < c.shard : a.attempt < c.attempt;
+  });
+  H->failed_shards = (uint32_t)std::count(ts.begin(), ts.end(), (uint8_t)255);
+  *handle = H;
+  if (hwork[vfk::kWorkStatus] & vfk::kStatusCapacity) return VF_ECAPACITY;
+  if (H->failed_shards) return VF_EFAIL;
+  return VF_OK;
+}
+
+int vf_build(const uint64_t *keys, const uint64_t *values, uint64_t n, int32_t b, double eps,
+             uint64_t seed, const vf_opts *o, void *workspace, uint64_t workspace_bytes,
+             void *structure, uint64_t structure_bytes, hipStream_t stream,
+             vf_handle **handle) {
+  return build_common(keys, values, n, b, eps, seed, o, workspace, workspace_bytes, structure,
+                      structure_bytes, stream, handle, 0);
+}
+
+int vfilter_build(const uint64_t *keys, uint64_t n, int32_t b, double eps, uint64_t seed,
+                  const vf_opts *o, void *workspace, uint64_t workspace_bytes, void *structure,
+                  uint64_t structure_bytes, hipStream_t stream, vf_handle **handle) {
+  return build_common(keys, nullptr, n, b, eps, seed, o, workspace, workspace_bytes, structure,
+                      structure_bytes, stream, handle, 1);
+}
+
+static int query_common(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
+                        hipStream_t stream, int32_t want_filter) {
+  if (!h || h->magic != kMagic || h->is_filter != want_filter) return VF_EINVAL;
+  if (n && (!keys || !out)) return VF_EINVAL;
+  if (vfk::launch_query(h->G, h->cells, h->cell_bytes, h->tseed, keys, n, out, h->ncu, stream) !=
+      hipSuccess)
+    return VF_EHIP;
+  return VF_OK;
+}
+
+int vf_query(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
+             hipStream_t stream) {
+  return query_common(h, keys, n, out, stream, 0);
+}
+
+int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8_t *out,
+                     hipStream_t stream) {
+  return query_common(h, keys, n, out, stream, 1);
+}
+
+int vf_info(const vf_handle *h, vf_info_t *out) {
+  if (!h || h->magic != kMagic || !out) return VF_EINVAL;
+  out->is_filter = h->is_filter;
+  out->b = h->b;
+  out->h = h->h;
+  out->S = h->S;
+  out->M = h->g.M;
+  out->c_num = h->g.c_num;
+  out->c_den = h->g.c_den;
+  out->sigma = h->g.sigma;
+  out->l = h->g.l;
+  out->V = h->g.V;
+  out->n = h->n;
+  out->seed = h->seed;
+  out->cell_bytes = h->cell_bytes;
+  out->failed_shards = h->failed_shards;
+  out->n_failures = h->n_fail_total;
+  out->space_bits = (uint64_t)h->S * h->g.V * (uint64_t)h->b;
+  out->cells = h->cells;
+  out->local_seeds = h->tseed;
+  out->ms_count = h->ms[0];
+  out->ms_scatter = h->ms[1];
+  out->ms_build = h->ms[2];
+  return VF_OK;
+}
+
+int vf_failures(const vf_handle *h, vf_failure *out, uint32_t cap, uint32_t *count) {
+  if (!h || h->magic != kMagic || !count || (cap && !out)) return VF_EINVAL;
+  *count = h->n_fail_total;
+  const uint32_t k = std::min<uint32_t>(cap, (uint32_t)h->fails.size());
+  for (uint32_t i = 0; i < k; i++) out[i] = h->fails[i];
+  return VF_OK;
+}
+
+void vf_free(vf_handle *h) {
+  if (h && h->magic == kMagic) {
+    h->magic = 0;
+    delete h;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,857 @@
+// gfx950 kernels of the epsilon-cost sharded VFunc / VFilter (S. Vigna,
+// arXiv 2503.18397): signature hashing and shard bucketing (section 4), the
+// per-shard fuse-graph construction (section 4.2) with round-synchronous
+// peeling and Gaussian elimination of the 2-core over GF(2) (sections 3.3,
+// 4.2, 4.3), reverse-order assignment (section 4.3) and the three-probe
+// query (eq. (MWHC)).
+//
+// Definitions every kernel follows (the library's reading of the paper):
+//  * signature = (fin(key ^ k_hi), fin(key ^ k_lo)) with fin the SplitMix64
+//    finalizer and (k_hi, k_lo, k_fp) the first three SplitMix64 outputs
+//    from the user seed;
+//  * shard = top h bits of the first word; segment g = (F * l) >> 32 with F
+//    the 32 bits right below the shard bits (fixed-point inversion);
+//  * offsets = three sigma-bit fields of the second word (local seed t = 0)
+//    or of fin(second word + t * golden gamma) (t > 0);
+//  * fingerprint = top b bits of fin(hi ^ lo ^ k_fp);
+//  * peeling is round-synchronous (degrees frozen at the start of a round,
+//    hinge = first degree-one vertex of the edge);
+//  * the 2-core system gets its lexicographically smallest solution
+//    (vertex 0 most significant): the pivot of every row is its highest
+//    vertex and free vertices are zero.  The elimination below visits
+//    columns from the top of the shard down, so every pivot row it emits
+//    already has its highest vertex as pivot; any pivot choice among the
+//    candidate rows leads to the same solution.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vf_launch.h"
+
+namespace vfk {
+
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
+
+__device__ __forceinline__ uint64_t fin64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t shard_of(uint64_t hi, uint32_t h) {
+  return h ? (uint32_t)(hi >> (64 - h)) : 0u;
+}
+
+// Fuse 3-graph edge of a signature: one vertex in each of the segments
+// g, g + 1, g + 2 of the shard.
+__device__ __forceinline__ void edge3(const Geo &G, uint64_t hi, uint64_t lo,
+                                      uint32_t t, uint32_t &v0, uint32_t &v1,
+                                      uint32_t &v2) {
+  uint32_t F = (uint32_t)((hi << G.h) >> 32);
+  uint32_t g = __umulhi(F, G.l);
+  uint64_t L = t ? fin64(lo + (uint64_t)t * kGamma) : lo;
+  uint32_t s = 1u << G.sigma, m = s - 1;
+  v0 = g * s + ((uint32_t)L & m);
+  v1 = (g + 1) * s + ((uint32_t)(L >> G.sigma) & m);
+  v2 = (g + 2) * s + ((uint32_t)(L >> (2 * G.sigma)) & m);
+}
+
+__device__ __forceinline__ uint64_t fingerprint(const Geo &G, uint64_t hi, uint64_t lo) {
+  uint64_t f = fin64(hi ^ lo ^ G.kfp);
+  return G.b >= 64 ? f : f >> (64 - G.b);
+}
+
+// Packed edge: three 21-bit vertices (cells per shard < 2^21).
+__device__ __forceinline__ uint64_t pack3(uint32_t a, uint32_t b, uint32_t c) {
+  return (uint64_t)a | ((uint64_t)b << 21) | ((uint64_t)c << 42);
+}
+__device__ __forceinline__ void unpack3(uint64_t e, uint32_t v[3]) {
+  v[0] = (uint32_t)(e & 0x1FFFFF);
+  v[1] = (uint32_t)((e >> 21) & 0x1FFFFF);
+  v[2] = (uint32_t)(e >> 42);
+}
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_min64(uint64_t x) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    uint64_t y = __shfl_xor(x, d);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t x) {
+  for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
+  return x;
+}
+
+// Exclusive prefix sum across the wave.
+__device__ __forceinline__ uint32_t wave_exscan(uint32_t x) {
+  uint32_t lane = lane_id(), inc = x;
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(inc, d);
+    if (lane >= (uint32_t)d) inc += y;
+  }
+  return inc - x;
+}
+
+// Reserve one slot per lane with pred in a list whose length lives in LDS;
+// every lane of the wave must call it.
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *counter) {
+  uint64_t mask = __ballot(pred);
+  if (mask == 0) return 0;
+  uint32_t lane = lane_id();
+  int leader = __ffsll((long long)mask) - 1;
+  uint32_t base = 0;
+  if ((int)lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  return base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+constexpr uint32_t kLdsHistMax = 16384;
+
+// Keys per shard (section 4: shard = high signature bits).
+__global__ void k_count(const uint64_t *__restrict__ keys, uint64_t n, uint64_t khi,
+                        uint32_t h, uint32_t S, uint32_t *__restrict__ counts) {
+  extern __shared__ uint32_t hist[];
+  const bool lds = S <= kLdsHistMax;
+  if (lds) {
+    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+  }
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t j = shard_of(fin64(keys[i] ^ khi), h);
+    if (lds) atomicAdd(&hist[j], 1u);
+    else atomicAdd(&counts[j], 1u);
+  }
+  if (lds) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x)
+      if (hist[i]) atomicAdd(&counts[i], hist[i]);
+  }
+}
+
+// Exclusive scan of the shard counts (one workgroup) and the largest shard.
+__global__ void k_scan(const uint32_t *__restrict__ counts, uint32_t S,
+                       uint64_t *__restrict__ offsets, uint64_t *__restrict__ cursor,
+                       uint32_t *__restrict__ max_out) {
+  __shared__ uint64_t part[1024];
+  __shared__ uint32_t mx[1024];
+  const uint32_t T = blockDim.x, tid = threadIdx.x;
+  const uint32_t per = (S + T - 1) / T;
+  const uint32_t lo = tid * per, hi = min(S, lo + per);
+  uint64_t sum = 0;
+  uint32_t m = 0;
+  for (uint32_t i = lo; i < hi; i++) {
+    sum += counts[i];
+    m = max(m, counts[i]);
+  }
+  part[tid] = sum;
+  mx[tid] = m;
+  __syncthreads();
+  for (uint32_t d = 1; d < T; d <<= 1) {
+    uint64_t add = tid >= d ? part[tid - d] : 0;
+    uint32_t mm = tid >= d ? mx[tid - d] : 0;
+    __syncthreads();
+    part[tid] += add;
+    mx[tid] = max(mx[tid], mm);
+    __syncthreads();
+  }
+  uint64_t run = part[tid] - sum;
+  for (uint32_t i = lo; i < hi; i++) {
+    offsets[i] = run;
+    cursor[i] = run;
+    run += counts[i];
+  }
+  if (tid == T - 1) {
+    offsets[S] = part[tid];
+    *max_out = mx[tid];
+  }
+}
+
+constexpr int kScatterThreads = 256;
+constexpr int kScatterPer = 16;
+constexpr uint32_t kScatterLdsMax = 8192;
+
+// Group keys (and values) by shard: a counting sort whose per-workgroup
+// counts reserve each shard's range with one atomic per shard.
+__global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ vals,
+                          uint64_t n, uint64_t khi, uint32_t h, uint32_t S,
+                          unsigned long long *__restrict__ cursor,
+                          uint64_t *__restrict__ bkeys, uint64_t *__restrict__ bvals) {
+  extern __shared__ uint64_t sbase[];
+  uint32_t *cnt = (uint32_t *)(sbase + (S <= kScatterLdsMax ? S : 0));
+  const bool lds = S <= kScatterLdsMax;
+  const uint64_t chunk = (uint64_t)kScatterThreads * kScatterPer;
+  const uint64_t nchunks = (n + chunk - 1) / chunk;
+  for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    if (lds) {
+      for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) cnt[i] = 0;
+      __syncthreads();
+    }
+    uint32_t js[kScatterPer], rk[kScatterPer];
+#pragma unroll
+    for (int q = 0; q < kScatterPer; q++) {
+      uint64_t i = c * chunk + (uint64_t)q * kScatterThreads + threadIdx.x;
+      js[q] = 0xFFFFFFFFu;
+      if (i < n) {
+        js[q] = shard_of(fin64(keys[i] ^ khi), h);
+        if (lds) rk[q] = atomicAdd(&cnt[js[q]], 1u);
+      }
+    }
+    if (lds) {
+      __syncthreads();
+      for (uint32_t j = threadIdx.x; j < S; j += blockDim.x)
+        if (cnt[j]) sbase[j] = atomicAdd(&cursor[j], (unsigned long long)cnt[j]);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kScatterPer; q++) {
+      uint64_t i = c * chunk + (uint64_t)q * kScatterThreads + threadIdx.x;
+      if (js[q] != 0xFFFFFFFFu) {
+        uint64_t pos = lds ? sbase[js[q]] + rk[q] : atomicAdd(&cursor[js[q]], 1ull);
+        bkeys[pos] = keys[i];
+        if (vals) bvals[pos] = vals[i];
+      }
+    }
+    if (lds) __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- shard build
+
+// Per-workgroup scratch (global memory), sized for the largest shard.
+struct Scratch {
+  uint64_t *E;      // packed edges
+  uint64_t *R;      // right sides (values or fingerprints)
+  uint32_t *deg;    // vertex degrees
+  uint32_t *xr;     // xor of incident edge indices (Djamal's trick, section 4.3)
+  uint8_t *pe;      // 1 = edge peeled
+  uint32_t *stack;  // peeled edges in round order: index | side << 30
+  uint32_t *rst;    // round starts in stack
+  uint32_t *F0, *F1;// frontiers of degree-one vertices
+  uint32_t *core;   // core edges grouped by their top vertex (entry groups)
+  uint32_t *cb;     // group starts
+  uint32_t *cc;     // group cursors
+  uint32_t *poff;   // pivot record offsets
+  uint32_t *plog;   // pivot records
+};
+
+__host__ __device__ inline uint64_t align8(uint64_t x) { return (x + 7) & ~7ull; }
+
+// Core rows enter the elimination window in groups: the 32 columns of one
+// ring word (segments of at least 32 vertices) or one segment (smaller
+// segments), keyed by the row's top vertex.
+__host__ __device__ inline uint32_t entry_shift(uint32_t sigma) { return sigma < 5 ? sigma : 5; }
+__host__ __device__ inline uint64_t max_groups(uint64_t V, uint32_t l) { return (V >> 5) + l + 8; }
+
+__host__ __device__ inline uint64_t scratch_layout(uint8_t *base, uint32_t M, uint64_t V,
+                                                  uint32_t l, uint32_t logcap, Scratch *s) {
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    uint8_t *p = base ? base + o : nullptr;
+    o += align8(bytes);
+    return p;
+  };
+  uint64_t m = (uint64_t)M + 1;
+  Scratch t;
+  t.E = (uint64_t *)take(8 * m);
+  t.R = (uint64_t *)take(8 * m);
+  t.deg = (uint32_t *)take(4 * V);
+  t.xr = (uint32_t *)take(4 * V);
+  t.pe = (uint8_t *)take(m);
+  t.stack = (uint32_t *)take(4 * m);
+  t.rst = (uint32_t *)take(4 * (m + 2));
+  t.F0 = (uint32_t *)take(4 * V);
+  t.F1 = (uint32_t *)take(4 * V);
+  t.core = (uint32_t *)take(4 * m);
+  t.cb = (uint32_t *)take(4 * max_groups(V, l));
+  t.cc = (uint32_t *)take(4 * max_groups(V, l));
+  t.poff = (uint32_t *)take(4 * m);
+  t.plog = (uint32_t *)take(4 * (uint64_t)logcap);
+  if (s) *s = t;
+  return o;
+}
+
+uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap) {
+  return scratch_layout(nullptr, M, V, l, logcap, nullptr);
+}
+
+// Ring rows of the elimination window hold 4 segments (4 s bits): a window
+// row always lies within 3 consecutive segments (see band_solve).
+__host__ __device__ inline uint32_t ring_words(uint32_t sigma) {
+  uint32_t bits = 4u << sigma;
+  return bits < 32 ? 1u : bits / 32;
+}
+
+// Bytes of one window slot: ring row + rhs (8) + popcount (4) + free-list entry (4).
+__host__ __device__ inline uint32_t slot_bytes(uint32_t sigma) {
+  return 4 * ring_words(sigma) + 16;
+}
+
+uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes) {
+  uint32_t reserve = 1024;  // batch arrays of the back-substitution
+  uint32_t n = (lds_bytes - reserve) / slot_bytes(sigma);
+  n = n > 1024 ? 1024 : n;
+  return n & ~7u;  // keeps the 8-byte right sides after the rows aligned
+}
+
+enum { kSolveOk = 0, kSolveInconsistent = 1, kSolveCapacity = 2 };
+
+// Gaussian elimination of the 2-core over GF(2), one wavefront.  Core rows
+// enter the window when the sweep reaches their entry group; columns are
+// visited from the highest vertex down.  For column c every window row that
+// contains c is a candidate; one of them (fewest nonzeros first: least fill)
+// becomes the pivot row of c and is xored into the other candidates.  A row
+// in the window while segment G is swept only has vertices in segments
+// G-2..G, so it fits a ring of 4 segments addressed by vertex mod 4s.
+// Pivot rows are appended to a log: [column, count, rhs lo, rhs hi,
+// vertices...]; poff[i] is the offset of the i-th (descending column).
+__device__ int band_solve(const BuildArgs &A, const Scratch &sc, uint8_t *lds,
+                          uint32_t *np_out) {
+  const Geo &G = A.G;
+  const uint32_t lane = lane_id();
+  const uint32_t sigma = G.sigma, s = 1u << sigma;
+  const uint32_t ringbits = 4u << sigma, ringmask = ringbits - 1;
+  const uint32_t RW = ring_words(sigma);
+  const uint32_t W = A.wmax;
+  const uint32_t NQ = (W + 63) / 64;
+  uint32_t *rows = (uint32_t *)lds;
+  uint64_t *rrhs = (uint64_t *)(lds + (uint64_t)4 * RW * W);
+  uint32_t *rpop = (uint32_t *)(rrhs + W);
+  uint32_t *freel = rpop + W;
+
+  for (uint32_t i = lane; i < W; i += 64) {
+    rpop[i] = 0;
+    freel[i] = i;
+  }
+  uint32_t nfree = W;
+  uint32_t lp = 0, np = 0;
+  wave_sync();
+
+  const uint32_t gsh = entry_shift(sigma);
+  // rows of entry group g join the window
+  auto enter = [&](uint32_t g) -> bool {
+    const uint32_t rb = sc.cb[g], re = sc.cb[g + 1];
+    for (uint32_t r0 = rb; r0 < re; r0 += 64) {
+      uint32_t cnt = min(64u, re - r0);
+      if (cnt > nfree) return false;
+      if (lane < cnt) {
+        uint32_t e = sc.core[r0 + lane];
+        uint32_t slot = freel[nfree - 1 - lane];
+        uint32_t v[3];
+        unpack3(sc.E[e], v);
+        uint32_t *row = rows + (uint64_t)slot * RW;
+        for (uint32_t u = 0; u < RW; u++) row[u] = 0;
+        for (int k = 0; k < 3; k++) {
+          uint32_t p = v[k] & ringmask;
+          row[p >> 5] |= 1u << (p & 31);
+        }
+        rrhs[slot] = sc.R[e];
+        rpop[slot] = 3;
+      }
+      nfree -= cnt;
+      wave_sync();
+    }
+    return true;
+  };
+
+  for (int Gs = (int)G.l + 1; Gs >= 0; Gs--) {
+    if (gsh < 5 && !enter((uint32_t)Gs)) return kSolveCapacity;
+    // sweep the columns of segment Gs from the top
+    const uint32_t gbase = Gs >= 2 ? (uint32_t)(Gs - 2) * s : 0u;
+    const uint32_t gring = gbase & ringmask;
+    const uint32_t segtop = (uint32_t)(Gs + 1) * s - 1, segbot = (uint32_t)Gs * s;
+    uint32_t c = segtop;
+    for (;;) {
+      if (gsh == 5 && !enter(c >> 5)) return kSolveCapacity;
+      const uint32_t cpos = c & ringmask, word = cpos >> 5;
+      const uint32_t wlo_col = max(segbot, c - (cpos & 31));  // lowest column of this word in the segment
+      const uint32_t lowbit = (wlo_col & ringmask) & 31;
+      uint32_t hibit = cpos & 31;
+      auto colmask_below = [&](uint32_t top) -> uint32_t {
+        // OR over live rows of this word, restricted to bits lowbit..top
+        uint32_t acc = 0;
+        for (uint32_t q = 0; q < NQ; q++) {
+          uint32_t slot = q * 64 + lane;
+          if (slot < W && rpop[slot]) acc |= rows[(uint64_t)slot * RW + word];
+        }
+        acc = wave_or(acc);
+        uint32_t hm = top >= 31 ? 0xFFFFFFFFu : ((2u << top) - 1u);
+        uint32_t lm = ~((1u << lowbit) - 1u);
+        return acc & hm & lm;
+      };
+      uint32_t colmask = colmask_below(hibit);
+      while (colmask) {
+        const uint32_t b = 31 - __clz(colmask);
+        const uint32_t col = (c - (cpos & 31)) + b;
+        // candidates and pivot (fewest nonzeros, then lowest slot)
+        uint64_t best = ~0ull;
+        uint64_t cand[16];
+        for (uint32_t q = 0; q < NQ; q++) {
+          uint32_t slot = q * 64 + lane;
+          bool has = slot < W && rpop[slot] &&
+                     ((rows[(uint64_t)slot * RW + word] >> b) & 1u);
+          cand[q] = __ballot(has);
+          if (has) {
+            uint64_t key = ((uint64_t)rpop[slot] << 32) | slot;
+            best = key < best ? key : best;
+          }
+        }
+        best = wave_min64(best);
+        const uint32_t p = (uint32_t)best;
+        const uint32_t *prow = rows + (uint64_t)p * RW;
+        // emit the pivot row (all vertices below col)
+        uint32_t mycnt = 0;
+        for (uint32_t u = lane; u < RW; u += 64) {
+          uint32_t bits = prow[u];
+          if (u == word) bits &= ~(1u << b);
+          mycnt += __popc(bits);
+        }
+        const uint32_t tot = wave_sum(mycnt);
+        uint32_t pre = wave_exscan(mycnt);
+        if (lp + 4 + tot > A.logcap) return kSolveCapacity;
+        const uint64_t prhs = rrhs[p];
+        if (lane == 0) {
+          sc.plog[lp] = col;
+          sc.plog[lp + 1] = tot;
+          sc.plog[lp + 2] = (uint32_t)prhs;
+          sc.plog[lp + 3] = (uint32_t)(prhs >> 32);
+          sc.poff[np] = lp;
+        }
+        for (uint32_t u = lane; u < RW; u += 64) {
+          uint32_t bits = prow[u];
+          if (u == word) bits &= ~(1u << b);
+          while (bits) {
+            uint32_t bb = __ffs(bits) - 1;
+            bits &= bits - 1;
+            uint32_t pos = u * 32 + bb;
+            sc.plog[lp + 4 + pre++] = gbase + ((pos - gring) & ringmask);
+          }
+        }
+        lp += 4 + tot;
+        np++;
+        // eliminate col from the other candidate rows
+        for (uint32_t q = 0; q < NQ; q++) {
+          uint64_t m = cand[q];
+          if (q == p / 64) m &= ~(1ull << (p % 64));
+          while (m) {
+            const uint32_t x = q * 64 + (uint32_t)(__ffsll((long long)m) - 1);
+            m &= m - 1;
+            uint32_t *xrow = rows + (uint64_t)x * RW;
+            uint32_t pc = 0;
+            for (uint32_t u = lane; u < RW; u += 64) {
+              uint32_t nv = xrow[u] ^ prow[u];
+              xrow[u] = nv;
+              pc += __popc(nv);
+            }
+            pc = wave_sum(pc);
+            const uint64_t xr = rrhs[x] ^ prhs;
+            wave_sync();
+            if (lane == 0) {
+              rrhs[x] = xr;
+              rpop[x] = pc;
+            }
+            if (pc == 0) {
+              if (xr != 0) return kSolveInconsistent;
+              if (lane == 0) freel[nfree] = x;
+              nfree++;
+            }
+            wave_sync();
+          }
+        }
+        if (lane == 0) {
+          rpop[p] = 0;
+          freel[nfree] = p;
+        }
+        nfree++;
+        wave_sync();
+        colmask = b > lowbit ? colmask_below(b - 1) : 0u;
+      }
+      if (wlo_col == segbot) break;
+      c = wlo_col - 1;
+    }
+  }
+  *np_out = np;
+  return kSolveOk;
+}
+
+// Back-substitution in increasing pivot column, 64 pivots per step: each
+// lane gathers the values of vertices below its batch, then the in-batch
+// dependencies are resolved lane by lane.  Values of free vertices are 0.
+template <typename T>
+__device__ void back_substitute(const Scratch &sc, uint32_t np, T *wl, uint32_t *bcol) {
+  const uint32_t lane = lane_id();
+  for (uint32_t bs = 0; bs < np; bs += 64) {
+    const uint32_t i = bs + lane;
+    const bool valid = i < np;
+    const uint32_t *rec = valid ? sc.plog + sc.poff[np - 1 - i] : nullptr;
+    const uint32_t col = valid ? rec[0] : 0xFFFFFFFFu;
+    bcol[lane] = col;
+    wave_sync();
+    const uint32_t bmin = bcol[0];
+    uint64_t acc = 0, dep = 0;
+    if (valid) {
+      acc = (uint64_t)rec[2] | ((uint64_t)rec[3] << 32);
+      const uint32_t cnt = rec[1];
+      for (uint32_t e = 0; e < cnt; e++) {
+        const uint32_t v = rec[4 + e];
+        if (v < bmin) {
+          acc ^= (uint64_t)wl[v];
+        } else {
+          uint32_t lo = 0, hi = lane;  // bcol is increasing; v < col
+          while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (bcol[mid] < v) lo = mid + 1;
+            else hi = mid;
+          }
+          if (lo < lane && bcol[lo] == v) dep |= 1ull << lo;
+        }
+      }
+    }
+    uint64_t x = acc;
+    for (uint32_t k = 0; k < 64 && bs + k < np; k++) {
+      uint64_t xk = __shfl(x, (int)k);
+      if ((dep >> k) & 1ull) x ^= xk;
+    }
+    if (valid) wl[col] = (T)x;
+    wave_sync();
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBuildThreads)
+k_build(BuildArgs A) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  __shared__ uint32_t sh_j, sh_nf, sh_nn, sh_nst, sh_st, sh_np, sh_k, sh_t;
+  const Geo &G = A.G;
+  const uint32_t tid = threadIdx.x, NT = blockDim.x;
+  const uint64_t V = G.V;
+  Scratch sc;
+  scratch_layout(A.scratch + (uint64_t)blockIdx.x * A.scratch_stride, A.M, V, G.l, A.logcap, &sc);
+  T *cells = (T *)A.cells;
+
+  for (;;) {
+    if (tid == 0) sh_j = atomicAdd(&A.work[kWorkNext], 1u);
+    __syncthreads();
+    const uint32_t j = sh_j;
+    if (j >= G.S) break;
+    const uint64_t base = A.offsets[j];
+    const uint32_t m = (uint32_t)(A.offsets[j + 1] - base);
+    T *wg = cells + (uint64_t)j * V;  // this shard's cells in HBM
+    T *wl = A.cells_in_lds ? (T *)lds : wg;
+
+    // right sides: values (Problem 1) or fingerprints (Problem 2)
+    for (uint32_t i = tid; i < m; i += NT) {
+      const uint64_t key = A.bkeys[base + i];
+      if (G.is_filter) {
+        sc.R[i] = fingerprint(G, fin64(key ^ G.khi), fin64(key ^ G.klo));
+      } else {
+        sc.R[i] = A.bvals[base + i] & G.vmask;
+      }
+    }
+
+    uint32_t t = 0;
+    uint8_t result_t = 255;
+    for (; t < A.tmax; t++) {
+      // edges of this attempt, cleared vertex state
+      for (uint32_t i = tid; i < m; i += NT) {
+        const uint64_t key = A.bkeys[base + i];
+        uint32_t v0, v1, v2;
+        edge3(G, fin64(key ^ G.khi), fin64(key ^ G.klo), t, v0, v1, v2);
+        sc.E[i] = pack3(v0, v1, v2);
+        sc.pe[i] = 0;
+      }
+      for (uint64_t v = tid; v < V; v += NT) {
+        sc.deg[v] = 0;
+        sc.xr[v] = 0;
+      }
+      __syncthreads();
+      // incidence: degree and xor of incident edges
+      for (uint32_t i = tid; i < m; i += NT) {
+        uint32_t v[3];
+        unpack3(sc.E[i], v);
+        for (int k = 0; k < 3; k++) {
+          atomicAdd(&sc.deg[v[k]], 1u);
+          atomicXor(&sc.xr[v[k]], i);
+        }
+      }
+      if (tid == 0) {
+        sh_nf = 0;
+        sh_nst = 0;
+      }
+      __syncthreads();
+      // round-synchronous peeling
+      for (uint64_t v0 = 0; v0 < V; v0 += NT) {
+        const uint64_t v = v0 + tid;
+        const bool one = v < V && sc.deg[v] == 1;
+        const uint32_t pos = wave_append(one, &sh_nf);
+        if (one) sc.F0[pos] = (uint32_t)v;
+      }
+      __syncthreads();
+      uint32_t nf = sh_nf, nrounds = 0, nst = 0;
+      uint32_t *cur = sc.F0, *nxt = sc.F1;
+      if (tid == 0) sc.rst[0] = 0;
+      while (nf) {
+        // select with the degrees of the start of the round
+        for (uint32_t i0 = 0; i0 < nf; i0 += NT) {
+          const uint32_t i = i0 + tid;
+          bool take = false;
+          uint32_t e = 0, side = 0;
+          if (i < nf) {
+            const uint32_t v = cur[i];
+            if (sc.deg[v] == 1) {
+              e = sc.xr[v];
+              uint32_t a[3];
+              unpack3(sc.E[e], a);
+              side = a[0] == v ? 0u : (a[1] == v ? 1u : 2u);
+              take = true;
+              for (uint32_t k = 0; k < side; k++)
+                if (sc.deg[a[k]] == 1) take = false;
+            }
+          }
+          const uint32_t pos = wave_append(take, &sh_nst);
+          if (take) {
+            sc.stack[pos] = e | (side << 30);
+            sc.pe[e] = 1;
+          }
+        }
+        if (tid == 0) sh_nn = 0;
+        __syncthreads();
+        const uint32_t r0 = nst, r1 = sh_nst;
+        // remove the selected edges
+        for (uint32_t i0 = r0; i0 < r1; i0 += NT) {
+          const uint32_t i = i0 + tid;
+          bool push[3] = {false, false, false};
+          uint32_t a[3] = {0, 0, 0};
+          if (i < r1) {
+            const uint32_t e = sc.stack[i] & 0x3FFFFFFFu;
+            unpack3(sc.E[e], a);
+            for (int k = 0; k < 3; k++) {
+              const uint32_t old = atomicSub(&sc.deg[a[k]], 1u);
+              atomicXor(&sc.xr[a[k]], e);
+              push[k] = old == 2;
+            }
+          }
+          for (int k = 0; k < 3; k++) {
+            const uint32_t pos = wave_append(push[k], &sh_nn);
+            if (push[k]) nxt[pos] = a[k];
+          }
+        }
+        __syncthreads();
+        nst = r1;
+        nrounds++;
+        if (tid == 0) sc.rst[nrounds] = nst;
+        nf = sh_nn;
+        uint32_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        __syncthreads();
+      }
+
+      // 2-core edges, grouped by the entry group of their top vertex
+      const uint32_t gsh = entry_shift(G.sigma);
+      const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
+      for (uint32_t g = tid; g < ngroups; g += NT) sc.cc[g] = 0;
+      __syncthreads();
+      for (uint32_t i = tid; i < m; i += NT)
+        if (!sc.pe[i]) atomicAdd(&sc.cc[(uint32_t)(sc.E[i] >> 42) >> gsh], 1u);
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t run = 0;
+        for (uint32_t g = 0; g < ngroups; g++) {
+          uint32_t c = sc.cc[g];
+          sc.cb[g] = run;
+          sc.cc[g] = run;
+          run += c;
+        }
+        sh_k = run;
+      }
+      __syncthreads();
+      for (uint32_t i = tid; i < m; i += NT)
+        if (!sc.pe[i]) {
+          const uint32_t g = (uint32_t)(sc.E[i] >> 42) >> gsh;
+          sc.core[atomicAdd(&sc.cc[g], 1u)] = i;
+        }
+      __syncthreads();
+      const uint32_t k = sh_k;
+
+      uint32_t np = 0;
+      if (tid < 64) {
+        int st = kSolveOk;
+        if (k) st = band_solve(A, sc, lds, &np);
+        if (tid == 0) {
+          sh_st = (uint32_t)st;
+          sh_np = np;
+        }
+      }
+      __syncthreads();
+      const uint32_t st = sh_st;
+      np = sh_np;
+      if (st == kSolveCapacity) {
+        if (tid == 0) atomicOr(&A.work[kWorkStatus], kStatusCapacity);
+        break;
+      }
+      if (st == kSolveInconsistent) {
+        if (tid == 0) {
+          const uint32_t idx = atomicAdd(&A.work[kWorkFails], 1u);
+          if (idx < A.fail_cap) A.fails[idx] = FailRec{j, t, 1u, k};
+        }
+        __syncthreads();
+        continue;
+      }
+      // cells: zero, core values by back-substitution, then peeled edges
+      for (uint64_t v = tid; v < V; v += NT) wl[v] = (T)0;
+      __syncthreads();
+      if (tid < 64 && np) {
+        uint32_t *bcol = (uint32_t *)(lds + (A.cells_in_lds ? A.lds_bytes - 256 : 0));
+        back_substitute<T>(sc, np, wl, bcol);
+      }
+      __syncthreads();
+      for (int r = (int)nrounds - 1; r >= 0; r--) {
+        const uint32_t e0 = sc.rst[r], e1 = sc.rst[r + 1];
+        for (uint32_t i = e0 + tid; i < e1; i += NT) {
+          const uint32_t ent = sc.stack[i];
+          const uint32_t e = ent & 0x3FFFFFFFu, side = ent >> 30;
+          uint32_t a[3];
+          unpack3(sc.E[e], a);
+          uint64_t val = sc.R[e];
+          for (uint32_t q = 0; q < 3; q++)
+            if (q != side) val ^= (uint64_t)wl[a[q]];
+          wl[a[side]] = (T)val;
+        }
+        __syncthreads();
+      }
+      if (A.cells_in_lds)
+        for (uint64_t v = tid; v < V; v += NT) wg[v] = wl[v];
+      result_t = (uint8_t)t;
+      break;
+    }
+    if (result_t == 255) {
+      // every attempt failed (or a capacity limit was hit): zero cells
+      for (uint64_t v = tid; v < V; v += NT) wg[v] = (T)0;
+    }
+    if (tid == 0) A.tseed[j] = result_t;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ query
+
+template <typename T>
+__global__ void k_query(Geo G, const T *__restrict__ cells, const uint8_t *__restrict__ tseed,
+                        const uint64_t *__restrict__ keys, uint64_t n, void *__restrict__ out) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = keys[i];
+    const uint64_t hi = fin64(key ^ G.khi), lo = fin64(key ^ G.klo);
+    const uint32_t j = shard_of(hi, G.h);
+    uint32_t v0, v1, v2;
+    edge3(G, hi, lo, tseed[j], v0, v1, v2);
+    const T *w = cells + (uint64_t)j * G.V;
+    const T x = w[v0] ^ w[v1] ^ w[v2];
+    if (G.is_filter) ((uint8_t *)out)[i] = (uint64_t)x == fingerprint(G, hi, lo);
+    else ((T *)out)[i] = x;
+  }
+}
+
+// ----------------------------------------------------------------- launch
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (!n) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
+                        uint32_t S, uint32_t *counts, int ncu, hipStream_t s) {
+  if (!n) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  uint64_t cap = (uint64_t)ncu * (S <= 1024 ? 8 : 4);
+  if (blocks > cap) blocks = cap;
+  size_t shm = S <= kLdsHistMax ? (size_t)S * 4 : 0;
+  hipLaunchKernelGGL(k_count, dim3((uint32_t)blocks), dim3(256), shm, s, keys, n, khi, h, S,
+                     counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t *counts, uint32_t S, uint64_t *offsets,
+                       uint64_t *cursor, uint32_t *max_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, S, offsets, cursor, max_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n,
+                          uint64_t khi, uint32_t h, uint32_t S, uint64_t *cursor,
+                          uint64_t *bkeys, uint64_t *bvals, int ncu, hipStream_t s) {
+  if (!n) return hipSuccess;
+  const uint64_t chunk = (uint64_t)kScatterThreads * kScatterPer;
+  uint64_t blocks = (n + chunk - 1) / chunk;
+  uint64_t cap = (uint64_t)ncu * 4;
+  if (blocks > cap) blocks = cap;
+  size_t shm = S <= kScatterLdsMax ? (size_t)S * 12 : 0;
+  hipLaunchKernelGGL(k_scatter, dim3((uint32_t)blocks), dim3(kScatterThreads), shm, s, keys, vals,
+                     n, khi, h, S, (unsigned long long *)cursor, bkeys, bvals);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_build_t(const BuildArgs &a, int nwg, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_build<T>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)a.lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_build<T>, dim3(nwg), dim3(kBuildThreads), a.lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s) {
+  switch (a.cell_bytes) {
+    case 1: return launch_build_t<uint8_t>(a, nwg, s);
+    case 2: return launch_build_t<uint16_t>(a, nwg, s);
+    case 4: return launch_build_t<uint32_t>(a, nwg, s);
+    default: return launch_build_t<uint64_t>(a, nwg, s);
+  }
+}
+
+hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
+                        const uint8_t *tseed, const uint64_t *keys, uint64_t n,
+                        void *out, int ncu, hipStream_t s) {
+  if (!n) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  uint64_t cap = (uint64_t)ncu * 64;
+  if (blocks > cap) blocks = cap;
+  dim3 g((uint32_t)blocks), b(256);
+  switch (cell_bytes) {
+    case 1: hipLaunchKernelGGL(k_query<uint8_t>, g, b, 0, s, G, (const uint8_t *)cells, tseed, keys, n, out); break;
+    case 2: hipLaunchKernelGGL(k_query<uint16_t>, g, b, 0, s, G, (const uint16_t *)cells, tseed, keys, n, out); break;
+    case 4: hipLaunchKernelGGL(k_query<uint32_t>, g, b, 0, s, G, (const uint32_t *)cells, tseed, keys, n, out); break;
+    default: hipLaunchKernelGGL(k_query<uint64_t>, g, b, 0, s, G, (const uint64_t *)cells, tseed, keys, n, out); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vfk

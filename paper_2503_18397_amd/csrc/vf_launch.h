@@ -1,0 +1,71 @@
+// Internal interface between the host orchestration (vf_api.cpp) and the
+// gfx950 kernels (vf_device.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vfk {
+
+// Per-structure constants every kernel needs.
+struct Geo {
+  uint64_t khi, klo, kfp;  // seed words of the two signature halves and fingerprint
+  uint64_t V;              // cells per shard
+  uint64_t vmask;          // low-b-bit mask of values and fingerprints
+  uint32_t h;              // shard bits
+  uint32_t S;              // shards
+  uint32_t l;              // start segments per shard
+  uint32_t sigma;          // lg segment size
+  uint32_t b;              // value / fingerprint bits
+  uint32_t is_filter;
+};
+
+struct FailRec {
+  uint32_t shard, attempt, kind, core_edges;
+};
+
+// Counters shared by all build workgroups.
+enum : uint32_t { kWorkNext = 0, kWorkFails = 1, kWorkStatus = 2, kWorkWords = 4 };
+enum : uint32_t { kStatusCapacity = 1u };
+
+struct BuildArgs {
+  Geo G;
+  const uint64_t *bkeys;    // keys grouped by shard
+  const uint64_t *bvals;    // values grouped by shard (function only)
+  const uint64_t *offsets;  // S + 1 shard starts
+  void *cells;              // S * V cells of cell_bytes
+  uint8_t *tseed;           // S local seeds (255: failed)
+  uint8_t *scratch;         // per-workgroup scratch, scratch_stride bytes each
+  uint64_t scratch_stride;
+  uint32_t *work;           // kWorkWords counters
+  FailRec *fails;
+  uint32_t fail_cap;
+  uint32_t M;               // keys in the largest shard
+  uint32_t tmax;            // local seeds per shard
+  uint32_t wmax;            // elimination window slots
+  uint32_t logcap;          // pivot log words per workgroup
+  uint32_t lds_bytes;       // dynamic LDS of the launch
+  uint32_t cell_bytes;      // 1, 2, 4 or 8
+  uint32_t cells_in_lds;    // 1: shard cells fit in LDS during assignment
+};
+
+constexpr int kBuildThreads = 256;
+constexpr uint32_t kLdsBudget = 160 * 1024;
+
+uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap);
+uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes);
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_count(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
+                        uint32_t S, uint32_t *counts, int ncu, hipStream_t s);
+hipError_t launch_scan(const uint32_t *counts, uint32_t S, uint64_t *offsets,
+                       uint64_t *cursor, uint32_t *max_out, hipStream_t s);
+hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n,
+                          uint64_t khi, uint32_t h, uint32_t S, uint64_t *cursor,
+                          uint64_t *bkeys, uint64_t *bvals, int ncu, hipStream_t s);
+hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s);
+hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
+                        const uint8_t *tseed, const uint64_t *keys, uint64_t n,
+                        void *out, int ncu, hipStream_t s);
+
+}  // namespace vfk

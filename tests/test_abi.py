@@ -1,0 +1,72 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/vf.h declares, and its host-side planning agrees with the paper's
+formulas (no GPU compute is called here)."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "vf.h")
+LIB = os.path.join(ROOT, "paper_2503_18397_amd", "libvf.so")
+
+
+def _declared():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void)\s+\**\s*(vf\w*|vfilter\w*)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ("vf_plan", "vf_build", "vf_query", "vfilter_build", "vfilter_contains",
+                 "vf_info", "vf_failures", "vf_free", "vf_default_opts"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first (python -m paper_2503_18397_amd.build)"
+    out = subprocess.check_output(["nm", "-D", "--defined-only", LIB], text=True)
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    lib = C.CDLL(LIB)
+    for name in _declared():
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_binding_exports_the_same_names():
+    import paper_2503_18397_amd as vf
+    for name in _declared():
+        assert hasattr(vf, name), name
+
+
+def test_plan_uses_eq_logballsbins_and_sizes_the_cells():
+    import paper_2503_18397_amd as vf
+    for n, eps in [(1 << 27, 0.0175), (10**6, 0.001), (1 << 20, 0.05), (5000, 0.5)]:
+        s = vf.vf_plan(n, 8, eps, True, None)
+        assert s.h == O.shard_bits_eps(n, eps)
+        S = 1 << s.h
+        g = O.geometry(s.shard_cap, s.h)
+        assert s.structure_bytes >= S * g["V"]  # one byte per cell at b = 8
+        assert s.shard_cap >= n / S
+    s = vf.vf_plan(1 << 27, 8, 0.0175, True, None)
+    assert s.h == 11 and s.shard_cap < 1.05 * (1 << 16)
+
+
+def test_plan_rejects_bad_arguments():
+    import paper_2503_18397_amd as vf
+    for b in (0, 65):
+        with pytest.raises(vf.VFError) as e:
+            vf.vf_plan(1000, b, 0.01, True, None)
+        assert e.value.code == vf.VF_EINVAL
+    with pytest.raises(vf.VFError):
+        vf.vf_plan(1000, 8, 0.0, True, None)  # no eps and no h
+    with pytest.raises(vf.VFError):
+        vf.vf_plan(1000, 8, 0.01, True, vf.vf_default_opts(tmax=0))
+    with pytest.raises(vf.VFError):
+        vf.vf_plan(1000, 8, 0.01, True, vf.vf_default_opts(h=25))

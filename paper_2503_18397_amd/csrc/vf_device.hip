@@ -72,39 +72,64 @@ __device__ __forceinline__ void unpack3(uint64_t e, uint32_t v[3]) {
 
 // ---------------------------------------------------------------- helpers
 
+// Orders LDS traffic between the lanes of one wavefront (the LDS serves a
+// wavefront's instructions in order; this only stops compiler reordering).
 __device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Also waits for the wavefront's global-memory stores, for data exchanged
+// between lanes through global memory.
+__device__ __forceinline__ void wave_sync_global() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
-  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
-  return x;
+// Cross-lane reductions with DPP (VALU only, no LDS round trip): within each
+// row of 16 lanes quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror
+// and row_mirror leave the row's total in every lane; the four row totals
+// are then combined from lanes 0, 16, 32 and 48.
+#define VF_DPP(x, ctrl, id) __builtin_amdgcn_update_dpp((id), (x), (ctrl), 0xF, 0xF, false)
+constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E, kRowHalfMirror = 0x141, kRowMirror = 0x140;
+
+__device__ __forceinline__ uint32_t readlane(uint32_t x, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
+}
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int lane) {
+  return (uint64_t)readlane((uint32_t)x, lane) | ((uint64_t)readlane((uint32_t)(x >> 32), lane) << 32);
 }
 
-__device__ __forceinline__ uint64_t wave_min64(uint64_t x) {
-  for (int d = 32; d >= 1; d >>= 1) {
-    uint64_t y = __shfl_xor(x, d);
-    x = y < x ? y : x;
-  }
-  return x;
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+  x += VF_DPP(x, kQuadSwap1, 0u);
+  x += VF_DPP(x, kQuadSwap2, 0u);
+  x += VF_DPP(x, kRowHalfMirror, 0u);
+  x += VF_DPP(x, kRowMirror, 0u);
+  return readlane(x, 0) + readlane(x, 16) + readlane(x, 32) + readlane(x, 48);
 }
 
 __device__ __forceinline__ uint32_t wave_or(uint32_t x) {
-  for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
-  return x;
+  x |= VF_DPP(x, kQuadSwap1, 0u);
+  x |= VF_DPP(x, kQuadSwap2, 0u);
+  x |= VF_DPP(x, kRowHalfMirror, 0u);
+  x |= VF_DPP(x, kRowMirror, 0u);
+  return readlane(x, 0) | readlane(x, 16) | readlane(x, 32) | readlane(x, 48);
 }
 
-// Exclusive prefix sum across the wave.
-__device__ __forceinline__ uint32_t wave_exscan(uint32_t x) {
-  uint32_t lane = lane_id(), inc = x;
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(inc, d);
-    if (lane >= (uint32_t)d) inc += y;
-  }
-  return inc - x;
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+  x = min(x, (uint32_t)VF_DPP(x, kQuadSwap1, 0xFFFFFFFFu));
+  x = min(x, (uint32_t)VF_DPP(x, kQuadSwap2, 0xFFFFFFFFu));
+  x = min(x, (uint32_t)VF_DPP(x, kRowHalfMirror, 0xFFFFFFFFu));
+  x = min(x, (uint32_t)VF_DPP(x, kRowMirror, 0xFFFFFFFFu));
+  return min(min(readlane(x, 0), readlane(x, 16)), min(readlane(x, 32), readlane(x, 48)));
+}
+
+// Number of set bits of mask in lanes below this one.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
 // Reserve one slot per lane with pred in a list whose length lives in LDS;
@@ -116,8 +141,8 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *counter) {
   int leader = __ffsll((long long)mask) - 1;
   uint32_t base = 0;
   if ((int)lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-  base = __shfl(base, leader);
-  return base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+  base = readlane(base, leader);
+  return base + lanes_below(mask);
 }
 
 // ------------------------------------------------------------ small kernels
@@ -252,6 +277,8 @@ struct Scratch {
   uint32_t *rst;    // round starts in stack
   uint32_t *F0, *F1;// frontiers of degree-one vertices
   uint32_t *core;   // core edges grouped by their top vertex (entry groups)
+  uint64_t *cE;     // packed edges of the grouped core rows
+  uint64_t *cR;     // right sides of the grouped core rows
   uint32_t *cb;     // group starts
   uint32_t *cc;     // group cursors
   uint32_t *poff;   // pivot record offsets
@@ -286,6 +313,8 @@ __host__ __device__ inline uint64_t scratch_layout(uint8_t *base, uint32_t M, ui
   t.F0 = (uint32_t *)take(4 * V);
   t.F1 = (uint32_t *)take(4 * V);
   t.core = (uint32_t *)take(4 * m);
+  t.cE = (uint64_t *)take(8 * m);
+  t.cR = (uint64_t *)take(8 * m);
   t.cb = (uint32_t *)take(4 * max_groups(V, l));
   t.cc = (uint32_t *)take(4 * max_groups(V, l));
   t.poff = (uint32_t *)take(4 * m);
@@ -305,15 +334,19 @@ __host__ __device__ inline uint32_t ring_words(uint32_t sigma) {
   return bits < 32 ? 1u : bits / 32;
 }
 
+// Rows are stored with a stride of ring_words + 1 words: lanes that read the
+// same word of consecutive slots then hit distinct LDS banks.
+__host__ __device__ inline uint32_t row_stride(uint32_t sigma) { return ring_words(sigma) + 1; }
+
 // Bytes of one window slot: ring row + rhs (8) + popcount (4) + free-list entry (4).
 __host__ __device__ inline uint32_t slot_bytes(uint32_t sigma) {
-  return 4 * ring_words(sigma) + 16;
+  return 4 * row_stride(sigma) + 16;
 }
 
 uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes) {
   uint32_t reserve = 1024;  // batch arrays of the back-substitution
   uint32_t n = (lds_bytes - reserve) / slot_bytes(sigma);
-  n = n > 1024 ? 1024 : n;
+  n = n > 512 ? 512 : n;  // at most 8 slot groups per lane (band_solve)
   return n & ~7u;  // keeps the 8-byte right sides after the rows aligned
 }
 
@@ -328,58 +361,76 @@ enum { kSolveOk = 0, kSolveInconsistent = 1, kSolveCapacity = 2 };
 // G-2..G, so it fits a ring of 4 segments addressed by vertex mod 4s.
 // Pivot rows are appended to a log: [column, count, rhs lo, rhs hi,
 // vertices...]; poff[i] is the offset of the i-th (descending column).
-__device__ int band_solve(const BuildArgs &A, const Scratch &sc, uint8_t *lds,
-                          uint32_t *np_out) {
+//
+// Slot s of the window belongs to lane s % 64, which keeps the slot's word
+// of the current 32 columns, its popcount and its right side in registers;
+// candidates, pivot choice and the column mask therefore need no LDS
+// traffic, only the row updates do.
+constexpr uint32_t kMaxSlots = 512;
+constexpr int kQM = kMaxSlots / 64;
+
+__device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc, uint8_t *lds,
+                                          uint32_t *np_out) {
   const Geo &G = A.G;
+  uint32_t *const plog = sc.plog;
+  uint32_t *const poff = sc.poff;
+  const uint32_t *const cb = sc.cb;
+  const uint64_t *const cE = sc.cE;
+  const uint64_t *const cR = sc.cR;
+  const uint32_t logcap = A.logcap;
   const uint32_t lane = lane_id();
   const uint32_t sigma = G.sigma, s = 1u << sigma;
-  const uint32_t ringbits = 4u << sigma, ringmask = ringbits - 1;
+  const uint32_t ringmask = (4u << sigma) - 1;
   const uint32_t RW = ring_words(sigma);
+  const uint32_t RS = row_stride(sigma);
   const uint32_t W = A.wmax;
-  const uint32_t NQ = (W + 63) / 64;
   uint32_t *rows = (uint32_t *)lds;
-  uint64_t *rrhs = (uint64_t *)(lds + (uint64_t)4 * RW * W);
+  uint64_t *rrhs = (uint64_t *)(lds + (uint64_t)4 * RS * W);
   uint32_t *rpop = (uint32_t *)(rrhs + W);
   uint32_t *freel = rpop + W;
 
+  // free slots form a stack that hands out low slots first; only slot groups
+  // below the high-water mark are ever scanned
   for (uint32_t i = lane; i < W; i += 64) {
     rpop[i] = 0;
-    freel[i] = i;
+    freel[i] = W - 1 - i;
   }
-  uint32_t nfree = W;
-  uint32_t lp = 0, np = 0;
+  uint32_t nfree = W, NQ = 0, lp = 0, np = 0;
+  const uint32_t gsh = entry_shift(sigma);
   wave_sync();
 
-  const uint32_t gsh = entry_shift(sigma);
   // rows of entry group g join the window
   auto enter = [&](uint32_t g) -> bool {
-    const uint32_t rb = sc.cb[g], re = sc.cb[g + 1];
+    const uint32_t rb = cb[g], re = cb[g + 1];
     for (uint32_t r0 = rb; r0 < re; r0 += 64) {
-      uint32_t cnt = min(64u, re - r0);
+      const uint32_t cnt = min(64u, re - r0);
       if (cnt > nfree) return false;
       if (lane < cnt) {
-        uint32_t e = sc.core[r0 + lane];
-        uint32_t slot = freel[nfree - 1 - lane];
+        const uint64_t e = cE[r0 + lane];
+        const uint64_t rhs = cR[r0 + lane];
+        const uint32_t slot = freel[nfree - 1 - lane];
         uint32_t v[3];
-        unpack3(sc.E[e], v);
-        uint32_t *row = rows + (uint64_t)slot * RW;
+        unpack3(e, v);
+        uint32_t *row = rows + (uint64_t)slot * RS;
         for (uint32_t u = 0; u < RW; u++) row[u] = 0;
         for (int k = 0; k < 3; k++) {
-          uint32_t p = v[k] & ringmask;
+          const uint32_t p = v[k] & ringmask;
           row[p >> 5] |= 1u << (p & 31);
         }
-        rrhs[slot] = sc.R[e];
+        rrhs[slot] = rhs;
         rpop[slot] = 3;
       }
       nfree -= cnt;
+      NQ = max(NQ, (W - nfree + 63) / 64);
       wave_sync();
     }
     return true;
   };
 
+  uint32_t cw[kQM], pop[kQM];
+  uint64_t rh[kQM];
   for (int Gs = (int)G.l + 1; Gs >= 0; Gs--) {
     if (gsh < 5 && !enter((uint32_t)Gs)) return kSolveCapacity;
-    // sweep the columns of segment Gs from the top
     const uint32_t gbase = Gs >= 2 ? (uint32_t)(Gs - 2) * s : 0u;
     const uint32_t gring = gbase & ringmask;
     const uint32_t segtop = (uint32_t)(Gs + 1) * s - 1, segbot = (uint32_t)Gs * s;
@@ -387,107 +438,138 @@ __device__ int band_solve(const BuildArgs &A, const Scratch &sc, uint8_t *lds,
     for (;;) {
       if (gsh == 5 && !enter(c >> 5)) return kSolveCapacity;
       const uint32_t cpos = c & ringmask, word = cpos >> 5;
-      const uint32_t wlo_col = max(segbot, c - (cpos & 31));  // lowest column of this word in the segment
-      const uint32_t lowbit = (wlo_col & ringmask) & 31;
-      uint32_t hibit = cpos & 31;
-      auto colmask_below = [&](uint32_t top) -> uint32_t {
-        // OR over live rows of this word, restricted to bits lowbit..top
-        uint32_t acc = 0;
-        for (uint32_t q = 0; q < NQ; q++) {
-          uint32_t slot = q * 64 + lane;
-          if (slot < W && rpop[slot]) acc |= rows[(uint64_t)slot * RW + word];
+      const uint32_t wbase = c - (cpos & 31);  // column of bit 0 of this word
+      const uint32_t wlo_col = max(segbot, wbase);
+      const uint32_t lowbit = wlo_col - wbase, hibit = cpos & 31;
+      const uint32_t range = (hibit >= 31 ? 0xFFFFFFFFu : ((2u << hibit) - 1u)) &
+                             ~((1u << lowbit) - 1u);
+      // register caches of this word
+      uint32_t orv = 0;
+#pragma unroll
+      for (int q = 0; q < kQM; q++) {
+        cw[q] = 0;
+        pop[q] = 0;
+        rh[q] = 0;
+        if ((uint32_t)q < NQ) {
+          const uint32_t slot = (uint32_t)q * 64 + lane;
+          if (slot < W) {
+            pop[q] = rpop[slot];
+            if (pop[q]) {
+              cw[q] = rows[(uint64_t)slot * RS + word] & range;
+              rh[q] = rrhs[slot];
+            }
+          }
         }
-        acc = wave_or(acc);
-        uint32_t hm = top >= 31 ? 0xFFFFFFFFu : ((2u << top) - 1u);
-        uint32_t lm = ~((1u << lowbit) - 1u);
-        return acc & hm & lm;
-      };
-      uint32_t colmask = colmask_below(hibit);
+        orv |= cw[q];
+      }
+      uint32_t colmask = wave_or(orv);
       while (colmask) {
         const uint32_t b = 31 - __clz(colmask);
-        const uint32_t col = (c - (cpos & 31)) + b;
+        const uint32_t col = wbase + b;
         // candidates and pivot (fewest nonzeros, then lowest slot)
-        uint64_t best = ~0ull;
-        uint64_t cand[16];
-        for (uint32_t q = 0; q < NQ; q++) {
-          uint32_t slot = q * 64 + lane;
-          bool has = slot < W && rpop[slot] &&
-                     ((rows[(uint64_t)slot * RW + word] >> b) & 1u);
+        uint64_t cand[kQM];
+        uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+        for (int q = 0; q < kQM; q++) {
+          const bool has = (cw[q] >> b) & 1u;
           cand[q] = __ballot(has);
-          if (has) {
-            uint64_t key = ((uint64_t)rpop[slot] << 32) | slot;
-            best = key < best ? key : best;
+          if (has) best = min(best, (min(pop[q], 0xFFFFu) << 16) | ((uint32_t)q * 64 + lane));
+        }
+        best = wave_min(best);
+        const uint32_t p = best & 0xFFFFu, pq = p >> 6, pl = p & 63u;
+        uint32_t pw = 0;
+        uint64_t prhs = 0;
+#pragma unroll
+        for (int q = 0; q < kQM; q++)
+          if ((uint32_t)q == pq) {
+            pw = readlane(cw[q], (int)pl);
+            prhs = readlane64(rh[q], (int)pl);
+            cand[q] &= ~(1ull << pl);
+          }
+        const uint32_t *prow = rows + (uint64_t)p * RS;
+        // emit the pivot row (all its vertices below col): every round each
+        // lane with bits left writes its lowest one at a ballot-counted slot
+        uint32_t pos = lp + 4;
+        for (uint32_t u0 = 0; u0 < RW; u0 += 64) {
+          const uint32_t u = u0 + lane;
+          uint32_t bits = u < RW ? prow[u] : 0u;
+          if (u == word) bits &= ~(1u << b);
+          for (;;) {
+            const uint64_t m = __ballot(bits != 0);
+            if (!m) break;
+            if (pos + (uint32_t)__popcll(m) > logcap) return kSolveCapacity;
+            if (bits) {
+              const uint32_t bb = __ffs(bits) - 1;
+              bits &= bits - 1;
+              plog[pos + lanes_below(m)] = gbase + ((u * 32 + bb - gring) & ringmask);
+            }
+            pos += (uint32_t)__popcll(m);
           }
         }
-        best = wave_min64(best);
-        const uint32_t p = (uint32_t)best;
-        const uint32_t *prow = rows + (uint64_t)p * RW;
-        // emit the pivot row (all vertices below col)
-        uint32_t mycnt = 0;
-        for (uint32_t u = lane; u < RW; u += 64) {
-          uint32_t bits = prow[u];
-          if (u == word) bits &= ~(1u << b);
-          mycnt += __popc(bits);
-        }
-        const uint32_t tot = wave_sum(mycnt);
-        uint32_t pre = wave_exscan(mycnt);
-        if (lp + 4 + tot > A.logcap) return kSolveCapacity;
-        const uint64_t prhs = rrhs[p];
         if (lane == 0) {
-          sc.plog[lp] = col;
-          sc.plog[lp + 1] = tot;
-          sc.plog[lp + 2] = (uint32_t)prhs;
-          sc.plog[lp + 3] = (uint32_t)(prhs >> 32);
-          sc.poff[np] = lp;
+          plog[lp] = col;
+          plog[lp + 1] = pos - (lp + 4);
+          plog[lp + 2] = (uint32_t)prhs;
+          plog[lp + 3] = (uint32_t)(prhs >> 32);
+          poff[np] = lp;
         }
-        for (uint32_t u = lane; u < RW; u += 64) {
-          uint32_t bits = prow[u];
-          if (u == word) bits &= ~(1u << b);
-          while (bits) {
-            uint32_t bb = __ffs(bits) - 1;
-            bits &= bits - 1;
-            uint32_t pos = u * 32 + bb;
-            sc.plog[lp + 4 + pre++] = gbase + ((pos - gring) & ringmask);
-          }
-        }
-        lp += 4 + tot;
+        lp = pos;
         np++;
         // eliminate col from the other candidate rows
-        for (uint32_t q = 0; q < NQ; q++) {
+        bool incons = false;
+#pragma unroll
+        for (int q = 0; q < kQM; q++) {
           uint64_t m = cand[q];
-          if (q == p / 64) m &= ~(1ull << (p % 64));
           while (m) {
-            const uint32_t x = q * 64 + (uint32_t)(__ffsll((long long)m) - 1);
+            const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
             m &= m - 1;
-            uint32_t *xrow = rows + (uint64_t)x * RW;
+            const uint32_t x = (uint32_t)q * 64 + xl;
+            uint32_t *xrow = rows + (uint64_t)x * RS;
             uint32_t pc = 0;
-            for (uint32_t u = lane; u < RW; u += 64) {
-              uint32_t nv = xrow[u] ^ prow[u];
-              xrow[u] = nv;
-              pc += __popc(nv);
+            for (uint32_t u0 = 0; u0 < RW; u0 += 64) {
+              const uint32_t u = u0 + lane;
+              if (u < RW) {
+                const uint32_t nv = xrow[u] ^ prow[u];
+                xrow[u] = nv;
+                pc += __popc(nv);
+              }
             }
             pc = wave_sum(pc);
-            const uint64_t xr = rrhs[x] ^ prhs;
-            wave_sync();
+            const uint64_t nr = readlane64(rh[q], (int)xl) ^ prhs;
+            if (lane == xl) {
+              cw[q] ^= pw;
+              pop[q] = pc;
+              rh[q] = nr;
+            }
             if (lane == 0) {
-              rrhs[x] = xr;
               rpop[x] = pc;
+              rrhs[x] = nr;
             }
             if (pc == 0) {
-              if (xr != 0) return kSolveInconsistent;
+              incons |= nr != 0;
               if (lane == 0) freel[nfree] = x;
               nfree++;
             }
-            wave_sync();
           }
         }
+        if (incons) return kSolveInconsistent;
+        // the pivot row leaves the window
+#pragma unroll
+        for (int q = 0; q < kQM; q++)
+          if ((uint32_t)q == pq && lane == pl) {
+            cw[q] = 0;
+            pop[q] = 0;
+          }
         if (lane == 0) {
           rpop[p] = 0;
           freel[nfree] = p;
         }
         nfree++;
         wave_sync();
-        colmask = b > lowbit ? colmask_below(b - 1) : 0u;
+        orv = 0;
+#pragma unroll
+        for (int q = 0; q < kQM; q++) orv |= cw[q];
+        colmask = wave_or(orv) & ((1u << b) - 1u);
       }
       if (wlo_col == segbot) break;
       c = wlo_col - 1;
@@ -501,7 +583,8 @@ __device__ int band_solve(const BuildArgs &A, const Scratch &sc, uint8_t *lds,
 // lane gathers the values of vertices below its batch, then the in-batch
 // dependencies are resolved lane by lane.  Values of free vertices are 0.
 template <typename T>
-__device__ void back_substitute(const Scratch &sc, uint32_t np, T *wl, uint32_t *bcol) {
+__device__ __forceinline__ void back_substitute(const Scratch &sc, uint32_t np, T *wl,
+                                                uint32_t *bcol, bool cells_global) {
   const uint32_t lane = lane_id();
   for (uint32_t bs = 0; bs < np; bs += 64) {
     const uint32_t i = bs + lane;
@@ -532,11 +615,12 @@ __device__ void back_substitute(const Scratch &sc, uint32_t np, T *wl, uint32_t 
     }
     uint64_t x = acc;
     for (uint32_t k = 0; k < 64 && bs + k < np; k++) {
-      uint64_t xk = __shfl(x, (int)k);
+      const uint64_t xk = readlane64(x, (int)k);
       if ((dep >> k) & 1ull) x ^= xk;
     }
     if (valid) wl[col] = (T)x;
-    wave_sync();
+    if (cells_global) wave_sync_global();
+    else wave_sync();
   }
 }
 
@@ -691,8 +775,11 @@ k_build(BuildArgs A) {
       __syncthreads();
       for (uint32_t i = tid; i < m; i += NT)
         if (!sc.pe[i]) {
-          const uint32_t g = (uint32_t)(sc.E[i] >> 42) >> gsh;
-          sc.core[atomicAdd(&sc.cc[g], 1u)] = i;
+          const uint64_t e = sc.E[i];
+          const uint32_t pos = atomicAdd(&sc.cc[(uint32_t)(e >> 42) >> gsh], 1u);
+          sc.core[pos] = i;
+          sc.cE[pos] = e;
+          sc.cR[pos] = sc.R[i];
         }
       __syncthreads();
       const uint32_t k = sh_k;
@@ -726,7 +813,7 @@ k_build(BuildArgs A) {
       __syncthreads();
       if (tid < 64 && np) {
         uint32_t *bcol = (uint32_t *)(lds + (A.cells_in_lds ? A.lds_bytes - 256 : 0));
-        back_substitute<T>(sc, np, wl, bcol);
+        back_substitute<T>(sc, np, wl, bcol, !A.cells_in_lds);
       }
       __syncthreads();
       for (int r = (int)nrounds - 1; r >= 0; r--) {

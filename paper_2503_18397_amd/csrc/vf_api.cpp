@@ -103,6 +103,25 @@ uint32_t shard_cap(uint64_t n, uint32_t S) {
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
+// Elimination-window slots a shard needs: measured peaks of the window are
+// about 0.6 s rows for fuse graphs at c = 1.12 (s = segment size); keep a
+// margin.
+uint32_t window_target(int32_t sigma) {
+  const uint32_t s = 1u << sigma;
+  return std::min<uint32_t>(512u, s / 2 + s / 8 + 32);
+}
+
+// How many single-wavefront build workgroups share one CU's LDS, and the
+// LDS each gets: as many as still leave every one a large enough window.
+void build_occupancy(int32_t sigma, uint32_t *per_cu, uint32_t *lds_bytes) {
+  const uint32_t want = window_target(sigma);
+  uint32_t best = 1;
+  for (uint32_t n = 2; n <= 8; n++)
+    if (vfk::window_slots((uint32_t)sigma, (vfk::kLdsBudget / n) & ~255u) >= want) best = n;
+  *per_cu = best;
+  *lds_bytes = (vfk::kLdsBudget / best) & ~255u;
+}
+
 int device_cus() {
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -122,7 +141,8 @@ struct Layout {
   uint64_t ws_bytes, st_bytes;
   uint64_t cells_bytes;
   // workspace offsets
-  uint64_t o_counts, o_offsets, o_cursor, o_meta, o_work, o_fails, o_bkeys, o_bvals, o_scratch;
+  uint64_t o_counts, o_offsets, o_cursor, o_meta, o_work, o_fails, o_overflow, o_bkeys, o_bvals,
+      o_scratch;
   uint32_t fail_cap;
 };
 
@@ -160,7 +180,13 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   }
   l.gcap.l += l.gcap.l / 8 + 8;
   l.cell_bytes = cell_bytes_for(b);
-  l.nwg = (uint32_t)std::max(1, std::min<int>(ncu > 0 ? ncu : 256, (int)l.S));
+  uint32_t per_cu, lds_bytes;
+  build_occupancy(l.gcap.sigma, &per_cu, &lds_bytes);
+  // the actual (smaller or equal) segment size may allow more workgroups
+  // per CU; scratch is sized for up to 4 per CU
+  per_cu = std::max<uint32_t>(per_cu, 4);
+  l.nwg = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>((uint64_t)per_cu * (ncu > 0 ? ncu : 256), l.S));
   l.logcap = 16u * l.cap + 4096u;
   // scratch is sized for the largest shard the buffers allow, with the
   // geometry of that size (the actual geometry is never larger)
@@ -179,6 +205,7 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   l.o_meta = take(16);
   l.o_work = take(4ull * vfk::kWorkWords);
   l.o_fails = take(sizeof(vfk::FailRec) * (uint64_t)l.fail_cap);
+  l.o_overflow = take(8ull * l.S);
   l.o_bkeys = take(8ull * std::max<uint64_t>(n, 1));
   l.o_bvals = is_filter ? 0 : take(8ull * std::max<uint64_t>(n, 1));
   l.o_scratch = take(l.scratch_stride * l.nwg);
@@ -280,6 +307,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   uint32_t *meta = (uint32_t *)(W + L.o_meta);
   uint32_t *work = (uint32_t *)(W + L.o_work);
   vfk::FailRec *fails = (vfk::FailRec *)(W + L.o_fails);
+  uint32_t *overflow = (uint32_t *)(W + L.o_overflow);
   uint64_t *bkeys = (uint64_t *)(W + L.o_bkeys);
   uint64_t *bvals = is_filter ? nullptr : (uint64_t *)(W + L.o_bvals);
   uint8_t *scratch = W + L.o_scratch;
@@ -343,19 +371,38 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   A.fail_cap = L.fail_cap;
   A.M = M;
   A.tmax = op.tmax;
-  A.lds_bytes = vfk::kLdsBudget - 1024;
+  uint32_t per_cu = 1;
+  build_occupancy(g.sigma, &per_cu, &A.lds_bytes);
   A.wmax = vfk::window_slots((uint32_t)g.sigma, A.lds_bytes);
+  const uint32_t nwg = std::min<uint32_t>(L.nwg, per_cu * (uint32_t)ncu);
   A.logcap = L.logcap;
   A.cell_bytes = L.cell_bytes;
-  A.cells_in_lds = g.V * L.cell_bytes + 256 <= A.lds_bytes ? 1u : 0u;
+  A.cells_in_lds = g.V * L.cell_bytes + 256 <= A.lds_bytes ? 1u : 0u;  // + batch columns
+  A.list = nullptr;
+  A.nlist = 0;
+  A.overflow = overflow;
   HIPCHK(vfk::launch_fill_u32(work, vfk::kWorkWords, 0, stream));
-  HIPCHK(vfk::launch_build(A, (int)L.nwg, stream));
-  pe.record(3, stream);
-
-  // 4. failure record
+  HIPCHK(vfk::launch_build(A, (int)nwg, stream));
   uint32_t hwork[vfk::kWorkWords];
   HIPCHK(hipMemcpyAsync(hwork, work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
+  if (hwork[vfk::kWorkCap]) {
+    // shards whose window outgrew their share of LDS: rebuild them from the
+    // attempt they reached, one workgroup per CU with all of its LDS
+    A.list = overflow;
+    A.nlist = hwork[vfk::kWorkCap];
+    A.overflow = nullptr;
+    A.lds_bytes = (vfk::kLdsBudget - 256) & ~255u;
+    A.wmax = vfk::window_slots((uint32_t)g.sigma, A.lds_bytes);
+    A.cells_in_lds = g.V * L.cell_bytes + 256 <= A.lds_bytes ? 1u : 0u;
+    HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkNext, 1, 0, stream));
+    HIPCHK(vfk::launch_build(A, (int)std::min<uint32_t>(nwg, (uint32_t)ncu), stream));
+    HIPCHK(hipMemcpyAsync(hwork, work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+  }
+  pe.record(3, stream);
+
+  // 4. failure record
   const uint32_t nf = std::min(hwork[vfk::kWorkFails], L.fail_cap);
   std::vector<vfk::FailRec> fr(nf);
   if (nf)

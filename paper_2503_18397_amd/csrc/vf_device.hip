@@ -265,6 +265,11 @@ __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__r
 }
 
 // ------------------------------------------------------------- shard build
+//
+// One wavefront builds one shard at a time, from its keys to its cells; a
+// workgroup is that single wavefront and several workgroups share a CU.
+// Vertex state for peeling lives in global memory (cached in L2), the
+// elimination window and (when they fit) the shard's cells live in LDS.
 
 // Per-workgroup scratch (global memory), sized for the largest shard.
 struct Scratch {
@@ -276,9 +281,8 @@ struct Scratch {
   uint32_t *stack;  // peeled edges in round order: index | side << 30
   uint32_t *rst;    // round starts in stack
   uint32_t *F0, *F1;// frontiers of degree-one vertices
-  uint32_t *core;   // core edges grouped by their top vertex (entry groups)
-  uint64_t *cE;     // packed edges of the grouped core rows
-  uint64_t *cR;     // right sides of the grouped core rows
+  uint64_t *cE;     // packed edges of the 2-core, grouped by entry group
+  uint64_t *cR;     // their right sides
   uint32_t *cb;     // group starts
   uint32_t *cc;     // group cursors
   uint32_t *poff;   // pivot record offsets
@@ -301,7 +305,7 @@ __host__ __device__ inline uint64_t scratch_layout(uint8_t *base, uint32_t M, ui
     o += align8(bytes);
     return p;
   };
-  uint64_t m = (uint64_t)M + 1;
+  const uint64_t m = (uint64_t)M + 1;
   Scratch t;
   t.E = (uint64_t *)take(8 * m);
   t.R = (uint64_t *)take(8 * m);
@@ -312,7 +316,6 @@ __host__ __device__ inline uint64_t scratch_layout(uint8_t *base, uint32_t M, ui
   t.rst = (uint32_t *)take(4 * (m + 2));
   t.F0 = (uint32_t *)take(4 * V);
   t.F1 = (uint32_t *)take(4 * V);
-  t.core = (uint32_t *)take(4 * m);
   t.cE = (uint64_t *)take(8 * m);
   t.cR = (uint64_t *)take(8 * m);
   t.cb = (uint32_t *)take(4 * max_groups(V, l));
@@ -327,26 +330,45 @@ uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap
   return scratch_layout(nullptr, M, V, l, logcap, nullptr);
 }
 
-// Ring rows of the elimination window hold 4 segments (4 s bits): a window
-// row always lies within 3 consecutive segments (see band_solve).
-__host__ __device__ inline uint32_t ring_words(uint32_t sigma) {
-  uint32_t bits = 4u << sigma;
-  return bits < 32 ? 1u : bits / 32;
-}
+// The elimination window stores each row over a ring of vertex positions.
+// While segment G is swept a window row only has vertices in segments
+// G-2..G, so segments of at least 32 vertices use a ring of 3 segments
+// (segment g at position (g mod 3) s); smaller segments use a ring of 4
+// segments (vertex v at v mod 4s), at most two words.
+struct Ring {
+  uint32_t sigma, s, three, words;
+  __host__ __device__ explicit Ring(uint32_t sg) : sigma(sg), s(1u << sg), three(sg >= 5) {
+    const uint32_t bits = three ? 3u * s : 4u * s;
+    words = bits < 32 ? 1u : bits / 32;
+  }
+  __device__ uint32_t pos(uint32_t v) const {
+    return three ? ((v >> sigma) % 3u) * s + (v & (s - 1)) : v & (4u * s - 1);
+  }
+  // vertex at ring position p of a row in the window of segment Gs
+  __device__ uint32_t vertex(uint32_t p, uint32_t Gs) const {
+    if (three) {
+      const uint32_t d = (Gs % 3u + 3u - (p >> sigma)) % 3u;
+      return (Gs - d) * s + (p & (s - 1));
+    }
+    const uint32_t gbase = Gs >= 2 ? (Gs - 2) * s : 0u, mask = 4u * s - 1;
+    return gbase + ((p - (gbase & mask)) & mask);
+  }
+};
 
-// Rows are stored with a stride of ring_words + 1 words: lanes that read the
-// same word of consecutive slots then hit distinct LDS banks.
-__host__ __device__ inline uint32_t row_stride(uint32_t sigma) { return ring_words(sigma) + 1; }
+// Rows are stored with a stride of ring words + 1: lanes that read the same
+// word of consecutive slots then hit distinct LDS banks.
+__host__ __device__ inline uint32_t row_stride(uint32_t sigma) { return Ring(sigma).words + 1; }
 
 // Bytes of one window slot: ring row + rhs (8) + popcount (4) + free-list entry (4).
-__host__ __device__ inline uint32_t slot_bytes(uint32_t sigma) {
-  return 4 * row_stride(sigma) + 16;
-}
+__host__ __device__ inline uint32_t slot_bytes(uint32_t sigma) { return 4 * row_stride(sigma) + 16; }
+
+constexpr uint32_t kMaxSlots = 512;
+constexpr int kQM = kMaxSlots / 64;
+constexpr uint32_t kBcolBytes = 256;  // batch columns of the back-substitution
 
 uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes) {
-  uint32_t reserve = 1024;  // batch arrays of the back-substitution
-  uint32_t n = (lds_bytes - reserve) / slot_bytes(sigma);
-  n = n > 512 ? 512 : n;  // at most 8 slot groups per lane (band_solve)
+  uint32_t n = (lds_bytes - kBcolBytes) / slot_bytes(sigma);
+  n = n > kMaxSlots ? kMaxSlots : n;
   return n & ~7u;  // keeps the 8-byte right sides after the rows aligned
 }
 
@@ -356,9 +378,7 @@ enum { kSolveOk = 0, kSolveInconsistent = 1, kSolveCapacity = 2 };
 // enter the window when the sweep reaches their entry group; columns are
 // visited from the highest vertex down.  For column c every window row that
 // contains c is a candidate; one of them (fewest nonzeros first: least fill)
-// becomes the pivot row of c and is xored into the other candidates.  A row
-// in the window while segment G is swept only has vertices in segments
-// G-2..G, so it fits a ring of 4 segments addressed by vertex mod 4s.
+// becomes the pivot row of c and is xored into the other candidates.
 // Pivot rows are appended to a log: [column, count, rhs lo, rhs hi,
 // vertices...]; poff[i] is the offset of the i-th (descending column).
 //
@@ -366,9 +386,6 @@ enum { kSolveOk = 0, kSolveInconsistent = 1, kSolveCapacity = 2 };
 // of the current 32 columns, its popcount and its right side in registers;
 // candidates, pivot choice and the column mask therefore need no LDS
 // traffic, only the row updates do.
-constexpr uint32_t kMaxSlots = 512;
-constexpr int kQM = kMaxSlots / 64;
-
 __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc, uint8_t *lds,
                                           uint32_t *np_out) {
   const Geo &G = A.G;
@@ -379,10 +396,10 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc,
   const uint64_t *const cR = sc.cR;
   const uint32_t logcap = A.logcap;
   const uint32_t lane = lane_id();
-  const uint32_t sigma = G.sigma, s = 1u << sigma;
-  const uint32_t ringmask = (4u << sigma) - 1;
-  const uint32_t RW = ring_words(sigma);
-  const uint32_t RS = row_stride(sigma);
+  const Ring ring(G.sigma);
+  const uint32_t s = ring.s;
+  const uint32_t RW = ring.words;
+  const uint32_t RS = RW + 1;
   const uint32_t W = A.wmax;
   uint32_t *rows = (uint32_t *)lds;
   uint64_t *rrhs = (uint64_t *)(lds + (uint64_t)4 * RS * W);
@@ -396,7 +413,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc,
     freel[i] = W - 1 - i;
   }
   uint32_t nfree = W, NQ = 0, lp = 0, np = 0;
-  const uint32_t gsh = entry_shift(sigma);
+  const uint32_t gsh = entry_shift(G.sigma);
   wave_sync();
 
   // rows of entry group g join the window
@@ -414,7 +431,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc,
         uint32_t *row = rows + (uint64_t)slot * RS;
         for (uint32_t u = 0; u < RW; u++) row[u] = 0;
         for (int k = 0; k < 3; k++) {
-          const uint32_t p = v[k] & ringmask;
+          const uint32_t p = ring.pos(v[k]);
           row[p >> 5] |= 1u << (p & 31);
         }
         rrhs[slot] = rhs;
@@ -431,13 +448,11 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc,
   uint64_t rh[kQM];
   for (int Gs = (int)G.l + 1; Gs >= 0; Gs--) {
     if (gsh < 5 && !enter((uint32_t)Gs)) return kSolveCapacity;
-    const uint32_t gbase = Gs >= 2 ? (uint32_t)(Gs - 2) * s : 0u;
-    const uint32_t gring = gbase & ringmask;
     const uint32_t segtop = (uint32_t)(Gs + 1) * s - 1, segbot = (uint32_t)Gs * s;
     uint32_t c = segtop;
     for (;;) {
       if (gsh == 5 && !enter(c >> 5)) return kSolveCapacity;
-      const uint32_t cpos = c & ringmask, word = cpos >> 5;
+      const uint32_t cpos = ring.pos(c), word = cpos >> 5;
       const uint32_t wbase = c - (cpos & 31);  // column of bit 0 of this word
       const uint32_t wlo_col = max(segbot, wbase);
       const uint32_t lowbit = wlo_col - wbase, hibit = cpos & 31;
@@ -501,7 +516,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc,
             if (bits) {
               const uint32_t bb = __ffs(bits) - 1;
               bits &= bits - 1;
-              plog[pos + lanes_below(m)] = gbase + ((u * 32 + bb - gring) & ringmask);
+              plog[pos + lanes_below(m)] = ring.vertex(u * 32 + bb, (uint32_t)Gs);
             }
             pos += (uint32_t)__popcll(m);
           }
@@ -586,10 +601,12 @@ template <typename T>
 __device__ __forceinline__ void back_substitute(const Scratch &sc, uint32_t np, T *wl,
                                                 uint32_t *bcol, bool cells_global) {
   const uint32_t lane = lane_id();
+  const uint32_t *const plog = sc.plog;
+  const uint32_t *const poff = sc.poff;
   for (uint32_t bs = 0; bs < np; bs += 64) {
     const uint32_t i = bs + lane;
     const bool valid = i < np;
-    const uint32_t *rec = valid ? sc.plog + sc.poff[np - 1 - i] : nullptr;
+    const uint32_t *rec = valid ? plog + poff[np - 1 - i] : nullptr;
     const uint32_t col = valid ? rec[0] : 0xFFFFFFFFu;
     bcol[lane] = col;
     wave_sync();
@@ -605,7 +622,7 @@ __device__ __forceinline__ void back_substitute(const Scratch &sc, uint32_t np, 
         } else {
           uint32_t lo = 0, hi = lane;  // bcol is increasing; v < col
           while (lo < hi) {
-            uint32_t mid = (lo + hi) >> 1;
+            const uint32_t mid = (lo + hi) >> 1;
             if (bcol[mid] < v) lo = mid + 1;
             else hi = mid;
           }
@@ -624,30 +641,57 @@ __device__ __forceinline__ void back_substitute(const Scratch &sc, uint32_t np, 
   }
 }
 
+// Exclusive prefix sum of a[0..n) in place (one wavefront), returns the total.
+__device__ __forceinline__ uint32_t wave_scan_array(uint32_t *a, uint32_t *b, uint32_t n) {
+  const uint32_t lane = lane_id();
+  const uint32_t per = (n + 63) / 64, lo = lane * per, hi = min(n, lo + per);
+  uint32_t sum = 0;
+  for (uint32_t i = lo; i < hi; i++) sum += a[i];
+  uint32_t inc = sum;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d);
+    if (lane >= (uint32_t)d) inc += y;
+  }
+  const uint32_t total = readlane(inc, 63);
+  uint32_t run = inc - sum;
+  for (uint32_t i = lo; i < hi; i++) {
+    const uint32_t c = a[i];
+    a[i] = run;
+    b[i] = run;
+    run += c;
+  }
+  return total;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(kBuildThreads)
-k_build(BuildArgs A) {
+__global__ void __launch_bounds__(64) k_build(BuildArgs A) {
   extern __shared__ __align__(16) uint8_t lds[];
-  __shared__ uint32_t sh_j, sh_nf, sh_nn, sh_nst, sh_st, sh_np, sh_k, sh_t;
   const Geo &G = A.G;
-  const uint32_t tid = threadIdx.x, NT = blockDim.x;
+  const uint32_t lane = lane_id();
   const uint64_t V = G.V;
   Scratch sc;
   scratch_layout(A.scratch + (uint64_t)blockIdx.x * A.scratch_stride, A.M, V, G.l, A.logcap, &sc);
   T *cells = (T *)A.cells;
 
   for (;;) {
-    if (tid == 0) sh_j = atomicAdd(&A.work[kWorkNext], 1u);
-    __syncthreads();
-    const uint32_t j = sh_j;
-    if (j >= G.S) break;
+    uint32_t j = 0;
+    if (lane == 0) j = atomicAdd(&A.work[kWorkNext], 1u);
+    j = readlane(j, 0);
+    uint32_t t0 = 0;
+    if (A.list) {
+      if (j >= A.nlist) break;
+      t0 = A.list[2 * j + 1];
+      j = A.list[2 * j];
+    } else if (j >= G.S) {
+      break;
+    }
     const uint64_t base = A.offsets[j];
     const uint32_t m = (uint32_t)(A.offsets[j + 1] - base);
     T *wg = cells + (uint64_t)j * V;  // this shard's cells in HBM
     T *wl = A.cells_in_lds ? (T *)lds : wg;
 
     // right sides: values (Problem 1) or fingerprints (Problem 2)
-    for (uint32_t i = tid; i < m; i += NT) {
+    for (uint32_t i = lane; i < m; i += 64) {
       const uint64_t key = A.bkeys[base + i];
       if (G.is_filter) {
         sc.R[i] = fingerprint(G, fin64(key ^ G.khi), fin64(key ^ G.klo));
@@ -656,24 +700,23 @@ k_build(BuildArgs A) {
       }
     }
 
-    uint32_t t = 0;
     uint8_t result_t = 255;
-    for (; t < A.tmax; t++) {
+    for (uint32_t t = t0; t < A.tmax; t++) {
       // edges of this attempt, cleared vertex state
-      for (uint32_t i = tid; i < m; i += NT) {
+      for (uint32_t i = lane; i < m; i += 64) {
         const uint64_t key = A.bkeys[base + i];
         uint32_t v0, v1, v2;
         edge3(G, fin64(key ^ G.khi), fin64(key ^ G.klo), t, v0, v1, v2);
         sc.E[i] = pack3(v0, v1, v2);
         sc.pe[i] = 0;
       }
-      for (uint64_t v = tid; v < V; v += NT) {
+      for (uint64_t v = lane; v < V; v += 64) {
         sc.deg[v] = 0;
         sc.xr[v] = 0;
       }
-      __syncthreads();
+      wave_sync_global();
       // incidence: degree and xor of incident edges
-      for (uint32_t i = tid; i < m; i += NT) {
+      for (uint32_t i = lane; i < m; i += 64) {
         uint32_t v[3];
         unpack3(sc.E[i], v);
         for (int k = 0; k < 3; k++) {
@@ -681,26 +724,25 @@ k_build(BuildArgs A) {
           atomicXor(&sc.xr[v[k]], i);
         }
       }
-      if (tid == 0) {
-        sh_nf = 0;
-        sh_nst = 0;
-      }
-      __syncthreads();
-      // round-synchronous peeling
-      for (uint64_t v0 = 0; v0 < V; v0 += NT) {
-        const uint64_t v = v0 + tid;
+      wave_sync_global();
+      // round-synchronous peeling; list appends are counted by ballot
+      uint32_t nf = 0;
+      for (uint64_t v0 = 0; v0 < V; v0 += 64) {
+        const uint64_t v = v0 + lane;
         const bool one = v < V && sc.deg[v] == 1;
-        const uint32_t pos = wave_append(one, &sh_nf);
-        if (one) sc.F0[pos] = (uint32_t)v;
+        const uint64_t bm = __ballot(one);
+        if (one) sc.F0[nf + lanes_below(bm)] = (uint32_t)v;
+        nf += (uint32_t)__popcll(bm);
       }
-      __syncthreads();
-      uint32_t nf = sh_nf, nrounds = 0, nst = 0;
+      wave_sync_global();
+      uint32_t nrounds = 0, nst = 0;
       uint32_t *cur = sc.F0, *nxt = sc.F1;
-      if (tid == 0) sc.rst[0] = 0;
+      if (lane == 0) sc.rst[0] = 0;
       while (nf) {
+        const uint32_t r0 = nst;
         // select with the degrees of the start of the round
-        for (uint32_t i0 = 0; i0 < nf; i0 += NT) {
-          const uint32_t i = i0 + tid;
+        for (uint32_t i0 = 0; i0 < nf; i0 += 64) {
+          const uint32_t i = i0 + lane;
           bool take = false;
           uint32_t e = 0, side = 0;
           if (i < nf) {
@@ -715,21 +757,21 @@ k_build(BuildArgs A) {
                 if (sc.deg[a[k]] == 1) take = false;
             }
           }
-          const uint32_t pos = wave_append(take, &sh_nst);
+          const uint64_t bm = __ballot(take);
           if (take) {
-            sc.stack[pos] = e | (side << 30);
+            sc.stack[nst + lanes_below(bm)] = e | (side << 30);
             sc.pe[e] = 1;
           }
+          nst += (uint32_t)__popcll(bm);
         }
-        if (tid == 0) sh_nn = 0;
-        __syncthreads();
-        const uint32_t r0 = nst, r1 = sh_nst;
+        wave_sync_global();
         // remove the selected edges
-        for (uint32_t i0 = r0; i0 < r1; i0 += NT) {
-          const uint32_t i = i0 + tid;
+        uint32_t nn = 0;
+        for (uint32_t i0 = r0; i0 < nst; i0 += 64) {
+          const uint32_t i = i0 + lane;
           bool push[3] = {false, false, false};
           uint32_t a[3] = {0, 0, 0};
-          if (i < r1) {
+          if (i < nst) {
             const uint32_t e = sc.stack[i] & 0x3FFFFFFFu;
             unpack3(sc.E[e], a);
             for (int k = 0; k < 3; k++) {
@@ -739,86 +781,72 @@ k_build(BuildArgs A) {
             }
           }
           for (int k = 0; k < 3; k++) {
-            const uint32_t pos = wave_append(push[k], &sh_nn);
-            if (push[k]) nxt[pos] = a[k];
+            const uint64_t bm = __ballot(push[k]);
+            if (push[k]) nxt[nn + lanes_below(bm)] = a[k];
+            nn += (uint32_t)__popcll(bm);
           }
         }
-        __syncthreads();
-        nst = r1;
         nrounds++;
-        if (tid == 0) sc.rst[nrounds] = nst;
-        nf = sh_nn;
+        if (lane == 0) sc.rst[nrounds] = nst;
+        wave_sync_global();
+        nf = nn;
         uint32_t *tmp = cur;
         cur = nxt;
         nxt = tmp;
-        __syncthreads();
       }
 
       // 2-core edges, grouped by the entry group of their top vertex
       const uint32_t gsh = entry_shift(G.sigma);
       const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
-      for (uint32_t g = tid; g < ngroups; g += NT) sc.cc[g] = 0;
-      __syncthreads();
-      for (uint32_t i = tid; i < m; i += NT)
+      for (uint32_t g = lane; g < ngroups; g += 64) sc.cc[g] = 0;
+      wave_sync_global();
+      for (uint32_t i = lane; i < m; i += 64)
         if (!sc.pe[i]) atomicAdd(&sc.cc[(uint32_t)(sc.E[i] >> 42) >> gsh], 1u);
-      __syncthreads();
-      if (tid == 0) {
-        uint32_t run = 0;
-        for (uint32_t g = 0; g < ngroups; g++) {
-          uint32_t c = sc.cc[g];
-          sc.cb[g] = run;
-          sc.cc[g] = run;
-          run += c;
-        }
-        sh_k = run;
-      }
-      __syncthreads();
-      for (uint32_t i = tid; i < m; i += NT)
+      wave_sync_global();
+      const uint32_t k = wave_scan_array(sc.cc, sc.cb, ngroups);
+      wave_sync_global();
+      for (uint32_t i = lane; i < m; i += 64)
         if (!sc.pe[i]) {
           const uint64_t e = sc.E[i];
           const uint32_t pos = atomicAdd(&sc.cc[(uint32_t)(e >> 42) >> gsh], 1u);
-          sc.core[pos] = i;
           sc.cE[pos] = e;
           sc.cR[pos] = sc.R[i];
         }
-      __syncthreads();
-      const uint32_t k = sh_k;
+      wave_sync_global();
 
       uint32_t np = 0;
-      if (tid < 64) {
-        int st = kSolveOk;
-        if (k) st = band_solve(A, sc, lds, &np);
-        if (tid == 0) {
-          sh_st = (uint32_t)st;
-          sh_np = np;
-        }
-      }
-      __syncthreads();
-      const uint32_t st = sh_st;
-      np = sh_np;
+      const int st = k ? band_solve(A, sc, lds, &np) : kSolveOk;
+      wave_sync_global();
       if (st == kSolveCapacity) {
-        if (tid == 0) atomicOr(&A.work[kWorkStatus], kStatusCapacity);
+        if (lane == 0) {
+          if (A.overflow) {
+            const uint32_t idx = atomicAdd(&A.work[kWorkCap], 1u);
+            A.overflow[2 * idx] = j;
+            A.overflow[2 * idx + 1] = t;
+          } else {
+            atomicOr(&A.work[kWorkStatus], kStatusCapacity);
+          }
+        }
         break;
       }
       if (st == kSolveInconsistent) {
-        if (tid == 0) {
+        if (lane == 0) {
           const uint32_t idx = atomicAdd(&A.work[kWorkFails], 1u);
           if (idx < A.fail_cap) A.fails[idx] = FailRec{j, t, 1u, k};
         }
-        __syncthreads();
         continue;
       }
       // cells: zero, core values by back-substitution, then peeled edges
-      for (uint64_t v = tid; v < V; v += NT) wl[v] = (T)0;
-      __syncthreads();
-      if (tid < 64 && np) {
-        uint32_t *bcol = (uint32_t *)(lds + (A.cells_in_lds ? A.lds_bytes - 256 : 0));
+      for (uint64_t v = lane; v < V; v += 64) wl[v] = (T)0;
+      if (A.cells_in_lds) wave_sync();
+      else wave_sync_global();
+      if (np) {
+        uint32_t *bcol = (uint32_t *)(lds + A.lds_bytes - kBcolBytes);
         back_substitute<T>(sc, np, wl, bcol, !A.cells_in_lds);
       }
-      __syncthreads();
       for (int r = (int)nrounds - 1; r >= 0; r--) {
         const uint32_t e0 = sc.rst[r], e1 = sc.rst[r + 1];
-        for (uint32_t i = e0 + tid; i < e1; i += NT) {
+        for (uint32_t i = e0 + lane; i < e1; i += 64) {
           const uint32_t ent = sc.stack[i];
           const uint32_t e = ent & 0x3FFFFFFFu, side = ent >> 30;
           uint32_t a[3];
@@ -828,19 +856,20 @@ k_build(BuildArgs A) {
             if (q != side) val ^= (uint64_t)wl[a[q]];
           wl[a[side]] = (T)val;
         }
-        __syncthreads();
+        if (A.cells_in_lds) wave_sync();
+        else wave_sync_global();
       }
       if (A.cells_in_lds)
-        for (uint64_t v = tid; v < V; v += NT) wg[v] = wl[v];
+        for (uint64_t v = lane; v < V; v += 64) wg[v] = wl[v];
       result_t = (uint8_t)t;
       break;
     }
     if (result_t == 255) {
       // every attempt failed (or a capacity limit was hit): zero cells
-      for (uint64_t v = tid; v < V; v += NT) wg[v] = (T)0;
+      for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
     }
-    if (tid == 0) A.tseed[j] = result_t;
-    __syncthreads();
+    if (lane == 0) A.tseed[j] = result_t;
+    wave_sync_global();
   }
 }
 
@@ -911,7 +940,7 @@ static hipError_t launch_build_t(const BuildArgs &a, int nwg, hipStream_t s) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)a.lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_build<T>, dim3(nwg), dim3(kBuildThreads), a.lds_bytes, s, a);
+  hipLaunchKernelGGL(k_build<T>, dim3(nwg), dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ struct FailRec {
 };
 
 // Counters shared by all build workgroups.
-enum : uint32_t { kWorkNext = 0, kWorkFails = 1, kWorkStatus = 2, kWorkWords = 4 };
+enum : uint32_t { kWorkNext = 0, kWorkFails = 1, kWorkStatus = 2, kWorkCap = 3, kWorkWords = 4 };
 enum : uint32_t { kStatusCapacity = 1u };
 
 struct BuildArgs {
@@ -47,10 +47,17 @@ struct BuildArgs {
   uint32_t lds_bytes;       // dynamic LDS of the launch
   uint32_t cell_bytes;      // 1, 2, 4 or 8
   uint32_t cells_in_lds;    // 1: shard cells fit in LDS during assignment
+  // Shards to build: all (list == nullptr, taken in order) or the nlist
+  // (shard, first local seed) pairs of list.
+  const uint32_t *list;
+  uint32_t nlist;
+  // Shards whose elimination window outgrew the LDS of this launch are
+  // appended here as (shard, local seed) pairs for a launch with more LDS;
+  // nullptr: such shards fail with kStatusCapacity.
+  uint32_t *overflow;
 };
 
-constexpr int kBuildThreads = 256;
-constexpr uint32_t kLdsBudget = 160 * 1024;
+constexpr uint32_t kLdsBudget = 160 * 1024;  // LDS of one CU
 
 uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap);
 uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes);

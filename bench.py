@@ -34,6 +34,7 @@ def parse():
     p.add_argument("--eps", type=float, default=0.0175)
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--data-seed", type=int, default=2027)
+    p.add_argument("--sigma", type=int, default=None, help="override lg segment size")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-shards", type=int, default=16)
     return p.parse_args()
@@ -86,7 +87,7 @@ def main():
     queries, is_member = S.queries(keys, Q, args.data_seed)
     n_neg = int((~is_member).sum().item())
     out = torch.empty(Q, dtype=torch.uint8, device=dev)
-    opts = vf.vf_default_opts()
+    opts = vf.vf_default_opts(sigma=args.sigma)
     sz = vf.vf_plan(n, args.b, args.eps, True, opts)
     ws = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=dev)
     st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)

@@ -32,8 +32,11 @@
  *     single unsharded graph of at least 800 000 keys.  For small shards the
  *     paper fixes no segment size; we take the smallest s for which the
  *     expected number of duplicate edges of a shard, m / (2 c s^2)
- *     (section 4.2), is at most 1/8.  ell = max(1, ceil(c M / s) - 2),
- *     V = (ell + 2) s.
+ *     (section 4.2), is at most 1/8.  Section 4 leaves shard sizing to
+ *     simulation when no bound is known: simulated with this oracle, c = 1.12
+ *     fails in most attempts below 2^16 keys per shard (a fuse graph with
+ *     few segments is overloaded in its middle), so shards below 2^16 keys
+ *     use c = 1.16.  ell = max(1, ceil(c M / s) - 2), V = (ell + 2) s.
  *  R7 peeling is round-synchronous: in round r every live edge that has a
  *     vertex of degree one (degrees as they stand when the round starts) is
  *     removed; its hinge is the first such vertex in edge order (its
@@ -190,9 +193,10 @@ void orc_geometry(uint32_t M, int32_t h, uint32_t c_num, uint32_t c_den,
                   int32_t sigma_override, orc_geom *g) {
   int large = M >= 800000u;
   if (c_num == 0 || c_den == 0) {
-    if (!large) { c_num = 112; c_den = 100; }      /* 1.12 */
-    else if (h > 0) { c_num = 1105; c_den = 1000; } /* 1.105 */
-    else { c_num = 1125; c_den = 1000; }            /* 1.125 */
+    if (large && h > 0) { c_num = 1105; c_den = 1000; }  /* 1.105 */
+    else if (large) { c_num = 1125; c_den = 1000; }      /* 1.125 */
+    else if (M >= 65536u) { c_num = 112; c_den = 100; }  /* 1.12 */
+    else { c_num = 116; c_den = 100; }                   /* 1.16 */
   }
   int32_t sigma;
   if (sigma_override >= 0) {

@@ -56,14 +56,17 @@ struct Geometry {
 // elimination of the 2-core), c = 1.105 with lg s from eq. (nln) for larger
 // shards, c = 1.125 with lg s from eq. (ln) for a single large unsharded
 // graph.  Below 800 000 keys the segment size is the smallest power of two
-// with expected duplicate edges m / (2 c s^2) <= 1/8.  ell = max(1,
-// ceil(c M / s) - 2) start segments, V = (ell + 2) s cells per shard.
+// with expected duplicate edges m / (2 c s^2) <= 1/8.  Shards below 2^16
+// keys use c = 1.16: simulated (as section 4 suggests for sizing shards),
+// c = 1.12 fuse systems that small are unsolvable in most attempts.
+// ell = max(1, ceil(c M / s) - 2) start segments, V = (ell + 2) s cells.
 Geometry geometry(uint32_t M, int32_t h, uint32_t cn, uint32_t cd, int32_t sigma_ovr) {
   const bool large = M >= 800000u;
   if (cn == 0 || cd == 0) {
-    if (!large) { cn = 112; cd = 100; }
-    else if (h > 0) { cn = 1105; cd = 1000; }
-    else { cn = 1125; cd = 1000; }
+    if (large && h > 0) { cn = 1105; cd = 1000; }
+    else if (large) { cn = 1125; cd = 1000; }
+    else if (M >= 65536u) { cn = 112; cd = 100; }
+    else { cn = 116; cd = 100; }
   }
   int32_t sg;
   if (sigma_ovr >= 0) {

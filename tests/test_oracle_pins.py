@@ -160,6 +160,22 @@ def test_geometry_rules():
     assert g["sigma"] == math.floor(0.41 * lm * math.log(lm) - 3)
     g = O.geometry(0, 3)
     assert g["l"] == 1 and g["V"] == 3 << g["sigma"]
+    # below 2^16 keys per shard c = 1.16 (c = 1.12 is unsolvable too often)
+    assert (O.geometry(65535, 4)["c_num"], O.geometry(65536, 4)["c_num"]) == (116, 112)
+
+
+def test_small_shards_are_solvable_in_most_attempts():
+    """The size rule must leave small shards solvable: across sizes from 2^6
+    to 2^15 keys most first attempts succeed (failures are retried)."""
+    ok = tot = 0
+    for lm in range(6, 16):
+        m = 1 << lm
+        for t in range(4 if lm < 13 else 2):
+            keys = S.member_keys(m, 900 + 17 * lm + t).numpy().view(np.uint64)
+            B = O.build(keys, b=16, is_filter=True, h=0, seed=t, tmax=1)
+            ok += B.status == 0
+            tot += 1
+    assert ok >= 0.6 * tot
 
 
 def test_edge_fields():

@@ -377,6 +377,9 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   uint32_t per_cu = 1;
   build_occupancy(g.sigma, &per_cu, &A.lds_bytes);
   A.wmax = vfk::window_slots((uint32_t)g.sigma, A.lds_bytes);
+  // a window of at most 384 slots lets the kernel keep 6 instead of 8 slot
+  // groups per lane (overflowing shards go to the second launch)
+  if (A.wmax > 384 && window_target(g.sigma) <= 384) A.wmax = 384;
   const uint32_t nwg = std::min<uint32_t>(L.nwg, per_cu * (uint32_t)ncu);
   A.logcap = L.logcap;
   A.cell_bytes = L.cell_bytes;

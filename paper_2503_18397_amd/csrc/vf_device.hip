@@ -363,7 +363,6 @@ __host__ __device__ inline uint32_t row_stride(uint32_t sigma) { return Ring(sig
 __host__ __device__ inline uint32_t slot_bytes(uint32_t sigma) { return 4 * row_stride(sigma) + 16; }
 
 constexpr uint32_t kMaxSlots = 512;
-constexpr int kQM = kMaxSlots / 64;
 constexpr uint32_t kBcolBytes = 256;  // batch columns of the back-substitution
 
 uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes) {
@@ -386,6 +385,7 @@ enum { kSolveOk = 0, kSolveInconsistent = 1, kSolveCapacity = 2 };
 // of the current 32 columns, its popcount and its right side in registers;
 // candidates, pivot choice and the column mask therefore need no LDS
 // traffic, only the row updates do.
+template <int QM>
 __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc, uint8_t *lds,
                                           uint32_t *np_out) {
   const Geo &G = A.G;
@@ -416,9 +416,8 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc,
   const uint32_t gsh = entry_shift(G.sigma);
   wave_sync();
 
-  // rows of entry group g join the window
-  auto enter = [&](uint32_t g) -> bool {
-    const uint32_t rb = cb[g], re = cb[g + 1];
+  // core rows [rb, re) join the window
+  auto enter = [&](uint32_t rb, uint32_t re) -> bool {
     for (uint32_t r0 = rb; r0 < re; r0 += 64) {
       const uint32_t cnt = min(64u, re - r0);
       if (cnt > nfree) return false;
@@ -444,147 +443,208 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc,
     return true;
   };
 
-  uint32_t cw[kQM], pop[kQM];
-  uint64_t rh[kQM];
+  uint32_t cw[QM], pop[QM], cm[QM];
+  uint64_t rh[QM];
+  const uint32_t NW = (RW + 63) / 64;  // ring words per lane
   for (int Gs = (int)G.l + 1; Gs >= 0; Gs--) {
-    if (gsh < 5 && !enter((uint32_t)Gs)) return kSolveCapacity;
+    // group starts of this segment, one per lane (readlane per word)
+    const uint32_t g0 = gsh == 5 ? ((uint32_t)Gs * s) >> 5 : (uint32_t)Gs;
+    const uint32_t ng = gsh == 5 ? s >> 5 : 1u;  // groups (words) in the segment
+    const bool cached = ng < 64;
+    const uint32_t cbl = cached && lane <= ng ? cb[g0 + lane] : 0u;
+    auto cbv = [&](uint32_t i) { return cached ? readlane(cbl, (int)i) : cb[g0 + i]; };
+    if (gsh < 5 && !enter(cbv(0), cbv(1))) return kSolveCapacity;
     const uint32_t segtop = (uint32_t)(Gs + 1) * s - 1, segbot = (uint32_t)Gs * s;
     uint32_t c = segtop;
     for (;;) {
-      if (gsh == 5 && !enter(c >> 5)) return kSolveCapacity;
+      if (gsh == 5) {
+        const uint32_t wi = (c >> 5) - g0;
+        if (!enter(cbv(wi), cbv(wi + 1))) return kSolveCapacity;
+      }
       const uint32_t cpos = ring.pos(c), word = cpos >> 5;
       const uint32_t wbase = c - (cpos & 31);  // column of bit 0 of this word
       const uint32_t wlo_col = max(segbot, wbase);
       const uint32_t lowbit = wlo_col - wbase, hibit = cpos & 31;
       const uint32_t range = (hibit >= 31 ? 0xFFFFFFFFu : ((2u << hibit) - 1u)) &
                              ~((1u << lowbit) - 1u);
-      // register caches of this word
+      // register caches of this word (all loads issued together)
       uint32_t orv = 0;
 #pragma unroll
-      for (int q = 0; q < kQM; q++) {
-        cw[q] = 0;
-        pop[q] = 0;
-        rh[q] = 0;
-        if ((uint32_t)q < NQ) {
-          const uint32_t slot = (uint32_t)q * 64 + lane;
-          if (slot < W) {
-            pop[q] = rpop[slot];
-            if (pop[q]) {
-              cw[q] = rows[(uint64_t)slot * RS + word] & range;
-              rh[q] = rrhs[slot];
-            }
-          }
-        }
+      for (int q = 0; q < QM; q++) {
+        if ((uint32_t)q >= NQ) break;
+        const uint32_t slot = (uint32_t)q * 64 + lane;
+        const bool in = (uint32_t)q < NQ && slot < W;
+        const uint32_t sl = in ? slot : 0u;
+        pop[q] = rpop[sl];
+        cw[q] = rows[(uint64_t)sl * RS + word];
+        rh[q] = rrhs[sl];
+        if (!in) pop[q] = 0;
+        cw[q] = pop[q] ? cw[q] & range : 0u;
+        cm[q] = 0;
         orv |= cw[q];
       }
+      // 1. pivots of the word's columns, top down, on the register words
+      //    only: cm records which of this word's pivot rows (by index k) a row
+      //    has absorbed; lane k of pivtab/pivcol/pivrhs describes pivot k
       uint32_t colmask = wave_or(orv);
+      uint32_t k = 0, pivtab = 0, pivcol = 0, pivbits = 0;
+      uint64_t pivrhs = 0;
       while (colmask) {
         const uint32_t b = 31 - __clz(colmask);
-        const uint32_t col = wbase + b;
-        // candidates and pivot (fewest nonzeros, then lowest slot)
-        uint64_t cand[kQM];
+        uint64_t cand[QM];
         uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
-        for (int q = 0; q < kQM; q++) {
+        for (int q = 0; q < QM; q++) {
+        if ((uint32_t)q >= NQ) break;
           const bool has = (cw[q] >> b) & 1u;
           cand[q] = __ballot(has);
           if (has) best = min(best, (min(pop[q], 0xFFFFu) << 16) | ((uint32_t)q * 64 + lane));
         }
         best = wave_min(best);
         const uint32_t p = best & 0xFFFFu, pq = p >> 6, pl = p & 63u;
-        uint32_t pw = 0;
+        const uint32_t ppop = best >> 16;
+        uint32_t pw = 0, pcm = 0;
         uint64_t prhs = 0;
 #pragma unroll
-        for (int q = 0; q < kQM; q++)
+        for (int q = 0; q < QM; q++) {
+          if ((uint32_t)q >= NQ) break;
           if ((uint32_t)q == pq) {
             pw = readlane(cw[q], (int)pl);
+            pcm = readlane(cm[q], (int)pl);
             prhs = readlane64(rh[q], (int)pl);
-            cand[q] &= ~(1ull << pl);
-          }
-        const uint32_t *prow = rows + (uint64_t)p * RS;
-        // emit the pivot row (all its vertices below col): every round each
-        // lane with bits left writes its lowest one at a ballot-counted slot
-        uint32_t pos = lp + 4;
-        for (uint32_t u0 = 0; u0 < RW; u0 += 64) {
-          const uint32_t u = u0 + lane;
-          uint32_t bits = u < RW ? prow[u] : 0u;
-          if (u == word) bits &= ~(1u << b);
-          for (;;) {
-            const uint64_t m = __ballot(bits != 0);
-            if (!m) break;
-            if (pos + (uint32_t)__popcll(m) > logcap) return kSolveCapacity;
-            if (bits) {
-              const uint32_t bb = __ffs(bits) - 1;
-              bits &= bits - 1;
-              plog[pos + lanes_below(m)] = ring.vertex(u * 32 + bb, (uint32_t)Gs);
-            }
-            pos += (uint32_t)__popcll(m);
           }
         }
-        if (lane == 0) {
-          plog[lp] = col;
-          plog[lp + 1] = pos - (lp + 4);
-          plog[lp + 2] = (uint32_t)prhs;
-          plog[lp + 3] = (uint32_t)(prhs >> 32);
-          poff[np] = lp;
+        if (lane == k) {
+          pivtab = p;
+          pivcol = wbase + b;
+          pivrhs = prhs;
         }
-        lp = pos;
-        np++;
-        // eliminate col from the other candidate rows
+        const uint32_t kbit = pcm | (1u << k);
+#pragma unroll
+        for (int q = 0; q < QM; q++) {
+        if ((uint32_t)q >= NQ) break;
+          const bool isp = (uint32_t)q == pq && lane == pl;
+          if (((cand[q] >> lane) & 1ull) && !isp) {
+            cw[q] ^= pw;
+            cm[q] ^= kbit;
+            rh[q] ^= prhs;
+            pop[q] = min(pop[q] + ppop - 2u, 0xFFFFu);
+          }
+          if (isp) {
+            cw[q] = 0;
+            pop[q] = 0;
+            pivbits |= 1u << q;
+          }
+        }
+        k++;
+        orv = 0;
+#pragma unroll
+        for (int q = 0; q < QM; q++) {
+          if ((uint32_t)q >= NQ) break;
+          orv |= cw[q];
+        }
+        colmask = wave_or(orv) & ((1u << b) - 1u);
+      }
+      if (k) {
+        // 2. whole rows: every non-pivot row that absorbed pivots of this
+        //    word gets their rows (as they were when the word started) xored
+        //    in; a row that becomes zero leaves the window (inconsistent if
+        //    its right side is not zero)
         bool incons = false;
 #pragma unroll
-        for (int q = 0; q < kQM; q++) {
-          uint64_t m = cand[q];
+        for (int q = 0; q < QM; q++) {
+        if ((uint32_t)q >= NQ) break;
+          uint64_t m = __ballot(cm[q] != 0 && !((pivbits >> q) & 1u));
           while (m) {
             const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
             m &= m - 1;
             const uint32_t x = (uint32_t)q * 64 + xl;
+            const uint32_t cmx = readlane(cm[q], (int)xl);
             uint32_t *xrow = rows + (uint64_t)x * RS;
-            uint32_t pc = 0;
-            for (uint32_t u0 = 0; u0 < RW; u0 += 64) {
-              const uint32_t u = u0 + lane;
+            uint32_t any = 0;
+            for (uint32_t w = 0; w < NW; w++) {
+              const uint32_t u = w * 64 + lane;
               if (u < RW) {
-                const uint32_t nv = xrow[u] ^ prow[u];
-                xrow[u] = nv;
-                pc += __popc(nv);
+                uint32_t acc = xrow[u];
+                for (uint32_t bits = cmx; bits; bits &= bits - 1) {
+                  const uint32_t j = __ffs(bits) - 1;
+                  acc ^= rows[(uint64_t)readlane(pivtab, (int)j) * RS + u];
+                }
+                xrow[u] = acc;
+                any |= acc;
               }
             }
-            pc = wave_sum(pc);
-            const uint64_t nr = readlane64(rh[q], (int)xl) ^ prhs;
-            if (lane == xl) {
-              cw[q] ^= pw;
-              pop[q] = pc;
-              rh[q] = nr;
-            }
-            if (lane == 0) {
-              rpop[x] = pc;
-              rrhs[x] = nr;
-            }
-            if (pc == 0) {
-              incons |= nr != 0;
+            if (__ballot(any != 0) == 0) {
+              incons |= readlane64(rh[q], (int)xl) != 0;
+              if (lane == xl) pop[q] = 0;
               if (lane == 0) freel[nfree] = x;
               nfree++;
             }
           }
         }
         if (incons) return kSolveInconsistent;
-        // the pivot row leaves the window
+        // 3. pivot rows, last first (each only reads earlier pivots' rows,
+        //    none of which is rewritten): emit [column, count, rhs, vertices
+        //    below the column], then free the slot
+        for (int kk = (int)k - 1; kk >= 0; kk--) {
+          const uint32_t x = readlane(pivtab, kk), xq = x >> 6, xl = x & 63u;
+          const uint32_t col = readlane(pivcol, kk);
+          const uint64_t prhs = readlane64(pivrhs, kk);
+          uint32_t cmx = 0;
 #pragma unroll
-        for (int q = 0; q < kQM; q++)
-          if ((uint32_t)q == pq && lane == pl) {
-            cw[q] = 0;
-            pop[q] = 0;
+          for (int q = 0; q < QM; q++) {
+            if ((uint32_t)q >= NQ) break;
+            if ((uint32_t)q == xq) cmx = readlane(cm[q], (int)xl);
           }
-        if (lane == 0) {
-          rpop[p] = 0;
-          freel[nfree] = p;
+          const uint32_t *xrow = rows + (uint64_t)x * RS;
+          const uint32_t cb_ = ring.pos(col);
+          uint32_t pos = lp + 4;
+          for (uint32_t w = 0; w < NW; w++) {
+            const uint32_t u = w * 64 + lane;
+            uint32_t bits = 0;
+            if (u < RW) {
+              bits = xrow[u];
+              for (uint32_t cb2 = cmx; cb2; cb2 &= cb2 - 1) {
+                const uint32_t j = __ffs(cb2) - 1;
+                bits ^= rows[(uint64_t)readlane(pivtab, (int)j) * RS + u];
+              }
+              if (u == (cb_ >> 5)) bits &= ~(1u << (cb_ & 31));
+            }
+            for (;;) {
+              const uint64_t m = __ballot(bits != 0);
+              if (!m) break;
+              if (pos + (uint32_t)__popcll(m) > logcap) return kSolveCapacity;
+              if (bits) {
+                const uint32_t bb = __ffs(bits) - 1;
+                bits &= bits - 1;
+                plog[pos + lanes_below(m)] = ring.vertex(u * 32 + bb, (uint32_t)Gs);
+              }
+              pos += (uint32_t)__popcll(m);
+            }
+          }
+          if (lane == 0) {
+            plog[lp] = col;
+            plog[lp + 1] = pos - (lp + 4);
+            plog[lp + 2] = (uint32_t)prhs;
+            plog[lp + 3] = (uint32_t)(prhs >> 32);
+            poff[np + (uint32_t)kk] = lp;
+            freel[nfree] = x;
+          }
+          nfree++;
+          lp = pos;
         }
-        nfree++;
-        wave_sync();
-        orv = 0;
+        np += k;
+        // popcount estimates and right sides back to LDS for the next word
 #pragma unroll
-        for (int q = 0; q < kQM; q++) orv |= cw[q];
-        colmask = wave_or(orv) & ((1u << b) - 1u);
+        for (int q = 0; q < QM; q++) {
+        if ((uint32_t)q >= NQ) break;
+          const uint32_t slot = (uint32_t)q * 64 + lane;
+          if ((uint32_t)q < NQ && slot < W) {
+            rpop[slot] = pop[q];
+            rrhs[slot] = rh[q];
+          }
+        }
+        wave_sync();
       }
       if (wlo_col == segbot) break;
       c = wlo_col - 1;
@@ -663,7 +723,7 @@ __device__ __forceinline__ uint32_t wave_scan_array(uint32_t *a, uint32_t *b, ui
   return total;
 }
 
-template <typename T>
+template <typename T, int QM>
 __global__ void __launch_bounds__(64) k_build(BuildArgs A) {
   extern __shared__ __align__(16) uint8_t lds[];
   const Geo &G = A.G;
@@ -815,7 +875,7 @@ __global__ void __launch_bounds__(64) k_build(BuildArgs A) {
       wave_sync_global();
 
       uint32_t np = 0;
-      const int st = k ? band_solve(A, sc, lds, &np) : kSolveOk;
+      const int st = k ? band_solve<QM>(A, sc, lds, &np) : kSolveOk;
       wave_sync_global();
       if (st == kSolveCapacity) {
         if (lane == 0) {
@@ -934,14 +994,21 @@ hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_build_t(const BuildArgs &a, int nwg, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_build<T>,
+template <typename T, int QM>
+static hipError_t launch_build_q(const BuildArgs &a, int nwg, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_build<T, QM>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)a.lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_build<T>, dim3(nwg), dim3(64), a.lds_bytes, s, a);
+  hipLaunchKernelGGL((k_build<T, QM>), dim3(nwg), dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
+}
+
+// The elimination keeps up to QM slot groups of 64 window rows in
+// registers; fewer groups mean fewer instructions per column.
+template <typename T>
+static hipError_t launch_build_t(const BuildArgs &a, int nwg, hipStream_t s) {
+  return a.wmax <= 384 ? launch_build_q<T, 6>(a, nwg, s) : launch_build_q<T, 8>(a, nwg, s);
 }
 
 hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s) {

@@ -166,6 +166,7 @@ def main():
         "check": {"rc": rc, "members_all_true": members_ok, "negatives": n_neg,
                   "false_positives": fp, "fpr_x256": round(256 * fp / max(n_neg, 1), 4),
                   "failed_attempts": info["n_failures"],
+                  "relaunched_shards": info["relaunched_shards"],
                   "space_bits_per_key": round(info["space_bits"] / n, 4)},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

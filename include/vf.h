@@ -96,6 +96,10 @@ typedef struct vf_info_t {
    * the build stream: shard counting + scan, grouping keys by shard, and
    * the per-shard construction kernel. */
   float ms_count, ms_scatter, ms_build;
+  /* Shards whose elimination window outgrew a build workgroup's share of a
+   * CU's LDS and were rebuilt by a second launch with a whole CU's LDS
+   * (same result, slower). */
+  uint32_t relaunched_shards;
 } vf_info_t;
 
 /* One failed construction attempt of one shard. */

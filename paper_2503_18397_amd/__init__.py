@@ -48,7 +48,8 @@ class Info(C.Structure):
                 ("cell_bytes", C.c_uint32), ("failed_shards", C.c_uint32),
                 ("n_failures", C.c_uint32), ("space_bits", C.c_uint64),
                 ("cells", C.c_void_p), ("local_seeds", C.c_void_p),
-                ("ms_count", C.c_float), ("ms_scatter", C.c_float), ("ms_build", C.c_float)]
+                ("ms_count", C.c_float), ("ms_scatter", C.c_float), ("ms_build", C.c_float),
+                ("relaunched_shards", C.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

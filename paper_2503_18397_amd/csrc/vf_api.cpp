@@ -114,7 +114,7 @@ uint32_t window_target(int32_t sigma) {
   return std::min<uint32_t>(512u, s / 2 + s / 8 + 32);
 }
 
-// How many single-wavefront build workgroups share one CU's LDS, and the
+// How many build workgroups share one CU's LDS, and the
 // LDS each gets: as many as still leave every one a large enough window.
 void build_occupancy(int32_t sigma, uint32_t *per_cu, uint32_t *lds_bytes) {
   const uint32_t want = window_target(sigma);
@@ -236,6 +236,7 @@ struct vf_handle {
   uint32_t failed_shards;
   int ncu;
   float ms[3];
+  uint32_t relaunched;
 };
 
 namespace {
@@ -383,7 +384,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   const uint32_t nwg = std::min<uint32_t>(L.nwg, per_cu * (uint32_t)ncu);
   A.logcap = L.logcap;
   A.cell_bytes = L.cell_bytes;
-  A.cells_in_lds = g.V * L.cell_bytes + 256 <= A.lds_bytes ? 1u : 0u;  // + batch columns
+  A.cells_in_lds = g.V * L.cell_bytes + vfk::kLdsTail <= A.lds_bytes ? 1u : 0u;
   A.list = nullptr;
   A.nlist = 0;
   A.overflow = overflow;
@@ -400,7 +401,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
     A.overflow = nullptr;
     A.lds_bytes = (vfk::kLdsBudget - 256) & ~255u;
     A.wmax = vfk::window_slots((uint32_t)g.sigma, A.lds_bytes);
-    A.cells_in_lds = g.V * L.cell_bytes + 256 <= A.lds_bytes ? 1u : 0u;
+    A.cells_in_lds = g.V * L.cell_bytes + vfk::kLdsTail <= A.lds_bytes ? 1u : 0u;
     HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkNext, 1, 0, stream));
     HIPCHK(vfk::launch_build(A, (int)std::min<uint32_t>(nwg, (uint32_t)ncu), stream));
     HIPCHK(hipMemcpyAsync(hwork, work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
@@ -435,6 +436,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   H->tseed = tseed;
   H->ncu = ncu;
   H->n_fail_total = hwork[vfk::kWorkFails];
+  H->relaunched = hwork[vfk::kWorkCap];
   H->ms[0] = pe.between(0, 1);
   H->ms[1] = pe.between(1, 2);
   H->ms[2] = pe.between(2, 3);
@@ -507,6 +509,7 @@ int vf_info(const vf_handle *h, vf_info_t *out) {
   out->ms_count = h->ms[0];
   out->ms_scatter = h->ms[1];
   out->ms_build = h->ms[2];
+  out->relaunched_shards = h->relaunched;
   return VF_OK;
 }
 

@@ -359,35 +359,67 @@ struct Ring {
 // word of consecutive slots then hit distinct LDS banks.
 __host__ __device__ inline uint32_t row_stride(uint32_t sigma) { return Ring(sigma).words + 1; }
 
-// Bytes of one window slot: ring row + rhs (8) + popcount (4) + free-list entry (4).
-__host__ __device__ inline uint32_t slot_bytes(uint32_t sigma) { return 4 * row_stride(sigma) + 16; }
+// Bytes of one window slot: ring row + rhs (8) + popcount (2) + free-list entry (2).
+__host__ __device__ inline uint32_t slot_bytes(uint32_t sigma) { return 4 * row_stride(sigma) + 12; }
 
 constexpr uint32_t kMaxSlots = 512;
 constexpr uint32_t kBcolBytes = 256;  // batch columns of the back-substitution
 
 uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes) {
-  uint32_t n = (lds_bytes - kBcolBytes) / slot_bytes(sigma);
+  uint32_t n = (lds_bytes - kLdsTail) / slot_bytes(sigma);
   n = n > kMaxSlots ? kMaxSlots : n;
   return n & ~7u;  // keeps the 8-byte right sides after the rows aligned
 }
 
 enum { kSolveOk = 0, kSolveInconsistent = 1, kSolveCapacity = 2 };
 
-// Gaussian elimination of the 2-core over GF(2), one wavefront.  Core rows
-// enter the window when the sweep reaches their entry group; columns are
-// visited from the highest vertex down.  For column c every window row that
-// contains c is a candidate; one of them (fewest nonzeros first: least fill)
-// becomes the pivot row of c and is xored into the other candidates.
-// Pivot rows are appended to a log: [column, count, rhs lo, rhs hi,
-// vertices...]; poff[i] is the offset of the i-th (descending column).
+// Control block in LDS shared by the two wavefronts of a build workgroup.
+// The pivots found in one 32-column word travel from the eliminating
+// wavefront to the emitting one as a batch; the emitter hands the slots of
+// the emitted rows back in a return list.  Batches, return lists and the
+// abort flags are double-buffered by word parity: an entry written during
+// word i is read after the barrier that ends word i and rewritten only
+// during word i + 2, after every reader has passed the barrier of word i + 1.
+struct BandCtl {
+  uint32_t shard, t0, core, np;  // work item, core rows, pivots emitted
+  uint32_t flag[2];              // kSolveInconsistent | kSolveCapacity
+  uint32_t adv[2];               // 0: the word is taken again (window full)
+  uint32_t k[2], gs[2];          // pivots of each batch and its segment
+  uint32_t nret[2];
+  uint32_t slot[2][32], col[2][32], cm[2][32];
+  uint64_t rhs[2][32];
+  uint32_t ret[2][32];
+};
+static_assert(sizeof(BandCtl) + kBcolBytes <= kLdsTail, "LDS tail too small");
+
+__device__ __forceinline__ BandCtl *band_ctl(uint8_t *lds, uint32_t lds_bytes) {
+  return (BandCtl *)(lds + lds_bytes - kLdsTail);
+}
+
+// Gaussian elimination of the 2-core over GF(2) by the two wavefronts of
+// the workgroup.  Core rows enter the window when the sweep reaches their
+// entry group; columns are visited from the highest vertex down.  For
+// column c every window row that contains c is a candidate; one of them
+// (fewest nonzeros first: least fill) becomes the pivot row of c and is
+// xored into the other candidates.
 //
-// Slot s of the window belongs to lane s % 64, which keeps the slot's word
-// of the current 32 columns, its popcount and its right side in registers;
-// candidates, pivot choice and the column mask therefore need no LDS
-// traffic, only the row updates do.
+// Wavefront 0 eliminates, one 32-column word at a time.  Slot s of the
+// window belongs to its lane s % 64, which keeps the slot's word of the
+// current 32 columns, its popcount and its right side in registers;
+// candidates, pivot choice and the column mask need no LDS traffic, only
+// the row updates do.
+//
+// Wavefront 1 runs one word behind and appends the pivot rows of the
+// previous word to a log: [column, count, rhs lo, rhs hi, vertices below
+// the column]; poff[i] is the offset of the i-th (descending column).  A
+// pivot row is frozen once chosen, so emitting it overlaps the elimination
+// of the next word; its slot returns to wavefront 0 after the emission.
+//
+// Both wavefronts walk the same sequence of words and meet at one barrier
+// per word; the result (kSolve*) and the pivot count are the same in both.
 template <int QM>
 __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc, uint8_t *lds,
-                                          uint32_t *np_out) {
+                                          BandCtl *ctl, uint32_t wid, uint32_t *np_out) {
   const Geo &G = A.G;
   uint32_t *const plog = sc.plog;
   uint32_t *const poff = sc.poff;
@@ -403,24 +435,32 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc,
   const uint32_t W = A.wmax;
   uint32_t *rows = (uint32_t *)lds;
   uint64_t *rrhs = (uint64_t *)(lds + (uint64_t)4 * RS * W);
-  uint32_t *rpop = (uint32_t *)(rrhs + W);
-  uint32_t *freel = rpop + W;
+  uint16_t *rpop = (uint16_t *)(rrhs + W);
+  uint16_t *freel = rpop + W;
+  const uint32_t NW = (RW + 63) / 64;  // ring words per lane
 
   // free slots form a stack that hands out low slots first; only slot groups
   // below the high-water mark are ever scanned
-  for (uint32_t i = lane; i < W; i += 64) {
-    rpop[i] = 0;
-    freel[i] = W - 1 - i;
+  if (wid == 0) {
+    for (uint32_t i = lane; i < W; i += 64) {
+      rpop[i] = 0;
+      freel[i] = (uint16_t)(W - 1 - i);
+    }
+    if (lane == 0) {
+      ctl->flag[0] = ctl->flag[1] = 0;
+      ctl->nret[0] = ctl->nret[1] = 0;
+      ctl->k[0] = ctl->k[1] = 0;
+    }
   }
-  uint32_t nfree = W, NQ = 0, lp = 0, np = 0;
+  __syncthreads();
+  uint32_t nfree = W, NQ = 0;  // wavefront 0
+  uint32_t lp = 0, np = 0;     // wavefront 1
   const uint32_t gsh = entry_shift(G.sigma);
-  wave_sync();
 
-  // core rows [rb, re) join the window
-  auto enter = [&](uint32_t rb, uint32_t re) -> bool {
+  // core rows [rb, re) join the window (wavefront 0; re - rb <= nfree)
+  auto enter = [&](uint32_t rb, uint32_t re) {
     for (uint32_t r0 = rb; r0 < re; r0 += 64) {
       const uint32_t cnt = min(64u, re - r0);
-      if (cnt > nfree) return false;
       if (lane < cnt) {
         const uint64_t e = cE[r0 + lane];
         const uint64_t rhs = cR[r0 + lane];
@@ -440,218 +480,289 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc,
       NQ = max(NQ, (W - nfree + 63) / 64);
       wave_sync();
     }
+  };
+
+  // pivot rows of batch bsel, last first (each only reads earlier pivots'
+  // rows, none of which is rewritten), their slots into return list rsel
+  // (wavefront 1); false if the log is full
+  auto emit = [&](uint32_t bsel, uint32_t rsel) -> bool {
+    const uint32_t kp = ctl->k[bsel], Gs = ctl->gs[bsel];
+    const uint32_t pivtab = lane < kp ? ctl->slot[bsel][lane] : 0u;
+    const uint32_t pivcol = lane < kp ? ctl->col[bsel][lane] : 0u;
+    const uint32_t pivcm = lane < kp ? ctl->cm[bsel][lane] : 0u;
+    const uint64_t pivrhs = lane < kp ? ctl->rhs[bsel][lane] : 0ull;
+    for (int kk = (int)kp - 1; kk >= 0; kk--) {
+      const uint32_t x = readlane(pivtab, kk);
+      const uint32_t col = readlane(pivcol, kk);
+      const uint32_t cmx = readlane(pivcm, kk);
+      const uint64_t prhs = readlane64(pivrhs, kk);
+      const uint32_t *xrow = rows + (uint64_t)x * RS;
+      const uint32_t cb_ = ring.pos(col);
+      uint32_t pos = lp + 4;
+      for (uint32_t w = 0; w < NW; w++) {
+        const uint32_t u = w * 64 + lane;
+        uint32_t bits = 0;
+        if (u < RW) {
+          bits = xrow[u];
+          for (uint32_t cb2 = cmx; cb2; cb2 &= cb2 - 1) {
+            const uint32_t j = __ffs(cb2) - 1;
+            bits ^= rows[(uint64_t)readlane(pivtab, (int)j) * RS + u];
+          }
+          if (u == (cb_ >> 5)) bits &= ~(1u << (cb_ & 31));
+        }
+        for (;;) {
+          const uint64_t m = __ballot(bits != 0);
+          if (!m) break;
+          if (pos + (uint32_t)__popcll(m) > logcap) return false;
+          if (bits) {
+            const uint32_t bb = __ffs(bits) - 1;
+            bits &= bits - 1;
+            plog[pos + lanes_below(m)] = ring.vertex(u * 32 + bb, Gs);
+          }
+          pos += (uint32_t)__popcll(m);
+        }
+      }
+      if (lane == 0) {
+        plog[lp] = col;
+        plog[lp + 1] = pos - (lp + 4);
+        plog[lp + 2] = (uint32_t)prhs;
+        plog[lp + 3] = (uint32_t)(prhs >> 32);
+        poff[np + (uint32_t)kk] = lp;
+        ctl->ret[rsel][kk] = x;
+      }
+      lp = pos;
+    }
+    np += kp;
+    if (lane == 0) ctl->nret[rsel] = kp;
     return true;
   };
 
   uint32_t cw[QM], pop[QM], cm[QM];
   uint64_t rh[QM];
-  const uint32_t NW = (RW + 63) / 64;  // ring words per lane
-  for (int Gs = (int)G.l + 1; Gs >= 0; Gs--) {
+  uint32_t it = 0;
+  bool stop = false;
+  for (int Gs = (int)G.l + 1; Gs >= 0 && !stop; Gs--) {
     // group starts of this segment, one per lane (readlane per word)
     const uint32_t g0 = gsh == 5 ? ((uint32_t)Gs * s) >> 5 : (uint32_t)Gs;
     const uint32_t ng = gsh == 5 ? s >> 5 : 1u;  // groups (words) in the segment
     const bool cached = ng < 64;
-    const uint32_t cbl = cached && lane <= ng ? cb[g0 + lane] : 0u;
+    const uint32_t cbl = wid == 0 && cached && lane <= ng ? cb[g0 + lane] : 0u;
     auto cbv = [&](uint32_t i) { return cached ? readlane(cbl, (int)i) : cb[g0 + i]; };
-    if (gsh < 5 && !enter(cbv(0), cbv(1))) return kSolveCapacity;
     const uint32_t segtop = (uint32_t)(Gs + 1) * s - 1, segbot = (uint32_t)Gs * s;
     uint32_t c = segtop;
-    for (;;) {
-      if (gsh == 5) {
-        const uint32_t wi = (c >> 5) - g0;
-        if (!enter(cbv(wi), cbv(wi + 1))) return kSolveCapacity;
-      }
+    for (bool first = true;;) {
       const uint32_t cpos = ring.pos(c), word = cpos >> 5;
       const uint32_t wbase = c - (cpos & 31);  // column of bit 0 of this word
       const uint32_t wlo_col = max(segbot, wbase);
-      const uint32_t lowbit = wlo_col - wbase, hibit = cpos & 31;
-      const uint32_t range = (hibit >= 31 ? 0xFFFFFFFFu : ((2u << hibit) - 1u)) &
-                             ~((1u << lowbit) - 1u);
-      // register caches of this word (all loads issued together)
-      uint32_t orv = 0;
-#pragma unroll
-      for (int q = 0; q < QM; q++) {
-        if ((uint32_t)q >= NQ) break;
-        const uint32_t slot = (uint32_t)q * 64 + lane;
-        const bool in = (uint32_t)q < NQ && slot < W;
-        const uint32_t sl = in ? slot : 0u;
-        pop[q] = rpop[sl];
-        cw[q] = rows[(uint64_t)sl * RS + word];
-        rh[q] = rrhs[sl];
-        if (!in) pop[q] = 0;
-        cw[q] = pop[q] ? cw[q] & range : 0u;
-        cm[q] = 0;
-        orv |= cw[q];
-      }
-      // 1. pivots of the word's columns, top down, on the register words
-      //    only: cm records which of this word's pivot rows (by index k) a row
-      //    has absorbed; lane k of pivtab/pivcol/pivrhs describes pivot k
-      uint32_t colmask = wave_or(orv);
-      uint32_t k = 0, pivtab = 0, pivcol = 0, pivbits = 0;
-      uint64_t pivrhs = 0;
-      while (colmask) {
-        const uint32_t b = 31 - __clz(colmask);
-        uint64_t cand[QM];
-        uint32_t best = 0xFFFFFFFFu;
-#pragma unroll
-        for (int q = 0; q < QM; q++) {
-        if ((uint32_t)q >= NQ) break;
-          const bool has = (cw[q] >> b) & 1u;
-          cand[q] = __ballot(has);
-          if (has) best = min(best, (min(pop[q], 0xFFFFu) << 16) | ((uint32_t)q * 64 + lane));
+      const uint32_t cur = it & 1u, prev = cur ^ 1u;
+      if (wid == 0) {
+        // slots emitted during the previous word come back
+        const uint32_t nr = ctl->nret[prev];
+        if (lane < nr) freel[nfree + lane] = (uint16_t)ctl->ret[prev][lane];
+        nfree += nr;
+        wave_sync();
+        // rows whose top vertex is in this word (segment, below 32 vertices)
+        uint32_t rb = 0, re = 0;
+        if (gsh == 5) {
+          const uint32_t wi = (c >> 5) - g0;
+          rb = cbv(wi);
+          re = cbv(wi + 1);
+        } else if (first) {
+          rb = cbv(0);
+          re = cbv(1);
         }
-        best = wave_min(best);
-        const uint32_t p = best & 0xFFFFu, pq = p >> 6, pl = p & 63u;
-        const uint32_t ppop = best >> 16;
-        uint32_t pw = 0, pcm = 0;
-        uint64_t prhs = 0;
-#pragma unroll
-        for (int q = 0; q < QM; q++) {
-          if ((uint32_t)q >= NQ) break;
-          if ((uint32_t)q == pq) {
-            pw = readlane(cw[q], (int)pl);
-            pcm = readlane(cm[q], (int)pl);
-            prhs = readlane64(rh[q], (int)pl);
-          }
-        }
-        if (lane == k) {
-          pivtab = p;
-          pivcol = wbase + b;
-          pivrhs = prhs;
-        }
-        const uint32_t kbit = pcm | (1u << k);
-#pragma unroll
-        for (int q = 0; q < QM; q++) {
-        if ((uint32_t)q >= NQ) break;
-          const bool isp = (uint32_t)q == pq && lane == pl;
-          if (((cand[q] >> lane) & 1ull) && !isp) {
-            cw[q] ^= pw;
-            cm[q] ^= kbit;
-            rh[q] ^= prhs;
-            pop[q] = min(pop[q] + ppop - 2u, 0xFFFFu);
-          }
-          if (isp) {
-            cw[q] = 0;
-            pop[q] = 0;
-            pivbits |= 1u << q;
-          }
-        }
-        k++;
-        orv = 0;
-#pragma unroll
-        for (int q = 0; q < QM; q++) {
-          if ((uint32_t)q >= NQ) break;
-          orv |= cw[q];
-        }
-        colmask = wave_or(orv) & ((1u << b) - 1u);
-      }
-      if (k) {
-        // 2. whole rows: every non-pivot row that absorbed pivots of this
-        //    word gets their rows (as they were when the word started) xored
-        //    in; a row that becomes zero leaves the window (inconsistent if
-        //    its right side is not zero)
-        bool incons = false;
-#pragma unroll
-        for (int q = 0; q < QM; q++) {
-        if ((uint32_t)q >= NQ) break;
-          uint64_t m = __ballot(cm[q] != 0 && !((pivbits >> q) & 1u));
-          while (m) {
-            const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
-            m &= m - 1;
-            const uint32_t x = (uint32_t)q * 64 + xl;
-            const uint32_t cmx = readlane(cm[q], (int)xl);
-            uint32_t *xrow = rows + (uint64_t)x * RS;
-            uint32_t any = 0;
-            for (uint32_t w = 0; w < NW; w++) {
-              const uint32_t u = w * 64 + lane;
-              if (u < RW) {
-                uint32_t acc = xrow[u];
-                for (uint32_t bits = cmx; bits; bits &= bits - 1) {
-                  const uint32_t j = __ffs(bits) - 1;
-                  acc ^= rows[(uint64_t)readlane(pivtab, (int)j) * RS + u];
-                }
-                xrow[u] = acc;
-                any |= acc;
-              }
-            }
-            if (__ballot(any != 0) == 0) {
-              incons |= readlane64(rh[q], (int)xl) != 0;
-              if (lane == xl) pop[q] = 0;
-              if (lane == 0) freel[nfree] = x;
-              nfree++;
-            }
-          }
-        }
-        if (incons) return kSolveInconsistent;
-        // 3. pivot rows, last first (each only reads earlier pivots' rows,
-        //    none of which is rewritten): emit [column, count, rhs, vertices
-        //    below the column], then free the slot
-        for (int kk = (int)k - 1; kk >= 0; kk--) {
-          const uint32_t x = readlane(pivtab, kk), xq = x >> 6, xl = x & 63u;
-          const uint32_t col = readlane(pivcol, kk);
-          const uint64_t prhs = readlane64(pivrhs, kk);
-          uint32_t cmx = 0;
+        uint32_t k = 0, adv = 1;
+        if (re - rb > nfree) {
+          // window full: if the previous word's pivot rows are being
+          // emitted, wait one word for their slots; otherwise give up
+          if (it > 0 && ctl->k[prev] > 0) adv = 0;
+          else if (lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
+        } else {
+          enter(rb, re);
+          const uint32_t lowbit = wlo_col - wbase, hibit = cpos & 31;
+          const uint32_t range = (hibit >= 31 ? 0xFFFFFFFFu : ((2u << hibit) - 1u)) &
+                                 ~((1u << lowbit) - 1u);
+          // register caches of this word (all loads issued together)
+          uint32_t orv = 0;
 #pragma unroll
           for (int q = 0; q < QM; q++) {
             if ((uint32_t)q >= NQ) break;
-            if ((uint32_t)q == xq) cmx = readlane(cm[q], (int)xl);
+            const uint32_t slot = (uint32_t)q * 64 + lane;
+            const bool in = (uint32_t)q < NQ && slot < W;
+            const uint32_t sl = in ? slot : 0u;
+            pop[q] = rpop[sl];
+            cw[q] = rows[(uint64_t)sl * RS + word];
+            rh[q] = rrhs[sl];
+            if (!in) pop[q] = 0;
+            cw[q] = pop[q] ? cw[q] & range : 0u;
+            cm[q] = 0;
+            orv |= cw[q];
           }
-          const uint32_t *xrow = rows + (uint64_t)x * RS;
-          const uint32_t cb_ = ring.pos(col);
-          uint32_t pos = lp + 4;
-          for (uint32_t w = 0; w < NW; w++) {
-            const uint32_t u = w * 64 + lane;
-            uint32_t bits = 0;
-            if (u < RW) {
-              bits = xrow[u];
-              for (uint32_t cb2 = cmx; cb2; cb2 &= cb2 - 1) {
-                const uint32_t j = __ffs(cb2) - 1;
-                bits ^= rows[(uint64_t)readlane(pivtab, (int)j) * RS + u];
-              }
-              if (u == (cb_ >> 5)) bits &= ~(1u << (cb_ & 31));
-            }
-            for (;;) {
-              const uint64_t m = __ballot(bits != 0);
-              if (!m) break;
-              if (pos + (uint32_t)__popcll(m) > logcap) return kSolveCapacity;
-              if (bits) {
-                const uint32_t bb = __ffs(bits) - 1;
-                bits &= bits - 1;
-                plog[pos + lanes_below(m)] = ring.vertex(u * 32 + bb, (uint32_t)Gs);
-              }
-              pos += (uint32_t)__popcll(m);
-            }
-          }
-          if (lane == 0) {
-            plog[lp] = col;
-            plog[lp + 1] = pos - (lp + 4);
-            plog[lp + 2] = (uint32_t)prhs;
-            plog[lp + 3] = (uint32_t)(prhs >> 32);
-            poff[np + (uint32_t)kk] = lp;
-            freel[nfree] = x;
-          }
-          nfree++;
-          lp = pos;
-        }
-        np += k;
-        // popcount estimates and right sides back to LDS for the next word
+          // 1. pivots of the word's columns, top down, on the register words
+          //    only: cm records which of this word's pivot rows (by index k) a
+          //    row has absorbed; lane k of pivtab/pivcol/pivcm/pivrhs
+          //    describes pivot k
+          uint32_t colmask = wave_or(orv);
+          uint32_t pivtab = 0, pivcol = 0, pivcm = 0, pivbits = 0;
+          uint64_t pivrhs = 0;
+          while (colmask) {
+            const uint32_t b = 31 - __clz(colmask);
+            uint64_t cand[QM];
+            uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
-        for (int q = 0; q < QM; q++) {
-        if ((uint32_t)q >= NQ) break;
-          const uint32_t slot = (uint32_t)q * 64 + lane;
-          if ((uint32_t)q < NQ && slot < W) {
-            rpop[slot] = pop[q];
-            rrhs[slot] = rh[q];
+            for (int q = 0; q < QM; q++) {
+              if ((uint32_t)q >= NQ) break;
+              const bool has = (cw[q] >> b) & 1u;
+              cand[q] = __ballot(has);
+              if (has) best = min(best, (min(pop[q], 0xFFFFu) << 16) | ((uint32_t)q * 64 + lane));
+            }
+            best = wave_min(best);
+            const uint32_t p = best & 0xFFFFu, pq = p >> 6, pl = p & 63u;
+            const uint32_t ppop = best >> 16;
+            uint32_t pw = 0, pcm = 0;
+            uint64_t prhs = 0;
+#pragma unroll
+            for (int q = 0; q < QM; q++) {
+              if ((uint32_t)q >= NQ) break;
+              if ((uint32_t)q == pq) {
+                pw = readlane(cw[q], (int)pl);
+                pcm = readlane(cm[q], (int)pl);
+                prhs = readlane64(rh[q], (int)pl);
+              }
+            }
+            if (lane == k) {
+              pivtab = p;
+              pivcol = wbase + b;
+              pivcm = pcm;
+              pivrhs = prhs;
+            }
+            const uint32_t kbit = pcm | (1u << k);
+#pragma unroll
+            for (int q = 0; q < QM; q++) {
+              if ((uint32_t)q >= NQ) break;
+              const bool isp = (uint32_t)q == pq && lane == pl;
+              if (((cand[q] >> lane) & 1ull) && !isp) {
+                cw[q] ^= pw;
+                cm[q] ^= kbit;
+                rh[q] ^= prhs;
+                pop[q] = min(pop[q] + ppop - 2u, 0xFFFFu);
+              }
+              if (isp) {
+                cw[q] = 0;
+                pop[q] = 0;
+                pivbits |= 1u << q;
+              }
+            }
+            k++;
+            orv = 0;
+#pragma unroll
+            for (int q = 0; q < QM; q++) {
+              if ((uint32_t)q >= NQ) break;
+              orv |= cw[q];
+            }
+            colmask = wave_or(orv) & ((1u << b) - 1u);
+          }
+          if (k) {
+            // 2. whole rows: every non-pivot row that absorbed pivots of this
+            //    word gets their rows (as they were when the word started)
+            //    xored in; a row that becomes zero leaves the window
+            //    (inconsistent if its right side is not zero)
+            bool incons = false;
+#pragma unroll
+            for (int q = 0; q < QM; q++) {
+              if ((uint32_t)q >= NQ) break;
+              uint64_t m = __ballot(cm[q] != 0 && !((pivbits >> q) & 1u));
+              while (m) {
+                const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
+                m &= m - 1;
+                const uint32_t x = (uint32_t)q * 64 + xl;
+                const uint32_t cmx = readlane(cm[q], (int)xl);
+                uint32_t *xrow = rows + (uint64_t)x * RS;
+                uint32_t any = 0;
+                for (uint32_t w = 0; w < NW; w++) {
+                  const uint32_t u = w * 64 + lane;
+                  if (u < RW) {
+                    uint32_t acc = xrow[u];
+                    for (uint32_t bits = cmx; bits; bits &= bits - 1) {
+                      const uint32_t j = __ffs(bits) - 1;
+                      acc ^= rows[(uint64_t)readlane(pivtab, (int)j) * RS + u];
+                    }
+                    xrow[u] = acc;
+                    any |= acc;
+                  }
+                }
+                if (__ballot(any != 0) == 0) {
+                  incons |= readlane64(rh[q], (int)xl) != 0;
+                  if (lane == xl) pop[q] = 0;
+                  if (lane == 0) freel[nfree] = (uint16_t)x;
+                  nfree++;
+                }
+              }
+            }
+            if (incons && lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveInconsistent);
+            // popcount estimates and right sides back to LDS for the next word
+#pragma unroll
+            for (int q = 0; q < QM; q++) {
+              if ((uint32_t)q >= NQ) break;
+              const uint32_t slot = (uint32_t)q * 64 + lane;
+              if ((uint32_t)q < NQ && slot < W) {
+                rpop[slot] = (uint16_t)pop[q];
+                rrhs[slot] = rh[q];
+              }
+            }
+            // the batch for wavefront 1
+            if (lane < k) {
+              ctl->slot[cur][lane] = pivtab;
+              ctl->col[cur][lane] = pivcol;
+              ctl->cm[cur][lane] = pivcm;
+              ctl->rhs[cur][lane] = pivrhs;
+            }
           }
         }
-        wave_sync();
+        if (lane == 0) {
+          ctl->k[cur] = k;
+          ctl->gs[cur] = (uint32_t)Gs;
+          ctl->adv[cur] = adv;
+        }
+      } else {
+        if (it == 0) {
+          if (lane == 0) ctl->nret[cur] = 0;
+        } else if (!emit(prev, cur)) {
+          if (lane == 0) {
+            ctl->nret[cur] = 0;
+            atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
+          }
+        }
       }
+      __syncthreads();
+      it++;
+      if (ctl->flag[cur]) {
+        stop = true;
+        break;
+      }
+      if (!ctl->adv[cur]) continue;
+      first = false;
       if (wlo_col == segbot) break;
       c = wlo_col - 1;
     }
   }
-  *np_out = np;
-  return kSolveOk;
+  uint32_t fl;
+  if (stop) {
+    fl = ctl->flag[(it - 1) & 1u];
+  } else {
+    // the pivots of the last word
+    const uint32_t cur = it & 1u, prev = cur ^ 1u;
+    if (wid == 1) {
+      if (it > 0 && !emit(prev, cur) && lane == 0)
+        atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
+      if (lane == 0) ctl->np = np;
+    }
+    __syncthreads();
+    fl = ctl->flag[cur];
+  }
+  *np_out = ctl->np;
+  if (fl & kSolveInconsistent) return kSolveInconsistent;
+  return fl ? kSolveCapacity : kSolveOk;
 }
 
 // Back-substitution in increasing pivot column, 64 pivots per step: each
@@ -723,162 +834,181 @@ __device__ __forceinline__ uint32_t wave_scan_array(uint32_t *a, uint32_t *b, ui
   return total;
 }
 
+// One workgroup of two wavefronts builds one shard at a time.  Wavefront 0
+// does everything but the emission of pivot rows, which wavefront 1 does
+// during the elimination (band_solve); the two meet at workgroup barriers.
 template <typename T, int QM>
-__global__ void __launch_bounds__(64) k_build(BuildArgs A) {
+__global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   extern __shared__ __align__(16) uint8_t lds[];
   const Geo &G = A.G;
   const uint32_t lane = lane_id();
+  const uint32_t wid = threadIdx.x >> 6;
   const uint64_t V = G.V;
   Scratch sc;
   scratch_layout(A.scratch + (uint64_t)blockIdx.x * A.scratch_stride, A.M, V, G.l, A.logcap, &sc);
   T *cells = (T *)A.cells;
+  BandCtl *const ctl = band_ctl(lds, A.lds_bytes);
 
   for (;;) {
-    uint32_t j = 0;
-    if (lane == 0) j = atomicAdd(&A.work[kWorkNext], 1u);
-    j = readlane(j, 0);
-    uint32_t t0 = 0;
-    if (A.list) {
-      if (j >= A.nlist) break;
-      t0 = A.list[2 * j + 1];
-      j = A.list[2 * j];
-    } else if (j >= G.S) {
-      break;
+    if (threadIdx.x == 0) {
+      uint32_t j = atomicAdd(&A.work[kWorkNext], 1u), t0 = 0;
+      if (A.list) {
+        if (j < A.nlist) {
+          t0 = A.list[2 * j + 1];
+          j = A.list[2 * j];
+        } else {
+          j = 0xFFFFFFFFu;
+        }
+      } else if (j >= G.S) {
+        j = 0xFFFFFFFFu;
+      }
+      ctl->shard = j;
+      ctl->t0 = t0;
     }
+    __syncthreads();
+    const uint32_t j = ctl->shard, t0 = ctl->t0;
+    if (j == 0xFFFFFFFFu) break;
     const uint64_t base = A.offsets[j];
     const uint32_t m = (uint32_t)(A.offsets[j + 1] - base);
     T *wg = cells + (uint64_t)j * V;  // this shard's cells in HBM
     T *wl = A.cells_in_lds ? (T *)lds : wg;
 
     // right sides: values (Problem 1) or fingerprints (Problem 2)
-    for (uint32_t i = lane; i < m; i += 64) {
-      const uint64_t key = A.bkeys[base + i];
-      if (G.is_filter) {
-        sc.R[i] = fingerprint(G, fin64(key ^ G.khi), fin64(key ^ G.klo));
-      } else {
-        sc.R[i] = A.bvals[base + i] & G.vmask;
+    if (wid == 0) {
+      for (uint32_t i = lane; i < m; i += 64) {
+        const uint64_t key = A.bkeys[base + i];
+        if (G.is_filter) {
+          sc.R[i] = fingerprint(G, fin64(key ^ G.khi), fin64(key ^ G.klo));
+        } else {
+          sc.R[i] = A.bvals[base + i] & G.vmask;
+        }
       }
     }
 
     uint8_t result_t = 255;
     for (uint32_t t = t0; t < A.tmax; t++) {
-      // edges of this attempt, cleared vertex state
-      for (uint32_t i = lane; i < m; i += 64) {
-        const uint64_t key = A.bkeys[base + i];
-        uint32_t v0, v1, v2;
-        edge3(G, fin64(key ^ G.khi), fin64(key ^ G.klo), t, v0, v1, v2);
-        sc.E[i] = pack3(v0, v1, v2);
-        sc.pe[i] = 0;
-      }
-      for (uint64_t v = lane; v < V; v += 64) {
-        sc.deg[v] = 0;
-        sc.xr[v] = 0;
-      }
-      wave_sync_global();
-      // incidence: degree and xor of incident edges
-      for (uint32_t i = lane; i < m; i += 64) {
-        uint32_t v[3];
-        unpack3(sc.E[i], v);
-        for (int k = 0; k < 3; k++) {
-          atomicAdd(&sc.deg[v[k]], 1u);
-          atomicXor(&sc.xr[v[k]], i);
+      uint32_t nrounds = 0;
+      if (wid == 0) {
+        // edges of this attempt, cleared vertex state
+        for (uint32_t i = lane; i < m; i += 64) {
+          const uint64_t key = A.bkeys[base + i];
+          uint32_t v0, v1, v2;
+          edge3(G, fin64(key ^ G.khi), fin64(key ^ G.klo), t, v0, v1, v2);
+          sc.E[i] = pack3(v0, v1, v2);
+          sc.pe[i] = 0;
         }
-      }
-      wave_sync_global();
-      // round-synchronous peeling; list appends are counted by ballot
-      uint32_t nf = 0;
-      for (uint64_t v0 = 0; v0 < V; v0 += 64) {
-        const uint64_t v = v0 + lane;
-        const bool one = v < V && sc.deg[v] == 1;
-        const uint64_t bm = __ballot(one);
-        if (one) sc.F0[nf + lanes_below(bm)] = (uint32_t)v;
-        nf += (uint32_t)__popcll(bm);
-      }
-      wave_sync_global();
-      uint32_t nrounds = 0, nst = 0;
-      uint32_t *cur = sc.F0, *nxt = sc.F1;
-      if (lane == 0) sc.rst[0] = 0;
-      while (nf) {
-        const uint32_t r0 = nst;
-        // select with the degrees of the start of the round
-        for (uint32_t i0 = 0; i0 < nf; i0 += 64) {
-          const uint32_t i = i0 + lane;
-          bool take = false;
-          uint32_t e = 0, side = 0;
-          if (i < nf) {
-            const uint32_t v = cur[i];
-            if (sc.deg[v] == 1) {
-              e = sc.xr[v];
-              uint32_t a[3];
-              unpack3(sc.E[e], a);
-              side = a[0] == v ? 0u : (a[1] == v ? 1u : 2u);
-              take = true;
-              for (uint32_t k = 0; k < side; k++)
-                if (sc.deg[a[k]] == 1) take = false;
-            }
-          }
-          const uint64_t bm = __ballot(take);
-          if (take) {
-            sc.stack[nst + lanes_below(bm)] = e | (side << 30);
-            sc.pe[e] = 1;
-          }
-          nst += (uint32_t)__popcll(bm);
+        for (uint64_t v = lane; v < V; v += 64) {
+          sc.deg[v] = 0;
+          sc.xr[v] = 0;
         }
         wave_sync_global();
-        // remove the selected edges
-        uint32_t nn = 0;
-        for (uint32_t i0 = r0; i0 < nst; i0 += 64) {
-          const uint32_t i = i0 + lane;
-          bool push[3] = {false, false, false};
-          uint32_t a[3] = {0, 0, 0};
-          if (i < nst) {
-            const uint32_t e = sc.stack[i] & 0x3FFFFFFFu;
-            unpack3(sc.E[e], a);
-            for (int k = 0; k < 3; k++) {
-              const uint32_t old = atomicSub(&sc.deg[a[k]], 1u);
-              atomicXor(&sc.xr[a[k]], e);
-              push[k] = old == 2;
-            }
-          }
+        // incidence: degree and xor of incident edges
+        for (uint32_t i = lane; i < m; i += 64) {
+          uint32_t v[3];
+          unpack3(sc.E[i], v);
           for (int k = 0; k < 3; k++) {
-            const uint64_t bm = __ballot(push[k]);
-            if (push[k]) nxt[nn + lanes_below(bm)] = a[k];
-            nn += (uint32_t)__popcll(bm);
+            atomicAdd(&sc.deg[v[k]], 1u);
+            atomicXor(&sc.xr[v[k]], i);
           }
         }
-        nrounds++;
-        if (lane == 0) sc.rst[nrounds] = nst;
         wave_sync_global();
-        nf = nn;
-        uint32_t *tmp = cur;
-        cur = nxt;
-        nxt = tmp;
-      }
-
-      // 2-core edges, grouped by the entry group of their top vertex
-      const uint32_t gsh = entry_shift(G.sigma);
-      const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
-      for (uint32_t g = lane; g < ngroups; g += 64) sc.cc[g] = 0;
-      wave_sync_global();
-      for (uint32_t i = lane; i < m; i += 64)
-        if (!sc.pe[i]) atomicAdd(&sc.cc[(uint32_t)(sc.E[i] >> 42) >> gsh], 1u);
-      wave_sync_global();
-      const uint32_t k = wave_scan_array(sc.cc, sc.cb, ngroups);
-      wave_sync_global();
-      for (uint32_t i = lane; i < m; i += 64)
-        if (!sc.pe[i]) {
-          const uint64_t e = sc.E[i];
-          const uint32_t pos = atomicAdd(&sc.cc[(uint32_t)(e >> 42) >> gsh], 1u);
-          sc.cE[pos] = e;
-          sc.cR[pos] = sc.R[i];
+        // round-synchronous peeling; list appends are counted by ballot
+        uint32_t nf = 0;
+        for (uint64_t v0 = 0; v0 < V; v0 += 64) {
+          const uint64_t v = v0 + lane;
+          const bool one = v < V && sc.deg[v] == 1;
+          const uint64_t bm = __ballot(one);
+          if (one) sc.F0[nf + lanes_below(bm)] = (uint32_t)v;
+          nf += (uint32_t)__popcll(bm);
         }
-      wave_sync_global();
+        wave_sync_global();
+        uint32_t nst = 0;
+        uint32_t *cur = sc.F0, *nxt = sc.F1;
+        if (lane == 0) sc.rst[0] = 0;
+        while (nf) {
+          const uint32_t r0 = nst;
+          // select with the degrees of the start of the round
+          for (uint32_t i0 = 0; i0 < nf; i0 += 64) {
+            const uint32_t i = i0 + lane;
+            bool take = false;
+            uint32_t e = 0, side = 0;
+            if (i < nf) {
+              const uint32_t v = cur[i];
+              if (sc.deg[v] == 1) {
+                e = sc.xr[v];
+                uint32_t a[3];
+                unpack3(sc.E[e], a);
+                side = a[0] == v ? 0u : (a[1] == v ? 1u : 2u);
+                take = true;
+                for (uint32_t k = 0; k < side; k++)
+                  if (sc.deg[a[k]] == 1) take = false;
+              }
+            }
+            const uint64_t bm = __ballot(take);
+            if (take) {
+              sc.stack[nst + lanes_below(bm)] = e | (side << 30);
+              sc.pe[e] = 1;
+            }
+            nst += (uint32_t)__popcll(bm);
+          }
+          wave_sync_global();
+          // remove the selected edges
+          uint32_t nn = 0;
+          for (uint32_t i0 = r0; i0 < nst; i0 += 64) {
+            const uint32_t i = i0 + lane;
+            bool push[3] = {false, false, false};
+            uint32_t a[3] = {0, 0, 0};
+            if (i < nst) {
+              const uint32_t e = sc.stack[i] & 0x3FFFFFFFu;
+              unpack3(sc.E[e], a);
+              for (int k = 0; k < 3; k++) {
+                const uint32_t old = atomicSub(&sc.deg[a[k]], 1u);
+                atomicXor(&sc.xr[a[k]], e);
+                push[k] = old == 2;
+              }
+            }
+            for (int k = 0; k < 3; k++) {
+              const uint64_t bm = __ballot(push[k]);
+              if (push[k]) nxt[nn + lanes_below(bm)] = a[k];
+              nn += (uint32_t)__popcll(bm);
+            }
+          }
+          nrounds++;
+          if (lane == 0) sc.rst[nrounds] = nst;
+          wave_sync_global();
+          nf = nn;
+          uint32_t *tmp = cur;
+          cur = nxt;
+          nxt = tmp;
+        }
+
+        // 2-core edges, grouped by the entry group of their top vertex
+        const uint32_t gsh = entry_shift(G.sigma);
+        const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
+        for (uint32_t g = lane; g < ngroups; g += 64) sc.cc[g] = 0;
+        wave_sync_global();
+        for (uint32_t i = lane; i < m; i += 64)
+          if (!sc.pe[i]) atomicAdd(&sc.cc[(uint32_t)(sc.E[i] >> 42) >> gsh], 1u);
+        wave_sync_global();
+        const uint32_t k = wave_scan_array(sc.cc, sc.cb, ngroups);
+        wave_sync_global();
+        for (uint32_t i = lane; i < m; i += 64)
+          if (!sc.pe[i]) {
+            const uint64_t e = sc.E[i];
+            const uint32_t pos = atomicAdd(&sc.cc[(uint32_t)(e >> 42) >> gsh], 1u);
+            sc.cE[pos] = e;
+            sc.cR[pos] = sc.R[i];
+          }
+        wave_sync_global();
+        if (lane == 0) ctl->core = k;
+      }
+      __syncthreads();
+      const uint32_t k = ctl->core;
 
       uint32_t np = 0;
-      const int st = k ? band_solve<QM>(A, sc, lds, &np) : kSolveOk;
-      wave_sync_global();
+      const int st = k ? band_solve<QM>(A, sc, lds, ctl, wid, &np) : kSolveOk;
       if (st == kSolveCapacity) {
-        if (lane == 0) {
+        if (wid == 0 && lane == 0) {
           if (A.overflow) {
             const uint32_t idx = atomicAdd(&A.work[kWorkCap], 1u);
             A.overflow[2 * idx] = j;
@@ -890,12 +1020,14 @@ __global__ void __launch_bounds__(64) k_build(BuildArgs A) {
         break;
       }
       if (st == kSolveInconsistent) {
-        if (lane == 0) {
+        if (wid == 0 && lane == 0) {
           const uint32_t idx = atomicAdd(&A.work[kWorkFails], 1u);
           if (idx < A.fail_cap) A.fails[idx] = FailRec{j, t, 1u, k};
         }
         continue;
       }
+      result_t = (uint8_t)t;
+      if (wid != 0) break;
       // cells: zero, core values by back-substitution, then peeled edges
       for (uint64_t v = lane; v < V; v += 64) wl[v] = (T)0;
       if (A.cells_in_lds) wave_sync();
@@ -921,17 +1053,19 @@ __global__ void __launch_bounds__(64) k_build(BuildArgs A) {
       }
       if (A.cells_in_lds)
         for (uint64_t v = lane; v < V; v += 64) wg[v] = wl[v];
-      result_t = (uint8_t)t;
       break;
     }
-    if (result_t == 255) {
-      // every attempt failed (or a capacity limit was hit): zero cells
-      for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
+    if (wid == 0) {
+      if (result_t == 255) {
+        // every attempt failed (or a capacity limit was hit): zero cells
+        for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
+      }
+      if (lane == 0) A.tseed[j] = result_t;
     }
-    if (lane == 0) A.tseed[j] = result_t;
-    wave_sync_global();
+    __syncthreads();
   }
 }
+
 
 // ------------------------------------------------------------------ query
 
@@ -1000,7 +1134,7 @@ static hipError_t launch_build_q(const BuildArgs &a, int nwg, hipStream_t s) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)a.lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_build<T, QM>), dim3(nwg), dim3(64), a.lds_bytes, s, a);
+  hipLaunchKernelGGL((k_build<T, QM>), dim3(nwg), dim3(kBuildThreads), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 

@@ -58,6 +58,12 @@ struct BuildArgs {
 };
 
 constexpr uint32_t kLdsBudget = 160 * 1024;  // LDS of one CU
+// Bytes at the end of a build workgroup's dynamic LDS that hold the control
+// block shared by its two wavefronts and the back-substitution columns.
+constexpr uint32_t kLdsTail = 2048;
+// Threads of a build workgroup: one wavefront eliminates, the other emits
+// the pivot rows of the previous word.
+constexpr uint32_t kBuildThreads = 128;
 
 uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap);
 uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes);

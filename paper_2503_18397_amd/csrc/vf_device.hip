@@ -272,14 +272,16 @@ __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__r
 // elimination window and (when they fit) the shard's cells live in LDS.
 
 // Per-workgroup scratch (global memory), sized for the largest shard.
+// Edges, right sides and the peeling order are kept twice: the assignment
+// of one shard reads one copy while the next shard is peeled into the other.
 struct Scratch {
-  uint64_t *E;      // packed edges
-  uint64_t *R;      // right sides (values or fingerprints)
-  uint32_t *deg;    // vertex degrees
-  uint32_t *xr;     // xor of incident edge indices (Djamal's trick, section 4.3)
-  uint8_t *pe;      // 1 = edge peeled
-  uint32_t *stack;  // peeled edges in round order: index | side << 30
-  uint32_t *rst;    // round starts in stack
+  uint64_t *E[2];      // packed edges
+  uint64_t *R[2];      // right sides (values or fingerprints)
+  uint32_t *deg;       // vertex degrees
+  uint32_t *xr;        // xor of incident edge indices (Djamal's trick, section 4.3)
+  uint8_t *pe;         // 1 = edge peeled
+  uint32_t *stack[2];  // peeled edges in round order: index | side << 30
+  uint32_t *rst[2];    // round starts in stack
   uint32_t *F0, *F1;// frontiers of degree-one vertices
   uint64_t *cE;     // packed edges of the 2-core, grouped by entry group
   uint64_t *cR;     // their right sides
@@ -307,13 +309,15 @@ __host__ __device__ inline uint64_t scratch_layout(uint8_t *base, uint32_t M, ui
   };
   const uint64_t m = (uint64_t)M + 1;
   Scratch t;
-  t.E = (uint64_t *)take(8 * m);
-  t.R = (uint64_t *)take(8 * m);
+  for (int i = 0; i < 2; i++) {
+    t.E[i] = (uint64_t *)take(8 * m);
+    t.R[i] = (uint64_t *)take(8 * m);
+    t.stack[i] = (uint32_t *)take(4 * m);
+    t.rst[i] = (uint32_t *)take(4 * (m + 2));
+  }
   t.deg = (uint32_t *)take(4 * V);
   t.xr = (uint32_t *)take(4 * V);
   t.pe = (uint8_t *)take(m);
-  t.stack = (uint32_t *)take(4 * m);
-  t.rst = (uint32_t *)take(4 * (m + 2));
   t.F0 = (uint32_t *)take(4 * V);
   t.F1 = (uint32_t *)take(4 * V);
   t.cE = (uint64_t *)take(8 * m);
@@ -382,6 +386,8 @@ enum { kSolveOk = 0, kSolveInconsistent = 1, kSolveCapacity = 2 };
 // during word i + 2, after every reader has passed the barrier of word i + 1.
 struct BandCtl {
   uint32_t shard, t0, core, np;  // work item, core rows, pivots emitted
+  uint32_t rounds;               // peeling rounds
+  uint32_t dup;                  // 1: two core rows contradict each other
   uint32_t flag[2];              // kSolveInconsistent | kSolveCapacity
   uint32_t adv[2];               // 0: the word is taken again (window full)
   uint32_t k[2], gs[2];          // pivots of each batch and its segment
@@ -834,9 +840,16 @@ __device__ __forceinline__ uint32_t wave_scan_array(uint32_t *a, uint32_t *b, ui
   return total;
 }
 
-// One workgroup of two wavefronts builds one shard at a time.  Wavefront 0
-// does everything but the emission of pivot rows, which wavefront 1 does
-// during the elimination (band_solve); the two meet at workgroup barriers.
+// A shard whose 2-core is solved waits for its assignment.
+struct Pending {
+  uint32_t shard, t, np, nrounds, buf;
+};
+
+// One workgroup of two wavefronts builds shards one after the other.
+// Wavefront 0 computes right sides and edges and peels shard i (into copy
+// i % 2 of the edge arrays) while wavefront 1 assigns the cells of shard
+// i - 1; then both eliminate the 2-core of shard i (wavefront 1 emitting
+// the pivot rows); the two meet at workgroup barriers.
 template <typename T, int QM>
 __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   extern __shared__ __align__(16) uint8_t lds[];
@@ -848,7 +861,42 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   scratch_layout(A.scratch + (uint64_t)blockIdx.x * A.scratch_stride, A.M, V, G.l, A.logcap, &sc);
   T *cells = (T *)A.cells;
   BandCtl *const ctl = band_ctl(lds, A.lds_bytes);
+  uint32_t *const bcol = (uint32_t *)(lds + A.lds_bytes - kBcolBytes);
 
+  // cells of a solved shard: zero, core values by back-substitution, then
+  // the peeled edges in reverse round order (one wavefront)
+  auto assign = [&](const Pending &P) {
+    T *wg = cells + (uint64_t)P.shard * V;
+    T *wl = A.cells_in_lds ? (T *)lds : wg;
+    const uint64_t *E = sc.E[P.buf], *R = sc.R[P.buf];
+    const uint32_t *stk = sc.stack[P.buf], *rst = sc.rst[P.buf];
+    for (uint64_t v = lane; v < V; v += 64) wl[v] = (T)0;
+    if (A.cells_in_lds) wave_sync();
+    else wave_sync_global();
+    if (P.np) back_substitute<T>(sc, P.np, wl, bcol, !A.cells_in_lds);
+    for (int r = (int)P.nrounds - 1; r >= 0; r--) {
+      const uint32_t e0 = rst[r], e1 = rst[r + 1];
+      for (uint32_t i = e0 + lane; i < e1; i += 64) {
+        const uint32_t ent = stk[i];
+        const uint32_t e = ent & 0x3FFFFFFFu, side = ent >> 30;
+        uint32_t a[3];
+        unpack3(E[e], a);
+        uint64_t val = R[e];
+        for (uint32_t q = 0; q < 3; q++)
+          if (q != side) val ^= (uint64_t)wl[a[q]];
+        wl[a[side]] = (T)val;
+      }
+      if (A.cells_in_lds) wave_sync();
+      else wave_sync_global();
+    }
+    if (A.cells_in_lds)
+      for (uint64_t v = lane; v < V; v += 64) wg[v] = wl[v];
+    if (lane == 0) A.tseed[P.shard] = (uint8_t)P.t;
+  };
+
+  bool pend = false;
+  Pending P{0, 0, 0, 0, 0};
+  uint32_t buf = 0;
   for (;;) {
     if (threadIdx.x == 0) {
       uint32_t j = atomicAdd(&A.work[kWorkNext], 1u), t0 = 0;
@@ -867,25 +915,30 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
     }
     __syncthreads();
     const uint32_t j = ctl->shard, t0 = ctl->t0;
-    if (j == 0xFFFFFFFFu) break;
+    if (pend && wid == 1) assign(P);
+    pend = false;
+    if (j == 0xFFFFFFFFu) {
+      __syncthreads();
+      break;
+    }
     const uint64_t base = A.offsets[j];
     const uint32_t m = (uint32_t)(A.offsets[j + 1] - base);
-    T *wg = cells + (uint64_t)j * V;  // this shard's cells in HBM
-    T *wl = A.cells_in_lds ? (T *)lds : wg;
+    uint64_t *const E = sc.E[buf], *const R = sc.R[buf];
+    uint32_t *const stk = sc.stack[buf], *const rst = sc.rst[buf];
 
     // right sides: values (Problem 1) or fingerprints (Problem 2)
     if (wid == 0) {
       for (uint32_t i = lane; i < m; i += 64) {
         const uint64_t key = A.bkeys[base + i];
         if (G.is_filter) {
-          sc.R[i] = fingerprint(G, fin64(key ^ G.khi), fin64(key ^ G.klo));
+          R[i] = fingerprint(G, fin64(key ^ G.khi), fin64(key ^ G.klo));
         } else {
-          sc.R[i] = A.bvals[base + i] & G.vmask;
+          R[i] = A.bvals[base + i] & G.vmask;
         }
       }
     }
 
-    uint8_t result_t = 255;
+    bool solved = false;
     for (uint32_t t = t0; t < A.tmax; t++) {
       uint32_t nrounds = 0;
       if (wid == 0) {
@@ -894,7 +947,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
           const uint64_t key = A.bkeys[base + i];
           uint32_t v0, v1, v2;
           edge3(G, fin64(key ^ G.khi), fin64(key ^ G.klo), t, v0, v1, v2);
-          sc.E[i] = pack3(v0, v1, v2);
+          E[i] = pack3(v0, v1, v2);
           sc.pe[i] = 0;
         }
         for (uint64_t v = lane; v < V; v += 64) {
@@ -905,7 +958,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         // incidence: degree and xor of incident edges
         for (uint32_t i = lane; i < m; i += 64) {
           uint32_t v[3];
-          unpack3(sc.E[i], v);
+          unpack3(E[i], v);
           for (int k = 0; k < 3; k++) {
             atomicAdd(&sc.deg[v[k]], 1u);
             atomicXor(&sc.xr[v[k]], i);
@@ -924,7 +977,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         wave_sync_global();
         uint32_t nst = 0;
         uint32_t *cur = sc.F0, *nxt = sc.F1;
-        if (lane == 0) sc.rst[0] = 0;
+        if (lane == 0) rst[0] = 0;
         while (nf) {
           const uint32_t r0 = nst;
           // select with the degrees of the start of the round
@@ -937,7 +990,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
               if (sc.deg[v] == 1) {
                 e = sc.xr[v];
                 uint32_t a[3];
-                unpack3(sc.E[e], a);
+                unpack3(E[e], a);
                 side = a[0] == v ? 0u : (a[1] == v ? 1u : 2u);
                 take = true;
                 for (uint32_t k = 0; k < side; k++)
@@ -946,7 +999,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
             }
             const uint64_t bm = __ballot(take);
             if (take) {
-              sc.stack[nst + lanes_below(bm)] = e | (side << 30);
+              stk[nst + lanes_below(bm)] = e | (side << 30);
               sc.pe[e] = 1;
             }
             nst += (uint32_t)__popcll(bm);
@@ -959,8 +1012,8 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
             bool push[3] = {false, false, false};
             uint32_t a[3] = {0, 0, 0};
             if (i < nst) {
-              const uint32_t e = sc.stack[i] & 0x3FFFFFFFu;
-              unpack3(sc.E[e], a);
+              const uint32_t e = stk[i] & 0x3FFFFFFFu;
+              unpack3(E[e], a);
               for (int k = 0; k < 3; k++) {
                 const uint32_t old = atomicSub(&sc.deg[a[k]], 1u);
                 atomicXor(&sc.xr[a[k]], e);
@@ -974,7 +1027,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
             }
           }
           nrounds++;
-          if (lane == 0) sc.rst[nrounds] = nst;
+          if (lane == 0) rst[nrounds] = nst;
           wave_sync_global();
           nf = nn;
           uint32_t *tmp = cur;
@@ -988,25 +1041,50 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         for (uint32_t g = lane; g < ngroups; g += 64) sc.cc[g] = 0;
         wave_sync_global();
         for (uint32_t i = lane; i < m; i += 64)
-          if (!sc.pe[i]) atomicAdd(&sc.cc[(uint32_t)(sc.E[i] >> 42) >> gsh], 1u);
+          if (!sc.pe[i]) atomicAdd(&sc.cc[(uint32_t)(E[i] >> 42) >> gsh], 1u);
         wave_sync_global();
         const uint32_t k = wave_scan_array(sc.cc, sc.cb, ngroups);
         wave_sync_global();
         for (uint32_t i = lane; i < m; i += 64)
           if (!sc.pe[i]) {
-            const uint64_t e = sc.E[i];
+            const uint64_t e = E[i];
             const uint32_t pos = atomicAdd(&sc.cc[(uint32_t)(e >> 42) >> gsh], 1u);
             sc.cE[pos] = e;
-            sc.cR[pos] = sc.R[i];
+            sc.cR[pos] = R[i];
           }
         wave_sync_global();
-        if (lane == 0) ctl->core = k;
+        // two 2-core rows with the same vertices and different right sides
+        // (the usual reason for an inconsistent system) end the attempt
+        // before the elimination: rows are listed by top vertex in the
+        // degree array, which peeling no longer needs
+        uint32_t *const head = sc.deg, *const next = sc.F0;
+        for (uint64_t v = lane; v < V; v += 64) head[v] = 0xFFFFFFFFu;
+        wave_sync_global();
+        for (uint32_t i = lane; i < k; i += 64)
+          next[i] = atomicExch(&head[(uint32_t)(sc.cE[i] >> 42)], i);
+        wave_sync_global();
+        bool clash = false;
+        for (uint32_t i = lane; i < k; i += 64) {
+          const uint64_t e = sc.cE[i], r = sc.cR[i];
+          for (uint32_t x = next[i]; x != 0xFFFFFFFFu; x = next[x])
+            clash |= sc.cE[x] == e && sc.cR[x] != r;
+        }
+        const bool dup = __ballot(clash) != 0;
+        if (lane == 0) {
+          ctl->core = k;
+          ctl->rounds = nrounds;
+          ctl->dup = dup ? 1u : 0u;
+        }
       }
       __syncthreads();
       const uint32_t k = ctl->core;
+      nrounds = ctl->rounds;
+      const bool dup = ctl->dup != 0;
+      __syncthreads();  // both have read the block before wavefront 0 rewrites it
 
       uint32_t np = 0;
-      const int st = k ? band_solve<QM>(A, sc, lds, ctl, wid, &np) : kSolveOk;
+      const int st = dup ? kSolveInconsistent
+                         : (k ? band_solve<QM>(A, sc, lds, ctl, wid, &np) : kSolveOk);
       if (st == kSolveCapacity) {
         if (wid == 0 && lane == 0) {
           if (A.overflow) {
@@ -1026,46 +1104,20 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         }
         continue;
       }
-      result_t = (uint8_t)t;
-      if (wid != 0) break;
-      // cells: zero, core values by back-substitution, then peeled edges
-      for (uint64_t v = lane; v < V; v += 64) wl[v] = (T)0;
-      if (A.cells_in_lds) wave_sync();
-      else wave_sync_global();
-      if (np) {
-        uint32_t *bcol = (uint32_t *)(lds + A.lds_bytes - kBcolBytes);
-        back_substitute<T>(sc, np, wl, bcol, !A.cells_in_lds);
-      }
-      for (int r = (int)nrounds - 1; r >= 0; r--) {
-        const uint32_t e0 = sc.rst[r], e1 = sc.rst[r + 1];
-        for (uint32_t i = e0 + lane; i < e1; i += 64) {
-          const uint32_t ent = sc.stack[i];
-          const uint32_t e = ent & 0x3FFFFFFFu, side = ent >> 30;
-          uint32_t a[3];
-          unpack3(sc.E[e], a);
-          uint64_t val = sc.R[e];
-          for (uint32_t q = 0; q < 3; q++)
-            if (q != side) val ^= (uint64_t)wl[a[q]];
-          wl[a[side]] = (T)val;
-        }
-        if (A.cells_in_lds) wave_sync();
-        else wave_sync_global();
-      }
-      if (A.cells_in_lds)
-        for (uint64_t v = lane; v < V; v += 64) wg[v] = wl[v];
+      P = Pending{j, t, np, nrounds, buf};
+      pend = true;
+      buf ^= 1u;
+      solved = true;
       break;
     }
-    if (wid == 0) {
-      if (result_t == 255) {
-        // every attempt failed (or a capacity limit was hit): zero cells
-        for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
-      }
-      if (lane == 0) A.tseed[j] = result_t;
+    if (!solved && wid == 0) {
+      // every attempt failed (or a capacity limit was hit): zero cells
+      T *wg = cells + (uint64_t)j * V;
+      for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
+      if (lane == 0) A.tseed[j] = 255;
     }
-    __syncthreads();
   }
 }
-
 
 // ------------------------------------------------------------------ query
 

@@ -144,8 +144,8 @@ struct Layout {
   uint64_t ws_bytes, st_bytes;
   uint64_t cells_bytes;
   // workspace offsets
-  uint64_t o_counts, o_offsets, o_cursor, o_meta, o_work, o_fails, o_overflow, o_bkeys, o_bvals,
-      o_scratch;
+  uint64_t o_counts, o_offsets, o_cursor, o_meta, o_work, o_fails, o_overflow, o_order, o_bkeys,
+      o_bvals, o_scratch;
   uint32_t fail_cap;
 };
 
@@ -209,6 +209,7 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   l.o_work = take(4ull * vfk::kWorkWords);
   l.o_fails = take(sizeof(vfk::FailRec) * (uint64_t)l.fail_cap);
   l.o_overflow = take(8ull * l.S);
+  l.o_order = take(8ull * l.S);
   l.o_bkeys = take(8ull * std::max<uint64_t>(n, 1));
   l.o_bvals = is_filter ? 0 : take(8ull * std::max<uint64_t>(n, 1));
   l.o_scratch = take(l.scratch_stride * l.nwg);
@@ -312,6 +313,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   uint32_t *work = (uint32_t *)(W + L.o_work);
   vfk::FailRec *fails = (vfk::FailRec *)(W + L.o_fails);
   uint32_t *overflow = (uint32_t *)(W + L.o_overflow);
+  uint32_t *order = (uint32_t *)(W + L.o_order);
   uint64_t *bkeys = (uint64_t *)(W + L.o_bkeys);
   uint64_t *bvals = is_filter ? nullptr : (uint64_t *)(W + L.o_bvals);
   uint8_t *scratch = W + L.o_scratch;
@@ -345,7 +347,8 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
       vfk::build_scratch_bytes(M, g.V, g.l, L.logcap) > L.scratch_stride)
     return VF_ENOSPC;
 
-  // 2. group keys by shard
+  // 2. group keys by shard; build order (largest shards first)
+  HIPCHK(vfk::launch_order(counts, L.S, M, order, stream));
   HIPCHK(vfk::launch_scatter(keys, values, n, sw[0], (uint32_t)L.h, L.S, cursor, bkeys, bvals,
                              ncu, stream));
   pe.record(2, stream);
@@ -385,8 +388,8 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   A.logcap = L.logcap;
   A.cell_bytes = L.cell_bytes;
   A.cells_in_lds = g.V * L.cell_bytes + vfk::kLdsTail <= A.lds_bytes ? 1u : 0u;
-  A.list = nullptr;
-  A.nlist = 0;
+  A.list = order;
+  A.nlist = L.S;
   A.overflow = overflow;
   HIPCHK(vfk::launch_fill_u32(work, vfk::kWorkWords, 0, stream));
   HIPCHK(vfk::launch_build(A, (int)nwg, stream));

@@ -1138,6 +1138,39 @@ __global__ void k_query(Geo G, const T *__restrict__ cells, const uint8_t *__res
   }
 }
 
+// Build order: shards with more keys first.  A shard's 2-core, and with it
+// its elimination time, grows quickly with its load, so handing out the
+// largest shards first leaves the quick ones for the end of the launch.
+// Shards are bucketed by M - count (deficits of 1023 or more share the last
+// bucket); the order inside a bucket is arbitrary.
+__global__ void __launch_bounds__(1024) k_order(const uint32_t *__restrict__ counts, uint32_t S,
+                                                uint32_t M, uint32_t *__restrict__ list) {
+  __shared__ uint32_t hist[1024];
+  const uint32_t tid = threadIdx.x;
+  hist[tid] = 0;
+  __syncthreads();
+  for (uint32_t j = tid; j < S; j += 1024) atomicAdd(&hist[min(M - counts[j], 1023u)], 1u);
+  __syncthreads();
+  // exclusive prefix sum over the 1024 buckets
+  const uint32_t own = hist[tid];
+  uint32_t inc = own;
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    __syncthreads();
+    const uint32_t y = tid >= d ? hist[tid - d] : 0u;
+    __syncthreads();
+    inc += y;
+    hist[tid] = inc;
+  }
+  __syncthreads();
+  hist[tid] = inc - own;
+  __syncthreads();
+  for (uint32_t j = tid; j < S; j += 1024) {
+    const uint32_t pos = atomicAdd(&hist[min(M - counts[j], 1023u)], 1u);
+    list[2 * pos] = j;
+    list[2 * pos + 1] = 0;
+  }
+}
+
 // ----------------------------------------------------------------- launch
 
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
@@ -1163,6 +1196,12 @@ hipError_t launch_count(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t
 hipError_t launch_scan(const uint32_t *counts, uint32_t S, uint64_t *offsets,
                        uint64_t *cursor, uint32_t *max_out, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, S, offsets, cursor, max_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const uint32_t *counts, uint32_t S, uint32_t M, uint32_t *list,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, counts, S, M, list);
   return hipGetLastError();
 }
 

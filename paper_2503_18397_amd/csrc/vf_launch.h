@@ -73,6 +73,8 @@ hipError_t launch_count(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t
                         uint32_t S, uint32_t *counts, int ncu, hipStream_t s);
 hipError_t launch_scan(const uint32_t *counts, uint32_t S, uint64_t *offsets,
                        uint64_t *cursor, uint32_t *max_out, hipStream_t s);
+hipError_t launch_order(const uint32_t *counts, uint32_t S, uint32_t M, uint32_t *list,
+                        hipStream_t s);
 hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n,
                           uint64_t khi, uint32_t h, uint32_t S, uint64_t *cursor,
                           uint64_t *bkeys, uint64_t *bvals, int ncu, hipStream_t s);

@@ -1121,20 +1121,54 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
 
 // ------------------------------------------------------------------ query
 
-template <typename T>
-__global__ void k_query(Geo G, const T *__restrict__ cells, const uint8_t *__restrict__ tseed,
-                        const uint64_t *__restrict__ keys, uint64_t n, void *__restrict__ out) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t key = keys[i];
-    const uint64_t hi = fin64(key ^ G.khi), lo = fin64(key ^ G.klo);
-    const uint32_t j = shard_of(hi, G.h);
-    uint32_t v0, v1, v2;
-    edge3(G, hi, lo, tseed[j], v0, v1, v2);
-    const T *w = cells + (uint64_t)j * G.V;
-    const T x = w[v0] ^ w[v1] ^ w[v2];
-    if (G.is_filter) ((uint8_t *)out)[i] = (uint64_t)x == fingerprint(G, hi, lo);
-    else ((T *)out)[i] = x;
+// Each thread answers QP queries that are a grid apart (coalesced per
+// step): the loads of the QP independent queries are in flight together.
+// The local seeds are copied to LDS when they fit (up to kSeedLds shards),
+// which leaves the three cell probes as the only gathers from memory.
+constexpr uint32_t kSeedLds = 16384;
+
+template <typename T, int QP>
+__global__ void __launch_bounds__(256) k_query(Geo G, const T *__restrict__ cells,
+                                               const uint8_t *__restrict__ tseed,
+                                               const uint64_t *__restrict__ keys, uint64_t n,
+                                               void *__restrict__ out) {
+  extern __shared__ uint8_t seeds_lds[];
+  const bool lds_seeds = G.S <= kSeedLds;
+  if (lds_seeds) {
+    for (uint32_t i = threadIdx.x; i < G.S; i += blockDim.x) seeds_lds[i] = tseed[i];
+    __syncthreads();
+  }
+  const uint8_t *const ts = lds_seeds ? seeds_lds : tseed;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i0 < n;
+       i0 += stride * QP) {
+    uint64_t hi[QP], lo[QP];
+#pragma unroll
+    for (int k = 0; k < QP; k++) {
+      const uint64_t i = i0 + (uint64_t)k * stride;
+      const uint64_t key = i < n ? keys[i] : 0ull;
+      hi[k] = fin64(key ^ G.khi);
+      lo[k] = fin64(key ^ G.klo);
+    }
+    uint32_t t[QP];
+#pragma unroll
+    for (int k = 0; k < QP; k++) t[k] = ts[shard_of(hi[k], G.h)];
+    T x[QP];
+#pragma unroll
+    for (int k = 0; k < QP; k++) {
+      uint32_t v0, v1, v2;
+      edge3(G, hi[k], lo[k], t[k], v0, v1, v2);
+      const T *w = cells + (uint64_t)shard_of(hi[k], G.h) * G.V;
+      x[k] = w[v0] ^ w[v1] ^ w[v2];
+    }
+#pragma unroll
+    for (int k = 0; k < QP; k++) {
+      const uint64_t i = i0 + (uint64_t)k * stride;
+      if (i < n) {
+        if (G.is_filter) ((uint8_t *)out)[i] = (uint64_t)x[k] == fingerprint(G, hi[k], lo[k]);
+        else ((T *)out)[i] = x[k];
+      }
+    }
   }
 }
 
@@ -1249,15 +1283,18 @@ hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
                         const uint8_t *tseed, const uint64_t *keys, uint64_t n,
                         void *out, int ncu, hipStream_t s) {
   if (!n) return hipSuccess;
-  uint64_t blocks = (n + 255) / 256;
-  uint64_t cap = (uint64_t)ncu * 64;
+  constexpr int QP = 4;
+  // 8 workgroups of 4 wavefronts per CU, each thread QP queries per step
+  uint64_t blocks = (n + 256 * QP - 1) / (256 * QP);
+  const uint64_t cap = (uint64_t)ncu * 8;
   if (blocks > cap) blocks = cap;
   dim3 g((uint32_t)blocks), b(256);
+  const size_t shm = G.S <= kSeedLds ? G.S : 0;
   switch (cell_bytes) {
-    case 1: hipLaunchKernelGGL(k_query<uint8_t>, g, b, 0, s, G, (const uint8_t *)cells, tseed, keys, n, out); break;
-    case 2: hipLaunchKernelGGL(k_query<uint16_t>, g, b, 0, s, G, (const uint16_t *)cells, tseed, keys, n, out); break;
-    case 4: hipLaunchKernelGGL(k_query<uint32_t>, g, b, 0, s, G, (const uint32_t *)cells, tseed, keys, n, out); break;
-    default: hipLaunchKernelGGL(k_query<uint64_t>, g, b, 0, s, G, (const uint64_t *)cells, tseed, keys, n, out); break;
+    case 1: hipLaunchKernelGGL((k_query<uint8_t, QP>), g, b, shm, s, G, (const uint8_t *)cells, tseed, keys, n, out); break;
+    case 2: hipLaunchKernelGGL((k_query<uint16_t, QP>), g, b, shm, s, G, (const uint16_t *)cells, tseed, keys, n, out); break;
+    case 4: hipLaunchKernelGGL((k_query<uint32_t, QP>), g, b, shm, s, G, (const uint32_t *)cells, tseed, keys, n, out); break;
+    default: hipLaunchKernelGGL((k_query<uint64_t, QP>), g, b, shm, s, G, (const uint64_t *)cells, tseed, keys, n, out); break;
   }
   return hipGetLastError();
 }

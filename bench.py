@@ -22,6 +22,22 @@ sys.path.insert(0, ROOT)
 METRIC = "build Mkeys/s + query Gq/s (VFilter b=8, 2^27 keys); serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of this workload measured with rocprofv3 PMC counters
+# (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy); see
+# profiles/vfilter_b8_n2p27_hbm_traffic_pmc.md.  They hold for the kernel
+# source with this SHA-256 prefix only and are reported as null otherwise.
+PMC_SOURCE_SHA = "effedba0354ac888"
+PMC_TRAFFIC_BYTES = {"k_build": 106.24e9, "k_query": 410.90e9, "k_scatter": 7.04e9,
+                     "k_count+k_scan": 1.08e9}
+
+
+def pmc_traffic(kernel: str):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2503_18397_amd", "csrc", "vf_device.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return PMC_TRAFFIC_BYTES.get(kernel) if sha == PMC_SOURCE_SHA else None
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -137,7 +153,8 @@ def main():
         "k_count+k_scan": {"ms": k_count_ms, "bytes": 8 * n},
         "k_scatter": {"ms": k_scatter_ms, "bytes": 8 * n + 8 * n},
     }
-    for k in kern.values():
+    for name, k in kern.items():
+        k["traffic"] = pmc_traffic(name)
         k["GB/s"] = round(k["bytes"] / (k["ms"] * 1e-3) / 1e9, 2) if k["ms"] > 0 else None
         k["frac"] = round(k["GB/s"] / HBM_PEAK_GBS, 5) if k["GB/s"] else None
     dom = "k_build" if k_build_ms >= query_ms else "k_query"
@@ -171,7 +188,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5) if achieved else None,
-                     "traffic": None},
+                     "traffic": pmc_traffic(dom)},
         "kernels": kern,
     }
     if not args.no_cpu_baseline:

@@ -34,9 +34,14 @@
  *     expected number of duplicate edges of a shard, m / (2 c s^2)
  *     (section 4.2), is at most 1/8.  Section 4 leaves shard sizing to
  *     simulation when no bound is known: simulated with this oracle, c = 1.12
- *     fails in most attempts below 2^16 keys per shard (a fuse graph with
- *     few segments is overloaded in its middle), so shards below 2^16 keys
- *     use c = 1.16.  ell = max(1, ceil(c M / s) - 2), V = (ell + 2) s.
+ *     fails in most attempts below 2^16 keys per shard, and so does any
+ *     fixed c near it at some sizes (a fuse graph with few segments is
+ *     overloaded in its middle; section 4.2 notes that for small n the
+ *     factor grows towards that of general random hypergraphs).  Graphs
+ *     below 2^16 keys therefore use Graf and Lemire's size-dependent factor,
+ *     whose estimates section 4.2 says the paper partly adopts:
+ *     c = 0.875 + 0.25 ln(10^6) / ln(max(m, 10)), rounded up to thousandths.
+ *     ell = max(1, ceil(c M / s) - 2), V = (ell + 2) s.
  *  R7 peeling is round-synchronous: in round r every live edge that has a
  *     vertex of degree one (degrees as they stand when the round starts) is
  *     removed; its hinge is the first such vertex in edge order (its
@@ -196,7 +201,13 @@ void orc_geometry(uint32_t M, int32_t h, uint32_t c_num, uint32_t c_den,
     if (large && h > 0) { c_num = 1105; c_den = 1000; }  /* 1.105 */
     else if (large) { c_num = 1125; c_den = 1000; }      /* 1.125 */
     else if (M >= 65536u) { c_num = 112; c_den = 100; }  /* 1.12 */
-    else { c_num = 116; c_den = 100; }                   /* 1.16 */
+    else {
+      /* small graphs: Graf and Lemire's factor 0.875 + 0.25 ln(10^6) / ln m
+       * (m at least 10), rounded up to thousandths */
+      double x = 875.0 + 250.0 * log(1e6) / log((double)(M < 10u ? 10u : M));
+      c_num = (uint32_t)ceil(x - 1e-9);
+      c_den = 1000;
+    }
   }
   int32_t sigma;
   if (sigma_override >= 0) {

@@ -56,9 +56,12 @@ struct Geometry {
 // elimination of the 2-core), c = 1.105 with lg s from eq. (nln) for larger
 // shards, c = 1.125 with lg s from eq. (ln) for a single large unsharded
 // graph.  Below 800 000 keys the segment size is the smallest power of two
-// with expected duplicate edges m / (2 c s^2) <= 1/8.  Shards below 2^16
-// keys use c = 1.16: simulated (as section 4 suggests for sizing shards),
-// c = 1.12 fuse systems that small are unsolvable in most attempts.
+// with expected duplicate edges m / (2 c s^2) <= 1/8.  Graphs below 2^16
+// keys use Graf and Lemire's size-dependent factor 0.875 + 0.25 ln(10^6) /
+// ln m (section 4.2: the factor grows for small n; the paper partly adopts
+// their estimates): simulated (as section 4 suggests for sizing shards),
+// fuse systems that small are unsolvable in most attempts at c = 1.12 and,
+// at some sizes, at any fixed c near it.
 // ell = max(1, ceil(c M / s) - 2) start segments, V = (ell + 2) s cells.
 Geometry geometry(uint32_t M, int32_t h, uint32_t cn, uint32_t cd, int32_t sigma_ovr) {
   const bool large = M >= 800000u;
@@ -66,7 +69,13 @@ Geometry geometry(uint32_t M, int32_t h, uint32_t cn, uint32_t cd, int32_t sigma
     if (large && h > 0) { cn = 1105; cd = 1000; }
     else if (large) { cn = 1125; cd = 1000; }
     else if (M >= 65536u) { cn = 112; cd = 100; }
-    else { cn = 116; cd = 100; }
+    else {
+      // small graphs: Graf and Lemire's factor 0.875 + 0.25 ln(10^6) / ln m
+      // (m at least 10), rounded up to thousandths
+      const double x = 875.0 + 250.0 * std::log(1e6) / std::log((double)(M < 10u ? 10u : M));
+      cn = (uint32_t)std::ceil(x - 1e-9);
+      cd = 1000;
+    }
   }
   int32_t sg;
   if (sigma_ovr >= 0) {
@@ -220,6 +229,86 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   return VF_OK;
 }
 
+// Buffers of a batch of unsharded functions.  Workspace: work counters,
+// failure records, overflow list, per-class build orders, scratch; the
+// structure: instance descriptors, local seeds, cells (8-byte aligned per
+// instance).
+struct BatchLayout {
+  uint64_t count = 0, keys = 0;
+  std::vector<vfk::BatchItem> items;
+  uint32_t maxM = 0, maxl = 1;
+  uint64_t maxV = 0;
+  int32_t maxsigma = 0;
+  uint32_t nwg = 0, logcap = 0, fail_cap = 0;
+  uint64_t scratch_stride = 0;
+  uint64_t o_work = 0, o_fails = 0, o_overflow = 0, o_order = 0, o_scratch = 0, ws_bytes = 0;
+  uint64_t s_items = 0, s_seeds = 0, s_cells = 0, cells_bytes = 0, st_bytes = 0;
+};
+
+int make_batch_layout(uint64_t count, const uint64_t *n, const int32_t *b, const vf_opts &o,
+                      int ncu, BatchLayout *L) {
+  if (!count || !n || !b || count > 0xFFFFFFFFull) return VF_EINVAL;
+  if (o.tmax < 1 || o.tmax > 255) return VF_EINVAL;
+  if ((o.c_num == 0) != (o.c_den == 0)) return VF_EINVAL;
+  if (o.c_num && o.c_num < o.c_den) return VF_EINVAL;
+  if (o.sigma > 20) return VF_EINVAL;
+  BatchLayout l;
+  l.count = count;
+  l.items.resize(count);
+  uint64_t cell_off = 0;
+  for (uint64_t i = 0; i < count; i++) {
+    if (b[i] < 1 || b[i] > 64 || n[i] > 0xFFFFFFFFull) return VF_EINVAL;
+    const Geometry g = geometry((uint32_t)n[i], 0, o.c_num, o.c_den, o.sigma);
+    if (g.V > kMaxCells) return VF_ECAPACITY;
+    vfk::BatchItem &it = l.items[i];
+    it.key_off = l.keys;
+    it.cell_off = cell_off;
+    it.V = g.V;
+    it.vmask = b[i] >= 64 ? ~0ull : ((1ull << b[i]) - 1);
+    it.n = (uint32_t)n[i];
+    it.l = g.l;
+    it.sigma = (uint32_t)g.sigma;
+    it.b = (uint32_t)b[i];
+    it.cell_bytes = cell_bytes_for(b[i]);
+    it.c_num = g.c_num;
+    it.c_den = g.c_den;
+    it.pad = 0;
+    l.keys += n[i];
+    cell_off += (g.V * it.cell_bytes + 7) & ~7ull;
+    l.maxM = std::max(l.maxM, it.n);
+    l.maxV = std::max(l.maxV, g.V);
+    l.maxl = std::max(l.maxl, g.l);
+    l.maxsigma = std::max(l.maxsigma, g.sigma);
+  }
+  uint32_t per_cu, lds_bytes;
+  build_occupancy(l.maxsigma, &per_cu, &lds_bytes);
+  l.nwg = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>((uint64_t)per_cu * (ncu > 0 ? ncu : 256), count));
+  l.logcap = 16u * l.maxM + 4096u;
+  l.scratch_stride = align256(vfk::build_scratch_bytes(l.maxM, l.maxV, l.maxl, l.logcap));
+  l.fail_cap = (uint32_t)std::min<uint64_t>(4ull * count + 1024u, 0xFFFFFFF0ull);
+  uint64_t o_ = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t at = o_;
+    o_ += align256(bytes);
+    return at;
+  };
+  l.o_work = take(4ull * vfk::kWorkWords);
+  l.o_fails = take(sizeof(vfk::FailRec) * (uint64_t)l.fail_cap);
+  l.o_overflow = take(8ull * count);
+  l.o_order = take(8ull * count);
+  l.o_scratch = take(l.scratch_stride * l.nwg);
+  l.ws_bytes = o_;
+  o_ = 0;
+  l.s_items = take(sizeof(vfk::BatchItem) * count);
+  l.s_seeds = take(count);
+  l.cells_bytes = align256(cell_off);
+  l.s_cells = take(l.cells_bytes);
+  l.st_bytes = o_;
+  *L = std::move(l);
+  return VF_OK;
+}
+
 }  // namespace
 
 struct vf_handle {
@@ -238,6 +327,12 @@ struct vf_handle {
   int ncu;
   float ms[3];
   uint32_t relaunched;
+  // batches (kind 1): one descriptor and local seed per instance
+  int32_t kind;
+  uint64_t count;
+  std::vector<vfk::BatchItem> items;
+  std::vector<uint8_t> seeds;
+  const vfk::BatchItem *items_dev;
 };
 
 namespace {
@@ -391,6 +486,9 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   A.list = order;
   A.nlist = L.S;
   A.overflow = overflow;
+  A.items = nullptr;
+  A.scr_V = g.V;
+  A.scr_l = g.l;
   HIPCHK(vfk::launch_fill_u32(work, vfk::kWorkWords, 0, stream));
   HIPCHK(vfk::launch_build(A, (int)nwg, stream));
   uint32_t hwork[vfk::kWorkWords];
@@ -471,7 +569,7 @@ int vfilter_build(const uint64_t *keys, uint64_t n, int32_t b, double eps, uint6
 
 static int query_common(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
                         hipStream_t stream, int32_t want_filter) {
-  if (!h || h->magic != kMagic || h->is_filter != want_filter) return VF_EINVAL;
+  if (!h || h->magic != kMagic || h->kind != 0 || h->is_filter != want_filter) return VF_EINVAL;
   if (n && (!keys || !out)) return VF_EINVAL;
   if (vfk::launch_query(h->G, h->cells, h->cell_bytes, h->tseed, keys, n, out, h->ncu, stream) !=
       hipSuccess)
@@ -487,6 +585,214 @@ int vf_query(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
 int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8_t *out,
                      hipStream_t stream) {
   return query_common(h, keys, n, out, stream, 1);
+}
+
+int vf_batch_plan(uint64_t count, const uint64_t *n, const int32_t *b, const vf_opts *o,
+                  vf_sizes *out) {
+  if (!out) return VF_EINVAL;
+  vf_opts d;
+  vf_default_opts(&d);
+  BatchLayout L;
+  const int rc = make_batch_layout(count, n, b, o ? *o : d, device_cus(), &L);
+  if (rc) return rc;
+  out->structure_bytes = L.st_bytes;
+  out->workspace_bytes = L.ws_bytes;
+  out->h = 0;
+  out->shard_cap = L.maxM;
+  return VF_OK;
+}
+
+int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
+                   const uint64_t *n, const int32_t *b, uint64_t seed, const vf_opts *o,
+                   void *ws, uint64_t ws_bytes, void *st, uint64_t st_bytes,
+                   hipStream_t stream, vf_handle **handle) {
+  if (!handle || !ws || !st) return VF_EINVAL;
+  vf_opts d;
+  vf_default_opts(&d);
+  const vf_opts &op = o ? *o : d;
+  const int ncu = device_cus();
+  if (ncu <= 0) return VF_EHIP;
+  BatchLayout L;
+  int rc = make_batch_layout(count, n, b, op, ncu, &L);
+  if (rc) return rc;
+  if (L.keys && (!keys || !values)) return VF_EINVAL;
+  if (ws_bytes < L.ws_bytes || st_bytes < L.st_bytes) return VF_ENOSPC;
+
+  uint8_t *W = (uint8_t *)ws;
+  uint32_t *work = (uint32_t *)(W + L.o_work);
+  vfk::FailRec *fails = (vfk::FailRec *)(W + L.o_fails);
+  uint32_t *overflow = (uint32_t *)(W + L.o_overflow);
+  uint32_t *order = (uint32_t *)(W + L.o_order);
+  uint8_t *S8 = (uint8_t *)st;
+  vfk::BatchItem *items = (vfk::BatchItem *)(S8 + L.s_items);
+  uint8_t *tseed = S8 + L.s_seeds;
+  uint8_t *cells = S8 + L.s_cells;
+  uint64_t sw[3];
+  seed_words(seed, sw);
+
+#define HIPCHK(x)                         \
+  do {                                    \
+    if ((x) != hipSuccess) return VF_EHIP; \
+  } while (0)
+
+  // build orders: instances of each cell width, largest first
+  std::vector<uint32_t> ord(2 * count);
+  uint64_t cls_begin[5] = {0, 0, 0, 0, 0};
+  {
+    std::vector<uint32_t> idx(count);
+    for (uint64_t i = 0; i < count; i++) idx[i] = (uint32_t)i;
+    auto cls = [&](uint32_t i) {
+      const uint32_t cb = L.items[i].cell_bytes;
+      return cb == 1 ? 0 : cb == 2 ? 1 : cb == 4 ? 2 : 3;
+    };
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t c) {
+      return cls(a) != cls(c) ? cls(a) < cls(c) : L.items[a].n > L.items[c].n;
+    });
+    for (uint64_t i = 0; i < count; i++) {
+      ord[2 * i] = idx[i];
+      ord[2 * i + 1] = 0;
+      cls_begin[cls(idx[i]) + 1] = i + 1;
+    }
+    for (int c = 1; c < 5; c++) cls_begin[c] = std::max(cls_begin[c], cls_begin[c - 1]);
+  }
+  PhaseEvents pe;
+  pe.record(0, stream);
+  HIPCHK(hipMemcpyAsync(items, L.items.data(), sizeof(vfk::BatchItem) * count,
+                        hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(order, ord.data(), 8ull * count, hipMemcpyHostToDevice, stream));
+  HIPCHK(vfk::launch_fill_u32(work, vfk::kWorkWords, 0, stream));
+  pe.record(1, stream);
+  pe.record(2, stream);
+
+  vfk::BuildArgs A{};
+  A.G.khi = sw[0];
+  A.G.klo = sw[1];
+  A.G.kfp = sw[2];
+  A.G.h = 0;
+  A.G.S = 1;
+  A.G.is_filter = 0;
+  A.bkeys = keys;
+  A.bvals = values;
+  A.offsets = nullptr;
+  A.cells = cells;
+  A.tseed = tseed;
+  A.scratch = W + L.o_scratch;
+  A.scratch_stride = L.scratch_stride;
+  A.work = work;
+  A.fails = fails;
+  A.fail_cap = L.fail_cap;
+  A.M = L.maxM;
+  A.tmax = op.tmax;
+  A.logcap = L.logcap;
+  A.items = items;
+  A.scr_V = L.maxV;
+  A.scr_l = L.maxl;
+  static const uint32_t kClassBytes[4] = {1, 2, 4, 8};
+  for (int c = 0; c < 4; c++) {
+    const uint64_t c0 = cls_begin[c], c1 = cls_begin[c + 1];
+    if (c1 == c0) continue;
+    int32_t sg = 0;
+    for (uint64_t i = c0; i < c1; i++) sg = std::max(sg, (int32_t)L.items[ord[2 * i]].sigma);
+    uint32_t per_cu = 1;
+    A.cell_bytes = kClassBytes[c];
+    build_occupancy(sg, &per_cu, &A.lds_bytes);
+    A.wmax = vfk::window_slots((uint32_t)sg, A.lds_bytes);
+    if (A.wmax > 384 && window_target(sg) <= 384) A.wmax = 384;
+    A.cells_in_lds = 1;  // per instance when its cells fit
+    A.list = order + 2 * c0;
+    A.nlist = (uint32_t)(c1 - c0);
+    A.nlist_dev = nullptr;
+    A.overflow = overflow;
+    const uint32_t nwg =
+        (uint32_t)std::min<uint64_t>(std::min<uint64_t>(L.nwg, (uint64_t)per_cu * ncu), c1 - c0);
+    HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkNext, 1, 0, stream));
+    HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkCap, 1, 0, stream));
+    HIPCHK(vfk::launch_build(A, (int)nwg, stream));
+    // instances whose window outgrew their share of LDS, again with a
+    // whole CU's LDS; the list length is read on the device (no host wait)
+    A.list = overflow;
+    A.nlist = 0;
+    A.nlist_dev = work + vfk::kWorkCap;
+    A.overflow = nullptr;
+    A.lds_bytes = (vfk::kLdsBudget - 256) & ~255u;
+    A.wmax = vfk::window_slots((uint32_t)sg, A.lds_bytes);
+    HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkNext, 1, 0, stream));
+    HIPCHK(vfk::launch_build(A, (int)std::min<uint32_t>(nwg, (uint32_t)ncu), stream));
+  }
+  pe.record(3, stream);
+  uint32_t hwork[vfk::kWorkWords];
+  HIPCHK(hipMemcpyAsync(hwork, work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const uint32_t nf = std::min(hwork[vfk::kWorkFails], L.fail_cap);
+  std::vector<vfk::FailRec> fr(nf);
+  if (nf)
+    HIPCHK(hipMemcpyAsync(fr.data(), fails, nf * sizeof(vfk::FailRec), hipMemcpyDeviceToHost,
+                          stream));
+  std::vector<uint8_t> ts(count);
+  HIPCHK(hipMemcpyAsync(ts.data(), tseed, count, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+#undef HIPCHK
+
+  vf_handle *H = new (std::nothrow) vf_handle();
+  if (!H) return VF_EHIP;
+  H->magic = kMagic;
+  H->kind = 1;
+  H->is_filter = 0;
+  H->b = 0;
+  H->h = 0;
+  H->S = (uint32_t)count;
+  H->g = Geometry{L.maxM, 0, 0, L.maxl, L.maxsigma, L.maxV};
+  H->n = L.keys;
+  H->seed = seed;
+  H->cell_bytes = 0;
+  H->G = A.G;
+  H->cells = cells;
+  H->tseed = tseed;
+  H->ncu = ncu;
+  H->n_fail_total = hwork[vfk::kWorkFails];
+  H->relaunched = hwork[vfk::kWorkRelaunch];
+  H->ms[0] = pe.between(0, 1);
+  H->ms[1] = 0.f;
+  H->ms[2] = pe.between(2, 3);
+  for (const auto &f : fr) H->fails.push_back(vf_failure{f.shard, f.attempt, f.kind, f.core_edges});
+  std::sort(H->fails.begin(), H->fails.end(), [](const vf_failure &a, const vf_failure &c) {
+    return a.shard != c.shard ? a.shard < c.shard : a.attempt < c.attempt;
+  });
+  H->failed_shards = (uint32_t)std::count(ts.begin(), ts.end(), (uint8_t)255);
+  H->count = count;
+  H->items = std::move(L.items);
+  H->seeds = std::move(ts);
+  H->items_dev = items;
+  *handle = H;
+  if (hwork[vfk::kWorkStatus] & vfk::kStatusCapacity) return VF_ECAPACITY;
+  if (H->failed_shards) return VF_EFAIL;
+  return VF_OK;
+}
+
+int vf_batch_query(const vf_handle *h, const uint32_t *inst, const uint64_t *keys, uint64_t nq,
+                   uint64_t *out, hipStream_t stream) {
+  if (!h || h->magic != kMagic || h->kind != 1) return VF_EINVAL;
+  if (nq && (!inst || !keys || !out)) return VF_EINVAL;
+  if (vfk::launch_query_batch(h->G, h->items_dev, h->count, (const uint8_t *)h->cells, h->tseed,
+                              inst, keys, nq, out, h->ncu, stream) != hipSuccess)
+    return VF_EHIP;
+  return VF_OK;
+}
+
+int vf_batch_item(const vf_handle *h, uint64_t i, vf_batch_item_t *out) {
+  if (!h || h->magic != kMagic || h->kind != 1 || !out || i >= h->count) return VF_EINVAL;
+  const vfk::BatchItem &it = h->items[i];
+  out->n = it.n;
+  out->b = (int32_t)it.b;
+  out->c_num = it.c_num;
+  out->c_den = it.c_den;
+  out->sigma = (int32_t)it.sigma;
+  out->l = it.l;
+  out->V = it.V;
+  out->cell_bytes = it.cell_bytes;
+  out->local_seed = h->seeds[i];
+  out->cells = (const uint8_t *)h->cells + it.cell_off;
+  return VF_OK;
 }
 
 int vf_info(const vf_handle *h, vf_info_t *out) {
@@ -507,6 +813,10 @@ int vf_info(const vf_handle *h, vf_info_t *out) {
   out->failed_shards = h->failed_shards;
   out->n_failures = h->n_fail_total;
   out->space_bits = (uint64_t)h->S * h->g.V * (uint64_t)h->b;
+  if (h->kind == 1) {
+    out->space_bits = 0;
+    for (const auto &it : h->items) out->space_bits += it.V * (uint64_t)it.b;
+  }
   out->cells = h->cells;
   out->local_seeds = h->tseed;
   out->ms_count = h->ms[0];

@@ -160,8 +160,36 @@ def test_geometry_rules():
     assert g["sigma"] == math.floor(0.41 * lm * math.log(lm) - 3)
     g = O.geometry(0, 3)
     assert g["l"] == 1 and g["V"] == 3 << g["sigma"]
-    # below 2^16 keys per shard c = 1.16 (c = 1.12 is unsolvable too often)
-    assert (O.geometry(65535, 4)["c_num"], O.geometry(65536, 4)["c_num"]) == (116, 112)
+    # below 2^16 keys per graph the factor grows as the graph shrinks
+    # (0.875 + 0.25 ln 10^6 / ln m, in thousandths), down to c = 1.12 at 2^16
+    small = [O.geometry(m, 4) for m in (10, 100, 1000, 10000, 65535)]
+    cs = [g["c_num"] / g["c_den"] for g in small]
+    assert cs == sorted(cs, reverse=True) and cs[-1] > 1.12
+    for m, g in zip((10, 100, 1000, 10000, 65535), small):
+        assert g["c_den"] == 1000
+        assert abs(g["c_num"] / 1000 - (0.875 + 0.25 * math.log(1e6) / math.log(m))) <= 0.001
+    assert (O.geometry(65536, 4)["c_num"], O.geometry(65536, 4)["c_den"]) == (112, 100)
+
+
+def test_sizes_that_a_fixed_factor_left_unsolvable_now_build():
+    """Regression pin: at c = 1.16 these sizes (found in a batch of 10^5
+    instances) failed every one of 255 local seeds; with the size-dependent
+    factor most first attempts succeed and every build finishes."""
+    first = 0
+    sizes = (246, 439, 491, 924, 1420)
+    for m in sizes:
+        for t in range(4):
+            keys = S.member_keys(m, 4000 + 7 * m + t).numpy().view(np.uint64)
+            vals = S.values(m, 8, 4000 + 7 * m + t).numpy().view(np.uint64)
+            B = O.build(keys, vals, b=8, is_filter=False, h=0, seed=t)
+            assert B.status == 0, (m, t)
+            first += int(B.t[0]) == 0
+    assert first >= 0.6 * 4 * len(sizes)
+    # the old factor really is unsolvable there: 8 local seeds of 1420 keys
+    keys = S.member_keys(1420, 77).numpy().view(np.uint64)
+    vals = S.values(1420, 8, 77).numpy().view(np.uint64)
+    B = O.build(keys, vals, b=8, is_filter=False, h=0, seed=0, tmax=8, c=(116, 100))
+    assert B.status != 0
 
 
 def test_small_shards_are_solvable_in_most_attempts():

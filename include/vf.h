@@ -170,6 +170,63 @@ int vf_info(const vf_handle *h, vf_info_t *out);
 int vf_failures(const vf_handle *h, vf_failure *out, uint32_t cap,
                 uint32_t *count);
 
+/* ---- Batches of independent static functions -------------------------
+ * Many unsharded functions (Problem 1, h = 0) of uneven sizes and value
+ * widths built by one persistent launch per cell width (1, 2, 4, 8 bytes)
+ * instead of one build per function.  Instance i is exactly the structure
+ * vf_build would give for its keys, values, b_i and the batch seed with
+ * h = 0: geometry by the size rule of section 4.2 for M = n_i, local seed,
+ * failure record (shard field = instance index) and cells. */
+
+/* One instance of a batch (host copy). */
+typedef struct vf_batch_item_t {
+  uint64_t n;             /* keys                                        */
+  int32_t b;              /* value bits                                  */
+  uint32_t c_num, c_den;  /* expansion factor                            */
+  int32_t sigma;          /* segment size 2^sigma                        */
+  uint32_t l;             /* start segments                              */
+  uint64_t V;             /* cells = (l + 2) 2^sigma                     */
+  uint32_t cell_bytes;    /* 1, 2, 4 or 8                                */
+  uint32_t local_seed;    /* successful local seed, 255 = failed         */
+  const void *cells;      /* device: V cells of cell_bytes               */
+} vf_batch_item_t;
+
+/* Buffer sizes for a batch of count instances with n[i] keys of b[i] bits
+ * (host arrays).  out->h is 0, out->shard_cap the largest n[i].
+ * Errors: VF_EINVAL (count 0, null arrays, b outside 1..64), VF_ECAPACITY
+ * (an instance too large for one graph of 2^21 cells). */
+int vf_batch_plan(uint64_t count, const uint64_t *n, const int32_t *b,
+                  const vf_opts *o, vf_sizes *out);
+
+/* Build a batch.
+ *   keys, values device; the keys (and values) of instance i follow those
+ *                of instance i - 1 (n[0] + ... + n[count-1] words each);
+ *                the low b[i] bits of a value are stored
+ *   count, n, b  instances and their sizes and value bits (host arrays)
+ *   seed, o      hash seed shared by all instances; o->h is ignored
+ *   workspace, structure  device buffers of at least vf_batch_plan() bytes
+ *   handle       receives a batch handle (also on VF_EFAIL)
+ * The keys are used in place (no grouping pass); every launch is enqueued
+ * on stream and the call synchronizes once at the end to read the failure
+ * record.  Errors: VF_EINVAL, VF_ENOSPC, VF_EFAIL (an instance failed all
+ * local seeds), VF_ECAPACITY, VF_EHIP. */
+int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
+                   const uint64_t *n, const int32_t *b, uint64_t seed,
+                   const vf_opts *o, void *workspace, uint64_t workspace_bytes,
+                   void *structure, uint64_t structure_bytes,
+                   hipStream_t stream, vf_handle **handle);
+
+/* Query a batch: out[i] = value of keys[i] in instance inst[i] (eq. (MWHC)
+ * in that instance), as a uint64 word.  inst, keys and out are device
+ * arrays of nq entries; an instance index >= count gives all ones.
+ * Errors: VF_EINVAL (null pointers, or a handle that is not a batch). */
+int vf_batch_query(const vf_handle *h, const uint32_t *inst, const uint64_t *keys,
+                   uint64_t nq, uint64_t *out, hipStream_t stream);
+
+/* Describe instance i of a batch.  Errors: VF_EINVAL (not a batch handle,
+ * i out of range, out NULL). */
+int vf_batch_item(const vf_handle *h, uint64_t i, vf_batch_item_t *out);
+
 /* Free the host-side handle only; the caller still owns every buffer. */
 void vf_free(vf_handle *h);
 

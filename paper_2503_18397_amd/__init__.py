@@ -55,6 +55,16 @@ class Info(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("b", C.c_int32), ("c_num", C.c_uint32),
+                ("c_den", C.c_uint32), ("sigma", C.c_int32), ("l", C.c_uint32),
+                ("V", C.c_uint64), ("cell_bytes", C.c_uint32), ("local_seed", C.c_uint32),
+                ("cells", C.c_void_p)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Failure(C.Structure):
     _fields_ = [("shard", C.c_uint32), ("attempt", C.c_uint32), ("kind", C.c_uint32),
                 ("core_edges", C.c_uint32)]
@@ -80,12 +90,18 @@ _lib.vf_info.argtypes = [_vp, C.POINTER(Info)]
 _lib.vf_failures.argtypes = [_vp, C.POINTER(Failure), C.c_uint32, C.POINTER(C.c_uint32)]
 _lib.vf_free.argtypes = [_vp]
 _lib.vf_free.restype = None
+_lib.vf_batch_plan.argtypes = [_u64, _vp, _vp, C.POINTER(Opts), C.POINTER(Sizes)]
+_lib.vf_batch_build.argtypes = [_vp, _vp, _u64, _vp, _vp, _u64, C.POINTER(Opts), _vp, _u64,
+                                _vp, _u64, _vp, C.POINTER(_vp)]
+_lib.vf_batch_query.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp]
+_lib.vf_batch_item.argtypes = [_vp, _u64, C.POINTER(BatchItem)]
 for _f in ("vf_plan", "vf_build", "vfilter_build", "vf_query", "vfilter_contains", "vf_info",
-           "vf_failures"):
+           "vf_failures", "vf_batch_plan", "vf_batch_build", "vf_batch_query", "vf_batch_item"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build",
-           "vfilter_contains", "vf_info", "vf_failures", "vf_free")
+           "vfilter_contains", "vf_info", "vf_failures", "vf_free", "vf_batch_plan",
+           "vf_batch_build", "vf_batch_query", "vf_batch_item")
 
 
 def _check(rc: int, where: str) -> None:
@@ -174,6 +190,49 @@ def vf_free(handle) -> None:
     _lib.vf_free(handle)
 
 
+def _host_arrays(n, b):
+    import numpy as np
+    n = np.ascontiguousarray(np.asarray(n, dtype=np.uint64))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.int32))
+    if n.shape != b.shape or n.ndim != 1:
+        raise ValueError("n and b must be 1-d arrays of the same length")
+    return n, b
+
+
+def vf_batch_plan(n, b, opts: Opts | None = None) -> Sizes:
+    n, b = _host_arrays(n, b)
+    s = Sizes()
+    _check(_lib.vf_batch_plan(n.size, n.ctypes.data, b.ctypes.data,
+                              C.byref(opts) if opts else None, C.byref(s)), "vf_batch_plan")
+    return s
+
+
+def vf_batch_build(keys, values, n, b, seed, opts, workspace, structure, stream=None):
+    """Returns (rc, handle) like vf_build; n and b are host arrays."""
+    n, b = _host_arrays(n, b)
+    h = C.c_void_p()
+    rc = _lib.vf_batch_build(_dev_ptr(keys, "keys"), _dev_ptr(values, "values"), n.size,
+                             n.ctypes.data, b.ctypes.data, seed,
+                             C.byref(opts) if opts else None, _dev_ptr(workspace, "workspace"),
+                             workspace.numel(), _dev_ptr(structure, "structure"),
+                             structure.numel(), _stream(stream), C.byref(h))
+    if rc not in (VF_OK, VF_EFAIL):
+        raise VFError(rc, "vf_batch_build")
+    return rc, h
+
+
+def vf_batch_query(handle, inst, keys, out, stream=None) -> None:
+    _check(_lib.vf_batch_query(handle, _dev_ptr(inst, "inst"), _dev_ptr(keys, "keys"),
+                               keys.numel(), _dev_ptr(out, "out"), _stream(stream)),
+           "vf_batch_query")
+
+
+def vf_batch_item(handle, i: int) -> dict:
+    it = BatchItem()
+    _check(_lib.vf_batch_item(handle, i, C.byref(it)), "vf_batch_item")
+    return it.as_dict()
+
+
 _CELL_DTYPE = {1: torch.uint8, 2: torch.int16, 4: torch.int32, 8: torch.int64}
 
 
@@ -240,6 +299,66 @@ class Structure:
                 out = torch.empty(keys.numel(), dtype=_CELL_DTYPE[self.info["cell_bytes"]],
                                   device=keys.device)
             vf_query(self.handle, keys, out, stream)
+        return out
+
+    def free(self) -> None:
+        if self.handle:
+            vf_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+@dataclass
+class Batch:
+    """A batch of independent static functions built by one launch per cell
+    width (``vf_batch_build``); instance i has keys[off[i]:off[i+1]]."""
+    handle: C.c_void_p
+    rc: int
+    structure: torch.Tensor
+    workspace: torch.Tensor | None
+
+    @classmethod
+    def build(cls, keys: torch.Tensor, values: torch.Tensor, n, b, *, seed: int = 0,
+              sigma: int | None = None, c: tuple | None = None, tmax: int | None = None,
+              stream=None):
+        opts = vf_default_opts(sigma=sigma, tmax=tmax)
+        if c is not None:
+            opts.c_num, opts.c_den = c
+        sz = vf_batch_plan(n, b, opts)
+        dev = keys.device
+        ws = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=dev)
+        st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
+        rc, hd = vf_batch_build(keys, values, n, b, seed, opts, ws, st, stream)
+        return cls(hd, rc, st, ws)
+
+    @property
+    def info(self) -> dict:
+        return vf_info(self.handle)
+
+    @property
+    def failures(self) -> list:
+        return vf_failures(self.handle)
+
+    def item(self, i: int) -> dict:
+        return vf_batch_item(self.handle, i)
+
+    def cells(self, i: int) -> torch.Tensor:
+        """Device view of instance i's V cells."""
+        it = self.item(i)
+        off = it["cells"] - self.structure.data_ptr()
+        nbytes = it["V"] * it["cell_bytes"]
+        return self.structure[off: off + nbytes].view(_CELL_DTYPE[it["cell_bytes"]])
+
+    def query(self, inst: torch.Tensor, keys: torch.Tensor, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+        vf_batch_query(self.handle, inst, keys, out, stream)
         return out
 
     def free(self) -> None:

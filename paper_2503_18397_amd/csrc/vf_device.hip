@@ -369,10 +369,14 @@ __host__ __device__ inline uint32_t slot_bytes(uint32_t sigma) { return 4 * row_
 constexpr uint32_t kMaxSlots = 512;
 constexpr uint32_t kBcolBytes = 256;  // batch columns of the back-substitution
 
-uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes) {
+__host__ __device__ inline uint32_t window_slots_for(uint32_t sigma, uint32_t lds_bytes) {
   uint32_t n = (lds_bytes - kLdsTail) / slot_bytes(sigma);
   n = n > kMaxSlots ? kMaxSlots : n;
   return n & ~7u;  // keeps the 8-byte right sides after the rows aligned
+}
+
+uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes) {
+  return window_slots_for(sigma, lds_bytes);
 }
 
 enum { kSolveOk = 0, kSolveInconsistent = 1, kSolveCapacity = 2 };
@@ -424,9 +428,9 @@ __device__ __forceinline__ BandCtl *band_ctl(uint8_t *lds, uint32_t lds_bytes) {
 // Both wavefronts walk the same sequence of words and meet at one barrier
 // per word; the result (kSolve*) and the pivot count are the same in both.
 template <int QM>
-__device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc, uint8_t *lds,
-                                          BandCtl *ctl, uint32_t wid, uint32_t *np_out) {
-  const Geo &G = A.G;
+__device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint32_t W,
+                                          const Scratch &sc, uint8_t *lds, BandCtl *ctl,
+                                          uint32_t wid, uint32_t *np_out) {
   uint32_t *const plog = sc.plog;
   uint32_t *const poff = sc.poff;
   const uint32_t *const cb = sc.cb;
@@ -438,7 +442,6 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Scratch &sc,
   const uint32_t s = ring.s;
   const uint32_t RW = ring.words;
   const uint32_t RS = RW + 1;
-  const uint32_t W = A.wmax;
   uint32_t *rows = (uint32_t *)lds;
   uint64_t *rrhs = (uint64_t *)(lds + (uint64_t)4 * RS * W);
   uint16_t *rpop = (uint16_t *)(rrhs + W);
@@ -841,8 +844,11 @@ __device__ __forceinline__ uint32_t wave_scan_array(uint32_t *a, uint32_t *b, ui
 }
 
 // A shard whose 2-core is solved waits for its assignment.
+template <typename T>
 struct Pending {
-  uint32_t shard, t, np, nrounds, buf;
+  T *cells;  // the shard's cells in HBM
+  uint64_t V;
+  uint32_t shard, t, np, nrounds, buf, in_lds;
 };
 
 // One workgroup of two wavefronts builds shards one after the other.
@@ -853,27 +859,27 @@ struct Pending {
 template <typename T, int QM>
 __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   extern __shared__ __align__(16) uint8_t lds[];
-  const Geo &G = A.G;
+  Geo G = A.G;
   const uint32_t lane = lane_id();
   const uint32_t wid = threadIdx.x >> 6;
-  const uint64_t V = G.V;
   Scratch sc;
-  scratch_layout(A.scratch + (uint64_t)blockIdx.x * A.scratch_stride, A.M, V, G.l, A.logcap, &sc);
-  T *cells = (T *)A.cells;
+  scratch_layout(A.scratch + (uint64_t)blockIdx.x * A.scratch_stride, A.M, A.scr_V, A.scr_l,
+                 A.logcap, &sc);
   BandCtl *const ctl = band_ctl(lds, A.lds_bytes);
   uint32_t *const bcol = (uint32_t *)(lds + A.lds_bytes - kBcolBytes);
 
   // cells of a solved shard: zero, core values by back-substitution, then
   // the peeled edges in reverse round order (one wavefront)
-  auto assign = [&](const Pending &P) {
-    T *wg = cells + (uint64_t)P.shard * V;
-    T *wl = A.cells_in_lds ? (T *)lds : wg;
+  auto assign = [&](const Pending<T> &P) {
+    const uint64_t V = P.V;
+    T *wg = P.cells;
+    T *wl = P.in_lds ? (T *)lds : wg;
     const uint64_t *E = sc.E[P.buf], *R = sc.R[P.buf];
     const uint32_t *stk = sc.stack[P.buf], *rst = sc.rst[P.buf];
     for (uint64_t v = lane; v < V; v += 64) wl[v] = (T)0;
-    if (A.cells_in_lds) wave_sync();
+    if (P.in_lds) wave_sync();
     else wave_sync_global();
-    if (P.np) back_substitute<T>(sc, P.np, wl, bcol, !A.cells_in_lds);
+    if (P.np) back_substitute<T>(sc, P.np, wl, bcol, !P.in_lds);
     for (int r = (int)P.nrounds - 1; r >= 0; r--) {
       const uint32_t e0 = rst[r], e1 = rst[r + 1];
       for (uint32_t i = e0 + lane; i < e1; i += 64) {
@@ -886,22 +892,22 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
           if (q != side) val ^= (uint64_t)wl[a[q]];
         wl[a[side]] = (T)val;
       }
-      if (A.cells_in_lds) wave_sync();
+      if (P.in_lds) wave_sync();
       else wave_sync_global();
     }
-    if (A.cells_in_lds)
+    if (P.in_lds)
       for (uint64_t v = lane; v < V; v += 64) wg[v] = wl[v];
     if (lane == 0) A.tseed[P.shard] = (uint8_t)P.t;
   };
 
   bool pend = false;
-  Pending P{0, 0, 0, 0, 0};
+  Pending<T> P{nullptr, 0, 0, 0, 0, 0, 0, 0};
   uint32_t buf = 0;
   for (;;) {
     if (threadIdx.x == 0) {
       uint32_t j = atomicAdd(&A.work[kWorkNext], 1u), t0 = 0;
       if (A.list) {
-        if (j < A.nlist) {
+        if (j < (A.nlist_dev ? *A.nlist_dev : A.nlist)) {
           t0 = A.list[2 * j + 1];
           j = A.list[2 * j];
         } else {
@@ -921,8 +927,28 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       __syncthreads();
       break;
     }
-    const uint64_t base = A.offsets[j];
-    const uint32_t m = (uint32_t)(A.offsets[j + 1] - base);
+    uint64_t base;
+    uint32_t m;
+    T *wg;
+    if (A.items) {
+      const BatchItem it = A.items[j];
+      G.V = it.V;
+      G.l = it.l;
+      G.sigma = it.sigma;
+      G.b = it.b;
+      G.vmask = it.vmask;
+      base = it.key_off;
+      m = it.n;
+      wg = (T *)((uint8_t *)A.cells + it.cell_off);
+    } else {
+      base = A.offsets[j];
+      m = (uint32_t)(A.offsets[j + 1] - base);
+      wg = (T *)A.cells + (uint64_t)j * G.V;
+    }
+    const uint64_t V = G.V;
+    const uint32_t in_lds =
+        A.cells_in_lds && V * sizeof(T) + kLdsTail <= A.lds_bytes ? 1u : 0u;
+    const uint32_t W = min(A.wmax, window_slots_for(G.sigma, A.lds_bytes));
     uint64_t *const E = sc.E[buf], *const R = sc.R[buf];
     uint32_t *const stk = sc.stack[buf], *const rst = sc.rst[buf];
 
@@ -1084,11 +1110,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
 
       uint32_t np = 0;
       const int st = dup ? kSolveInconsistent
-                         : (k ? band_solve<QM>(A, sc, lds, ctl, wid, &np) : kSolveOk);
+                         : (k ? band_solve<QM>(A, G, W, sc, lds, ctl, wid, &np) : kSolveOk);
       if (st == kSolveCapacity) {
         if (wid == 0 && lane == 0) {
           if (A.overflow) {
             const uint32_t idx = atomicAdd(&A.work[kWorkCap], 1u);
+            atomicAdd(&A.work[kWorkRelaunch], 1u);
             A.overflow[2 * idx] = j;
             A.overflow[2 * idx + 1] = t;
           } else {
@@ -1104,7 +1131,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         }
         continue;
       }
-      P = Pending{j, t, np, nrounds, buf};
+      P = Pending<T>{wg, V, j, t, np, nrounds, buf, in_lds};
       pend = true;
       buf ^= 1u;
       solved = true;
@@ -1112,7 +1139,6 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
     }
     if (!solved && wid == 0) {
       // every attempt failed (or a capacity limit was hit): zero cells
-      T *wg = cells + (uint64_t)j * V;
       for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
       if (lane == 0) A.tseed[j] = 255;
     }
@@ -1169,6 +1195,56 @@ __global__ void __launch_bounds__(256) k_query(Geo G, const T *__restrict__ cell
         else ((T *)out)[i] = x[k];
       }
     }
+  }
+}
+
+// Query of a batch of unsharded functions: instance inst[i]'s geometry
+// comes from its descriptor; the answer is widened to 64 bits.
+__global__ void __launch_bounds__(256) k_query_batch(Geo G, const BatchItem *__restrict__ items,
+                                                     uint64_t count,
+                                                     const uint8_t *__restrict__ cells,
+                                                     const uint8_t *__restrict__ tseed,
+                                                     const uint32_t *__restrict__ inst,
+                                                     const uint64_t *__restrict__ keys, uint64_t n,
+                                                     uint64_t *__restrict__ out) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t q = inst[i];
+    if (q >= count) {
+      out[i] = ~0ull;
+      continue;
+    }
+    const BatchItem it = items[q];
+    Geo g = G;
+    g.V = it.V;
+    g.l = it.l;
+    g.sigma = it.sigma;
+    g.h = 0;
+    const uint64_t key = keys[i];
+    const uint64_t hi = fin64(key ^ G.khi), lo = fin64(key ^ G.klo);
+    uint32_t v0, v1, v2;
+    edge3(g, hi, lo, tseed[q], v0, v1, v2);
+    const uint8_t *w = cells + it.cell_off;
+    uint64_t x;
+    switch (it.cell_bytes) {
+      case 1: x = (uint64_t)(w[v0] ^ w[v1] ^ w[v2]); break;
+      case 2: {
+        const uint16_t *c = (const uint16_t *)w;
+        x = (uint64_t)(c[v0] ^ c[v1] ^ c[v2]);
+        break;
+      }
+      case 4: {
+        const uint32_t *c = (const uint32_t *)w;
+        x = (uint64_t)(c[v0] ^ c[v1] ^ c[v2]);
+        break;
+      }
+      default: {
+        const uint64_t *c = (const uint64_t *)w;
+        x = c[v0] ^ c[v1] ^ c[v2];
+        break;
+      }
+    }
+    out[i] = x;
   }
 }
 
@@ -1277,6 +1353,19 @@ hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s) {
     case 4: return launch_build_t<uint32_t>(a, nwg, s);
     default: return launch_build_t<uint64_t>(a, nwg, s);
   }
+}
+
+hipError_t launch_query_batch(const Geo &G, const BatchItem *items, uint64_t count,
+                              const uint8_t *cells, const uint8_t *tseed, const uint32_t *inst,
+                              const uint64_t *keys, uint64_t n, uint64_t *out, int ncu,
+                              hipStream_t s) {
+  if (!n) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  const uint64_t cap = (uint64_t)ncu * 16;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL(k_query_batch, dim3((uint32_t)blocks), dim3(256), 0, s, G, items, count,
+                     cells, tseed, inst, keys, n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,

@@ -20,12 +20,34 @@ struct Geo {
   uint32_t is_filter;
 };
 
+// One instance of a batch: an unsharded structure with its own keys,
+// geometry and cells (cell_off bytes into the batch's cell area).
+struct BatchItem {
+  uint64_t key_off;   // first key (and value) of the instance
+  uint64_t cell_off;  // byte offset of its cells
+  uint64_t V;         // cells
+  uint64_t vmask;     // low-b-bit mask
+  uint32_t n;         // keys
+  uint32_t l, sigma, b;
+  uint32_t cell_bytes;
+  uint32_t c_num, c_den;
+  uint32_t pad;
+};
+static_assert(sizeof(BatchItem) == 64, "BatchItem layout");
+
 struct FailRec {
   uint32_t shard, attempt, kind, core_edges;
 };
 
 // Counters shared by all build workgroups.
-enum : uint32_t { kWorkNext = 0, kWorkFails = 1, kWorkStatus = 2, kWorkCap = 3, kWorkWords = 4 };
+enum : uint32_t {
+  kWorkNext = 0,       // next work item
+  kWorkFails = 1,      // failure records written
+  kWorkStatus = 2,     // kStatus* bits
+  kWorkCap = 3,        // items appended to the overflow list by this launch
+  kWorkRelaunch = 4,   // items appended to overflow lists by all launches
+  kWorkWords = 5
+};
 enum : uint32_t { kStatusCapacity = 1u };
 
 struct BuildArgs {
@@ -51,10 +73,18 @@ struct BuildArgs {
   // (shard, first local seed) pairs of list.
   const uint32_t *list;
   uint32_t nlist;
+  const uint32_t *nlist_dev;  // if set, the list length is read from here
   // Shards whose elimination window outgrew the LDS of this launch are
   // appended here as (shard, local seed) pairs for a launch with more LDS;
   // nullptr: such shards fail with kStatusCapacity.
   uint32_t *overflow;
+  // Batch mode: work item j is instance j of items (G then only supplies
+  // the seed words and the function/filter kind); nullptr: item j is shard
+  // j of one sharded structure.
+  const BatchItem *items;
+  // Largest cells and segment count over all items (scratch layout).
+  uint64_t scr_V;
+  uint32_t scr_l;
 };
 
 constexpr uint32_t kLdsBudget = 160 * 1024;  // LDS of one CU
@@ -79,6 +109,10 @@ hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n
                           uint64_t khi, uint32_t h, uint32_t S, uint64_t *cursor,
                           uint64_t *bkeys, uint64_t *bvals, int ncu, hipStream_t s);
 hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s);
+hipError_t launch_query_batch(const Geo &G, const BatchItem *items, uint64_t count,
+                              const uint8_t *cells, const uint8_t *tseed, const uint32_t *inst,
+                              const uint64_t *keys, uint64_t n, uint64_t *out, int ncu,
+                              hipStream_t s);
 hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
                         const uint8_t *tseed, const uint64_t *keys, uint64_t n,
                         void *out, int ncu, hipStream_t s);

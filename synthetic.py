@@ -92,3 +92,17 @@ def queries(keys: torch.Tensor, q: int, data_seed: int, member_share_per_256: in
     neg = negative_keys(n, q, data_seed, start=0, device=device)
     out = torch.where(is_member, keys[idx], neg)
     return out, is_member
+
+
+def batch_shape(count: int, data_seed: int, lo: int = 10, hi: int = 50000,
+                bits=(1, 4, 8, 16, 32)):
+    """Sizes and value widths of a batch of independent instances: sizes
+    log-uniform in [lo, hi] (floor of exp of a uniform draw between ln lo and
+    ln hi), widths uniform over bits, from numpy's PCG64 seeded with
+    data_seed.  Returns two numpy arrays (uint64 sizes, int32 widths)."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(data_seed))
+    n = np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi), count)))
+    n = np.clip(n, lo, hi).astype(np.uint64)
+    b = rng.choice(np.asarray(bits, dtype=np.int32), count).astype(np.int32)
+    return n, b

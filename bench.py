@@ -53,7 +53,112 @@ def parse():
     p.add_argument("--sigma", type=int, default=None, help="override lg segment size")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-shards", type=int, default=16)
+    p.add_argument("--workload", choices=("vfilter", "batch"), default="vfilter",
+                   help="vfilter: the sharded VFilter (default); batch: 100 000 independent "
+                        "VFuncs of 10..50 000 keys in one launch per cell width, against "
+                        "one build per instance")
+    p.add_argument("--batch-count", type=int, default=100000)
+    p.add_argument("--batch-sample", type=int, default=300,
+                   help="instances built one by one for the per-instance comparison")
     return p.parse_args()
+
+
+def batch_main(args) -> None:
+    """Batched uneven instances: one build launch per cell width for all
+    instances (vf_batch_build) against one vf_build per instance, timed on
+    a random sample of the same instances."""
+    import numpy as np
+    import torch
+    import synthetic as S
+    import paper_2503_18397_amd as vf
+
+    dev = torch.device("cuda:0")
+    n, b = S.batch_shape(args.batch_count, args.data_seed + 2)
+    total = int(n.sum())
+    print(f"[bench] batch: {n.size} instances, {total} keys", file=sys.stderr, flush=True)
+    keys = S.member_keys(total, args.data_seed + 2, device=dev)
+    vals = S.values(total, 32, args.data_seed + 2, device=dev)
+    inst = torch.repeat_interleave(torch.arange(n.size, dtype=torch.int32, device=dev),
+                                   torch.as_tensor(n.astype(np.int64), device=dev))
+    out = torch.empty(total, dtype=torch.int64, device=dev)
+    opts = vf.vf_default_opts()
+    sz = vf.vf_batch_plan(n, b, opts)
+    ws = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=dev)
+    st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def step():
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        rc, h = vf.vf_batch_build(keys, vals, n, b, args.seed, opts, ws, st, stream)
+        e[1].record(stream)
+        vf.vf_batch_query(h, inst, keys, out, stream)
+        e[2].record(stream)
+        e[2].synchronize()
+        info = vf.vf_info(h)
+        res = (rc, e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), info)
+        vf.vf_free(h)
+        return res
+
+    for i in range(args.warmup):
+        step()
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        recs.append(step())
+        print(f"[bench] batch step {i}: build {recs[-1][1]:.3f} ms, query {recs[-1][2]:.3f} ms",
+              file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    rc, _, _, info = recs[-1]
+    build_ms = sum(r[1] for r in recs) / len(recs)
+    query_ms = sum(r[2] for r in recs) / len(recs)
+    bits = torch.as_tensor(b.astype(np.int64), device=dev)[inst.long()]
+    ok = bool(torch.equal(out, vals & ((torch.ones_like(bits) << bits) - 1)))
+
+    # one build per instance (vf_build with h = 0), buffers allocated once
+    rng = np.random.default_rng(args.data_seed)
+    sample = rng.choice(n.size, min(args.batch_sample, n.size), replace=False)
+    off = np.concatenate([[0], np.cumsum(n.astype(np.int64))])
+    o1 = vf.vf_default_opts(h=0)
+    big = max(vf.vf_plan(int(n[i]), int(b[i]), 0.0, False, o1).workspace_bytes for i in sample)
+    bst = max(vf.vf_plan(int(n[i]), int(b[i]), 0.0, False, o1).structure_bytes for i in sample)
+    ws1 = torch.empty(big, dtype=torch.uint8, device=dev)
+    st1 = torch.empty(bst, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    keys_done = 0
+    for i in sample:
+        k = keys[off[i]:off[i + 1]]
+        v = vals[off[i]:off[i + 1]]
+        rc1, h1 = vf.vf_build(k, v, int(b[i]), 0.0, args.seed, o1, ws1, st1, stream)
+        vf.vf_free(h1)
+        keys_done += int(n[i])
+    torch.cuda.synchronize()
+    per_s = time.perf_counter() - t1
+    batched = total / (build_ms * 1e-3) / 1e6
+    single = keys_done / per_s / 1e6
+    res = {
+        "metric": "batched build Mkeys/s (independent VFuncs, one launch per cell width)",
+        "value": round(batched, 3), "unit": "Mkeys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "build_ms": round(build_ms, 3), "query_ms": round(query_ms, 3),
+        "query": {"value": round(total / (query_ms * 1e-3) / 1e9, 4), "unit": "Gq/s"},
+        "higher_is_better": True, "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{n.size} VFuncs, sizes log-uniform in [10, 50000], "
+                               "b uniform in {1,4,8,16,32}, h = 0 each",
+                   "instances": int(n.size), "keys": total},
+        "check": {"rc": rc, "all_members_answer_their_value": ok,
+                  "failed_instances": info["failed_shards"],
+                  "failed_attempts": info["n_failures"],
+                  "relaunched_instances": info["relaunched_shards"],
+                  "space_bits_per_key": round(info["space_bits"] / total, 4)},
+        "per_instance_launches": {"value": round(single, 3), "unit": "Mkeys/s",
+                                  "instances_timed": int(sample.size), "keys": keys_done,
+                                  "seconds": round(per_s, 3)},
+        "speedup_vs_per_instance": round(batched / single, 2),
+    }
+    print(json.dumps(res), flush=True)
 
 
 def cpu_baseline(args) -> dict:
@@ -91,6 +196,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "batch":
+        batch_main(args)
+        return
     import torch
     import synthetic as S
     import paper_2503_18397_amd as vf

@@ -32,7 +32,10 @@
  *     single unsharded graph of at least 800 000 keys.  For small shards the
  *     paper fixes no segment size; we take the smallest s for which the
  *     expected number of duplicate edges of a shard, m / (2 c s^2)
- *     (section 4.2), is at most 1/8.  Section 4 leaves shard sizing to
+ *     (section 4.2), is at most 1/8, but at most s = 2^9: larger segments
+ *     cost locality (section 4.2), and a duplicate edge only costs a retry
+ *     with the next local seed (R4), so shards beyond about 73 000 keys
+ *     accept more duplicate edges (1.4 expected at 800 000 keys) instead.  Section 4 leaves shard sizing to
  *     simulation when no bound is known: simulated with this oracle, c = 1.12
  *     fails in most attempts below 2^16 keys per shard, and so does any
  *     fixed c near it at some sizes (a fuse graph with few segments is
@@ -217,9 +220,9 @@ void orc_geometry(uint32_t M, int32_t h, uint32_t c_num, uint32_t c_den,
     sigma = (int32_t)floor(0.41 * lm * log(lm) - 3.0);
   } else if (large) { /* eq. (ln), Graf and Lemire's segment size */
     sigma = (int32_t)floor(log((double)M) / log(3.33) + 2.25);
-  } else { /* smallest s with m / (2 c s^2) <= 1/8 */
+  } else { /* smallest s with m / (2 c s^2) <= 1/8, at most 2^9 */
     sigma = 0;
-    while ((uint64_t)c_num << (2 * sigma) < 4ULL * M * c_den) sigma++;
+    while (sigma < 9 && (uint64_t)c_num << (2 * sigma) < 4ULL * M * c_den) sigma++;
   }
   if (sigma < 0) sigma = 0;
   if (sigma > 20) sigma = 20;

@@ -56,7 +56,8 @@ struct Geometry {
 // elimination of the 2-core), c = 1.105 with lg s from eq. (nln) for larger
 // shards, c = 1.125 with lg s from eq. (ln) for a single large unsharded
 // graph.  Below 800 000 keys the segment size is the smallest power of two
-// with expected duplicate edges m / (2 c s^2) <= 1/8.  Graphs below 2^16
+// with expected duplicate edges m / (2 c s^2) <= 1/8, at most 2^9 (larger
+// segments cost locality; a duplicate edge only costs a retry).  Graphs below 2^16
 // keys use Graf and Lemire's size-dependent factor 0.875 + 0.25 ln(10^6) /
 // ln m (section 4.2: the factor grows for small n; the paper partly adopts
 // their estimates): simulated (as section 4 suggests for sizing shards),
@@ -87,7 +88,7 @@ Geometry geometry(uint32_t M, int32_t h, uint32_t cn, uint32_t cd, int32_t sigma
     sg = (int32_t)std::floor(std::log((double)M) / std::log(3.33) + 2.25);
   } else {
     sg = 0;
-    while (((uint64_t)cn << (2 * sg)) < 4ull * M * cd) sg++;
+    while (sg < 9 && ((uint64_t)cn << (2 * sg)) < 4ull * M * cd) sg++;
   }
   sg = std::min(std::max(sg, 0), 20);
   const uint64_t den = (uint64_t)cd << sg;
@@ -176,12 +177,15 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   l.S = 1u << h;
   l.cap = shard_cap(n, l.S);
   l.gcap = geometry(l.cap, h, o.c_num, o.c_den, o.sigma);
-  // the rule for c and s changes at 800 000 keys: size buffers for the
-  // larger of the two sides, plus one spare segment
-  if (l.cap >= 800000u) {
-    Geometry below = geometry(799999u, h, o.c_num, o.c_den, o.sigma);
-    if (below.V > l.gcap.V) l.gcap.V = below.V;
-    if (below.l > l.gcap.l) l.gcap.l = below.l;
+  // the rule for c and s changes at 2^16 and 800 000 keys: size buffers for
+  // the larger side of each change, plus one spare segment
+  for (uint32_t edge : {65535u, 799999u}) {
+    if (l.cap > edge) {
+      Geometry below = geometry(edge, h, o.c_num, o.c_den, o.sigma);
+      if (below.V > l.gcap.V) l.gcap.V = below.V;
+      if (below.l > l.gcap.l) l.gcap.l = below.l;
+      if (below.sigma > l.gcap.sigma) l.gcap.sigma = below.sigma;
+    }
   }
   l.gcap.V += 1ull << l.gcap.sigma;
   // smaller shards may use smaller segments and hence more of them: bound

@@ -151,6 +151,12 @@ def test_geometry_rules():
     assert g["l"] == math.ceil(c * 66535 / s) - 2
     # duplicate-edge rule: m / (2 c s^2) <= 1/8, and not with s / 2
     assert 66535 / (2 * c * s * s) <= 1 / 8 < 66535 / (2 * c * (s / 2) ** 2)
+    # ... but segments stay at 2^9 up to 800 000 keys (locality; duplicates
+    # are retried): the rule would ask 2^10 from about 73 400 keys
+    for m in (73400, 73500, 300000, 799999):
+        g = O.geometry(m, 2)
+        assert g["sigma"] == 9 and (g["c_num"], g["c_den"]) == (112, 100)
+        assert g["l"] == math.ceil(1.12 * m / 512) - 2
     g = O.geometry(10**6, 0)  # unsharded large graph: eq. (ln), c = 1.125
     assert (g["c_num"], g["c_den"], g["sigma"]) == (1125, 1000, 13)
     assert g["sigma"] == math.floor(math.log(10**6) / math.log(3.33) + 2.25)

@@ -53,14 +53,76 @@ def parse():
     p.add_argument("--sigma", type=int, default=None, help="override lg segment size")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-shards", type=int, default=16)
-    p.add_argument("--workload", choices=("vfilter", "batch"), default="vfilter",
+    p.add_argument("--workload", choices=("vfilter", "batch", "serve"), default="vfilter",
                    help="vfilter: the sharded VFilter (default); batch: 100 000 independent "
                         "VFuncs of 10..50 000 keys in one launch per cell width, against "
-                        "one build per instance")
+                        "one build per instance; serve: a Poisson stream of builds and "
+                        "query batches served with --slots slots against one request at a time")
+    p.add_argument("--slots", type=int, default=4)
+    p.add_argument("--serve-builds", type=int, default=48)
+    p.add_argument("--serve-queries", type=int, default=480)
     p.add_argument("--batch-count", type=int, default=100000)
     p.add_argument("--batch-sample", type=int, default=300,
                    help="instances built one by one for the per-instance comparison")
     return p.parse_args()
+
+
+def serve_main(args) -> None:
+    """Serving loop: builds (10^3..10^7 keys, b in {4,8,16}, VFunc:VFilter
+    1:1) and query batches (1..10^6 keys, 90% members) arriving as Poisson
+    streams, served with --slots slots and again one request at a time; the
+    same trace both times, structures resident in HBM (200 GB budget)."""
+    import torch
+    import synthetic as S
+    from paper_2503_18397_amd.serve import Request, Server, poisson_trace
+
+    dev = torch.device("cuda:0")
+    ev = poisson_trace(args.data_seed + 4, args.serve_builds, args.serve_queries,
+                       build_rate=40.0, query_rate=400.0)
+    data = {}
+    for e in ev:
+        if e["kind"] != "query":
+            data[e["id"]] = (S.member_keys(e["n"], 300 + e["id"], device=dev),
+                             S.values(e["n"], e["b"], 300 + e["id"], device=dev))
+    for j, e in enumerate(ev):
+        if e["kind"] == "query":
+            e["keys"], _ = S.queries(data[e["target"]][0], e["n"], 700 + j,
+                                     member_share_per_256=230)
+    torch.cuda.synchronize()
+    print(f"[bench] serve: {args.serve_builds} builds, {args.serve_queries} query batches",
+          file=sys.stderr, flush=True)
+
+    def serve(slots):
+        srv = Server(slots=slots)
+        t0 = time.perf_counter()
+        for j, e in enumerate(ev):
+            while time.perf_counter() - t0 < e["t"]:
+                time.sleep(0.0002)
+            if e["kind"] == "query":
+                srv.submit(Request(10000 + j, "query", e["keys"], target=e["target"]))
+            else:
+                k, v = data[e["id"]]
+                srv.submit(Request(e["id"], e["kind"], k, v, b=e["b"], eps=args.eps))
+        st = srv.drain(timeout=600)
+        srv.close()
+        return st.summary()
+
+    serve(args.slots)  # warm-up (allocator, kernels)
+    mixed = serve(args.slots)
+    print(f"[bench] served: {mixed}", file=sys.stderr, flush=True)
+    one = serve(1)
+    print(f"[bench] one at a time: {one}", file=sys.stderr, flush=True)
+    res = {
+        "metric": "serve p50/p99 ms and keys/s (Poisson builds and query batches)",
+        "value": mixed.get("build", {}).get("keys_per_s"), "unit": "built keys/s",
+        "higher_is_better": True, "n_gpus": 1, "vs_baseline": None, "data": "synthetic",
+        "config": {"workload": f"{args.serve_builds} builds (10^3..10^7 keys, b in {{4,8,16}}, "
+                               f"VFunc:VFilter 1:1) at 40/s, {args.serve_queries} query batches "
+                               "(1..10^6 keys, 90% members) at 400/s, 200 GB HBM budget",
+                   "slots": args.slots},
+        "served": mixed, "one_at_a_time": one,
+    }
+    print(json.dumps(res), flush=True)
 
 
 def batch_main(args) -> None:
@@ -198,6 +260,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         batch_main(args)
+        return
+    if args.workload == "serve":
+        serve_main(args)
         return
     import torch
     import synthetic as S

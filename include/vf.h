@@ -154,6 +154,21 @@ int vfilter_build(const uint64_t *keys, uint64_t n, int32_t b, double eps,
                   uint64_t structure_bytes, hipStream_t stream,
                   vf_handle **handle);
 
+/* Build a static filter from keys in host memory (pinned memory gives the
+ * full PCIe rate), as vfilter_build would from the same keys on the device.
+ * The keys are copied in chunks of `chunk` keys (0: one copy) on a stream
+ * of the library's that overlaps each copy with the shard counting of the
+ * previous chunks (section 4: one pass assigns keys to shards by their
+ * signatures); the device copy lives in the workspace, which must hold
+ * vf_plan().workspace_bytes plus 8 n bytes rounded up to 256.  The call
+ * returns once every chunk has been copied (keys may then be reused).
+ * Errors: as vfilter_build. */
+int vfilter_build_host(const uint64_t *keys, uint64_t n, int32_t b, double eps,
+                       uint64_t seed, const vf_opts *o, uint64_t chunk,
+                       void *workspace, uint64_t workspace_bytes,
+                       void *structure, uint64_t structure_bytes,
+                       hipStream_t stream, vf_handle **handle);
+
 /* Filter query: out[i] = 1 if keys[i] may be in the set, 0 if it is not
  * (sections 3.1 and 4.5).  out is n bytes of device memory.
  * Errors: VF_EINVAL (null handle/pointers, or a function handle). */

@@ -84,6 +84,8 @@ _lib.vf_build.argtypes = [_vp, _vp, _u64, _i32, _dbl, _u64, C.POINTER(Opts), _vp
                           _u64, _vp, C.POINTER(_vp)]
 _lib.vfilter_build.argtypes = [_vp, _u64, _i32, _dbl, _u64, C.POINTER(Opts), _vp, _u64, _vp,
                                _u64, _vp, C.POINTER(_vp)]
+_lib.vfilter_build_host.argtypes = [_vp, _u64, _i32, _dbl, _u64, C.POINTER(Opts), _u64, _vp,
+                                    _u64, _vp, _u64, _vp, C.POINTER(_vp)]
 _lib.vf_query.argtypes = [_vp, _vp, _u64, _vp, _vp]
 _lib.vfilter_contains.argtypes = [_vp, _vp, _u64, _vp, _vp]
 _lib.vf_info.argtypes = [_vp, C.POINTER(Info)]
@@ -96,12 +98,13 @@ _lib.vf_batch_build.argtypes = [_vp, _vp, _u64, _vp, _vp, _u64, C.POINTER(Opts),
 _lib.vf_batch_query.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp]
 _lib.vf_batch_item.argtypes = [_vp, _u64, C.POINTER(BatchItem)]
 for _f in ("vf_plan", "vf_build", "vfilter_build", "vf_query", "vfilter_contains", "vf_info",
-           "vf_failures", "vf_batch_plan", "vf_batch_build", "vf_batch_query", "vf_batch_item"):
+           "vf_failures", "vf_batch_plan", "vf_batch_build", "vf_batch_query", "vf_batch_item",
+           "vfilter_build_host"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build",
            "vfilter_contains", "vf_info", "vf_failures", "vf_free", "vf_batch_plan",
-           "vf_batch_build", "vf_batch_query", "vf_batch_item")
+           "vf_batch_build", "vf_batch_query", "vf_batch_item", "vfilter_build_host")
 
 
 def _check(rc: int, where: str) -> None:
@@ -159,6 +162,23 @@ def vfilter_build(keys, b, eps, seed, opts, workspace, structure, stream=None):
                             structure.numel(), _stream(stream), C.byref(h))
     if rc not in (VF_OK, VF_EFAIL):
         raise VFError(rc, "vfilter_build")
+    return rc, h
+
+
+def vfilter_build_host(keys, b, eps, seed, opts, workspace, structure, chunk=1 << 28,
+                       stream=None):
+    """keys: a contiguous int64 CPU tensor (pinned for the full PCIe rate);
+    workspace: vf_plan().workspace_bytes + 8 n rounded up to 256 bytes."""
+    if keys.is_cuda or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous host tensor")
+    h = C.c_void_p()
+    rc = _lib.vfilter_build_host(keys.data_ptr(), keys.numel(), b, eps, seed,
+                                 C.byref(opts) if opts else None, chunk,
+                                 _dev_ptr(workspace, "workspace"), workspace.numel(),
+                                 _dev_ptr(structure, "structure"), structure.numel(),
+                                 _stream(stream), C.byref(h))
+    if rc not in (VF_OK, VF_EFAIL):
+        raise VFError(rc, "vfilter_build_host")
     return rc, h
 
 

@@ -389,10 +389,22 @@ int vf_plan(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts 
   return VF_OK;
 }
 
+// Keys in host memory: copied into the workspace past the planned bytes in
+// chunks on a copy stream of the library's, each chunk counted by shard as
+// soon as it has arrived (the next chunk's copy overlaps the counting).
+struct HostKeys {
+  const uint64_t *keys = nullptr;  // host
+  uint64_t chunk = 0;              // keys per copy
+};
+
 static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n, int32_t b,
                         double eps, uint64_t seed, const vf_opts *o, void *ws,
                         uint64_t ws_bytes, void *st, uint64_t st_bytes, hipStream_t stream,
-                        vf_handle **handle, int32_t is_filter) {
+                        vf_handle **handle, int32_t is_filter, const HostKeys *hk = nullptr) {
+  if (hk) {
+    if (!hk->keys && n) return VF_EINVAL;
+    keys = hk->keys;
+  }
   if (!handle || !ws || !st || (n && !keys) || (!is_filter && n && !values)) return VF_EINVAL;
   vf_opts d;
   vf_default_opts(&d);
@@ -402,7 +414,8 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   Layout L;
   int rc = make_layout(n, b, eps, is_filter, op, ncu, &L);
   if (rc) return rc;
-  if (ws_bytes < L.ws_bytes || st_bytes < L.st_bytes) return VF_ENOSPC;
+  const uint64_t ws_need = L.ws_bytes + (hk ? align256(8 * n) : 0);
+  if (ws_bytes < ws_need || st_bytes < L.st_bytes) return VF_ENOSPC;
 
   uint8_t *W = (uint8_t *)ws;
   uint32_t *counts = (uint32_t *)(W + L.o_counts);
@@ -432,7 +445,34 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   pe.record(0, stream);
   HIPCHK(vfk::launch_fill_u32(counts, L.S, 0, stream));
   HIPCHK(vfk::launch_fill_u32(meta, 4, 0, stream));
-  HIPCHK(vfk::launch_count(keys, n, sw[0], (uint32_t)L.h, L.S, counts, ncu, stream));
+  if (hk && n) {
+    uint64_t *dk = (uint64_t *)(W + L.ws_bytes);
+    const uint64_t chunk = hk->chunk ? hk->chunk : n;
+    hipStream_t cs = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+    for (auto &e : ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    // the copy stream starts after the work already on the build stream
+    ok = ok && hipEventRecord(ev[1], stream) == hipSuccess &&
+         hipStreamWaitEvent(cs, ev[1], 0) == hipSuccess;
+    for (uint64_t c0 = 0, i = 0; ok && c0 < n; c0 += chunk, i++) {
+      const uint64_t cnt = std::min(chunk, n - c0);
+      hipEvent_t e = ev[i & 1];
+      ok = hipMemcpyAsync(dk + c0, hk->keys + c0, 8 * cnt, hipMemcpyHostToDevice, cs) ==
+               hipSuccess &&
+           hipEventRecord(e, cs) == hipSuccess && hipStreamWaitEvent(stream, e, 0) == hipSuccess &&
+           vfk::launch_count(dk + c0, cnt, sw[0], (uint32_t)L.h, L.S, counts, ncu, stream) ==
+               hipSuccess;
+    }
+    if (cs) ok = (hipStreamSynchronize(cs) == hipSuccess) && ok;
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (!ok) return VF_EHIP;
+    keys = dk;
+  } else {
+    HIPCHK(vfk::launch_count(keys, n, sw[0], (uint32_t)L.h, L.S, counts, ncu, stream));
+  }
   HIPCHK(vfk::launch_scan(counts, L.S, offsets, cursor, meta, stream));
   pe.record(1, stream);
   uint32_t hmeta[4] = {0, 0, 0, 0};
@@ -569,6 +609,17 @@ int vfilter_build(const uint64_t *keys, uint64_t n, int32_t b, double eps, uint6
                   uint64_t structure_bytes, hipStream_t stream, vf_handle **handle) {
   return build_common(keys, nullptr, n, b, eps, seed, o, workspace, workspace_bytes, structure,
                       structure_bytes, stream, handle, 1);
+}
+
+int vfilter_build_host(const uint64_t *keys, uint64_t n, int32_t b, double eps, uint64_t seed,
+                       const vf_opts *o, uint64_t chunk, void *workspace,
+                       uint64_t workspace_bytes, void *structure, uint64_t structure_bytes,
+                       hipStream_t stream, vf_handle **handle) {
+  HostKeys hk;
+  hk.keys = keys;
+  hk.chunk = chunk;
+  return build_common(nullptr, nullptr, n, b, eps, seed, o, workspace, workspace_bytes,
+                      structure, structure_bytes, stream, handle, 1, &hk);
 }
 
 static int query_common(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,

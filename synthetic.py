@@ -16,7 +16,8 @@ choosing its kind from a third stream.
 
 All functions take and return int64 torch tensors holding the 64-bit patterns
 and run unchanged on the CPU or a GPU, so the same seed gives bit-identical
-inputs on both.  Every product is below 2^63, so no signed overflow occurs.
+inputs on both.  Every product is below 2^63 (member indices are scaled in
+16-bit halves), so no signed overflow occurs.
 """
 from __future__ import annotations
 
@@ -79,6 +80,12 @@ def values(n: int, b: int, data_seed: int, device="cpu") -> torch.Tensor:
     return v & ((1 << b) - 1) if b < 63 else v & 0x7FFFFFFFFFFFFFFF
 
 
+def _scale(u: torch.Tensor, n: int) -> torch.Tensor:
+    """floor(u * n / 2^32) for 32-bit u and n <= 2^32 without 64-bit
+    overflow (u split into 16-bit halves)."""
+    return ((u >> 16) * n + (((u & 0xFFFF) * n) >> 16)) >> 16
+
+
 def queries(keys: torch.Tensor, q: int, data_seed: int, member_share_per_256: int = 128):
     """q queries: each is a member (uniform, with replacement) with
     probability member_share_per_256 / 256, else a fresh non-member.
@@ -88,7 +95,7 @@ def queries(keys: torch.Tensor, q: int, data_seed: int, member_share_per_256: in
     j = torch.arange(q, dtype=torch.int64, device=device)
     r = feistel(j, data_seed ^ 0x0A5E7A11)
     is_member = ((r >> 56) & 0xFF) < member_share_per_256
-    idx = ((r & M32) * n) >> 32  # uniform in [0, n)
+    idx = _scale(r & M32, n)  # uniform in [0, n)
     neg = negative_keys(n, q, data_seed, start=0, device=device)
     out = torch.where(is_member, keys[idx], neg)
     return out, is_member
@@ -106,3 +113,19 @@ def batch_shape(count: int, data_seed: int, lo: int = 10, hi: int = 50000,
     n = np.clip(n, lo, hi).astype(np.uint64)
     b = rng.choice(np.asarray(bits, dtype=np.int32), count).astype(np.int32)
     return n, b
+
+
+def queries_chunk(n: int, start: int, count: int, data_seed: int,
+                  member_share_per_256: int = 128, device="cpu"):
+    """Queries start .. start + count - 1 of the stream that queries(keys,
+    q, data_seed) draws for the n member keys member_keys(n, data_seed),
+    computed without the key array (members are recomputed from their
+    index), so very large streams can be made in pieces.  Returns
+    (queries, is_member)."""
+    j = torch.arange(start, start + count, dtype=torch.int64, device=device)
+    r = feistel(j, data_seed ^ 0x0A5E7A11)
+    is_member = ((r >> 56) & 0xFF) < member_share_per_256
+    idx = _scale(r & M32, n)
+    mem = feistel(2 * idx, data_seed)
+    neg = feistel(2 * (n + j) + 1, data_seed)
+    return torch.where(is_member, mem, neg), is_member

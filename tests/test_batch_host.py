@@ -48,3 +48,21 @@ def test_batch_shape_is_log_uniform():
     assert abs(below - 0.5) < 5 * math.sqrt(0.25 / n.size)
     # the mean size matches the log-uniform mean (hi - lo) / ln(hi / lo)
     assert abs(n.mean() / ((50000 - 10) / math.log(5000)) - 1) < 0.05
+
+
+def test_synthetic_query_chunks_match_the_whole_stream():
+    import torch
+    keys = S.member_keys(1000, 9)
+    q, m = S.queries(keys, 5000, 9)
+    q2, m2 = S.queries_chunk(1000, 1200, 2000, 9)
+    assert torch.equal(q[1200:3200], q2) and torch.equal(m[1200:3200], m2)
+
+
+def test_member_index_scaling_is_exact_up_to_2_32_keys():
+    import torch
+    rng = np.random.default_rng(5)
+    u = rng.integers(0, 2 ** 32, 4000, dtype=np.int64)
+    for n in (1, 1000, 2 ** 31 - 1, 2 ** 31, 2 ** 32 - 1, 2 ** 32):
+        got = S._scale(torch.as_tensor(u), n).numpy()
+        want = np.array([(int(x) * n) >> 32 for x in u], dtype=np.int64)
+        assert np.array_equal(got, want), n

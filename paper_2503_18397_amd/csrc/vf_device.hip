@@ -395,10 +395,11 @@ struct BandCtl {
   uint32_t flag[2];              // kSolveInconsistent | kSolveCapacity
   uint32_t adv[2];               // 0: the word is taken again (window full)
   uint32_t k[2], gs[2];          // pivots of each batch and its segment
+  uint32_t nq[2];                // slot groups in use during the batch's word
   uint32_t nret[2];
   uint32_t slot[2][32], col[2][32], cm[2][32];
   uint64_t rhs[2][32];
-  uint32_t ret[2][32];
+  uint16_t ret[2][64];           // slots handed back to wavefront 0
 };
 static_assert(sizeof(BandCtl) + kBcolBytes <= kLdsTail, "LDS tail too small");
 
@@ -537,7 +538,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
         plog[lp + 2] = (uint32_t)prhs;
         plog[lp + 3] = (uint32_t)(prhs >> 32);
         poff[np + (uint32_t)kk] = lp;
-        ctl->ret[rsel][kk] = x;
+        ctl->ret[rsel][kk] = (uint16_t)x;
       }
       lp = pos;
     }
@@ -564,6 +565,10 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       const uint32_t wbase = c - (cpos & 31);  // column of bit 0 of this word
       const uint32_t wlo_col = max(segbot, wbase);
       const uint32_t cur = it & 1u, prev = cur ^ 1u;
+      // lane k of pivtab/pivcol/pivcm/pivrhs describes pivot k of the word;
+      // bit q of pivbits marks the lane's slot of group q as a pivot row
+      uint32_t pivtab = 0, pivcol = 0, pivcm = 0, pivbits = 0;
+      uint64_t pivrhs = 0;
       if (wid == 0) {
         // slots emitted during the previous word come back
         const uint32_t nr = ctl->nret[prev];
@@ -612,8 +617,6 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           //    row has absorbed; lane k of pivtab/pivcol/pivcm/pivrhs
           //    describes pivot k
           uint32_t colmask = wave_or(orv);
-          uint32_t pivtab = 0, pivcol = 0, pivcm = 0, pivbits = 0;
-          uint64_t pivrhs = 0;
           while (colmask) {
             const uint32_t b = 31 - __clz(colmask);
             uint64_t cand[QM];
@@ -672,51 +675,17 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
             colmask = wave_or(orv) & ((1u << b) - 1u);
           }
           if (k) {
-            // 2. whole rows: every non-pivot row that absorbed pivots of this
-            //    word gets their rows (as they were when the word started)
-            //    xored in; a row that becomes zero leaves the window
-            //    (inconsistent if its right side is not zero)
-            bool incons = false;
-#pragma unroll
-            for (int q = 0; q < QM; q++) {
-              if ((uint32_t)q >= NQ) break;
-              uint64_t m = __ballot(cm[q] != 0 && !((pivbits >> q) & 1u));
-              while (m) {
-                const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
-                m &= m - 1;
-                const uint32_t x = (uint32_t)q * 64 + xl;
-                const uint32_t cmx = readlane(cm[q], (int)xl);
-                uint32_t *xrow = rows + (uint64_t)x * RS;
-                uint32_t any = 0;
-                for (uint32_t w = 0; w < NW; w++) {
-                  const uint32_t u = w * 64 + lane;
-                  if (u < RW) {
-                    uint32_t acc = xrow[u];
-                    for (uint32_t bits = cmx; bits; bits &= bits - 1) {
-                      const uint32_t j = __ffs(bits) - 1;
-                      acc ^= rows[(uint64_t)readlane(pivtab, (int)j) * RS + u];
-                    }
-                    xrow[u] = acc;
-                    any |= acc;
-                  }
-                }
-                if (__ballot(any != 0) == 0) {
-                  incons |= readlane64(rh[q], (int)xl) != 0;
-                  if (lane == xl) pop[q] = 0;
-                  if (lane == 0) freel[nfree] = (uint16_t)x;
-                  nfree++;
-                }
-              }
-            }
-            if (incons && lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveInconsistent);
-            // popcount estimates and right sides back to LDS for the next word
+            // popcount estimates and right sides (final after phase 1) back
+            // to LDS; the combination masks of the odd slot groups go to the
+            // rows' padding words for wavefront 1
 #pragma unroll
             for (int q = 0; q < QM; q++) {
               if ((uint32_t)q >= NQ) break;
               const uint32_t slot = (uint32_t)q * 64 + lane;
-              if ((uint32_t)q < NQ && slot < W) {
+              if (slot < W) {
                 rpop[slot] = (uint16_t)pop[q];
                 rrhs[slot] = rh[q];
+                if (q & 1) rows[(uint64_t)slot * RS + RW] = (pivbits >> q) & 1u ? 0u : cm[q];
               }
             }
             // the batch for wavefront 1
@@ -732,6 +701,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           ctl->k[cur] = k;
           ctl->gs[cur] = (uint32_t)Gs;
           ctl->adv[cur] = adv;
+          ctl->nq[cur] = NQ;
         }
       } else {
         if (it == 0) {
@@ -742,6 +712,77 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
             atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
           }
         }
+      }
+      __syncthreads();
+      // 2. whole rows: every non-pivot row that absorbed pivots of this word
+      //    gets their rows (as they were when the word started) xored in;
+      //    wavefront 0 takes the even slot groups (masks in registers),
+      //    wavefront 1 the odd ones (masks in the rows' padding words).  A row
+      //    that becomes zero is dead (inconsistent if its right side is not
+      //    zero); its slot goes back to the free list.
+      if (const uint32_t kc = ctl->k[cur]) {
+        const uint32_t ptab = wid == 0 ? pivtab : (lane < kc ? ctl->slot[cur][lane] : 0u);
+        auto apply = [&](uint32_t x, uint32_t cmx) -> bool {
+          uint32_t *xrow = rows + (uint64_t)x * RS;
+          uint32_t any = 0;
+          for (uint32_t w = 0; w < NW; w++) {
+            const uint32_t u = w * 64 + lane;
+            if (u < RW) {
+              uint32_t acc = xrow[u];
+              for (uint32_t bits = cmx; bits; bits &= bits - 1) {
+                const uint32_t j = __ffs(bits) - 1;
+                acc ^= rows[(uint64_t)readlane(ptab, (int)j) * RS + u];
+              }
+              xrow[u] = acc;
+              any |= acc;
+            }
+          }
+          return __ballot(any != 0) == 0;
+        };
+        bool incons = false;
+        if (wid == 0) {
+#pragma unroll
+          for (int q = 0; q < QM; q += 2) {
+            if ((uint32_t)q >= NQ) break;
+            uint64_t m = __ballot(cm[q] != 0 && !((pivbits >> q) & 1u));
+            while (m) {
+              const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
+              m &= m - 1;
+              const uint32_t x = (uint32_t)q * 64 + xl;
+              if (apply(x, readlane(cm[q], (int)xl))) {
+                incons |= readlane64(rh[q], (int)xl) != 0;
+                if (lane == 0) {
+                  rpop[x] = 0;
+                  freel[nfree] = (uint16_t)x;
+                }
+                nfree++;
+              }
+            }
+          }
+        } else {
+          const uint32_t nq = ctl->nq[cur];
+          uint32_t nr = ctl->nret[cur];
+          for (uint32_t q = 1; q < nq; q += 2) {
+            const uint32_t slot = q * 64 + lane;
+            const uint32_t cmv = slot < W ? rows[(uint64_t)slot * RS + RW] : 0u;
+            uint64_t m = __ballot(cmv != 0);
+            while (m) {
+              const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
+              m &= m - 1;
+              const uint32_t x = q * 64 + xl;
+              if (apply(x, readlane(cmv, (int)xl))) {
+                incons |= rrhs[x] != 0;
+                if (lane == 0) {
+                  rpop[x] = 0;
+                  if (nr < 64) ctl->ret[cur][nr] = (uint16_t)x;
+                }
+                nr = nr < 64 ? nr + 1 : nr;  // beyond 64 a dead slot stays taken
+              }
+            }
+          }
+          if (lane == 0) ctl->nret[cur] = nr;
+        }
+        if (incons && lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveInconsistent);
       }
       __syncthreads();
       it++;

@@ -47,6 +47,8 @@ class Geom(C.Structure):
         ("sigma", C.c_int32),
         ("l", C.c_uint32),
         ("V", C.c_uint64),
+        ("mwhc", C.c_uint32),
+        ("part", C.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -80,6 +82,9 @@ def lib():
         L.orc_fingerprint.argtypes = [C.c_uint64, C.c_uint64, u64p, C.c_int32]
         L.orc_edge.argtypes = [C.c_uint64, C.c_uint64, C.c_int32, C.c_uint32,
                                C.c_int32, C.c_uint32, u32p]
+        L.orc_edge_mwhc.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, u32p]
+        L.orc_geometry_mwhc.argtypes = [C.c_uint32, C.c_int32, C.c_uint32, C.c_uint32,
+                                        C.c_void_p]
         L.orc_lambert_w0.restype = C.c_double
         L.orc_lambert_w0.argtypes = [C.c_double]
         L.orc_shard_bits_eps.restype = C.c_int32
@@ -139,6 +144,12 @@ def edge(hi: int, lo: int, h: int, l: int, sigma: int, t: int) -> tuple:
     return tuple(int(x) for x in v)
 
 
+def edge_mwhc(lo: int, part: int, t: int) -> tuple:
+    v = np.zeros(3, np.uint32)
+    lib().orc_edge_mwhc(lo, part, t, v)
+    return tuple(int(x) for x in v)
+
+
 def fingerprint(hi: int, lo: int, seed: int, b: int) -> int:
     return int(lib().orc_fingerprint(hi, lo, seed_words(seed), b))
 
@@ -169,10 +180,14 @@ def dupfuse(n, c, eta, alpha=0.41, beta=-3.0) -> float:
     return lib().orc_dupfuse(n, c, eta, alpha, beta)
 
 
-def geometry(M: int, h: int, c: tuple | None = None, sigma: int = -1) -> dict:
+def geometry(M: int, h: int, c: tuple | None = None, sigma: int = -1,
+             mwhc: bool = False) -> dict:
     g = Geom()
     cn, cd = c if c else (0, 0)
-    lib().orc_geometry(M, h, cn, cd, sigma, C.byref(g))
+    if mwhc:
+        lib().orc_geometry_mwhc(M, h, cn, cd, C.byref(g))
+    else:
+        lib().orc_geometry(M, h, cn, cd, sigma, C.byref(g))
     return g.as_dict()
 
 
@@ -223,7 +238,8 @@ class Built:
     status: int               # 0 ok, 1 some built shard failed
 
 
-def plan(keys, h: int, seed: int, c: tuple | None = None, sigma: int = -1):
+def plan(keys, h: int, seed: int, c: tuple | None = None, sigma: int = -1,
+         mwhc: bool = False):
     keys = _u64(keys)
     g = Geom()
     counts = np.zeros(1 << h, np.uint32)
@@ -231,15 +247,20 @@ def plan(keys, h: int, seed: int, c: tuple | None = None, sigma: int = -1):
     rc = lib().orc_plan(keys, keys.size, h, seed, cn, cd, sigma, C.byref(g), counts)
     if rc != 0:
         raise ValueError("bad shard bits")
+    if mwhc:  # same largest shard, MWHC geometry (R11)
+        gm = Geom()
+        lib().orc_geometry_mwhc(g.M, h, cn, cd, C.byref(gm))
+        g = gm
     return g, counts
 
 
 def build(keys, values=None, *, b: int, is_filter: bool, h: int, seed: int,
           tmax: int = 255, c: tuple | None = None, sigma: int = -1,
-          shards=None) -> Built:
-    """Build the listed shards (all if None) of a VFunc / VFilter."""
+          shards=None, mwhc: bool = False) -> Built:
+    """Build the listed shards (all if None) of a VFunc / VFilter (fuse
+    graphs, or MWHC 3-partite hypergraphs with mwhc=True)."""
     keys = _u64(keys)
-    g, counts = plan(keys, h, seed, c, sigma)
+    g, counts = plan(keys, h, seed, c, sigma, mwhc)
     S = 1 << h
     sh = np.arange(S, dtype=np.uint32) if shards is None else \
         np.ascontiguousarray(np.asarray(shards, np.uint32))

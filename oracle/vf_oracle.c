@@ -45,6 +45,15 @@
  *     whose estimates section 4.2 says the paper partly adopts:
  *     c = 0.875 + 0.25 ln(10^6) / ln(max(m, 10)), rounded up to thousandths.
  *     ell = max(1, ceil(c M / s) - 2), V = (ell + 2) s.
+ *  R11 MWHC (section 4.1): a 3-partite 3-hypergraph with three parts of
+ *     ceil(c M / 3) vertices, c = 1.23 (the section's example); vertex i of
+ *     an edge is i * part + ((f_i * part) >> 21) with f_i the i-th 21-bit
+ *     field of L_t (R4).  The construction is peel-only, as in the paper:
+ *     an attempt that leaves any edge unpeeled fails (kind 2) and the shard
+ *     moves to its next local seed.  The paper bounds the shard count by
+ *     eq. (dupmwhc) because it restarts globally on a duplicate edge; with
+ *     local seeds a duplicate costs one shard's retry, so h comes from
+ *     eq. (logballsbins) alone.
  *  R7 peeling is round-synchronous: in round r every live edge that has a
  *     vertex of degree one (degrees as they stand when the round starts) is
  *     removed; its hinge is the first such vertex in edge order (its
@@ -118,6 +127,18 @@ void orc_edge(uint64_t hi, uint64_t lo, int32_t h, uint32_t l, int32_t sigma,
   uint64_t s = 1ULL << sigma;
   for (int i = 0; i < 3; i++)
     v[i] = (uint32_t)((g + (uint64_t)i) * s + ((L >> (i * sigma)) & (s - 1)));
+}
+
+/* R11: the MWHC edge of a signature (section 4.1, the 3-partite
+ * construction): vertex i lies in part i of `part` vertices, at the
+ * fixed-point image of the i-th 21-bit field of L_t (R4).  Shard bits and
+ * segments play no role. */
+void orc_edge_mwhc(uint64_t lo, uint32_t part, uint32_t t, uint32_t v[3]) {
+  uint64_t L = t == 0 ? lo : orc_mix64(lo + (uint64_t)t * GOLDEN_GAMMA);
+  for (int i = 0; i < 3; i++) {
+    uint64_t f = (L >> (21 * i)) & ((1ULL << 21) - 1);
+    v[i] = (uint32_t)((uint64_t)i * part + ((f * part) >> 21));
+  }
 }
 
 /* --------------------------------------------------------- parameter math */
@@ -237,6 +258,30 @@ void orc_geometry(uint32_t M, int32_t h, uint32_t c_num, uint32_t c_den,
   g->sigma = sigma;
   g->l = l;
   g->V = ((uint64_t)l + 2) << sigma;
+  g->mwhc = 0;
+  g->part = 0;
+}
+
+/* R11: MWHC geometry: c = 1.23 (section 4.1's example) unless given, three
+ * parts of ceil(c M / 3) vertices. */
+void orc_geometry_mwhc(uint32_t M, int32_t h, uint32_t c_num, uint32_t c_den,
+                       orc_geom *g) {
+  if (c_num == 0 || c_den == 0) {
+    c_num = 123;
+    c_den = 100;
+  }
+  uint64_t den = 3ULL * c_den;
+  uint64_t part = ((uint64_t)c_num * M + den - 1) / den;
+  if (part == 0) part = 1;
+  g->M = M;
+  g->h = h;
+  g->c_num = c_num;
+  g->c_den = c_den;
+  g->sigma = 0;
+  g->l = 1;
+  g->V = 3 * part;
+  g->mwhc = 1;
+  g->part = (uint32_t)part;
 }
 
 /* --------------------------------------------------------------- solvers */
@@ -492,6 +537,8 @@ int32_t orc_build(const uint64_t *keys, const uint64_t *values, uint64_t n,
   uint64_t *slo = (uint64_t *)malloc((M ? M : 1) * sizeof(uint64_t));
   uint64_t *srhs = (uint64_t *)malloc((M ? M : 1) * sizeof(uint64_t));
   uint32_t *e = (uint32_t *)malloc((3 * (size_t)M + 1) * sizeof(uint32_t));
+  int32_t *prd = (int32_t *)malloc(((size_t)M + 1) * sizeof(int32_t));
+  int8_t *psd = (int8_t *)malloc((size_t)M + 1);
   int32_t status = 0;
   *nrec = 0;
   uint32_t count = shards ? nshards : (uint32_t)S;
@@ -508,14 +555,26 @@ int32_t orc_build(const uint64_t *keys, const uint64_t *values, uint64_t n,
     }
     uint32_t t;
     for (t = 0; t < tmax; t++) {
-      for (uint32_t i = 0; i < m; i++)
-        orc_edge(shi[i], slo[i], g->h, g->l, g->sigma, t, &e[3 * i]);
+      for (uint32_t i = 0; i < m; i++) {
+        if (g->mwhc) orc_edge_mwhc(slo[i], g->part, t, &e[3 * i]);
+        else orc_edge(shi[i], slo[i], g->h, g->l, g->sigma, t, &e[3 * i]);
+      }
       uint32_t core = 0;
-      if (orc_solve(g->V, m, e, srhs, w, &core) == 0) break;
+      int32_t st;
+      if (g->mwhc) {
+        /* MWHC is peel-only (R11): any unpeeled edge fails the attempt */
+        orc_peel(g->V, m, e, prd, psd);
+        for (uint32_t i = 0; i < m; i++) core += prd[i] < 0;
+        st = core > 0;
+        if (!st) st = orc_solve(g->V, m, e, srhs, w, &core);
+      } else {
+        st = orc_solve(g->V, m, e, srhs, w, &core);
+      }
+      if (st == 0) break;
       if (*nrec < rec_cap) {
         rec[*nrec].shard = j;
         rec[*nrec].attempt = t;
-        rec[*nrec].kind = 1;
+        rec[*nrec].kind = g->mwhc ? 2 : 1;
         rec[*nrec].core_edges = core;
       }
       (*nrec)++;
@@ -523,6 +582,8 @@ int32_t orc_build(const uint64_t *keys, const uint64_t *values, uint64_t n,
     t_out[q] = t;
     if (t == tmax) status = 1;
   }
+  free(psd);
+  free(prd);
   free(e);
   free(srhs);
   free(slo);
@@ -554,7 +615,8 @@ void orc_query(const uint64_t *keys, uint64_t n, uint64_t seed, int32_t b,
       continue;
     }
     uint32_t v[3];
-    orc_edge(hi, lo, g->h, g->l, g->sigma, t_of_shard[j], v);
+    if (g->mwhc) orc_edge_mwhc(lo, g->part, t_of_shard[j], v);
+    else orc_edge(hi, lo, g->h, g->l, g->sigma, t_of_shard[j], v);
     const uint64_t *ws = w + (uint64_t)slot * g->V;
     uint64_t val = ws[v[0]] ^ ws[v[1]] ^ ws[v[2]];
     if (is_filter) out[i] = val == orc_fingerprint(hi, lo, sw, b);

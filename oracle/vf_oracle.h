@@ -29,14 +29,17 @@ typedef struct {
   uint32_t c_den;
   int32_t sigma;   /* segment size s = 2^sigma */
   uint32_t l;      /* number of start segments (ell) */
-  uint64_t V;      /* vertices per shard = (ell + 2) * s */
+  uint64_t V;      /* vertices per shard = (ell + 2) * s, or 3 * part */
+  uint32_t mwhc;   /* 1: MWHC 3-partite hypergraph (section 4.1) */
+  uint32_t part;   /* MWHC: vertices per part, ceil(c M / 3) */
 } orc_geom;
 
 /* One failed construction attempt of one shard. */
 typedef struct {
   uint32_t shard;
   uint32_t attempt;    /* local seed t of the attempt */
-  uint32_t kind;       /* 1 = inconsistent 2-core system */
+  uint32_t kind;       /* 1 = inconsistent 2-core system, 2 = MWHC graph
+                          not peelable */
   uint32_t core_edges; /* edges left unpeeled in that attempt */
 } orc_fail;
 
@@ -48,6 +51,7 @@ uint64_t orc_fingerprint(uint64_t hi, uint64_t lo, const uint64_t sw[3], int32_t
 uint32_t orc_shard_of(uint64_t hi, int32_t h);
 void orc_edge(uint64_t hi, uint64_t lo, int32_t h, uint32_t l, int32_t sigma,
               uint32_t t, uint32_t v[3]);
+void orc_edge_mwhc(uint64_t lo, uint32_t part, uint32_t t, uint32_t v[3]);
 
 /* parameter math */
 double orc_lambert_w0(double x);
@@ -58,6 +62,8 @@ double orc_logdupfuse(double n, double c, double eta, double alpha, double beta)
 double orc_dupfuse(double n, double c, double eta, double alpha, double beta);
 void orc_geometry(uint32_t M, int32_t h, uint32_t c_num, uint32_t c_den,
                   int32_t sigma_override, orc_geom *g);
+void orc_geometry_mwhc(uint32_t M, int32_t h, uint32_t c_num, uint32_t c_den,
+                       orc_geom *g);
 
 /* solvers on an explicit 3-hypergraph (edges e[3*i+0..2]) */
 int32_t orc_peel(uint64_t nv, uint32_t m, const uint32_t *e, int32_t *round,

@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--sigma", type=int, default=None, help="override lg segment size")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-shards", type=int, default=16)
-    p.add_argument("--workload", choices=("vfilter", "batch", "serve", "stream"),
+    p.add_argument("--workload", choices=("vfilter", "batch", "serve", "stream", "mwhc"),
                    default="vfilter",
                    help="vfilter: the sharded VFilter (default); batch: 100 000 independent "
                         "VFuncs of 10..50 000 keys in one launch per cell width, against "
@@ -329,7 +329,8 @@ def cpu_baseline(args) -> dict:
     k_np = keys.numpy().view(np.uint64)
     q_np = q.numpy().view(np.uint64)
     t0 = time.perf_counter()
-    built = O.build(k_np, b=args.b, is_filter=True, h=h_s, seed=args.seed)
+    built = O.build(k_np, b=args.b, is_filter=True, h=h_s, seed=args.seed,
+                    mwhc=args.workload == "mwhc")
     t1 = time.perf_counter()
     O.query(built, q_np)
     t2 = time.perf_counter()
@@ -359,6 +360,9 @@ def main():
     if args.workload == "stream":
         stream_main(args)
         return
+    mwhc = args.workload == "mwhc"
+    if mwhc and args.eps == 0.0175:
+        args.eps = 0.01  # section 4.1 sets epsilon = 0.01 for MWHC
     import torch
     import synthetic as S
     import paper_2503_18397_amd as vf
@@ -371,7 +375,7 @@ def main():
     queries, is_member = S.queries(keys, Q, args.data_seed)
     n_neg = int((~is_member).sum().item())
     out = torch.empty(Q, dtype=torch.uint8, device=dev)
-    opts = vf.vf_default_opts(sigma=args.sigma)
+    opts = vf.vf_default_opts(sigma=args.sigma, mwhc=int(mwhc))
     sz = vf.vf_plan(n, args.b, args.eps, True, opts)
     ws = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=dev)
     st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
@@ -422,7 +426,7 @@ def main():
         "k_scatter": {"ms": k_scatter_ms, "bytes": 8 * n + 8 * n},
     }
     for name, k in kern.items():
-        k["traffic"] = pmc_traffic(name)
+        k["traffic"] = None if mwhc else pmc_traffic(name)
         k["GB/s"] = round(k["bytes"] / (k["ms"] * 1e-3) / 1e9, 2) if k["ms"] > 0 else None
         k["frac"] = round(k["GB/s"] / HBM_PEAK_GBS, 5) if k["GB/s"] else None
     dom = "k_build" if k_build_ms >= query_ms else "k_query"
@@ -443,8 +447,11 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "VFilter b=8, n=2^27 uint64 keys, h=11 (2048 shards of ~2^16 keys), "
-                               "2^30 queries (50% members)",
+        "config": {"workload": (f"VFilter b={args.b}, n=2^{args.log2n} uint64 keys, "
+                                f"{'MWHC 3-partite hypergraphs' if mwhc else 'fuse graphs'}, "
+                                f"eps={args.eps} (h={info['h']}, {info['S']} shards of "
+                                f"~{n // max(info['S'], 1)} keys), 2^{args.log2q} queries "
+                                "(50% members)"),
                    "n": n, "queries": Q, "b": args.b, "eps": args.eps, "h": info["h"],
                    "M": info["M"], "sigma": info["sigma"], "l": info["l"], "V": V,
                    "c": f"{info['c_num']}/{info['c_den']}", "parallelism": "1 GPU"},
@@ -456,7 +463,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5) if achieved else None,
-                     "traffic": pmc_traffic(dom)},
+                     "traffic": None if mwhc else pmc_traffic(dom)},
         "kernels": kern,
     }
     if not args.no_cpu_baseline:

@@ -64,6 +64,10 @@ typedef struct vf_opts {
   uint32_t c_den;
   uint32_t tmax;      /* local seeds tried per shard, 1..255 (default 255) */
   double alpha;       /* Raab-Steger constant of eq. (ballsbins) (1.0)    */
+  int32_t mwhc;       /* 1: MWHC 3-partite hypergraphs (section 4.1): three
+                         parts of ceil(c M / 3) cells, c = 1.23 by default,
+                         peel-only (an attempt that does not peel fails, kind
+                         2); keys must be distinct.  0: fuse graphs. */
 } vf_opts;
 
 /* Sizes returned by vf_plan (upper bounds: the largest shard is known only
@@ -100,13 +104,15 @@ typedef struct vf_info_t {
    * CU's LDS and were rebuilt by a second launch with a whole CU's LDS
    * (same result, slower). */
   uint32_t relaunched_shards;
+  int32_t mwhc;           /* 1: MWHC hypergraphs (sigma 0, l 1, V = 3 parts) */
 } vf_info_t;
 
 /* One failed construction attempt of one shard. */
 typedef struct vf_failure {
   uint32_t shard;
   uint32_t attempt;    /* local seed t */
-  uint32_t kind;       /* 1 = the 2-core system was inconsistent */
+  uint32_t kind;       /* 1 = the 2-core system was inconsistent,
+                          2 = an MWHC hypergraph did not peel        */
   uint32_t core_edges; /* edges left by peeling in that attempt  */
 } vf_failure;
 

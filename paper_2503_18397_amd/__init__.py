@@ -32,7 +32,8 @@ class VFError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("h", C.c_int32), ("sigma", C.c_int32), ("c_num", C.c_uint32),
-                ("c_den", C.c_uint32), ("tmax", C.c_uint32), ("alpha", C.c_double)]
+                ("c_den", C.c_uint32), ("tmax", C.c_uint32), ("alpha", C.c_double),
+                ("mwhc", C.c_int32)]
 
 
 class Sizes(C.Structure):
@@ -49,7 +50,7 @@ class Info(C.Structure):
                 ("n_failures", C.c_uint32), ("space_bits", C.c_uint64),
                 ("cells", C.c_void_p), ("local_seeds", C.c_void_p),
                 ("ms_count", C.c_float), ("ms_scatter", C.c_float), ("ms_build", C.c_float),
-                ("relaunched_shards", C.c_uint32)]
+                ("relaunched_shards", C.c_uint32), ("mwhc", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -272,9 +273,10 @@ class Structure:
     @classmethod
     def build(cls, keys: torch.Tensor, values: torch.Tensor | None = None, *, b: int,
               eps: float = 0.0, seed: int = 0, h: int | None = None, sigma: int | None = None,
-              c: tuple | None = None, tmax: int | None = None, stream=None):
+              c: tuple | None = None, tmax: int | None = None, mwhc: bool = False,
+              stream=None):
         is_filter = values is None
-        opts = vf_default_opts(h=h, sigma=sigma, tmax=tmax)
+        opts = vf_default_opts(h=h, sigma=sigma, tmax=tmax, mwhc=int(mwhc))
         if c is not None:
             opts.c_num, opts.c_den = c
         sz = vf_plan(keys.numel(), b, eps, is_filter, opts)

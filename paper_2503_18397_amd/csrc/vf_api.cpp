@@ -50,7 +50,30 @@ struct Geometry {
   uint32_t M, c_num, c_den, l;
   int32_t sigma;
   uint64_t V;
+  uint32_t mwhc = 0, part = 0;  // MWHC: 3 parts of `part` vertices
 };
+
+// Section 4.1: MWHC 3-partite hypergraphs, c = 1.23 unless given, three
+// parts of ceil(c M / 3) vertices (sigma 0 and l 1 are placeholders).
+Geometry geometry_mwhc(uint32_t M, uint32_t cn, uint32_t cd) {
+  if (cn == 0 || cd == 0) {
+    cn = 123;
+    cd = 100;
+  }
+  const uint64_t den = 3ull * cd;
+  uint64_t part = ((uint64_t)cn * M + den - 1) / den;
+  if (part == 0) part = 1;
+  Geometry g;
+  g.M = M;
+  g.c_num = cn;
+  g.c_den = cd;
+  g.l = 1;
+  g.sigma = 0;
+  g.V = 3 * part;
+  g.mwhc = 1;
+  g.part = (uint32_t)std::min<uint64_t>(part, 0xFFFFFFFFull);
+  return g;
+}
 
 // Section 4.2: c = 1.12 for shards below 800 000 keys (solved with Gaussian
 // elimination of the 2-core), c = 1.105 with lg s from eq. (nln) for larger
@@ -176,7 +199,10 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   l.h = h;
   l.S = 1u << h;
   l.cap = shard_cap(n, l.S);
-  l.gcap = geometry(l.cap, h, o.c_num, o.c_den, o.sigma);
+  if (o.mwhc) {
+    l.gcap = geometry_mwhc(l.cap, o.c_num, o.c_den);
+  } else {
+    l.gcap = geometry(l.cap, h, o.c_num, o.c_den, o.sigma);
   // the rule for c and s changes at 2^16 and 800 000 keys: size buffers for
   // the larger side of each change, plus one spare segment
   for (uint32_t edge : {65535u, 799999u}) {
@@ -195,6 +221,7 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
     if (gk.l > l.gcap.l) l.gcap.l = gk.l;
   }
   l.gcap.l += l.gcap.l / 8 + 8;
+  }
   l.cell_bytes = cell_bytes_for(b);
   uint32_t per_cu, lds_bytes;
   build_occupancy(l.gcap.sigma, &per_cu, &lds_bytes);
@@ -203,7 +230,8 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   per_cu = std::max<uint32_t>(per_cu, 4);
   l.nwg = (uint32_t)std::max<uint64_t>(
       1, std::min<uint64_t>((uint64_t)per_cu * (ncu > 0 ? ncu : 256), l.S));
-  l.logcap = 16u * l.cap + 4096u;
+  // pivot log of the 2-core elimination (MWHC never eliminates)
+  l.logcap = o.mwhc ? 4096u : 16u * l.cap + 4096u;
   // scratch is sized for the largest shard the buffers allow, with the
   // geometry of that size (the actual geometry is never larger)
   l.scratch_stride =
@@ -372,6 +400,7 @@ void vf_default_opts(vf_opts *o) {
   o->c_den = 0;
   o->tmax = 255;
   o->alpha = 1.0;
+  o->mwhc = 0;
 }
 
 int vf_plan(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts *o,
@@ -480,7 +509,8 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   HIPCHK(hipStreamSynchronize(stream));
   const uint32_t M = hmeta[0];
   if (M > L.cap) return VF_ENOSPC;
-  const Geometry g = geometry(M, L.h, op.c_num, op.c_den, op.sigma);
+  const Geometry g =
+      op.mwhc ? geometry_mwhc(M, op.c_num, op.c_den) : geometry(M, L.h, op.c_num, op.c_den, op.sigma);
   if (g.V > kMaxCells) return VF_ECAPACITY;
   if ((uint64_t)L.S * g.V * L.cell_bytes > L.cells_bytes ||
       vfk::build_scratch_bytes(M, g.V, g.l, L.logcap) > L.scratch_stride)
@@ -505,6 +535,8 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   A.G.sigma = (uint32_t)g.sigma;
   A.G.b = (uint32_t)b;
   A.G.is_filter = (uint32_t)is_filter;
+  A.G.mwhc = g.mwhc;
+  A.G.part = g.part;
   A.bkeys = bkeys;
   A.bvals = bvals;
   A.offsets = offsets;
@@ -878,6 +910,7 @@ int vf_info(const vf_handle *h, vf_info_t *out) {
   out->ms_scatter = h->ms[1];
   out->ms_build = h->ms[2];
   out->relaunched_shards = h->relaunched;
+  out->mwhc = (int32_t)h->g.mwhc;
   return VF_OK;
 }
 

@@ -14,6 +14,9 @@
 //  * offsets = three sigma-bit fields of the second word (local seed t = 0)
 //    or of fin(second word + t * golden gamma) (t > 0);
 //  * fingerprint = top b bits of fin(hi ^ lo ^ k_fp);
+//  * MWHC (section 4.1): three parts of `part` vertices, vertex i the
+//    fixed-point image of the i-th 21-bit field of the offset word; an
+//    attempt that does not peel completely fails (peel-only);
 //  * peeling is round-synchronous (degrees frozen at the start of a round,
 //    hinge = first degree-one vertex of the edge);
 //  * the 2-core system gets its lexicographically smallest solution
@@ -43,9 +46,18 @@ __device__ __forceinline__ uint32_t shard_of(uint64_t hi, uint32_t h) {
 
 // Fuse 3-graph edge of a signature: one vertex in each of the segments
 // g, g + 1, g + 2 of the shard.
+// MWHC (section 4.1): one vertex in each of three parts, the fixed-point
+// image of a 21-bit field of the offset word.
 __device__ __forceinline__ void edge3(const Geo &G, uint64_t hi, uint64_t lo,
                                       uint32_t t, uint32_t &v0, uint32_t &v1,
                                       uint32_t &v2) {
+  if (G.mwhc) {
+    const uint64_t L = t ? fin64(lo + (uint64_t)t * kGamma) : lo, p = G.part;
+    v0 = (uint32_t)(((L & 0x1FFFFFull) * p) >> 21);
+    v1 = (uint32_t)(p + ((((L >> 21) & 0x1FFFFFull) * p) >> 21));
+    v2 = (uint32_t)(2 * p + ((((L >> 42) & 0x1FFFFFull) * p) >> 21));
+    return;
+  }
   uint32_t F = (uint32_t)((hi << G.h) >> 32);
   uint32_t g = __umulhi(F, G.l);
   uint64_t L = t ? fin64(lo + (uint64_t)t * kGamma) : lo;
@@ -266,10 +278,11 @@ __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__r
 
 // ------------------------------------------------------------- shard build
 //
-// One wavefront builds one shard at a time, from its keys to its cells; a
-// workgroup is that single wavefront and several workgroups share a CU.
-// Vertex state for peeling lives in global memory (cached in L2), the
-// elimination window and (when they fit) the shard's cells live in LDS.
+// A workgroup of two wavefronts builds one shard at a time, from its keys
+// to its cells, and several workgroups share a CU (as many as the LDS of
+// their elimination windows allows).  Vertex state for peeling lives in
+// global memory (cached in L2), the elimination window and (when they fit)
+// the shard's cells live in LDS.
 
 // Per-workgroup scratch (global memory), sized for the largest shard.
 // Edges, right sides and the peeling order are kept twice: the assignment
@@ -391,7 +404,8 @@ enum { kSolveOk = 0, kSolveInconsistent = 1, kSolveCapacity = 2 };
 struct BandCtl {
   uint32_t shard, t0, core, np;  // work item, core rows, pivots emitted
   uint32_t rounds;               // peeling rounds
-  uint32_t dup;                  // 1: two core rows contradict each other
+  uint32_t dup;                  // 1: two core rows contradict each other,
+                                 // 2: an MWHC hypergraph did not peel
   uint32_t flag[2];              // kSolveInconsistent | kSolveCapacity
   uint32_t adv[2];               // 0: the word is taken again (window full)
   uint32_t k[2], gs[2];          // pivots of each batch and its segment
@@ -1102,36 +1116,47 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
           nxt = tmp;
         }
 
-        // 2-core edges, grouped by the entry group of their top vertex
-        const uint32_t gsh = entry_shift(G.sigma);
-        const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
-        for (uint32_t g = lane; g < ngroups; g += 64) sc.cc[g] = 0;
-        wave_sync_global();
-        for (uint32_t i = lane; i < m; i += 64)
-          if (!sc.pe[i]) atomicAdd(&sc.cc[(uint32_t)(E[i] >> 42) >> gsh], 1u);
-        wave_sync_global();
-        const uint32_t k = wave_scan_array(sc.cc, sc.cb, ngroups);
-        wave_sync_global();
-        for (uint32_t i = lane; i < m; i += 64)
-          if (!sc.pe[i]) {
-            const uint64_t e = E[i];
-            const uint32_t pos = atomicAdd(&sc.cc[(uint32_t)(e >> 42) >> gsh], 1u);
-            sc.cE[pos] = e;
-            sc.cR[pos] = R[i];
-          }
-        wave_sync_global();
-        // two 2-core rows with the same vertices and different right sides
-        // (the usual reason for an inconsistent system) end the attempt
-        // before the elimination: rows are listed by top vertex in the
-        // degree array, which peeling no longer needs
+        // 2-core edges, grouped by the entry group of their top vertex (an
+        // MWHC hypergraph is peel-only: only its unpeeled edges are counted)
+        uint32_t k;
+        if (G.mwhc) {
+          uint32_t left = 0;
+          for (uint32_t i = lane; i < m; i += 64) left += sc.pe[i] ? 0u : 1u;
+          k = wave_sum(left);
+        } else {
+          const uint32_t gsh = entry_shift(G.sigma);
+          const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
+          for (uint32_t g = lane; g < ngroups; g += 64) sc.cc[g] = 0;
+          wave_sync_global();
+          for (uint32_t i = lane; i < m; i += 64)
+            if (!sc.pe[i]) atomicAdd(&sc.cc[(uint32_t)(E[i] >> 42) >> gsh], 1u);
+          wave_sync_global();
+          k = wave_scan_array(sc.cc, sc.cb, ngroups);
+          wave_sync_global();
+          for (uint32_t i = lane; i < m; i += 64)
+            if (!sc.pe[i]) {
+              const uint64_t e = E[i];
+              const uint32_t pos = atomicAdd(&sc.cc[(uint32_t)(e >> 42) >> gsh], 1u);
+              sc.cE[pos] = e;
+              sc.cR[pos] = R[i];
+            }
+          wave_sync_global();
+        }
+        // MWHC is peel-only: any unpeeled edge ends the attempt (kind 2).
+        // Otherwise two 2-core rows with the same vertices and different
+        // right sides (the usual reason for an inconsistent system) end the
+        // attempt before the elimination: rows are listed by top vertex in
+        // the degree array, which peeling no longer needs
+        const uint32_t kl = G.mwhc ? 0u : k;
         uint32_t *const head = sc.deg, *const next = sc.F0;
-        for (uint64_t v = lane; v < V; v += 64) head[v] = 0xFFFFFFFFu;
+        if (kl)
+          for (uint64_t v = lane; v < V; v += 64) head[v] = 0xFFFFFFFFu;
         wave_sync_global();
-        for (uint32_t i = lane; i < k; i += 64)
+        for (uint32_t i = lane; i < kl; i += 64)
           next[i] = atomicExch(&head[(uint32_t)(sc.cE[i] >> 42)], i);
         wave_sync_global();
         bool clash = false;
-        for (uint32_t i = lane; i < k; i += 64) {
+        for (uint32_t i = lane; i < kl; i += 64) {
           const uint64_t e = sc.cE[i], r = sc.cR[i];
           for (uint32_t x = next[i]; x != 0xFFFFFFFFu; x = next[x])
             clash |= sc.cE[x] == e && sc.cR[x] != r;
@@ -1140,18 +1165,18 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         if (lane == 0) {
           ctl->core = k;
           ctl->rounds = nrounds;
-          ctl->dup = dup ? 1u : 0u;
+          ctl->dup = G.mwhc && k ? 2u : (dup ? 1u : 0u);
         }
       }
       __syncthreads();
       const uint32_t k = ctl->core;
       nrounds = ctl->rounds;
-      const bool dup = ctl->dup != 0;
+      const uint32_t early = ctl->dup;  // 1: contradicting rows, 2: MWHC did not peel
       __syncthreads();  // both have read the block before wavefront 0 rewrites it
 
       uint32_t np = 0;
-      const int st = dup ? kSolveInconsistent
-                         : (k ? band_solve<QM>(A, G, W, sc, lds, ctl, wid, &np) : kSolveOk);
+      const int st = early ? kSolveInconsistent
+                           : (k ? band_solve<QM>(A, G, W, sc, lds, ctl, wid, &np) : kSolveOk);
       if (st == kSolveCapacity) {
         if (wid == 0 && lane == 0) {
           if (A.overflow) {
@@ -1168,7 +1193,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       if (st == kSolveInconsistent) {
         if (wid == 0 && lane == 0) {
           const uint32_t idx = atomicAdd(&A.work[kWorkFails], 1u);
-          if (idx < A.fail_cap) A.fails[idx] = FailRec{j, t, 1u, k};
+          if (idx < A.fail_cap) A.fails[idx] = FailRec{j, t, early == 2 ? 2u : 1u, k};
         }
         continue;
       }

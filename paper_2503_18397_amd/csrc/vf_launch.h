@@ -18,6 +18,8 @@ struct Geo {
   uint32_t sigma;          // lg segment size
   uint32_t b;              // value / fingerprint bits
   uint32_t is_filter;
+  uint32_t mwhc;           // 1: MWHC 3-partite hypergraph (peel-only)
+  uint32_t part;           // MWHC: vertices per part
 };
 
 // One instance of a batch: an unsharded structure with its own keys,
@@ -91,8 +93,9 @@ constexpr uint32_t kLdsBudget = 160 * 1024;  // LDS of one CU
 // Bytes at the end of a build workgroup's dynamic LDS that hold the control
 // block shared by its two wavefronts and the back-substitution columns.
 constexpr uint32_t kLdsTail = 2048;
-// Threads of a build workgroup: one wavefront eliminates, the other emits
-// the pivot rows of the previous word.
+// Threads of a build workgroup: one wavefront peels and eliminates, the
+// other emits the pivot rows of the previous word and assigns the cells of
+// the previous shard.
 constexpr uint32_t kBuildThreads = 128;
 
 uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap);

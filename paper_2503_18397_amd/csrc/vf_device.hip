@@ -110,6 +110,10 @@ constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E, kRowHalfMirror = 0x141, kRow
 __device__ __forceinline__ uint32_t readlane(uint32_t x, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
 }
+// A value the whole wavefront holds alike, kept in a scalar register.
+__device__ __forceinline__ uint32_t uniform(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
 __device__ __forceinline__ uint64_t readlane64(uint64_t x, int lane) {
   return (uint64_t)readlane((uint32_t)x, lane) | ((uint64_t)readlane((uint32_t)(x >> 32), lane) << 32);
 }
@@ -394,6 +398,10 @@ uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes) {
 
 enum { kSolveOk = 0, kSolveInconsistent = 1, kSolveCapacity = 2 };
 
+// A group count known at compile time (the elimination is instantiated per
+// count so that its per-group work unrolls without run-time guards).
+template <int N> struct Groups { static constexpr int value = N; };
+
 // Control block in LDS shared by the two wavefronts of a build workgroup.
 // The pivots found in one 32-column word travel from the eliminating
 // wavefront to the emitting one as a batch; the emitter hands the slots of
@@ -412,7 +420,6 @@ struct BandCtl {
   uint32_t nq[2];                // slot groups in use during the batch's word
   uint32_t nret[2];
   uint32_t slot[2][32], col[2][32], cm[2][32];
-  uint64_t rhs[2][32];
   uint16_t ret[2][64];           // slots handed back to wavefront 0
 };
 static_assert(sizeof(BandCtl) + kBcolBytes <= kLdsTail, "LDS tail too small");
@@ -461,7 +468,12 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   uint64_t *rrhs = (uint64_t *)(lds + (uint64_t)4 * RS * W);
   uint16_t *rpop = (uint16_t *)(rrhs + W);
   uint16_t *freel = rpop + W;
-  const uint32_t NW = (RW + 63) / 64;  // ring words per lane
+  const uint32_t NW = (RW + 2 + 63) / 64;  // row words and the right side, per lane
+  // Word u of the row in slot x is rows[x * umul(u) + uadd(u)]: words below
+  // RW are ring words, words RW and RW + 1 the low and high half of the
+  // right side, so one pass over u combines rows and right sides together.
+  auto umul = [&](uint32_t u) { return u < RW ? RS : 2u; };
+  auto uadd = [&](uint32_t u) { return u < RW ? u : RS * W + (u - RW); };
 
   // free slots form a stack that hands out low slots first; only slot groups
   // below the high-water mark are ever scanned
@@ -514,25 +526,30 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
     const uint32_t pivtab = lane < kp ? ctl->slot[bsel][lane] : 0u;
     const uint32_t pivcol = lane < kp ? ctl->col[bsel][lane] : 0u;
     const uint32_t pivcm = lane < kp ? ctl->cm[bsel][lane] : 0u;
-    const uint64_t pivrhs = lane < kp ? ctl->rhs[bsel][lane] : 0ull;
     for (int kk = (int)kp - 1; kk >= 0; kk--) {
       const uint32_t x = readlane(pivtab, kk);
       const uint32_t col = readlane(pivcol, kk);
       const uint32_t cmx = readlane(pivcm, kk);
-      const uint64_t prhs = readlane64(pivrhs, kk);
-      const uint32_t *xrow = rows + (uint64_t)x * RS;
       const uint32_t cb_ = ring.pos(col);
+      if (lp + 4 > logcap) return false;
       uint32_t pos = lp + 4;
       for (uint32_t w = 0; w < NW; w++) {
         const uint32_t u = w * 64 + lane;
         uint32_t bits = 0;
-        if (u < RW) {
-          bits = xrow[u];
+        if (u < RW + 2) {
+          // the pivot row as it was chosen: its row at the start of the word
+          // plus the earlier pivots of the word it absorbed
+          const uint32_t mu = umul(u), au = uadd(u);
+          bits = rows[x * mu + au];
           for (uint32_t cb2 = cmx; cb2; cb2 &= cb2 - 1) {
             const uint32_t j = __ffs(cb2) - 1;
-            bits ^= rows[(uint64_t)readlane(pivtab, (int)j) * RS + u];
+            bits ^= rows[readlane(pivtab, (int)j) * mu + au];
           }
           if (u == (cb_ >> 5)) bits &= ~(1u << (cb_ & 31));
+          if (u >= RW) {
+            plog[lp + 2 + (u - RW)] = bits;  // right side, low word first
+            bits = 0;
+          }
         }
         for (;;) {
           const uint64_t m = __ballot(bits != 0);
@@ -549,8 +566,6 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       if (lane == 0) {
         plog[lp] = col;
         plog[lp + 1] = pos - (lp + 4);
-        plog[lp + 2] = (uint32_t)prhs;
-        plog[lp + 3] = (uint32_t)(prhs >> 32);
         poff[np + (uint32_t)kk] = lp;
         ctl->ret[rsel][kk] = (uint16_t)x;
       }
@@ -562,7 +577,6 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   };
 
   uint32_t cw[QM], pop[QM], cm[QM];
-  uint64_t rh[QM];
   uint32_t it = 0;
   bool stop = false;
   for (int Gs = (int)G.l + 1; Gs >= 0 && !stop; Gs--) {
@@ -579,13 +593,12 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       const uint32_t wbase = c - (cpos & 31);  // column of bit 0 of this word
       const uint32_t wlo_col = max(segbot, wbase);
       const uint32_t cur = it & 1u, prev = cur ^ 1u;
-      // lane k of pivtab/pivcol/pivcm/pivrhs describes pivot k of the word;
-      // bit q of pivbits marks the lane's slot of group q as a pivot row
+      // lane k of pivtab/pivcol/pivcm describes pivot k of the word; bit q
+      // of pivbits marks the lane's slot of group q as a pivot row
       uint32_t pivtab = 0, pivcol = 0, pivcm = 0, pivbits = 0;
-      uint64_t pivrhs = 0;
       if (wid == 0) {
         // slots emitted during the previous word come back
-        const uint32_t nr = ctl->nret[prev];
+        const uint32_t nr = uniform(ctl->nret[prev]);
         if (lane < nr) freel[nfree + lane] = (uint16_t)ctl->ret[prev][lane];
         nfree += nr;
         wave_sync();
@@ -610,105 +623,104 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           const uint32_t lowbit = wlo_col - wbase, hibit = cpos & 31;
           const uint32_t range = (hibit >= 31 ? 0xFFFFFFFFu : ((2u << hibit) - 1u)) &
                                  ~((1u << lowbit) - 1u);
-          // register caches of this word (all loads issued together)
-          uint32_t orv = 0;
+          // the word's pivots with the slot groups in use fixed at compile time
+          auto pivots = [&](auto groups) {
+            constexpr int NG = decltype(groups)::value;
+            // register caches of this word (all loads issued together)
+            uint32_t orv = 0;
 #pragma unroll
-          for (int q = 0; q < QM; q++) {
-            if ((uint32_t)q >= NQ) break;
-            const uint32_t slot = (uint32_t)q * 64 + lane;
-            const bool in = (uint32_t)q < NQ && slot < W;
-            const uint32_t sl = in ? slot : 0u;
-            pop[q] = rpop[sl];
-            cw[q] = rows[(uint64_t)sl * RS + word];
-            rh[q] = rrhs[sl];
-            if (!in) pop[q] = 0;
-            cw[q] = pop[q] ? cw[q] & range : 0u;
-            cm[q] = 0;
-            orv |= cw[q];
-          }
-          // 1. pivots of the word's columns, top down, on the register words
-          //    only: cm records which of this word's pivot rows (by index k) a
-          //    row has absorbed; lane k of pivtab/pivcol/pivcm/pivrhs
-          //    describes pivot k
-          uint32_t colmask = wave_or(orv);
-          while (colmask) {
-            const uint32_t b = 31 - __clz(colmask);
-            uint64_t cand[QM];
-            uint32_t best = 0xFFFFFFFFu;
-#pragma unroll
-            for (int q = 0; q < QM; q++) {
-              if ((uint32_t)q >= NQ) break;
-              const bool has = (cw[q] >> b) & 1u;
-              cand[q] = __ballot(has);
-              if (has) best = min(best, (min(pop[q], 0xFFFFu) << 16) | ((uint32_t)q * 64 + lane));
-            }
-            best = wave_min(best);
-            const uint32_t p = best & 0xFFFFu, pq = p >> 6, pl = p & 63u;
-            const uint32_t ppop = best >> 16;
-            uint32_t pw = 0, pcm = 0;
-            uint64_t prhs = 0;
-#pragma unroll
-            for (int q = 0; q < QM; q++) {
-              if ((uint32_t)q >= NQ) break;
-              if ((uint32_t)q == pq) {
-                pw = readlane(cw[q], (int)pl);
-                pcm = readlane(cm[q], (int)pl);
-                prhs = readlane64(rh[q], (int)pl);
-              }
-            }
-            if (lane == k) {
-              pivtab = p;
-              pivcol = wbase + b;
-              pivcm = pcm;
-              pivrhs = prhs;
-            }
-            const uint32_t kbit = pcm | (1u << k);
-#pragma unroll
-            for (int q = 0; q < QM; q++) {
-              if ((uint32_t)q >= NQ) break;
-              const bool isp = (uint32_t)q == pq && lane == pl;
-              if (((cand[q] >> lane) & 1ull) && !isp) {
-                cw[q] ^= pw;
-                cm[q] ^= kbit;
-                rh[q] ^= prhs;
-                pop[q] = min(pop[q] + ppop - 2u, 0xFFFFu);
-              }
-              if (isp) {
-                cw[q] = 0;
-                pop[q] = 0;
-                pivbits |= 1u << q;
-              }
-            }
-            k++;
-            orv = 0;
-#pragma unroll
-            for (int q = 0; q < QM; q++) {
-              if ((uint32_t)q >= NQ) break;
+            for (int q = 0; q < NG; q++) {
+              const uint32_t slot = (uint32_t)q * 64 + lane;
+              const uint32_t sl = slot < W ? slot : 0u;
+              pop[q] = rpop[sl];
+              cw[q] = rows[(uint64_t)sl * RS + word];
+              if (slot >= W) pop[q] = 0;
+              cw[q] = pop[q] ? cw[q] & range : 0u;
+              cm[q] = 0;
               orv |= cw[q];
             }
-            colmask = wave_or(orv) & ((1u << b) - 1u);
-          }
-          if (k) {
-            // popcount estimates and right sides (final after phase 1) back
-            // to LDS; the combination masks of the odd slot groups go to the
-            // rows' padding words for wavefront 1
+            // 1. pivots of the word's columns, top down, on the register
+            //    words only: cm records which of this word's pivot rows (by
+            //    index k) a row has absorbed; lane k of pivtab/pivcol/pivcm
+            //    describes pivot k.  Right sides follow in the passes over
+            //    whole rows.  The pivot row itself takes part in its own
+            //    update (its word becomes zero, so it is never a candidate
+            //    again); pivbits marks it, and its popcount and mask are
+            //    dropped when they go back to LDS.
+            uint32_t colmask = wave_or(orv);
+            while (colmask) {
+              const uint32_t b = 31 - __clz(colmask), bit = 1u << b;
+              bool has[NG];
+              uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
-            for (int q = 0; q < QM; q++) {
-              if ((uint32_t)q >= NQ) break;
-              const uint32_t slot = (uint32_t)q * 64 + lane;
-              if (slot < W) {
-                rpop[slot] = (uint16_t)pop[q];
-                rrhs[slot] = rh[q];
-                if (q & 1) rows[(uint64_t)slot * RS + RW] = (pivbits >> q) & 1u ? 0u : cm[q];
+              for (int q = 0; q < NG; q++) {
+                has[q] = (cw[q] & bit) != 0;
+                // popcount estimates stay below 2^16
+                const uint32_t key = (pop[q] << 16) | ((uint32_t)q * 64 + lane);
+                best = min(best, has[q] ? key : 0xFFFFFFFFu);
+              }
+              best = wave_min(best);
+              const uint32_t p = best & 0xFFFFu, pq = p >> 6, pl = p & 63u;
+              const uint32_t dpop = (best >> 16) - 2u;
+              uint32_t pw = 0, pcm = 0;
+#pragma unroll
+              for (int q = 0; q < NG; q++) {
+                if ((uint32_t)q == pq) {
+                  pw = readlane(cw[q], (int)pl);
+                  pcm = readlane(cm[q], (int)pl);
+                }
+              }
+              if (lane == k) {
+                pivtab = p;
+                pivcol = wbase + b;
+                pivcm = pcm;
+              }
+              if (lane == pl) pivbits |= 1u << pq;
+              const uint32_t kbit = pcm | (1u << k);
+              orv = 0;
+#pragma unroll
+              for (int q = 0; q < NG; q++) {
+                if (has[q]) {
+                  cw[q] ^= pw;
+                  cm[q] ^= kbit;
+                  pop[q] = min(pop[q] + dpop, 0xFFFFu);
+                }
+                orv |= cw[q];
+              }
+              k++;
+              colmask = wave_or(orv) & (bit - 1u);
+            }
+            if (k) {
+              // popcount estimates back to LDS (zero marks a pivot row, no
+              // longer live in the window); the combination masks of the odd
+              // slot groups go to the rows' padding words for wavefront 1
+#pragma unroll
+              for (int q = 0; q < NG; q++) {
+                const uint32_t slot = (uint32_t)q * 64 + lane;
+                const bool piv = (pivbits >> q) & 1u;
+                if (slot < W) {
+                  rpop[slot] = piv ? (uint16_t)0 : (uint16_t)pop[q];
+                  if (q & 1) rows[(uint64_t)slot * RS + RW] = piv ? 0u : cm[q];
+                }
+              }
+              // the batch for wavefront 1
+              if (lane < k) {
+                ctl->slot[cur][lane] = pivtab;
+                ctl->col[cur][lane] = pivcol;
+                ctl->cm[cur][lane] = pivcm;
               }
             }
-            // the batch for wavefront 1
-            if (lane < k) {
-              ctl->slot[cur][lane] = pivtab;
-              ctl->col[cur][lane] = pivcol;
-              ctl->cm[cur][lane] = pivcm;
-              ctl->rhs[cur][lane] = pivrhs;
-            }
+          };
+          switch (uniform(NQ)) {
+            case 1: pivots(Groups<1>{}); break;
+            case 2: pivots(Groups<2>{}); break;
+            case 3: pivots(Groups<3>{}); break;
+            case 4: pivots(Groups<4>{}); break;
+            case 5: pivots(Groups<5>{}); break;
+            case 6: pivots(Groups<6>{}); break;
+            case 7: if constexpr (QM >= 7) pivots(Groups<7>{}); break;
+            case 8: if constexpr (QM >= 8) pivots(Groups<8>{}); break;
+            default: break;
           }
         }
         if (lane == 0) {
@@ -731,26 +743,30 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       // 2. whole rows: every non-pivot row that absorbed pivots of this word
       //    gets their rows (as they were when the word started) xored in;
       //    wavefront 0 takes the even slot groups (masks in registers),
-      //    wavefront 1 the odd ones (masks in the rows' padding words).  A row
-      //    that becomes zero is dead (inconsistent if its right side is not
-      //    zero); its slot goes back to the free list.
+      //    wavefront 1 the odd ones (masks in the rows' padding words).  The
+      //    right sides go along.  A row that becomes zero is dead
+      //    (inconsistent if its right side is not zero); its slot goes back
+      //    to the free list.
       if (const uint32_t kc = ctl->k[cur]) {
         const uint32_t ptab = wid == 0 ? pivtab : (lane < kc ? ctl->slot[cur][lane] : 0u);
-        auto apply = [&](uint32_t x, uint32_t cmx) -> bool {
-          uint32_t *xrow = rows + (uint64_t)x * RS;
-          uint32_t any = 0;
+        // true if the row became zero; rset: its right side is not zero
+        auto apply = [&](uint32_t x, uint32_t cmx, bool &rset) -> bool {
+          uint32_t any = 0, rany = 0;
           for (uint32_t w = 0; w < NW; w++) {
             const uint32_t u = w * 64 + lane;
-            if (u < RW) {
-              uint32_t acc = xrow[u];
+            if (u < RW + 2) {
+              const uint32_t mu = umul(u), au = uadd(u);
+              uint32_t acc = rows[x * mu + au];
               for (uint32_t bits = cmx; bits; bits &= bits - 1) {
                 const uint32_t j = __ffs(bits) - 1;
-                acc ^= rows[(uint64_t)readlane(ptab, (int)j) * RS + u];
+                acc ^= rows[readlane(ptab, (int)j) * mu + au];
               }
-              xrow[u] = acc;
-              any |= acc;
+              rows[x * mu + au] = acc;
+              if (u < RW) any |= acc;
+              else rany |= acc;
             }
           }
+          rset = __ballot(rany != 0) != 0;
           return __ballot(any != 0) == 0;
         };
         bool incons = false;
@@ -763,8 +779,9 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
               const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
               m &= m - 1;
               const uint32_t x = (uint32_t)q * 64 + xl;
-              if (apply(x, readlane(cm[q], (int)xl))) {
-                incons |= readlane64(rh[q], (int)xl) != 0;
+              bool rset;
+              if (apply(x, readlane(cm[q], (int)xl), rset)) {
+                incons |= rset;
                 if (lane == 0) {
                   rpop[x] = 0;
                   freel[nfree] = (uint16_t)x;
@@ -784,8 +801,9 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
               const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
               m &= m - 1;
               const uint32_t x = q * 64 + xl;
-              if (apply(x, readlane(cmv, (int)xl))) {
-                incons |= rrhs[x] != 0;
+              bool rset;
+              if (apply(x, readlane(cmv, (int)xl), rset)) {
+                incons |= rset;
                 if (lane == 0) {
                   rpop[x] = 0;
                   if (nr < 64) ctl->ret[cur][nr] = (uint16_t)x;

@@ -51,7 +51,8 @@ extern "C" {
 #define VF_EINVAL (-1)    /* bad argument (null pointer, b, eps, sizes)   */
 #define VF_ENOSPC (-2)    /* workspace or structure buffer too small      */
 #define VF_EFAIL (-3)     /* some shard failed every local seed           */
-#define VF_EHIP (-4)      /* a HIP runtime call failed                    */
+#define VF_EHIP (-4)      /* a HIP runtime call failed, or a build kernel
+                             gave up on an internal wait (a bug)           */
 #define VF_ECAPACITY (-5) /* a shard exceeded a fixed on-chip capacity of
                              this implementation (elimination window or
                              pivot log); the method itself did not fail    */

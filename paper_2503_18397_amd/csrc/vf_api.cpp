@@ -558,7 +558,6 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   const uint32_t nwg = std::min<uint32_t>(L.nwg, per_cu * (uint32_t)ncu);
   A.logcap = L.logcap;
   A.cell_bytes = L.cell_bytes;
-  A.cells_in_lds = g.V * L.cell_bytes + vfk::kLdsTail <= A.lds_bytes ? 1u : 0u;
   A.list = order;
   A.nlist = L.S;
   A.overflow = overflow;
@@ -578,7 +577,6 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
     A.overflow = nullptr;
     A.lds_bytes = (vfk::kLdsBudget - 256) & ~255u;
     A.wmax = vfk::window_slots((uint32_t)g.sigma, A.lds_bytes);
-    A.cells_in_lds = g.V * L.cell_bytes + vfk::kLdsTail <= A.lds_bytes ? 1u : 0u;
     HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkNext, 1, 0, stream));
     HIPCHK(vfk::launch_build(A, (int)std::min<uint32_t>(nwg, (uint32_t)ncu), stream));
     HIPCHK(hipMemcpyAsync(hwork, work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
@@ -623,6 +621,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   });
   H->failed_shards = (uint32_t)std::count(ts.begin(), ts.end(), (uint8_t)255);
   *handle = H;
+  if (hwork[vfk::kWorkStatus] & vfk::kStatusStalled) return VF_EHIP;
   if (hwork[vfk::kWorkStatus] & vfk::kStatusCapacity) return VF_ECAPACITY;
   if (H->failed_shards) return VF_EFAIL;
   return VF_OK;
@@ -785,7 +784,6 @@ int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
     build_occupancy(sg, &per_cu, &A.lds_bytes);
     A.wmax = vfk::window_slots((uint32_t)sg, A.lds_bytes);
     if (A.wmax > 384 && window_target(sg) <= 384) A.wmax = 384;
-    A.cells_in_lds = 1;  // per instance when its cells fit
     A.list = order + 2 * c0;
     A.nlist = (uint32_t)(c1 - c0);
     A.nlist_dev = nullptr;
@@ -851,6 +849,7 @@ int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
   H->seeds = std::move(ts);
   H->items_dev = items;
   *handle = H;
+  if (hwork[vfk::kWorkStatus] & vfk::kStatusStalled) return VF_EHIP;
   if (hwork[vfk::kWorkStatus] & vfk::kStatusCapacity) return VF_ECAPACITY;
   if (H->failed_shards) return VF_EFAIL;
   return VF_OK;

@@ -282,31 +282,40 @@ __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__r
 
 // ------------------------------------------------------------- shard build
 //
-// A workgroup of two wavefronts builds one shard at a time, from its keys
-// to its cells, and several workgroups share a CU (as many as the LDS of
-// their elimination windows allows).  Vertex state for peeling lives in
-// global memory (cached in L2), the elimination window and (when they fit)
-// the shard's cells live in LDS.
+// A workgroup of four wavefronts builds shards as a pipeline: wavefront 2
+// hashes and peels the next shard, wavefronts 0 and 1 eliminate the 2-core
+// of the current one, wavefront 3 assigns the cells of a solved one.
+// Several workgroups share a CU (as many as the LDS of their elimination
+// windows allows).  Vertex state for peeling lives in global memory (cached
+// in L2), the elimination window in LDS.
 
-// Per-workgroup scratch (global memory), sized for the largest shard.
-// Edges, right sides and the peeling order are kept twice: the assignment
-// of one shard reads one copy while the next shard is peeled into the other.
-struct Scratch {
-  uint64_t *E[2];      // packed edges
-  uint64_t *R[2];      // right sides (values or fingerprints)
-  uint32_t *deg;       // vertex degrees
-  uint32_t *xr;        // xor of incident edge indices (Djamal's trick, section 4.3)
-  uint8_t *pe;         // 1 = edge peeled
-  uint32_t *stack[2];  // peeled edges in round order: index | side << 30
-  uint32_t *rst[2];    // round starts in stack
-  uint32_t *F0, *F1;// frontiers of degree-one vertices
+// A shard in flight has a record of its own in global memory (sized for the
+// largest shard): its edges, right sides and peeling order (kept for the
+// assignment), its 2-core grouped for the elimination and the pivot rows.
+struct ShardBufs {
+  uint64_t *E;      // packed edges
+  uint64_t *R;      // right sides (values or fingerprints)
+  uint32_t *stack;  // peeled edges in round order: index | side << 30
+  uint32_t *rst;    // round starts in stack
   uint64_t *cE;     // packed edges of the 2-core, grouped by entry group
   uint64_t *cR;     // their right sides
   uint32_t *cb;     // group starts
-  uint32_t *cc;     // group cursors
   uint32_t *poff;   // pivot record offsets
   uint32_t *plog;   // pivot records
 };
+
+// Vertex state of the peeling wavefront (one copy per workgroup).
+struct FrontBufs {
+  uint32_t *deg;     // vertex degrees
+  uint32_t *xr;      // xor of incident edge indices (Djamal's trick, section 4.3)
+  uint8_t *pe;       // 1 = edge peeled
+  uint32_t *F0, *F1; // frontiers of degree-one vertices
+  uint32_t *cc;      // group cursors
+};
+
+// Shard records per workgroup: one being peeled, one being eliminated and
+// one being assigned.
+constexpr uint32_t kSlots = 3;
 
 __host__ __device__ inline uint64_t align8(uint64_t x) { return (x + 7) & ~7ull; }
 
@@ -316,8 +325,9 @@ __host__ __device__ inline uint64_t align8(uint64_t x) { return (x + 7) & ~7ull;
 __host__ __device__ inline uint32_t entry_shift(uint32_t sigma) { return sigma < 5 ? sigma : 5; }
 __host__ __device__ inline uint64_t max_groups(uint64_t V, uint32_t l) { return (V >> 5) + l + 8; }
 
-__host__ __device__ inline uint64_t scratch_layout(uint8_t *base, uint32_t M, uint64_t V,
-                                                  uint32_t l, uint32_t logcap, Scratch *s) {
+// Buffers of one shard record at base (nullptr: sizes only); returns its bytes.
+__host__ __device__ inline uint64_t slot_layout(uint8_t *base, uint32_t M, uint64_t V, uint32_t l,
+                                               uint32_t logcap, ShardBufs *sb) {
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) {
     uint8_t *p = base ? base + o : nullptr;
@@ -325,30 +335,45 @@ __host__ __device__ inline uint64_t scratch_layout(uint8_t *base, uint32_t M, ui
     return p;
   };
   const uint64_t m = (uint64_t)M + 1;
-  Scratch t;
-  for (int i = 0; i < 2; i++) {
-    t.E[i] = (uint64_t *)take(8 * m);
-    t.R[i] = (uint64_t *)take(8 * m);
-    t.stack[i] = (uint32_t *)take(4 * m);
-    t.rst[i] = (uint32_t *)take(4 * (m + 2));
-  }
-  t.deg = (uint32_t *)take(4 * V);
-  t.xr = (uint32_t *)take(4 * V);
-  t.pe = (uint8_t *)take(m);
-  t.F0 = (uint32_t *)take(4 * V);
-  t.F1 = (uint32_t *)take(4 * V);
+  ShardBufs t;
+  t.E = (uint64_t *)take(8 * m);
+  t.R = (uint64_t *)take(8 * m);
+  t.stack = (uint32_t *)take(4 * m);
+  t.rst = (uint32_t *)take(4 * (m + 2));
   t.cE = (uint64_t *)take(8 * m);
   t.cR = (uint64_t *)take(8 * m);
   t.cb = (uint32_t *)take(4 * max_groups(V, l));
-  t.cc = (uint32_t *)take(4 * max_groups(V, l));
   t.poff = (uint32_t *)take(4 * m);
   t.plog = (uint32_t *)take(4 * (uint64_t)logcap);
-  if (s) *s = t;
+  if (sb) *sb = t;
   return o;
 }
 
+// Vertex state of the peeling wavefront at base; returns its bytes.
+__host__ __device__ inline uint64_t front_layout(uint8_t *base, uint32_t M, uint64_t V, uint32_t l,
+                                                FrontBufs *fb) {
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    uint8_t *p = base ? base + o : nullptr;
+    o += align8(bytes);
+    return p;
+  };
+  const uint64_t m = (uint64_t)M + 1;
+  FrontBufs f;
+  f.deg = (uint32_t *)take(4 * V);
+  f.xr = (uint32_t *)take(4 * V);
+  f.pe = (uint8_t *)take(m);
+  f.F0 = (uint32_t *)take(4 * V);
+  f.F1 = (uint32_t *)take(4 * V);
+  f.cc = (uint32_t *)take(4 * max_groups(V, l));
+  if (fb) *fb = f;
+  return o;
+}
+
+// Scratch of one workgroup: kSlots shard records, then the vertex state.
 uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap) {
-  return scratch_layout(nullptr, M, V, l, logcap, nullptr);
+  return kSlots * slot_layout(nullptr, M, V, l, logcap, nullptr) +
+         front_layout(nullptr, M, V, l, nullptr);
 }
 
 // The elimination window stores each row over a ring of vertex positions.
@@ -410,10 +435,7 @@ template <int N> struct Groups { static constexpr int value = N; };
 // word i is read after the barrier that ends word i and rewritten only
 // during word i + 2, after every reader has passed the barrier of word i + 1.
 struct BandCtl {
-  uint32_t shard, t0, core, np;  // work item, core rows, pivots emitted
-  uint32_t rounds;               // peeling rounds
-  uint32_t dup;                  // 1: two core rows contradict each other,
-                                 // 2: an MWHC hypergraph did not peel
+  uint32_t np;                   // pivots emitted
   uint32_t flag[2];              // kSolveInconsistent | kSolveCapacity
   uint32_t adv[2];               // 0: the word is taken again (window full)
   uint32_t k[2], gs[2];          // pivots of each batch and its segment
@@ -422,10 +444,93 @@ struct BandCtl {
   uint32_t slot[2][32], col[2][32], cm[2][32];
   uint16_t ret[2][64];           // slots handed back to wavefront 0
 };
-static_assert(sizeof(BandCtl) + kBcolBytes <= kLdsTail, "LDS tail too small");
+
+// Shard records in flight and their states.  Each state has one owner, the
+// only wavefront that moves a record on from it: the peeling wavefront
+// (free, retry, give-up), the eliminating pair (ready, eliminating) or the
+// assigning wavefront (solved).
+enum : uint32_t {
+  kRecFree = 0,    // unused
+  kRecFront = 1,   // being peeled
+  kRecReady = 2,   // peeled, its 2-core waits for the elimination
+  kRecBand = 3,    // being eliminated
+  kRecSolved = 4,  // solved (or no 2-core), waits for the assignment
+  kRecRetry = 5,   // the elimination failed: peel again with the next local seed
+  kRecGiveUp = 6   // outgrew the window: cells cleared, shard left for a relaunch
+};
+struct ShardRec {
+  uint32_t state;
+  uint32_t shard, t;      // work item, local seed of the attempt
+  uint32_t m;             // keys
+  uint64_t base;          // first key of the item
+  uint64_t V, vmask;      // geometry of the item
+  uint64_t cells;         // address of the item's cells
+  uint32_t l, sigma, b;
+  uint32_t core, rounds;  // 2-core rows and peeling rounds of the attempt
+  uint32_t np;            // pivots of the solved 2-core
+  uint32_t order;         // position in the order records became ready
+  uint32_t pad;
+};
+struct PipeCtl {
+  ShardRec rec[kSlots];
+  uint32_t quit;     // no work is left and every record is free
+  uint32_t abort;    // a wait ran out: every wavefront of the workgroup ends
+  uint32_t pair[2];  // barriers reached by each eliminating wavefront
+  uint32_t pick;     // record the pair eliminates next (kSlots: none left)
+};
+constexpr uint32_t kPipeOff = (sizeof(BandCtl) + 15) & ~15u;
+static_assert(kPipeOff + sizeof(PipeCtl) + kBcolBytes <= kLdsTail, "LDS tail too small");
 
 __device__ __forceinline__ BandCtl *band_ctl(uint8_t *lds, uint32_t lds_bytes) {
   return (BandCtl *)(lds + lds_bytes - kLdsTail);
+}
+__device__ __forceinline__ PipeCtl *pipe_ctl(uint8_t *lds, uint32_t lds_bytes) {
+  return (PipeCtl *)(lds + lds_bytes - kLdsTail + kPipeOff);
+}
+
+__device__ __forceinline__ uint32_t lds_load(const uint32_t *p) {
+  return uniform(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+}
+// Publishes v at p after every earlier memory write of the wavefront.
+__device__ __forceinline__ void lds_publish(uint32_t *p, uint32_t v) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if (lane_id() == 0) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void acquire_wg() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup"); }
+
+// Longest wait of a build wavefront, in ticks of the 100 MHz wall clock.
+constexpr uint64_t kWaitLimit = 60ull * 100000000ull;
+
+// Waits until ready() (a value uniform across the wavefront) holds.  Every
+// wait ends: when another wavefront of the workgroup gave up, this one ends
+// too; after kWaitLimit it gives up itself (status kStatusStalled).
+template <class F>
+__device__ __forceinline__ void wait_for(PipeCtl *pc, uint32_t *work, F &&ready) {
+  if (ready()) return;
+  const uint64_t t0 = wall_clock64();
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    if (ready()) return;
+    if (lds_load(&pc->abort)) __builtin_amdgcn_endpgm();
+    if (wall_clock64() - t0 > kWaitLimit) {
+      if (lane_id() == 0) atomicOr(&work[kWorkStatus], kStatusStalled);
+      lds_publish(&pc->abort, 1u);
+      __builtin_amdgcn_endpgm();
+    }
+  }
+}
+
+// Barrier of the two eliminating wavefronts (the other wavefronts of the
+// workgroup run loops of their own, so the workgroup barrier is not
+// available): each publishes how many barriers it has reached and waits
+// until its partner has reached as many.
+__device__ __forceinline__ void pair_sync(PipeCtl *pc, uint32_t *work, uint32_t me,
+                                          uint32_t &gen) {
+  gen++;
+  lds_publish(&pc->pair[me], gen);
+  const uint32_t g = gen;
+  wait_for(pc, work, [&] { return lds_load(&pc->pair[me ^ 1u]) >= g; });
+  acquire_wg();
 }
 
 // Gaussian elimination of the 2-core over GF(2) by the two wavefronts of
@@ -451,8 +556,10 @@ __device__ __forceinline__ BandCtl *band_ctl(uint8_t *lds, uint32_t lds_bytes) {
 // per word; the result (kSolve*) and the pivot count are the same in both.
 template <int QM>
 __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint32_t W,
-                                          const Scratch &sc, uint8_t *lds, BandCtl *ctl,
-                                          uint32_t wid, uint32_t *np_out) {
+                                          const ShardBufs &sc, uint8_t *lds, BandCtl *ctl,
+                                          uint32_t wid, uint32_t *np_out, PipeCtl *pc,
+                                          uint32_t &gen) {
+  auto psync = [&] { pair_sync(pc, A.work, wid, gen); };
   uint32_t *const plog = sc.plog;
   uint32_t *const poff = sc.poff;
   const uint32_t *const cb = sc.cb;
@@ -488,7 +595,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       ctl->k[0] = ctl->k[1] = 0;
     }
   }
-  __syncthreads();
+  psync();
   uint32_t nfree = W, NQ = 0;  // wavefront 0
   uint32_t lp = 0, np = 0;     // wavefront 1
   const uint32_t gsh = entry_shift(G.sigma);
@@ -739,7 +846,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           }
         }
       }
-      __syncthreads();
+      psync();
       // 2. whole rows: every non-pivot row that absorbed pivots of this word
       //    gets their rows (as they were when the word started) xored in;
       //    wavefront 0 takes the even slot groups (masks in registers),
@@ -816,7 +923,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
         }
         if (incons && lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveInconsistent);
       }
-      __syncthreads();
+      psync();
       it++;
       if (ctl->flag[cur]) {
         stop = true;
@@ -839,7 +946,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
         atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
       if (lane == 0) ctl->np = np;
     }
-    __syncthreads();
+    psync();
     fl = ctl->flag[cur];
   }
   *np_out = ctl->np;
@@ -851,7 +958,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
 // lane gathers the values of vertices below its batch, then the in-batch
 // dependencies are resolved lane by lane.  Values of free vertices are 0.
 template <typename T>
-__device__ __forceinline__ void back_substitute(const Scratch &sc, uint32_t np, T *wl,
+__device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np, T *wl,
                                                 uint32_t *bcol, bool cells_global) {
   const uint32_t lane = lane_id();
   const uint32_t *const plog = sc.plog;
@@ -916,315 +1023,461 @@ __device__ __forceinline__ uint32_t wave_scan_array(uint32_t *a, uint32_t *b, ui
   return total;
 }
 
-// A shard whose 2-core is solved waits for its assignment.
-template <typename T>
-struct Pending {
-  T *cells;  // the shard's cells in HBM
-  uint64_t V;
-  uint32_t shard, t, np, nrounds, buf, in_lds;
-};
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  return (uint64_t)uniform((uint32_t)x) | ((uint64_t)uniform((uint32_t)(x >> 32)) << 32);
+}
 
-// One workgroup of two wavefronts builds shards one after the other.
-// Wavefront 0 computes right sides and edges and peels shard i (into copy
-// i % 2 of the edge arrays) while wavefront 1 assigns the cells of shard
-// i - 1; then both eliminate the 2-core of shard i (wavefront 1 emitting
-// the pivot rows); the two meet at workgroup barriers.
+// A grid of workgroups of four wavefronts takes work items (shards, or
+// instances of a batch) from a shared counter until none is left.  Within a
+// workgroup the items flow through three stages, each on its own records:
+//  - wavefront 2 takes an item, computes its right sides, then per attempt
+//    its edges, peeling order and 2-core; it retries failed attempts with
+//    the next local seed and clears the cells of items that fail them all;
+//  - wavefronts 0 and 1 eliminate the 2-core of the oldest ready record
+//    (wavefront 1 emitting the pivot rows);
+//  - wavefront 3 assigns the cells of solved records.
+// Peeling, elimination and assignment of consecutive items thus overlap.
 template <typename T, int QM>
 __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   extern __shared__ __align__(16) uint8_t lds[];
-  Geo G = A.G;
   const uint32_t lane = lane_id();
   const uint32_t wid = threadIdx.x >> 6;
-  Scratch sc;
-  scratch_layout(A.scratch + (uint64_t)blockIdx.x * A.scratch_stride, A.M, A.scr_V, A.scr_l,
-                 A.logcap, &sc);
+  uint8_t *const wbase = A.scratch + (uint64_t)blockIdx.x * A.scratch_stride;
+  const uint64_t slot_bytes = slot_layout(nullptr, A.M, A.scr_V, A.scr_l, A.logcap, nullptr);
+  auto bufs = [&](uint32_t s) {
+    ShardBufs sb;
+    slot_layout(wbase + (uint64_t)s * slot_bytes, A.M, A.scr_V, A.scr_l, A.logcap, &sb);
+    return sb;
+  };
   BandCtl *const ctl = band_ctl(lds, A.lds_bytes);
-  uint32_t *const bcol = (uint32_t *)(lds + A.lds_bytes - kBcolBytes);
+  PipeCtl *const pc = pipe_ctl(lds, A.lds_bytes);
+  ShardRec *const rec = pc->rec;
 
-  // cells of a solved shard: zero, core values by back-substitution, then
-  // the peeled edges in reverse round order (one wavefront)
-  auto assign = [&](const Pending<T> &P) {
-    const uint64_t V = P.V;
-    T *wg = P.cells;
-    T *wl = P.in_lds ? (T *)lds : wg;
-    const uint64_t *E = sc.E[P.buf], *R = sc.R[P.buf];
-    const uint32_t *stk = sc.stack[P.buf], *rst = sc.rst[P.buf];
-    for (uint64_t v = lane; v < V; v += 64) wl[v] = (T)0;
-    if (P.in_lds) wave_sync();
-    else wave_sync_global();
-    if (P.np) back_substitute<T>(sc, P.np, wl, bcol, !P.in_lds);
-    for (int r = (int)P.nrounds - 1; r >= 0; r--) {
-      const uint32_t e0 = rst[r], e1 = rst[r + 1];
-      for (uint32_t i = e0 + lane; i < e1; i += 64) {
-        const uint32_t ent = stk[i];
-        const uint32_t e = ent & 0x3FFFFFFFu, side = ent >> 30;
-        uint32_t a[3];
-        unpack3(E[e], a);
-        uint64_t val = R[e];
-        for (uint32_t q = 0; q < 3; q++)
-          if (q != side) val ^= (uint64_t)wl[a[q]];
-        wl[a[side]] = (T)val;
-      }
-      if (P.in_lds) wave_sync();
-      else wave_sync_global();
-    }
-    if (P.in_lds)
-      for (uint64_t v = lane; v < V; v += 64) wg[v] = wl[v];
-    if (lane == 0) A.tseed[P.shard] = (uint8_t)P.t;
+  if (threadIdx.x < kSlots) rec[threadIdx.x].state = kRecFree;
+  if (threadIdx.x == 0) {
+    pc->quit = 0;
+    pc->abort = 0;
+    pc->pair[0] = pc->pair[1] = 0;
+    pc->pick = kSlots;
+  }
+  // the only workgroup barrier: from here on the stages meet through records
+  __syncthreads();
+
+  auto state = [&](uint32_t s) { return lds_load(&rec[s].state); };
+  auto geo = [&](uint32_t s) {
+    Geo G = A.G;
+    G.V = uniform64(rec[s].V);
+    G.vmask = uniform64(rec[s].vmask);
+    G.l = uniform(rec[s].l);
+    G.sigma = uniform(rec[s].sigma);
+    G.b = uniform(rec[s].b);
+    return G;
   };
 
-  bool pend = false;
-  Pending<T> P{nullptr, 0, 0, 0, 0, 0, 0, 0};
-  uint32_t buf = 0;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      uint32_t j = atomicAdd(&A.work[kWorkNext], 1u), t0 = 0;
-      if (A.list) {
-        if (j < (A.nlist_dev ? *A.nlist_dev : A.nlist)) {
-          t0 = A.list[2 * j + 1];
-          j = A.list[2 * j];
-        } else {
-          j = 0xFFFFFFFFu;
-        }
-      } else if (j >= G.S) {
-        j = 0xFFFFFFFFu;
-      }
-      ctl->shard = j;
-      ctl->t0 = t0;
-    }
-    __syncthreads();
-    const uint32_t j = ctl->shard, t0 = ctl->t0;
-    if (pend && wid == 1) assign(P);
-    pend = false;
-    if (j == 0xFFFFFFFFu) {
-      __syncthreads();
-      break;
-    }
-    uint64_t base;
-    uint32_t m;
-    T *wg;
-    if (A.items) {
-      const BatchItem it = A.items[j];
-      G.V = it.V;
-      G.l = it.l;
-      G.sigma = it.sigma;
-      G.b = it.b;
-      G.vmask = it.vmask;
-      base = it.key_off;
-      m = it.n;
-      wg = (T *)((uint8_t *)A.cells + it.cell_off);
-    } else {
-      base = A.offsets[j];
-      m = (uint32_t)(A.offsets[j + 1] - base);
-      wg = (T *)A.cells + (uint64_t)j * G.V;
-    }
-    const uint64_t V = G.V;
-    const uint32_t in_lds =
-        A.cells_in_lds && V * sizeof(T) + kLdsTail <= A.lds_bytes ? 1u : 0u;
-    const uint32_t W = min(A.wmax, window_slots_for(G.sigma, A.lds_bytes));
-    uint64_t *const E = sc.E[buf], *const R = sc.R[buf];
-    uint32_t *const stk = sc.stack[buf], *const rst = sc.rst[buf];
+  if (wid == 2) {
+    // ------------------------------------------------ peeling (wavefront 2)
+    FrontBufs fb;
+    front_layout(wbase + (uint64_t)kSlots * slot_bytes, A.M, A.scr_V, A.scr_l, &fb);
 
-    // right sides: values (Problem 1) or fingerprints (Problem 2)
-    if (wid == 0) {
+    // edges, peeling order and grouped 2-core of attempt t; early = 1: two
+    // 2-core rows contradict each other, 2: an MWHC hypergraph did not peel
+    auto front = [&](const Geo &G, const ShardBufs &sb, uint32_t m, uint64_t base, uint32_t t,
+                     uint32_t &k_out, uint32_t &rounds_out, uint32_t &early_out) {
+      const uint64_t V = G.V;
+      uint64_t *const E = sb.E;
+      const uint64_t *const R = sb.R;
+      uint32_t *const stk = sb.stack, *const rst = sb.rst;
+      uint32_t nrounds = 0;
+      // edges of this attempt, cleared vertex state
       for (uint32_t i = lane; i < m; i += 64) {
         const uint64_t key = A.bkeys[base + i];
-        if (G.is_filter) {
-          R[i] = fingerprint(G, fin64(key ^ G.khi), fin64(key ^ G.klo));
-        } else {
-          R[i] = A.bvals[base + i] & G.vmask;
+        uint32_t v0, v1, v2;
+        edge3(G, fin64(key ^ G.khi), fin64(key ^ G.klo), t, v0, v1, v2);
+        E[i] = pack3(v0, v1, v2);
+        fb.pe[i] = 0;
+      }
+      for (uint64_t v = lane; v < V; v += 64) {
+        fb.deg[v] = 0;
+        fb.xr[v] = 0;
+      }
+      wave_sync_global();
+      // incidence: degree and xor of incident edges
+      for (uint32_t i = lane; i < m; i += 64) {
+        uint32_t v[3];
+        unpack3(E[i], v);
+        for (int k = 0; k < 3; k++) {
+          atomicAdd(&fb.deg[v[k]], 1u);
+          atomicXor(&fb.xr[v[k]], i);
         }
       }
-    }
-
-    bool solved = false;
-    for (uint32_t t = t0; t < A.tmax; t++) {
-      uint32_t nrounds = 0;
-      if (wid == 0) {
-        // edges of this attempt, cleared vertex state
-        for (uint32_t i = lane; i < m; i += 64) {
-          const uint64_t key = A.bkeys[base + i];
-          uint32_t v0, v1, v2;
-          edge3(G, fin64(key ^ G.khi), fin64(key ^ G.klo), t, v0, v1, v2);
-          E[i] = pack3(v0, v1, v2);
-          sc.pe[i] = 0;
-        }
-        for (uint64_t v = lane; v < V; v += 64) {
-          sc.deg[v] = 0;
-          sc.xr[v] = 0;
-        }
-        wave_sync_global();
-        // incidence: degree and xor of incident edges
-        for (uint32_t i = lane; i < m; i += 64) {
-          uint32_t v[3];
-          unpack3(E[i], v);
-          for (int k = 0; k < 3; k++) {
-            atomicAdd(&sc.deg[v[k]], 1u);
-            atomicXor(&sc.xr[v[k]], i);
-          }
-        }
-        wave_sync_global();
-        // round-synchronous peeling; list appends are counted by ballot
-        uint32_t nf = 0;
-        for (uint64_t v0 = 0; v0 < V; v0 += 64) {
-          const uint64_t v = v0 + lane;
-          const bool one = v < V && sc.deg[v] == 1;
-          const uint64_t bm = __ballot(one);
-          if (one) sc.F0[nf + lanes_below(bm)] = (uint32_t)v;
-          nf += (uint32_t)__popcll(bm);
-        }
-        wave_sync_global();
-        uint32_t nst = 0;
-        uint32_t *cur = sc.F0, *nxt = sc.F1;
-        if (lane == 0) rst[0] = 0;
-        while (nf) {
-          const uint32_t r0 = nst;
-          // select with the degrees of the start of the round
-          for (uint32_t i0 = 0; i0 < nf; i0 += 64) {
-            const uint32_t i = i0 + lane;
-            bool take = false;
-            uint32_t e = 0, side = 0;
-            if (i < nf) {
-              const uint32_t v = cur[i];
-              if (sc.deg[v] == 1) {
-                e = sc.xr[v];
-                uint32_t a[3];
-                unpack3(E[e], a);
-                side = a[0] == v ? 0u : (a[1] == v ? 1u : 2u);
-                take = true;
-                for (uint32_t k = 0; k < side; k++)
-                  if (sc.deg[a[k]] == 1) take = false;
-              }
-            }
-            const uint64_t bm = __ballot(take);
-            if (take) {
-              stk[nst + lanes_below(bm)] = e | (side << 30);
-              sc.pe[e] = 1;
-            }
-            nst += (uint32_t)__popcll(bm);
-          }
-          wave_sync_global();
-          // remove the selected edges
-          uint32_t nn = 0;
-          for (uint32_t i0 = r0; i0 < nst; i0 += 64) {
-            const uint32_t i = i0 + lane;
-            bool push[3] = {false, false, false};
-            uint32_t a[3] = {0, 0, 0};
-            if (i < nst) {
-              const uint32_t e = stk[i] & 0x3FFFFFFFu;
+      wave_sync_global();
+      // round-synchronous peeling; list appends are counted by ballot
+      uint32_t nf = 0;
+      for (uint64_t v0 = 0; v0 < V; v0 += 64) {
+        const uint64_t v = v0 + lane;
+        const bool one = v < V && fb.deg[v] == 1;
+        const uint64_t bm = __ballot(one);
+        if (one) fb.F0[nf + lanes_below(bm)] = (uint32_t)v;
+        nf += (uint32_t)__popcll(bm);
+      }
+      wave_sync_global();
+      uint32_t nst = 0;
+      uint32_t *cur = fb.F0, *nxt = fb.F1;
+      if (lane == 0) rst[0] = 0;
+      while (nf) {
+        const uint32_t r0 = nst;
+        // select with the degrees of the start of the round
+        for (uint32_t i0 = 0; i0 < nf; i0 += 64) {
+          const uint32_t i = i0 + lane;
+          bool take = false;
+          uint32_t e = 0, side = 0;
+          if (i < nf) {
+            const uint32_t v = cur[i];
+            if (fb.deg[v] == 1) {
+              e = fb.xr[v];
+              uint32_t a[3];
               unpack3(E[e], a);
-              for (int k = 0; k < 3; k++) {
-                const uint32_t old = atomicSub(&sc.deg[a[k]], 1u);
-                atomicXor(&sc.xr[a[k]], e);
-                push[k] = old == 2;
-              }
+              side = a[0] == v ? 0u : (a[1] == v ? 1u : 2u);
+              take = true;
+              for (uint32_t k = 0; k < side; k++)
+                if (fb.deg[a[k]] == 1) take = false;
             }
+          }
+          const uint64_t bm = __ballot(take);
+          if (take) {
+            stk[nst + lanes_below(bm)] = e | (side << 30);
+            fb.pe[e] = 1;
+          }
+          nst += (uint32_t)__popcll(bm);
+        }
+        wave_sync_global();
+        // remove the selected edges
+        uint32_t nn = 0;
+        for (uint32_t i0 = r0; i0 < nst; i0 += 64) {
+          const uint32_t i = i0 + lane;
+          bool push[3] = {false, false, false};
+          uint32_t a[3] = {0, 0, 0};
+          if (i < nst) {
+            const uint32_t e = stk[i] & 0x3FFFFFFFu;
+            unpack3(E[e], a);
             for (int k = 0; k < 3; k++) {
-              const uint64_t bm = __ballot(push[k]);
-              if (push[k]) nxt[nn + lanes_below(bm)] = a[k];
-              nn += (uint32_t)__popcll(bm);
+              const uint32_t old = atomicSub(&fb.deg[a[k]], 1u);
+              atomicXor(&fb.xr[a[k]], e);
+              push[k] = old == 2;
             }
           }
-          nrounds++;
-          if (lane == 0) rst[nrounds] = nst;
-          wave_sync_global();
-          nf = nn;
-          uint32_t *tmp = cur;
-          cur = nxt;
-          nxt = tmp;
+          for (int k = 0; k < 3; k++) {
+            const uint64_t bm = __ballot(push[k]);
+            if (push[k]) nxt[nn + lanes_below(bm)] = a[k];
+            nn += (uint32_t)__popcll(bm);
+          }
         }
-
-        // 2-core edges, grouped by the entry group of their top vertex (an
-        // MWHC hypergraph is peel-only: only its unpeeled edges are counted)
-        uint32_t k;
-        if (G.mwhc) {
-          uint32_t left = 0;
-          for (uint32_t i = lane; i < m; i += 64) left += sc.pe[i] ? 0u : 1u;
-          k = wave_sum(left);
-        } else {
-          const uint32_t gsh = entry_shift(G.sigma);
-          const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
-          for (uint32_t g = lane; g < ngroups; g += 64) sc.cc[g] = 0;
-          wave_sync_global();
-          for (uint32_t i = lane; i < m; i += 64)
-            if (!sc.pe[i]) atomicAdd(&sc.cc[(uint32_t)(E[i] >> 42) >> gsh], 1u);
-          wave_sync_global();
-          k = wave_scan_array(sc.cc, sc.cb, ngroups);
-          wave_sync_global();
-          for (uint32_t i = lane; i < m; i += 64)
-            if (!sc.pe[i]) {
-              const uint64_t e = E[i];
-              const uint32_t pos = atomicAdd(&sc.cc[(uint32_t)(e >> 42) >> gsh], 1u);
-              sc.cE[pos] = e;
-              sc.cR[pos] = R[i];
-            }
-          wave_sync_global();
-        }
-        // MWHC is peel-only: any unpeeled edge ends the attempt (kind 2).
-        // Otherwise two 2-core rows with the same vertices and different
-        // right sides (the usual reason for an inconsistent system) end the
-        // attempt before the elimination: rows are listed by top vertex in
-        // the degree array, which peeling no longer needs
-        const uint32_t kl = G.mwhc ? 0u : k;
-        uint32_t *const head = sc.deg, *const next = sc.F0;
-        if (kl)
-          for (uint64_t v = lane; v < V; v += 64) head[v] = 0xFFFFFFFFu;
+        nrounds++;
+        if (lane == 0) rst[nrounds] = nst;
         wave_sync_global();
-        for (uint32_t i = lane; i < kl; i += 64)
-          next[i] = atomicExch(&head[(uint32_t)(sc.cE[i] >> 42)], i);
-        wave_sync_global();
-        bool clash = false;
-        for (uint32_t i = lane; i < kl; i += 64) {
-          const uint64_t e = sc.cE[i], r = sc.cR[i];
-          for (uint32_t x = next[i]; x != 0xFFFFFFFFu; x = next[x])
-            clash |= sc.cE[x] == e && sc.cR[x] != r;
-        }
-        const bool dup = __ballot(clash) != 0;
-        if (lane == 0) {
-          ctl->core = k;
-          ctl->rounds = nrounds;
-          ctl->dup = G.mwhc && k ? 2u : (dup ? 1u : 0u);
-        }
+        nf = nn;
+        uint32_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
       }
-      __syncthreads();
-      const uint32_t k = ctl->core;
-      nrounds = ctl->rounds;
-      const uint32_t early = ctl->dup;  // 1: contradicting rows, 2: MWHC did not peel
-      __syncthreads();  // both have read the block before wavefront 0 rewrites it
 
-      uint32_t np = 0;
-      const int st = early ? kSolveInconsistent
-                           : (k ? band_solve<QM>(A, G, W, sc, lds, ctl, wid, &np) : kSolveOk);
-      if (st == kSolveCapacity) {
-        if (wid == 0 && lane == 0) {
-          if (A.overflow) {
-            const uint32_t idx = atomicAdd(&A.work[kWorkCap], 1u);
-            atomicAdd(&A.work[kWorkRelaunch], 1u);
-            A.overflow[2 * idx] = j;
-            A.overflow[2 * idx + 1] = t;
-          } else {
-            atomicOr(&A.work[kWorkStatus], kStatusCapacity);
+      // 2-core edges, grouped by the entry group of their top vertex (an
+      // MWHC hypergraph is peel-only: only its unpeeled edges are counted)
+      uint32_t k;
+      if (G.mwhc) {
+        uint32_t left = 0;
+        for (uint32_t i = lane; i < m; i += 64) left += fb.pe[i] ? 0u : 1u;
+        k = wave_sum(left);
+      } else {
+        const uint32_t gsh = entry_shift(G.sigma);
+        const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
+        for (uint32_t g = lane; g < ngroups; g += 64) fb.cc[g] = 0;
+        wave_sync_global();
+        for (uint32_t i = lane; i < m; i += 64)
+          if (!fb.pe[i]) atomicAdd(&fb.cc[(uint32_t)(E[i] >> 42) >> gsh], 1u);
+        wave_sync_global();
+        k = wave_scan_array(fb.cc, sb.cb, ngroups);
+        wave_sync_global();
+        for (uint32_t i = lane; i < m; i += 64)
+          if (!fb.pe[i]) {
+            const uint64_t e = E[i];
+            const uint32_t pos = atomicAdd(&fb.cc[(uint32_t)(e >> 42) >> gsh], 1u);
+            sb.cE[pos] = e;
+            sb.cR[pos] = R[i];
+          }
+        wave_sync_global();
+      }
+      // MWHC is peel-only: any unpeeled edge ends the attempt (kind 2).
+      // Otherwise two 2-core rows with the same vertices and different
+      // right sides (the usual reason for an inconsistent system) end the
+      // attempt before the elimination: rows are listed by top vertex in
+      // the degree array, which peeling no longer needs
+      const uint32_t kl = G.mwhc ? 0u : k;
+      uint32_t *const head = fb.deg, *const next = fb.F0;
+      if (kl)
+        for (uint64_t v = lane; v < V; v += 64) head[v] = 0xFFFFFFFFu;
+      wave_sync_global();
+      for (uint32_t i = lane; i < kl; i += 64)
+        next[i] = atomicExch(&head[(uint32_t)(sb.cE[i] >> 42)], i);
+      wave_sync_global();
+      bool clash = false;
+      for (uint32_t i = lane; i < kl; i += 64) {
+        const uint64_t e = sb.cE[i], r = sb.cR[i];
+        for (uint32_t x = next[i]; x != 0xFFFFFFFFu; x = next[x])
+          clash |= sb.cE[x] == e && sb.cR[x] != r;
+      }
+      const bool dup = __ballot(clash) != 0;
+      k_out = k;
+      rounds_out = nrounds;
+      early_out = G.mwhc && k ? 2u : (dup ? 1u : 0u);
+    };
+
+    // cells of a failed item are zero, its local seed 255
+    auto clear = [&](uint32_t s) {
+      const uint64_t V = uniform64(rec[s].V);
+      T *const wg = (T *)uniform64(rec[s].cells);
+      for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
+      if (lane == 0) A.tseed[uniform(rec[s].shard)] = 255;
+    };
+
+    uint32_t order = 0;
+    // attempts t, t + 1, ... of record s until one leaves a 2-core for the
+    // elimination (ready) or none (solved)
+    auto attempts = [&](uint32_t s, uint32_t t) {
+      const uint32_t j = uniform(rec[s].shard), m = uniform(rec[s].m);
+      const uint64_t base = uniform64(rec[s].base);
+      const ShardBufs sb = bufs(s);
+      const Geo G = geo(s);
+      for (; t < A.tmax; t++) {
+        uint32_t k, nrounds, early;
+        front(G, sb, m, base, t, k, nrounds, early);
+        if (early) {
+          if (lane == 0) {
+            const uint32_t idx = atomicAdd(&A.work[kWorkFails], 1u);
+            if (idx < A.fail_cap) A.fails[idx] = FailRec{j, t, early, k};
+          }
+          continue;
+        }
+        if (lane == 0) {
+          rec[s].t = t;
+          rec[s].core = k;
+          rec[s].rounds = nrounds;
+          rec[s].np = 0;
+          rec[s].order = order;
+        }
+        order += k ? 1u : 0u;
+        lds_publish(&rec[s].state, k ? kRecReady : kRecSolved);
+        return;
+      }
+      clear(s);
+      lds_publish(&rec[s].state, kRecFree);
+    };
+
+    bool exhausted = false;
+    for (;;) {
+      // failed eliminations first, then a new item into a free record
+      uint32_t s = kSlots, what = kRecFree;
+      bool done = false;
+      wait_for(pc, A.work, [&] {
+        uint32_t fr = kSlots, nfree = 0;
+        for (uint32_t i = 0; i < kSlots; i++) {
+          const uint32_t st = state(i);
+          if (st == kRecRetry || st == kRecGiveUp) {
+            s = i;
+            what = st;
+            return true;
+          }
+          if (st == kRecFree) {
+            nfree++;
+            if (fr == kSlots) fr = i;
           }
         }
+        if (!exhausted && fr < kSlots) {
+          s = fr;
+          what = kRecFree;
+          return true;
+        }
+        done = exhausted && nfree == kSlots;
+        return done;
+      });
+      acquire_wg();
+      if (done) {
+        lds_publish(&pc->quit, 1u);
         break;
       }
-      if (st == kSolveInconsistent) {
-        if (wid == 0 && lane == 0) {
-          const uint32_t idx = atomicAdd(&A.work[kWorkFails], 1u);
-          if (idx < A.fail_cap) A.fails[idx] = FailRec{j, t, early == 2 ? 2u : 1u, k};
-        }
+      if (what == kRecGiveUp) {
+        clear(s);
+        lds_publish(&rec[s].state, kRecFree);
         continue;
       }
-      P = Pending<T>{wg, V, j, t, np, nrounds, buf, in_lds};
-      pend = true;
-      buf ^= 1u;
-      solved = true;
-      break;
+      if (what == kRecRetry) {
+        if (lane == 0) rec[s].state = kRecFront;
+        attempts(s, uniform(rec[s].t) + 1u);
+        continue;
+      }
+      // the next work item
+      uint32_t j = 0xFFFFFFFFu, t0 = 0;
+      if (lane == 0) {
+        j = atomicAdd(&A.work[kWorkNext], 1u);
+        if (A.list) {
+          if (j < (A.nlist_dev ? *A.nlist_dev : A.nlist)) {
+            t0 = A.list[2 * j + 1];
+            j = A.list[2 * j];
+          } else {
+            j = 0xFFFFFFFFu;
+          }
+        } else if (j >= A.G.S) {
+          j = 0xFFFFFFFFu;
+        }
+      }
+      j = uniform(j);
+      t0 = uniform(t0);
+      if (j == 0xFFFFFFFFu) {
+        exhausted = true;
+        continue;
+      }
+      if (lane == 0) {
+        ShardRec &r = rec[s];
+        r.state = kRecFront;
+        r.shard = j;
+        r.t = t0;
+        if (A.items) {
+          const BatchItem it = A.items[j];
+          r.V = it.V;
+          r.vmask = it.vmask;
+          r.l = it.l;
+          r.sigma = it.sigma;
+          r.b = it.b;
+          r.base = it.key_off;
+          r.m = it.n;
+          r.cells = (uint64_t)((uint8_t *)A.cells + it.cell_off);
+        } else {
+          r.V = A.G.V;
+          r.vmask = A.G.vmask;
+          r.l = A.G.l;
+          r.sigma = A.G.sigma;
+          r.b = A.G.b;
+          r.base = A.offsets[j];
+          r.m = (uint32_t)(A.offsets[j + 1] - A.offsets[j]);
+          r.cells = (uint64_t)((T *)A.cells + (uint64_t)j * A.G.V);
+        }
+      }
+      wave_sync();
+      {
+        // right sides: values (Problem 1) or fingerprints (Problem 2)
+        const Geo G = geo(s);
+        const ShardBufs sb = bufs(s);
+        const uint32_t m = uniform(rec[s].m);
+        const uint64_t base = uniform64(rec[s].base);
+        for (uint32_t i = lane; i < m; i += 64) {
+          const uint64_t key = A.bkeys[base + i];
+          if (G.is_filter) {
+            sb.R[i] = fingerprint(G, fin64(key ^ G.khi), fin64(key ^ G.klo));
+          } else {
+            sb.R[i] = A.bvals[base + i] & G.vmask;
+          }
+        }
+      }
+      attempts(s, t0);
     }
-    if (!solved && wid == 0) {
-      // every attempt failed (or a capacity limit was hit): zero cells
+  } else if (wid < 2) {
+    // ------------------------------------------ elimination (wavefronts 0, 1)
+    uint32_t gen = 0;
+    for (;;) {
+      if (wid == 0) {
+        uint32_t s = kSlots;
+        wait_for(pc, A.work, [&] {
+          uint32_t best = 0xFFFFFFFFu;
+          s = kSlots;
+          for (uint32_t i = 0; i < kSlots; i++)
+            if (state(i) == kRecReady) {
+              const uint32_t o = lds_load(&rec[i].order);
+              if (o < best) {
+                best = o;
+                s = i;
+              }
+            }
+          return s < kSlots || lds_load(&pc->quit) != 0;
+        });
+        acquire_wg();
+        if (lane == 0) {
+          if (s < kSlots) rec[s].state = kRecBand;
+          pc->pick = s;
+        }
+      }
+      pair_sync(pc, A.work, wid, gen);
+      const uint32_t s = lds_load(&pc->pick);
+      if (s >= kSlots) break;
+      const ShardBufs sb = bufs(s);
+      const Geo G = geo(s);
+      const uint32_t W = min(A.wmax, window_slots_for(G.sigma, A.lds_bytes));
+      uint32_t np = 0;
+      const int st = band_solve<QM>(A, G, W, sb, lds, ctl, wid, &np, pc, gen);
+      if (wid == 0) {
+        const uint32_t j = uniform(rec[s].shard), t = uniform(rec[s].t);
+        uint32_t next = kRecSolved;
+        if (st == kSolveCapacity) {
+          if (lane == 0) {
+            if (A.overflow) {
+              const uint32_t idx = atomicAdd(&A.work[kWorkCap], 1u);
+              atomicAdd(&A.work[kWorkRelaunch], 1u);
+              A.overflow[2 * idx] = j;
+              A.overflow[2 * idx + 1] = t;
+            } else {
+              atomicOr(&A.work[kWorkStatus], kStatusCapacity);
+            }
+          }
+          next = kRecGiveUp;
+        } else if (st == kSolveInconsistent) {
+          if (lane == 0) {
+            const uint32_t idx = atomicAdd(&A.work[kWorkFails], 1u);
+            if (idx < A.fail_cap) A.fails[idx] = FailRec{j, t, 1u, uniform(rec[s].core)};
+          }
+          next = kRecRetry;
+        } else if (lane == 0) {
+          rec[s].np = np;
+        }
+        lds_publish(&rec[s].state, next);
+      }
+    }
+  } else {
+    // ----------------------------------------------- assignment (wavefront 3)
+    uint32_t *const bcol = (uint32_t *)(lds + A.lds_bytes - kBcolBytes);
+    for (;;) {
+      uint32_t s = kSlots;
+      wait_for(pc, A.work, [&] {
+        s = kSlots;
+        for (uint32_t i = 0; i < kSlots; i++)
+          if (s == kSlots && state(i) == kRecSolved) s = i;
+        return s < kSlots || lds_load(&pc->quit) != 0;
+      });
+      acquire_wg();
+      if (s >= kSlots) break;
+      // cells: zero, core values by back-substitution, then the peeled
+      // edges in reverse round order
+      const ShardBufs sb = bufs(s);
+      const uint64_t V = uniform64(rec[s].V);
+      T *const wg = (T *)uniform64(rec[s].cells);
+      const uint32_t np = uniform(rec[s].np), nrounds = uniform(rec[s].rounds);
       for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
-      if (lane == 0) A.tseed[j] = 255;
+      wave_sync_global();
+      if (np) back_substitute<T>(sb, np, wg, bcol, true);
+      for (int r = (int)nrounds - 1; r >= 0; r--) {
+        const uint32_t e0 = sb.rst[r], e1 = sb.rst[r + 1];
+        for (uint32_t i = e0 + lane; i < e1; i += 64) {
+          const uint32_t ent = sb.stack[i];
+          const uint32_t e = ent & 0x3FFFFFFFu, side = ent >> 30;
+          uint32_t a[3];
+          unpack3(sb.E[e], a);
+          uint64_t val = sb.R[e];
+          for (uint32_t q = 0; q < 3; q++)
+            if (q != side) val ^= (uint64_t)wg[a[q]];
+          wg[a[side]] = (T)val;
+        }
+        wave_sync_global();
+      }
+      if (lane == 0) A.tseed[uniform(rec[s].shard)] = (uint8_t)uniform(rec[s].t);
+      lds_publish(&rec[s].state, kRecFree);
     }
   }
 }

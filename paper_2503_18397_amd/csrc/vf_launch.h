@@ -50,7 +50,10 @@ enum : uint32_t {
   kWorkRelaunch = 4,   // items appended to overflow lists by all launches
   kWorkWords = 5
 };
-enum : uint32_t { kStatusCapacity = 1u };
+enum : uint32_t {
+  kStatusCapacity = 1u,  // a shard outgrew a fixed on-chip capacity
+  kStatusStalled = 2u    // a wait inside a build workgroup ran out (internal error)
+};
 
 struct BuildArgs {
   Geo G;
@@ -70,7 +73,6 @@ struct BuildArgs {
   uint32_t logcap;          // pivot log words per workgroup
   uint32_t lds_bytes;       // dynamic LDS of the launch
   uint32_t cell_bytes;      // 1, 2, 4 or 8
-  uint32_t cells_in_lds;    // 1: shard cells fit in LDS during assignment
   // Shards to build: all (list == nullptr, taken in order) or the nlist
   // (shard, first local seed) pairs of list.
   const uint32_t *list;
@@ -91,12 +93,12 @@ struct BuildArgs {
 
 constexpr uint32_t kLdsBudget = 160 * 1024;  // LDS of one CU
 // Bytes at the end of a build workgroup's dynamic LDS that hold the control
-// block shared by its two wavefronts and the back-substitution columns.
+// blocks shared by its wavefronts and the back-substitution columns.
 constexpr uint32_t kLdsTail = 2048;
-// Threads of a build workgroup: one wavefront peels and eliminates, the
-// other emits the pivot rows of the previous word and assigns the cells of
-// the previous shard.
-constexpr uint32_t kBuildThreads = 128;
+// Threads of a build workgroup: two wavefronts eliminate (one searches the
+// pivots, the other emits the pivot rows), one peels the next item and one
+// assigns the cells of solved items.
+constexpr uint32_t kBuildThreads = 256;
 
 uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap);
 uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes);

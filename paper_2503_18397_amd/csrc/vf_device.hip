@@ -554,6 +554,31 @@ __device__ __forceinline__ void pair_sync(PipeCtl *pc, uint32_t *work, uint32_t 
 //
 // Both wavefronts walk the same sequence of words and meet at one barrier
 // per word; the result (kSolve*) and the pivot count are the same in both.
+// Xor of word au of the rows of the pivots in the (wavefront-uniform) mask
+// cm: rows[pivot slot * mu + au], pivot k's slot in lane k of pivtab.  Four
+// loads are in flight at a time.
+__device__ __forceinline__ uint32_t xor_rows(const uint32_t *rows, uint32_t pivtab, uint32_t cm,
+                                             uint32_t mu, uint32_t au) {
+  uint32_t acc = 0;
+  while (__popc(cm) >= 4) {
+    const uint32_t j0 = __ffs(cm) - 1;
+    cm &= cm - 1;
+    const uint32_t j1 = __ffs(cm) - 1;
+    cm &= cm - 1;
+    const uint32_t j2 = __ffs(cm) - 1;
+    cm &= cm - 1;
+    const uint32_t j3 = __ffs(cm) - 1;
+    cm &= cm - 1;
+    const uint32_t a0 = rows[__umul24(readlane(pivtab, (int)j0), mu) + au];
+    const uint32_t a1 = rows[__umul24(readlane(pivtab, (int)j1), mu) + au];
+    const uint32_t a2 = rows[__umul24(readlane(pivtab, (int)j2), mu) + au];
+    const uint32_t a3 = rows[__umul24(readlane(pivtab, (int)j3), mu) + au];
+    acc ^= (a0 ^ a1) ^ (a2 ^ a3);
+  }
+  for (; cm; cm &= cm - 1) acc ^= rows[__umul24(readlane(pivtab, (int)(__ffs(cm) - 1)), mu) + au];
+  return acc;
+}
+
 template <int QM>
 __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint32_t W,
                                           const ShardBufs &sc, uint8_t *lds, BandCtl *ctl,
@@ -629,7 +654,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   // rows, none of which is rewritten), their slots into return list rsel
   // (wavefront 1); false if the log is full
   auto emit = [&](uint32_t bsel, uint32_t rsel) -> bool {
-    const uint32_t kp = ctl->k[bsel], Gs = ctl->gs[bsel];
+    const uint32_t kp = uniform(ctl->k[bsel]), Gs = uniform(ctl->gs[bsel]);
     const uint32_t pivtab = lane < kp ? ctl->slot[bsel][lane] : 0u;
     const uint32_t pivcol = lane < kp ? ctl->col[bsel][lane] : 0u;
     const uint32_t pivcm = lane < kp ? ctl->cm[bsel][lane] : 0u;
@@ -638,7 +663,8 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       const uint32_t col = readlane(pivcol, kk);
       const uint32_t cmx = readlane(pivcm, kk);
       const uint32_t cb_ = ring.pos(col);
-      if (lp + 4 > logcap) return false;
+      // a record takes at most 4 + 32 RW words (every ring bit set)
+      if (lp + 4 + 32 * RW > logcap) return false;
       uint32_t pos = lp + 4;
       for (uint32_t w = 0; w < NW; w++) {
         const uint32_t u = w * 64 + lane;
@@ -647,11 +673,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           // the pivot row as it was chosen: its row at the start of the word
           // plus the earlier pivots of the word it absorbed
           const uint32_t mu = umul(u), au = uadd(u);
-          bits = rows[x * mu + au];
-          for (uint32_t cb2 = cmx; cb2; cb2 &= cb2 - 1) {
-            const uint32_t j = __ffs(cb2) - 1;
-            bits ^= rows[readlane(pivtab, (int)j) * mu + au];
-          }
+          bits = rows[__umul24(x, mu) + au] ^ xor_rows(rows, pivtab, cmx, mu, au);
           if (u == (cb_ >> 5)) bits &= ~(1u << (cb_ & 31));
           if (u >= RW) {
             plog[lp + 2 + (u - RW)] = bits;  // right side, low word first
@@ -661,7 +683,6 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
         for (;;) {
           const uint64_t m = __ballot(bits != 0);
           if (!m) break;
-          if (pos + (uint32_t)__popcll(m) > logcap) return false;
           if (bits) {
             const uint32_t bb = __ffs(bits) - 1;
             bits &= bits - 1;
@@ -723,7 +744,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
         if (re - rb > nfree) {
           // window full: if the previous word's pivot rows are being
           // emitted, wait one word for their slots; otherwise give up
-          if (it > 0 && ctl->k[prev] > 0) adv = 0;
+          if (it > 0 && uniform(ctl->k[prev]) > 0) adv = 0;
           else if (lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
         } else {
           enter(rb, re);
@@ -854,7 +875,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       //    right sides go along.  A row that becomes zero is dead
       //    (inconsistent if its right side is not zero); its slot goes back
       //    to the free list.
-      if (const uint32_t kc = ctl->k[cur]) {
+      if (const uint32_t kc = uniform(ctl->k[cur])) {
         const uint32_t ptab = wid == 0 ? pivtab : (lane < kc ? ctl->slot[cur][lane] : 0u);
         // true if the row became zero; rset: its right side is not zero
         auto apply = [&](uint32_t x, uint32_t cmx, bool &rset) -> bool {
@@ -862,13 +883,9 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           for (uint32_t w = 0; w < NW; w++) {
             const uint32_t u = w * 64 + lane;
             if (u < RW + 2) {
-              const uint32_t mu = umul(u), au = uadd(u);
-              uint32_t acc = rows[x * mu + au];
-              for (uint32_t bits = cmx; bits; bits &= bits - 1) {
-                const uint32_t j = __ffs(bits) - 1;
-                acc ^= rows[readlane(ptab, (int)j) * mu + au];
-              }
-              rows[x * mu + au] = acc;
+              const uint32_t mu = umul(u), au = uadd(u), xa = __umul24(x, mu) + au;
+              const uint32_t acc = rows[xa] ^ xor_rows(rows, ptab, cmx, mu, au);
+              rows[xa] = acc;
               if (u < RW) any |= acc;
               else rany |= acc;
             }
@@ -898,8 +915,8 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
             }
           }
         } else {
-          const uint32_t nq = ctl->nq[cur];
-          uint32_t nr = ctl->nret[cur];
+          const uint32_t nq = uniform(ctl->nq[cur]);
+          uint32_t nr = uniform(ctl->nret[cur]);
           for (uint32_t q = 1; q < nq; q += 2) {
             const uint32_t slot = q * 64 + lane;
             const uint32_t cmv = slot < W ? rows[(uint64_t)slot * RS + RW] : 0u;
@@ -925,11 +942,11 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       }
       psync();
       it++;
-      if (ctl->flag[cur]) {
+      if (uniform(ctl->flag[cur])) {
         stop = true;
         break;
       }
-      if (!ctl->adv[cur]) continue;
+      if (!uniform(ctl->adv[cur])) continue;
       first = false;
       if (wlo_col == segbot) break;
       c = wlo_col - 1;
@@ -937,7 +954,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   }
   uint32_t fl;
   if (stop) {
-    fl = ctl->flag[(it - 1) & 1u];
+    fl = uniform(ctl->flag[(it - 1) & 1u]);
   } else {
     // the pivots of the last word
     const uint32_t cur = it & 1u, prev = cur ^ 1u;
@@ -947,9 +964,9 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       if (lane == 0) ctl->np = np;
     }
     psync();
-    fl = ctl->flag[cur];
+    fl = uniform(ctl->flag[cur]);
   }
-  *np_out = ctl->np;
+  *np_out = uniform(ctl->np);
   if (fl & kSolveInconsistent) return kSolveInconsistent;
   return fl ? kSolveCapacity : kSolveOk;
 }
@@ -1041,7 +1058,7 @@ template <typename T, int QM>
 __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   extern __shared__ __align__(16) uint8_t lds[];
   const uint32_t lane = lane_id();
-  const uint32_t wid = threadIdx.x >> 6;
+  const uint32_t wid = uniform(threadIdx.x >> 6);  // one value per wavefront
   uint8_t *const wbase = A.scratch + (uint64_t)blockIdx.x * A.scratch_stride;
   const uint64_t slot_bytes = slot_layout(nullptr, A.M, A.scr_V, A.scr_l, A.logcap, nullptr);
   auto bufs = [&](uint32_t s) {

@@ -1292,11 +1292,13 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
 
     bool exhausted = false;
     for (;;) {
-      // failed eliminations first, then a new item into a free record
+      // failed eliminations first, then a new item into a free record once
+      // no record waits for the elimination (taking items further ahead
+      // would only leave other workgroups idle at the end)
       uint32_t s = kSlots, what = kRecFree;
       bool done = false;
       wait_for(pc, A.work, [&] {
-        uint32_t fr = kSlots, nfree = 0;
+        uint32_t fr = kSlots, nfree = 0, nready = 0;
         for (uint32_t i = 0; i < kSlots; i++) {
           const uint32_t st = state(i);
           if (st == kRecRetry || st == kRecGiveUp) {
@@ -1308,8 +1310,9 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
             nfree++;
             if (fr == kSlots) fr = i;
           }
+          nready += st == kRecReady ? 1u : 0u;
         }
-        if (!exhausted && fr < kSlots) {
+        if (!exhausted && fr < kSlots && nready == 0) {
           s = fr;
           what = kRecFree;
           return true;

@@ -668,6 +668,9 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       uint32_t pos = lp + 4;
       for (uint32_t w = 0; w < NW; w++) {
         const uint32_t u = w * 64 + lane;
+        // with segments of 32 or more vertices a ring word lies in one
+        // segment: its bit bb is vertex vb + bb
+        const uint32_t vb = ring.three && u < RW ? ring.vertex(u * 32, Gs) : 0u;
         uint32_t bits = 0;
         if (u < RW + 2) {
           // the pivot row as it was chosen: its row at the start of the word
@@ -686,7 +689,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           if (bits) {
             const uint32_t bb = __ffs(bits) - 1;
             bits &= bits - 1;
-            plog[pos + lanes_below(m)] = ring.vertex(u * 32 + bb, Gs);
+            plog[pos + lanes_below(m)] = ring.three ? vb + bb : ring.vertex(u * 32 + bb, Gs);
           }
           pos += (uint32_t)__popcll(m);
         }

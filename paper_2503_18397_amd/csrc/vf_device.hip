@@ -992,22 +992,39 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
     wave_sync();
     const uint32_t bmin = bcol[0];
     uint64_t acc = 0, dep = 0;
+    // vertex v of the record, w its current value: vertices below the batch
+    // have their final values; a vertex in the batch's range is either a
+    // pivot column of the batch (a dependency, resolved below) or free (0)
+    auto take = [&](uint32_t v, uint64_t w) {
+      if (v < bmin) {
+        acc ^= w;
+      } else {
+        uint32_t lo = 0, hi = lane;  // bcol is increasing; v < col
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (bcol[mid] < v) lo = mid + 1;
+          else hi = mid;
+        }
+        if (lo < lane && bcol[lo] == v) dep |= 1ull << lo;
+      }
+    };
     if (valid) {
       acc = (uint64_t)rec[2] | ((uint64_t)rec[3] << 32);
       const uint32_t cnt = rec[1];
-      for (uint32_t e = 0; e < cnt; e++) {
-        const uint32_t v = rec[4 + e];
-        if (v < bmin) {
-          acc ^= (uint64_t)wl[v];
-        } else {
-          uint32_t lo = 0, hi = lane;  // bcol is increasing; v < col
-          while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (bcol[mid] < v) lo = mid + 1;
-            else hi = mid;
-          }
-          if (lo < lane && bcol[lo] == v) dep |= 1ull << lo;
-        }
+      const uint32_t *const ent = rec + 4;
+      uint32_t e = 0;
+      for (; e + 4 <= cnt; e += 4) {  // four entries and their values in flight
+        const uint32_t v0 = ent[e], v1 = ent[e + 1], v2 = ent[e + 2], v3 = ent[e + 3];
+        const uint64_t w0 = (uint64_t)wl[v0], w1 = (uint64_t)wl[v1];
+        const uint64_t w2 = (uint64_t)wl[v2], w3 = (uint64_t)wl[v3];
+        take(v0, w0);
+        take(v1, w1);
+        take(v2, w2);
+        take(v3, w3);
+      }
+      for (; e < cnt; e++) {
+        const uint32_t v = ent[e];
+        take(v, (uint64_t)wl[v]);
       }
     }
     uint64_t x = acc;

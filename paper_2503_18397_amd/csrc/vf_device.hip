@@ -658,7 +658,13 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
     const uint32_t pivtab = lane < kp ? ctl->slot[bsel][lane] : 0u;
     const uint32_t pivcol = lane < kp ? ctl->col[bsel][lane] : 0u;
     const uint32_t pivcm = lane < kp ? ctl->cm[bsel][lane] : 0u;
-    for (int kk = (int)kp - 1; kk >= 0; kk--) {
+    // with segments of 32 or more vertices a ring word lies in one segment:
+    // its bit bb is vertex vbase(u) + bb
+    auto vbase = [&](uint32_t u) { return ring.three && u < RW ? ring.vertex(u * 32, Gs) : 0u; };
+    const uint32_t vb0 = vbase(lane), mu0 = umul(lane), au0 = uadd(lane);
+    // pivot kk; when the row and its right side fit one word per lane
+    // (NW == 1), w0 is the lane's word of the pivot's row
+    auto one = [&](int kk, uint32_t w0) -> bool {
       const uint32_t x = readlane(pivtab, kk);
       const uint32_t col = readlane(pivcol, kk);
       const uint32_t cmx = readlane(pivcm, kk);
@@ -668,15 +674,14 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       uint32_t pos = lp + 4;
       for (uint32_t w = 0; w < NW; w++) {
         const uint32_t u = w * 64 + lane;
-        // with segments of 32 or more vertices a ring word lies in one
-        // segment: its bit bb is vertex vb + bb
-        const uint32_t vb = ring.three && u < RW ? ring.vertex(u * 32, Gs) : 0u;
+        const uint32_t vb = w == 0 ? vb0 : vbase(u);
         uint32_t bits = 0;
         if (u < RW + 2) {
           // the pivot row as it was chosen: its row at the start of the word
           // plus the earlier pivots of the word it absorbed
-          const uint32_t mu = umul(u), au = uadd(u);
-          bits = rows[__umul24(x, mu) + au] ^ xor_rows(rows, pivtab, cmx, mu, au);
+          const uint32_t mu = w == 0 ? mu0 : umul(u), au = w == 0 ? au0 : uadd(u);
+          bits = NW == 1 ? w0 : rows[__umul24(x, mu) + au];
+          if (cmx) bits ^= xor_rows(rows, pivtab, cmx, mu, au);
           if (u == (cb_ >> 5)) bits &= ~(1u << (cb_ & 31));
           if (u >= RW) {
             plog[lp + 2 + (u - RW)] = bits;  // right side, low word first
@@ -701,6 +706,23 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
         ctl->ret[rsel][kk] = (uint16_t)x;
       }
       lp = pos;
+      return true;
+    };
+    if (NW == 1) {
+      // the rows of up to eight pivots are loaded together
+      const bool in = lane < RW + 2;
+      for (int k0 = (int)kp - 1; k0 >= 0; k0 -= 8) {
+        uint32_t wv[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+          wv[i] = k0 - i >= 0 && in ? rows[__umul24(readlane(pivtab, k0 - i), mu0) + au0] : 0u;
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+          if (k0 - i >= 0 && !one(k0 - i, wv[i])) return false;
+      }
+    } else {
+      for (int kk = (int)kp - 1; kk >= 0; kk--)
+        if (!one(kk, 0u)) return false;
     }
     np += kp;
     if (lane == 0) ctl->nret[rsel] = kp;

@@ -441,6 +441,7 @@ struct BandCtl {
   uint32_t k[2], gs[2];          // pivots of each batch and its segment
   uint32_t nq[2];                // slot groups in use during the batch's word
   uint32_t nret[2];
+  uint32_t bseq;                 // words whose batch wavefront 0 has published
   uint32_t slot[2][32], col[2][32], cm[2][32];
   uint16_t ret[2][64];           // slots handed back to wavefront 0
 };
@@ -618,6 +619,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       ctl->flag[0] = ctl->flag[1] = 0;
       ctl->nret[0] = ctl->nret[1] = 0;
       ctl->k[0] = ctl->k[1] = 0;
+      ctl->bseq = 0;
     }
   }
   psync();
@@ -729,7 +731,36 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
     return true;
   };
 
-  uint32_t cw[QM], pop[QM], cm[QM];
+  // Rows absorb this word's pivots through a combination mask (bit k: the
+  // row of pivot k as it was when the word started).  A row that becomes
+  // zero is dead (inconsistent if its right side is not zero) and frees its
+  // slot.  apply() xors the masked pivot rows (slots in lanes of ptab) into
+  // row x, right side included; true if the row became zero, rset: its
+  // right side is not zero.
+  auto apply = [&](uint32_t x, uint32_t cmx, uint32_t ptab, bool &rset) -> bool {
+    uint32_t any = 0, rany = 0;
+    for (uint32_t w = 0; w < NW; w++) {
+      const uint32_t u = w * 64 + lane;
+      if (u < RW + 2) {
+        const uint32_t mu = umul(u), au = uadd(u), xa = __umul24(x, mu) + au;
+        const uint32_t acc = rows[xa] ^ xor_rows(rows, ptab, cmx, mu, au);
+        rows[xa] = acc;
+        if (u < RW) any |= acc;
+        else rany |= acc;
+      }
+    }
+    rset = __ballot(rany != 0) != 0;
+    return __ballot(any != 0) == 0;
+  };
+
+  // Active rows of a word (a bit within the word's columns) are gathered
+  // into up to QM register groups in slot order ("compact" index c =
+  // group * 64 + lane); csl holds their slots (kNoSlot past the last).
+  // Wavefront 1 takes the rows of compact index 3 mod 4 through the rows'
+  // padding words, wavefront 0 the others from its registers.
+  constexpr uint32_t kNoSlot = 0xFFFFu;
+  auto w1share = [](uint32_t c) { return (c & 3u) == 3u; };
+  uint32_t csl[QM], ccw[QM], cpop[QM], ccm[QM];
   uint32_t it = 0;
   bool stop = false;
   for (int Gs = (int)G.l + 1; Gs >= 0 && !stop; Gs--) {
@@ -746,9 +777,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       const uint32_t wbase = c - (cpos & 31);  // column of bit 0 of this word
       const uint32_t wlo_col = max(segbot, wbase);
       const uint32_t cur = it & 1u, prev = cur ^ 1u;
-      // lane k of pivtab/pivcol/pivcm describes pivot k of the word; bit q
-      // of pivbits marks the lane's slot of group q as a pivot row
-      uint32_t pivtab = 0, pivcol = 0, pivcm = 0, pivbits = 0;
+      bool incons = false;
       if (wid == 0) {
         // slots emitted during the previous word come back
         const uint32_t nr = uniform(ctl->nret[prev]);
@@ -766,6 +795,18 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           re = cbv(1);
         }
         uint32_t k = 0, adv = 1;
+        bool published = false;
+        // the word's batch (pivots, masks, counts) goes to wavefront 1
+        auto publish = [&] {
+          if (lane == 0) {
+            ctl->k[cur] = k;
+            ctl->gs[cur] = (uint32_t)Gs;
+            ctl->adv[cur] = adv;
+            ctl->nq[cur] = NQ;
+          }
+          lds_publish(&ctl->bseq, it + 1);
+          published = true;
+        };
         if (re - rb > nfree) {
           // window full: if the previous word's pivot rows are being
           // emitted, wait one word for their slots; otherwise give up
@@ -776,84 +817,87 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           const uint32_t lowbit = wlo_col - wbase, hibit = cpos & 31;
           const uint32_t range = (hibit >= 31 ? 0xFFFFFFFFu : ((2u << hibit) - 1u)) &
                                  ~((1u << lowbit) - 1u);
-          // the word's pivots with the slot groups in use fixed at compile time
-          auto pivots = [&](auto groups) {
-            constexpr int NG = decltype(groups)::value;
-            // register caches of this word (all loads issued together)
+          // 1. pivots of the word's columns, top down, on the active rows'
+          //    words in registers: lane k of pivtab/pivcol/pivcm describes
+          //    pivot k (slot, column, mask); bit g of cpiv marks the lane's
+          //    row of compact group g as a pivot row.  The pivot row takes
+          //    part in its own update (its word becomes zero, so it is never
+          //    a candidate again).  Right sides follow in the passes over
+          //    whole rows.
+          auto search = [&](auto cgroups) {
+            constexpr int NC = decltype(cgroups)::value;
+            uint32_t pivtab = 0, pivcol = 0, pivcm = 0, cpiv = 0;
             uint32_t orv = 0;
 #pragma unroll
-            for (int q = 0; q < NG; q++) {
-              const uint32_t slot = (uint32_t)q * 64 + lane;
-              const uint32_t sl = slot < W ? slot : 0u;
-              pop[q] = rpop[sl];
-              cw[q] = rows[(uint64_t)sl * RS + word];
-              if (slot >= W) pop[q] = 0;
-              cw[q] = pop[q] ? cw[q] & range : 0u;
-              cm[q] = 0;
-              orv |= cw[q];
+            for (int g = 0; g < NC; g++) {
+              const bool v = csl[g] != kNoSlot;
+              const uint32_t sl = v ? csl[g] : 0u;
+              cpop[g] = rpop[sl];
+              ccw[g] = rows[(uint64_t)sl * RS + word];
+              if (!v) cpop[g] = 0;
+              ccw[g] = v ? ccw[g] & range : 0u;
+              ccm[g] = 0;
+              orv |= ccw[g];
             }
-            // 1. pivots of the word's columns, top down, on the register
-            //    words only: cm records which of this word's pivot rows (by
-            //    index k) a row has absorbed; lane k of pivtab/pivcol/pivcm
-            //    describes pivot k.  Right sides follow in the passes over
-            //    whole rows.  The pivot row itself takes part in its own
-            //    update (its word becomes zero, so it is never a candidate
-            //    again); pivbits marks it, and its popcount and mask are
-            //    dropped when they go back to LDS.
             uint32_t colmask = wave_or(orv);
             while (colmask) {
               const uint32_t b = 31 - __clz(colmask), bit = 1u << b;
-              bool has[NG];
+              bool has[NC];
               uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
-              for (int q = 0; q < NG; q++) {
-                has[q] = (cw[q] & bit) != 0;
+              for (int g = 0; g < NC; g++) {
+                has[g] = (ccw[g] & bit) != 0;
                 // popcount estimates stay below 2^16
-                const uint32_t key = (pop[q] << 16) | ((uint32_t)q * 64 + lane);
-                best = min(best, has[q] ? key : 0xFFFFFFFFu);
+                const uint32_t key = (cpop[g] << 16) | ((uint32_t)g * 64 + lane);
+                best = min(best, has[g] ? key : 0xFFFFFFFFu);
               }
               best = wave_min(best);
-              const uint32_t p = best & 0xFFFFu, pq = p >> 6, pl = p & 63u;
+              const uint32_t p = best & 0xFFFFu, pg = p >> 6, pl = p & 63u;
               const uint32_t dpop = (best >> 16) - 2u;
-              uint32_t pw = 0, pcm = 0;
+              uint32_t pw = 0, pcm = 0, ps = 0;
 #pragma unroll
-              for (int q = 0; q < NG; q++) {
-                if ((uint32_t)q == pq) {
-                  pw = readlane(cw[q], (int)pl);
-                  pcm = readlane(cm[q], (int)pl);
+              for (int g = 0; g < NC; g++) {
+                if ((uint32_t)g == pg) {
+                  pw = readlane(ccw[g], (int)pl);
+                  pcm = readlane(ccm[g], (int)pl);
+                  ps = readlane(csl[g], (int)pl);
                 }
               }
               if (lane == k) {
-                pivtab = p;
+                pivtab = ps;
                 pivcol = wbase + b;
                 pivcm = pcm;
               }
-              if (lane == pl) pivbits |= 1u << pq;
+              if (lane == pl) cpiv |= 1u << pg;
               const uint32_t kbit = pcm | (1u << k);
               orv = 0;
 #pragma unroll
-              for (int q = 0; q < NG; q++) {
-                if (has[q]) {
-                  cw[q] ^= pw;
-                  cm[q] ^= kbit;
-                  pop[q] = min(pop[q] + dpop, 0xFFFFu);
+              for (int g = 0; g < NC; g++) {
+                if (has[g]) {
+                  ccw[g] ^= pw;
+                  ccm[g] ^= kbit;
+                  cpop[g] = min(cpop[g] + dpop, 0xFFFFu);
                 }
-                orv |= cw[q];
+                orv |= ccw[g];
               }
               k++;
               colmask = wave_or(orv) & (bit - 1u);
             }
             if (k) {
               // popcount estimates back to LDS (zero marks a pivot row, no
-              // longer live in the window); the combination masks of the odd
-              // slot groups go to the rows' padding words for wavefront 1
+              // longer live in the window); padding words: zero for every
+              // slot in use, then the masks of wavefront 1's rows
+              for (uint32_t q = 0; q < NQ; q++) {
+                const uint32_t slot = q * 64 + lane;
+                if (slot < W) rows[(uint64_t)slot * RS + RW] = 0u;
+              }
 #pragma unroll
-              for (int q = 0; q < NG; q++) {
-                const uint32_t slot = (uint32_t)q * 64 + lane;
-                const bool piv = (pivbits >> q) & 1u;
-                if (slot < W) {
-                  rpop[slot] = piv ? (uint16_t)0 : (uint16_t)pop[q];
-                  if (q & 1) rows[(uint64_t)slot * RS + RW] = piv ? 0u : cm[q];
+              for (int g = 0; g < NC; g++) {
+                const bool piv = (cpiv >> g) & 1u;
+                if (csl[g] != kNoSlot) {
+                  rpop[csl[g]] = piv ? (uint16_t)0 : (uint16_t)cpop[g];
+                  if (!piv && ccm[g] && w1share((uint32_t)g * 64 + lane))
+                    rows[(uint64_t)csl[g] * RS + RW] = ccm[g];
                 }
               }
               // the batch for wavefront 1
@@ -863,25 +907,97 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
                 ctl->cm[cur][lane] = pivcm;
               }
             }
+            publish();
+            // 2. whole rows, wavefront 0's share (see apply)
+            if (k) {
+#pragma unroll
+              for (int g = 0; g < NC; g++) {
+                const bool mine = csl[g] != kNoSlot && !((cpiv >> g) & 1u) && ccm[g] != 0 &&
+                                  !w1share((uint32_t)g * 64 + lane);
+                uint64_t m = __ballot(mine);
+                while (m) {
+                  const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
+                  m &= m - 1;
+                  const uint32_t x = readlane(csl[g], (int)xl);
+                  bool rset;
+                  if (apply(x, readlane(ccm[g], (int)xl), pivtab, rset)) {
+                    incons |= rset;
+                    if (lane == 0) {
+                      rpop[x] = 0;
+                      freel[nfree] = (uint16_t)x;
+                    }
+                    nfree++;
+                  }
+                }
+              }
+            }
           };
+          // the slot of the c-th active row: the r-th set bit of the mask of
+          // the group that holds it (binary search on the count below)
+          auto compact = [&](auto groups) -> uint32_t {
+            constexpr int NG = decltype(groups)::value;
+            uint64_t act[NG];
+            uint32_t off[NG + 1];
+            off[0] = 0;
+#pragma unroll
+            for (int q = 0; q < NG; q++) {
+              const uint32_t slot = (uint32_t)q * 64 + lane;
+              const uint32_t sl = slot < W ? slot : 0u;
+              const bool a = slot < W && rpop[sl] != 0 && (rows[(uint64_t)sl * RS + word] & range) != 0;
+              act[q] = __ballot(a);
+              off[q + 1] = off[q] + (uint32_t)__popcll(act[q]);
+            }
+            const uint32_t na = off[NG], nc = (na + 63) >> 6;
+#pragma unroll
+            for (int g = 0; g < QM; g++) {
+              const uint32_t ci = (uint32_t)g * 64 + lane;
+              uint32_t sl = kNoSlot;
+              if ((uint32_t)g < nc && ci < na) {
+                uint64_t msk = 0;
+                uint32_t base = 0, qs = 0;
+#pragma unroll
+                for (int q = 0; q < NG; q++)
+                  if (act[q] && ci >= off[q]) {
+                    msk = act[q];
+                    base = off[q];
+                    qs = (uint32_t)q;
+                  }
+                const uint32_t r = ci - base;
+                uint32_t lo = 0;
+#pragma unroll
+                for (uint32_t step = 32; step; step >>= 1)
+                  if ((uint32_t)__popcll(msk & ((1ull << (lo + step)) - 1ull)) <= r) lo += step;
+                sl = qs * 64 + lo;
+              }
+              csl[g] = sl;
+            }
+            return nc;
+          };
+          uint32_t nc = 0;
           switch (uniform(NQ)) {
-            case 1: pivots(Groups<1>{}); break;
-            case 2: pivots(Groups<2>{}); break;
-            case 3: pivots(Groups<3>{}); break;
-            case 4: pivots(Groups<4>{}); break;
-            case 5: pivots(Groups<5>{}); break;
-            case 6: pivots(Groups<6>{}); break;
-            case 7: if constexpr (QM >= 7) pivots(Groups<7>{}); break;
-            case 8: if constexpr (QM >= 8) pivots(Groups<8>{}); break;
+            case 1: nc = compact(Groups<1>{}); break;
+            case 2: nc = compact(Groups<2>{}); break;
+            case 3: nc = compact(Groups<3>{}); break;
+            case 4: nc = compact(Groups<4>{}); break;
+            case 5: nc = compact(Groups<5>{}); break;
+            case 6: nc = compact(Groups<6>{}); break;
+            case 7: if constexpr (QM >= 7) nc = compact(Groups<7>{}); break;
+            case 8: if constexpr (QM >= 8) nc = compact(Groups<8>{}); break;
+            default: break;
+          }
+          switch (uniform(nc)) {
+            case 1: search(Groups<1>{}); break;
+            case 2: search(Groups<2>{}); break;
+            case 3: search(Groups<3>{}); break;
+            case 4: search(Groups<4>{}); break;
+            case 5: search(Groups<5>{}); break;
+            case 6: search(Groups<6>{}); break;
+            case 7: if constexpr (QM >= 7) search(Groups<7>{}); break;
+            case 8: if constexpr (QM >= 8) search(Groups<8>{}); break;
             default: break;
           }
         }
-        if (lane == 0) {
-          ctl->k[cur] = k;
-          ctl->gs[cur] = (uint32_t)Gs;
-          ctl->adv[cur] = adv;
-          ctl->nq[cur] = NQ;
-        }
+        if (!published) publish();
       } else {
         if (it == 0) {
           if (lane == 0) ctl->nret[cur] = 0;
@@ -891,58 +1007,17 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
             atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
           }
         }
-      }
-      psync();
-      // 2. whole rows: every non-pivot row that absorbed pivots of this word
-      //    gets their rows (as they were when the word started) xored in;
-      //    wavefront 0 takes the even slot groups (masks in registers),
-      //    wavefront 1 the odd ones (masks in the rows' padding words).  The
-      //    right sides go along.  A row that becomes zero is dead
-      //    (inconsistent if its right side is not zero); its slot goes back
-      //    to the free list.
-      if (const uint32_t kc = uniform(ctl->k[cur])) {
-        const uint32_t ptab = wid == 0 ? pivtab : (lane < kc ? ctl->slot[cur][lane] : 0u);
-        // true if the row became zero; rset: its right side is not zero
-        auto apply = [&](uint32_t x, uint32_t cmx, bool &rset) -> bool {
-          uint32_t any = 0, rany = 0;
-          for (uint32_t w = 0; w < NW; w++) {
-            const uint32_t u = w * 64 + lane;
-            if (u < RW + 2) {
-              const uint32_t mu = umul(u), au = uadd(u), xa = __umul24(x, mu) + au;
-              const uint32_t acc = rows[xa] ^ xor_rows(rows, ptab, cmx, mu, au);
-              rows[xa] = acc;
-              if (u < RW) any |= acc;
-              else rany |= acc;
-            }
-          }
-          rset = __ballot(rany != 0) != 0;
-          return __ballot(any != 0) == 0;
-        };
-        bool incons = false;
-        if (wid == 0) {
-#pragma unroll
-          for (int q = 0; q < QM; q += 2) {
-            if ((uint32_t)q >= NQ) break;
-            uint64_t m = __ballot(cm[q] != 0 && !((pivbits >> q) & 1u));
-            while (m) {
-              const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
-              m &= m - 1;
-              const uint32_t x = (uint32_t)q * 64 + xl;
-              bool rset;
-              if (apply(x, readlane(cm[q], (int)xl), rset)) {
-                incons |= rset;
-                if (lane == 0) {
-                  rpop[x] = 0;
-                  freel[nfree] = (uint16_t)x;
-                }
-                nfree++;
-              }
-            }
-          }
-        } else {
+        // this word's batch from wavefront 0
+        const uint32_t want = it + 1;
+        wait_for(pc, A.work, [&] { return lds_load(&ctl->bseq) >= want; });
+        acquire_wg();
+        // 2. whole rows, wavefront 1's share: rows whose padding word holds
+        //    a mask
+        if (const uint32_t kc = uniform(ctl->k[cur])) {
+          const uint32_t ptab = lane < kc ? ctl->slot[cur][lane] : 0u;
           const uint32_t nq = uniform(ctl->nq[cur]);
           uint32_t nr = uniform(ctl->nret[cur]);
-          for (uint32_t q = 1; q < nq; q += 2) {
+          for (uint32_t q = 0; q < nq; q++) {
             const uint32_t slot = q * 64 + lane;
             const uint32_t cmv = slot < W ? rows[(uint64_t)slot * RS + RW] : 0u;
             uint64_t m = __ballot(cmv != 0);
@@ -951,7 +1026,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
               m &= m - 1;
               const uint32_t x = q * 64 + xl;
               bool rset;
-              if (apply(x, readlane(cmv, (int)xl), rset)) {
+              if (apply(x, readlane(cmv, (int)xl), ptab, rset)) {
                 incons |= rset;
                 if (lane == 0) {
                   rpop[x] = 0;
@@ -963,8 +1038,8 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           }
           if (lane == 0) ctl->nret[cur] = nr;
         }
-        if (incons && lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveInconsistent);
       }
+      if (incons && lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveInconsistent);
       psync();
       it++;
       if (uniform(ctl->flag[cur])) {

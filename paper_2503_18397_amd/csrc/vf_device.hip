@@ -608,6 +608,10 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   auto umul = [&](uint32_t u) { return u < RW ? RS : 2u; };
   auto uadd = [&](uint32_t u) { return u < RW ? u : RS * W + (u - RW); };
 
+  // ring words of free slots are kept zero (dead rows are zero, emitted
+  // pivot rows are cleared by the emitter), so a row enters by setting its
+  // three bits
+  for (uint32_t i = wid * 64 + lane; i < W * RS; i += 128) rows[i] = 0;
   // free slots form a stack that hands out low slots first; only slot groups
   // below the high-water mark are ever scanned
   if (wid == 0) {
@@ -638,10 +642,9 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
         uint32_t v[3];
         unpack3(e, v);
         uint32_t *row = rows + (uint64_t)slot * RS;
-        for (uint32_t u = 0; u < RW; u++) row[u] = 0;
         for (int k = 0; k < 3; k++) {
           const uint32_t p = ring.pos(v[k]);
-          row[p >> 5] |= 1u << (p & 31);
+          atomicOr(&row[p >> 5], 1u << (p & 31));
         }
         rrhs[slot] = rhs;
         rpop[slot] = 3;
@@ -701,6 +704,10 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           pos += (uint32_t)__popcll(m);
         }
       }
+      // the slot goes back with its ring words zero (no pivot emitted
+      // after this one reads it)
+      for (uint32_t w = 0; w < NW; w++)
+        if (w * 64 + lane < RW) rows[x * RS + w * 64 + lane] = 0u;
       if (lane == 0) {
         plog[lp] = col;
         plog[lp + 1] = pos - (lp + 4);
@@ -756,10 +763,11 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   // Active rows of a word (a bit within the word's columns) are gathered
   // into up to QM register groups in slot order ("compact" index c =
   // group * 64 + lane); csl holds their slots (kNoSlot past the last).
-  // Wavefront 1 takes the rows of compact index 3 mod 4 through the rows'
-  // padding words, wavefront 0 the others from its registers.
-  constexpr uint32_t kNoSlot = 0xFFFFu;
-  auto w1share = [](uint32_t c) { return (c & 3u) == 3u; };
+  // Wavefront 1 takes the rows whose compact index is below kW1Share mod 8
+  // through the rows' padding words, wavefront 0 the others from its
+  // registers.
+  constexpr uint32_t kNoSlot = 0xFFFFu, kW1Share = 3;
+  auto w1share = [](uint32_t c) { return (c & 7u) < kW1Share; };
   uint32_t csl[QM], ccw[QM], cpop[QM], ccm[QM];
   uint32_t it = 0;
   bool stop = false;

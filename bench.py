@@ -26,8 +26,8 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy); see
 # profiles/vfilter_b8_n2p27_hbm_traffic_pmc.md.  They hold for the kernel
 # source with this SHA-256 prefix only and are reported as null otherwise.
-PMC_SOURCE_SHA = "cc42bc6da97a5f21"
-PMC_TRAFFIC_BYTES = {"k_build": 106.60e9, "k_query": 410.87e9, "k_scatter": 7.02e9,
+PMC_SOURCE_SHA = "67a02e6ec5e82d17"
+PMC_TRAFFIC_BYTES = {"k_build": 112.91e9, "k_query": 410.87e9, "k_scatter": 7.06e9,
                      "k_count+k_scan": 1.08e9}
 
 

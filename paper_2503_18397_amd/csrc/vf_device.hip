@@ -102,10 +102,14 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // Cross-lane reductions with DPP (VALU only, no LDS round trip): within each
 // row of 16 lanes quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror
-// and row_mirror leave the row's total in every lane; the four row totals
-// are then combined from lanes 0, 16, 32 and 48.
+// and row_mirror leave the row's total in every lane.  For the idempotent
+// reductions (or, min) row_bcast:15 (into rows 1 and 3) and row_bcast:31
+// (into rows 2 and 3) then carry the lower rows' totals up, so lane 63 holds
+// the wavefront's; the sum combines the rows from lanes 0, 16, 32 and 48.
 #define VF_DPP(x, ctrl, id) __builtin_amdgcn_update_dpp((id), (x), (ctrl), 0xF, 0xF, false)
+#define VF_BCAST(x, ctrl, rows) __builtin_amdgcn_update_dpp((x), (x), (ctrl), (rows), 0xF, false)
 constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E, kRowHalfMirror = 0x141, kRowMirror = 0x140;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
 
 __device__ __forceinline__ uint32_t readlane(uint32_t x, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
@@ -131,7 +135,9 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t x) {
   x |= VF_DPP(x, kQuadSwap2, 0u);
   x |= VF_DPP(x, kRowHalfMirror, 0u);
   x |= VF_DPP(x, kRowMirror, 0u);
-  return readlane(x, 0) | readlane(x, 16) | readlane(x, 32) | readlane(x, 48);
+  x |= (uint32_t)VF_BCAST(x, kRowBcast15, 0xA);
+  x |= (uint32_t)VF_BCAST(x, kRowBcast31, 0xC);
+  return readlane(x, 63);
 }
 
 __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
@@ -139,7 +145,9 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
   x = min(x, (uint32_t)VF_DPP(x, kQuadSwap2, 0xFFFFFFFFu));
   x = min(x, (uint32_t)VF_DPP(x, kRowHalfMirror, 0xFFFFFFFFu));
   x = min(x, (uint32_t)VF_DPP(x, kRowMirror, 0xFFFFFFFFu));
-  return min(min(readlane(x, 0), readlane(x, 16)), min(readlane(x, 32), readlane(x, 48)));
+  x = min(x, (uint32_t)VF_BCAST(x, kRowBcast15, 0xA));
+  x = min(x, (uint32_t)VF_BCAST(x, kRowBcast31, 0xC));
+  return readlane(x, 63);
 }
 
 // Number of set bits of mask in lanes below this one.

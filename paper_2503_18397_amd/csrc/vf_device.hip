@@ -448,10 +448,11 @@ struct BandCtl {
   uint32_t adv[2];               // 0: the word is taken again (window full)
   uint32_t k[2], gs[2];          // pivots of each batch and its segment
   uint32_t nq[2];                // slot groups in use during the batch's word
-  uint32_t nret[2];
+  uint32_t nret[2][2];           // returned slots per batch parity and emitter
   uint32_t bseq;                 // words whose batch wavefront 0 has published
   uint32_t slot[2][32], col[2][32], cm[2][32];
-  uint16_t ret[2][64];           // slots handed back to wavefront 0
+  uint16_t ret[2][2][64];        // slots handed back to the searching wavefront
+                                 // (kRetClear: its ring words still need clearing)
 };
 
 // Shard records in flight and their states.  Each state has one owner, the
@@ -484,7 +485,7 @@ struct PipeCtl {
   ShardRec rec[kSlots];
   uint32_t quit;     // no work is left and every record is free
   uint32_t abort;    // a wait ran out: every wavefront of the workgroup ends
-  uint32_t pair[2];  // barriers reached by each eliminating wavefront
+  uint32_t bar[3];   // barriers reached by each eliminating wavefront
   uint32_t pick;     // record the pair eliminates next (kSlots: none left)
 };
 constexpr uint32_t kPipeOff = (sizeof(BandCtl) + 15) & ~15u;
@@ -529,18 +530,22 @@ __device__ __forceinline__ void wait_for(PipeCtl *pc, uint32_t *work, F &&ready)
   }
 }
 
-// Barrier of the two eliminating wavefronts (the other wavefronts of the
+// Barrier of the three eliminating wavefronts (the other wavefronts of the
 // workgroup run loops of their own, so the workgroup barrier is not
 // available): each publishes how many barriers it has reached and waits
-// until its partner has reached as many.
-__device__ __forceinline__ void pair_sync(PipeCtl *pc, uint32_t *work, uint32_t me,
+// until the other two have reached as many.
+__device__ __forceinline__ void band_sync(PipeCtl *pc, uint32_t *work, uint32_t me,
                                           uint32_t &gen) {
   gen++;
-  lds_publish(&pc->pair[me], gen);
-  const uint32_t g = gen;
-  wait_for(pc, work, [&] { return lds_load(&pc->pair[me ^ 1u]) >= g; });
+  lds_publish(&pc->bar[me], gen);
+  const uint32_t g = gen, o1 = me == 0 ? 1u : 0u, o2 = me == 2 ? 1u : 2u;
+  wait_for(pc, work, [&] { return min(lds_load(&pc->bar[o1]), lds_load(&pc->bar[o2])) >= g; });
   acquire_wg();
 }
+
+// A returned slot whose ring words the searching wavefront clears before
+// reusing it (a pivot row another pivot of its batch reads).
+constexpr uint16_t kRetClear = 0x8000;
 
 // Gaussian elimination of the 2-core over GF(2) by the two wavefronts of
 // the workgroup.  Core rows enter the window when the sweep reaches their
@@ -588,12 +593,14 @@ __device__ __forceinline__ uint32_t xor_rows(const uint32_t *rows, uint32_t pivt
   return acc;
 }
 
+// wid: 0 searches the pivots, 1 and 2 emit (emitter wid - 1).
 template <int QM>
 __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint32_t W,
                                           const ShardBufs &sc, uint8_t *lds, BandCtl *ctl,
                                           uint32_t wid, uint32_t *np_out, PipeCtl *pc,
                                           uint32_t &gen) {
-  auto psync = [&] { pair_sync(pc, A.work, wid, gen); };
+  auto psync = [&] { band_sync(pc, A.work, wid, gen); };
+  const uint32_t em = wid - 1;  // emitter index (wid != 0)
   uint32_t *const plog = sc.plog;
   uint32_t *const poff = sc.poff;
   const uint32_t *const cb = sc.cb;
@@ -617,9 +624,10 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   auto uadd = [&](uint32_t u) { return u < RW ? u : RS * W + (u - RW); };
 
   // ring words of free slots are kept zero (dead rows are zero, emitted
-  // pivot rows are cleared by the emitter), so a row enters by setting its
-  // three bits
-  for (uint32_t i = wid * 64 + lane; i < W * RS; i += 128) rows[i] = 0;
+  // pivot rows are cleared by their emitter or, when another pivot of the
+  // batch reads them, by the searching wavefront before reuse), so a row
+  // enters by setting its three bits
+  for (uint32_t i = wid * 64 + lane; i < W * RS; i += 192) rows[i] = 0;
   // free slots form a stack that hands out low slots first; only slot groups
   // below the high-water mark are ever scanned
   if (wid == 0) {
@@ -629,14 +637,16 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
     }
     if (lane == 0) {
       ctl->flag[0] = ctl->flag[1] = 0;
-      ctl->nret[0] = ctl->nret[1] = 0;
+      ctl->nret[0][0] = ctl->nret[0][1] = ctl->nret[1][0] = ctl->nret[1][1] = 0;
       ctl->k[0] = ctl->k[1] = 0;
       ctl->bseq = 0;
     }
   }
   psync();
-  uint32_t nfree = W, NQ = 0;  // wavefront 0
-  uint32_t lp = 0, np = 0;     // wavefront 1
+  uint32_t nfree = W, NQ = 0;  // searching wavefront
+  // each emitter writes its own half of the pivot log
+  const uint32_t loglo = wid ? em * (logcap / 2) : 0u, loghi = loglo + logcap / 2;
+  uint32_t lp = loglo, np = 0;  // emitters
   const uint32_t gsh = entry_shift(G.sigma);
 
   // core rows [rb, re) join the window (wavefront 0; re - rb <= nfree)
@@ -663,18 +673,23 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
     }
   };
 
-  // pivot rows of batch bsel, last first (each only reads earlier pivots'
-  // rows, none of which is rewritten), their slots into return list rsel
-  // (wavefront 1); false if the log is full
+  // pivot rows of batch bsel with this emitter's parity, last first (a row
+  // reads only rows of earlier pivots, none of which is rewritten), their
+  // slots into return list rsel; false if the emitter's half of the log is
+  // full
   auto emit = [&](uint32_t bsel, uint32_t rsel) -> bool {
     const uint32_t kp = uniform(ctl->k[bsel]), Gs = uniform(ctl->gs[bsel]);
     const uint32_t pivtab = lane < kp ? ctl->slot[bsel][lane] : 0u;
     const uint32_t pivcol = lane < kp ? ctl->col[bsel][lane] : 0u;
     const uint32_t pivcm = lane < kp ? ctl->cm[bsel][lane] : 0u;
+    // pivots whose row another pivot of the batch reads (possibly the other
+    // emitter's): their slots go back uncleared
+    const uint32_t refd = wave_or(pivcm);
     // with segments of 32 or more vertices a ring word lies in one segment:
     // its bit bb is vertex vbase(u) + bb
     auto vbase = [&](uint32_t u) { return ring.three && u < RW ? ring.vertex(u * 32, Gs) : 0u; };
     const uint32_t vb0 = vbase(lane), mu0 = umul(lane), au0 = uadd(lane);
+    uint32_t nr = 0;
     // pivot kk; when the row and its right side fit one word per lane
     // (NW == 1), w0 is the lane's word of the pivot's row
     auto one = [&](int kk, uint32_t w0) -> bool {
@@ -683,7 +698,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       const uint32_t cmx = readlane(pivcm, kk);
       const uint32_t cb_ = ring.pos(col);
       // a record takes at most 4 + 32 RW words (every ring bit set)
-      if (lp + 4 + 32 * RW > logcap) return false;
+      if (lp + 4 + 32 * RW > loghi) return false;
       uint32_t pos = lp + 4;
       for (uint32_t w = 0; w < NW; w++) {
         const uint32_t u = w * 64 + lane;
@@ -712,37 +727,41 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           pos += (uint32_t)__popcll(m);
         }
       }
-      // the slot goes back with its ring words zero (no pivot emitted
-      // after this one reads it)
-      for (uint32_t w = 0; w < NW; w++)
-        if (w * 64 + lane < RW) rows[x * RS + w * 64 + lane] = 0u;
+      const bool keep = (refd >> kk) & 1u;
+      if (!keep)
+        for (uint32_t w = 0; w < NW; w++)
+          if (w * 64 + lane < RW) rows[x * RS + w * 64 + lane] = 0u;
       if (lane == 0) {
         plog[lp] = col;
         plog[lp + 1] = pos - (lp + 4);
         poff[np + (uint32_t)kk] = lp;
-        ctl->ret[rsel][kk] = (uint16_t)x;
+        ctl->ret[rsel][em][nr] = (uint16_t)(x | (keep ? kRetClear : 0u));
       }
+      nr++;
       lp = pos;
       return true;
     };
+    // this emitter's pivots: kk = em, em + 2, ..., last first
+    const int top = (int)kp - 1 - (int)(((kp - 1) ^ em) & 1u);
     if (NW == 1) {
       // the rows of up to eight pivots are loaded together
       const bool in = lane < RW + 2;
-      for (int k0 = (int)kp - 1; k0 >= 0; k0 -= 8) {
+      for (int k0 = top; k0 >= 0; k0 -= 16) {
         uint32_t wv[8];
 #pragma unroll
         for (int i = 0; i < 8; i++)
-          wv[i] = k0 - i >= 0 && in ? rows[__umul24(readlane(pivtab, k0 - i), mu0) + au0] : 0u;
+          wv[i] = k0 - 2 * i >= 0 && in ? rows[__umul24(readlane(pivtab, k0 - 2 * i), mu0) + au0]
+                                       : 0u;
 #pragma unroll
         for (int i = 0; i < 8; i++)
-          if (k0 - i >= 0 && !one(k0 - i, wv[i])) return false;
+          if (k0 - 2 * i >= 0 && !one(k0 - 2 * i, wv[i])) return false;
       }
     } else {
-      for (int kk = (int)kp - 1; kk >= 0; kk--)
+      for (int kk = top; kk >= 0; kk -= 2)
         if (!one(kk, 0u)) return false;
     }
     np += kp;
-    if (lane == 0) ctl->nret[rsel] = kp;
+    if (lane == 0) ctl->nret[rsel][em] = nr;
     return true;
   };
 
@@ -771,11 +790,11 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   // Active rows of a word (a bit within the word's columns) are gathered
   // into up to QM register groups in slot order ("compact" index c =
   // group * 64 + lane); csl holds their slots (kNoSlot past the last).
-  // Wavefront 1 takes the rows whose compact index is below kW1Share mod 8
-  // through the rows' padding words, wavefront 0 the others from its
-  // registers.
-  constexpr uint32_t kNoSlot = 0xFFFFu, kW1Share = 3;
-  auto w1share = [](uint32_t c) { return (c & 7u) < kW1Share; };
+  // The searching wavefront takes the rows whose compact index is below
+  // kW0Share mod 8 from its registers; the emitters take the others through
+  // the rows' padding words, split by slot parity.
+  constexpr uint32_t kNoSlot = 0xFFFFu, kW0Share = 3;
+  auto w1share = [](uint32_t c) { return (c & 7u) >= kW0Share; };
   uint32_t csl[QM], ccw[QM], cpop[QM], ccm[QM];
   uint32_t it = 0;
   bool stop = false;
@@ -795,10 +814,19 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       const uint32_t cur = it & 1u, prev = cur ^ 1u;
       bool incons = false;
       if (wid == 0) {
-        // slots emitted during the previous word come back
-        const uint32_t nr = uniform(ctl->nret[prev]);
-        if (lane < nr) freel[nfree + lane] = (uint16_t)ctl->ret[prev][lane];
-        nfree += nr;
+        // slots emitted during the previous word come back (those marked
+        // kRetClear with their ring words cleared here)
+        for (uint32_t e2 = 0; e2 < 2; e2++) {
+          const uint32_t nr = uniform(ctl->nret[prev][e2]);
+          const uint32_t ent = lane < nr ? (uint32_t)ctl->ret[prev][e2][lane] : 0u;
+          for (uint64_t fm = __ballot(lane < nr && (ent & kRetClear)); fm; fm &= fm - 1) {
+            const uint32_t x = readlane(ent, (int)(__ffsll((long long)fm) - 1)) & ~(uint32_t)kRetClear;
+            for (uint32_t w = 0; w < NW; w++)
+              if (w * 64 + lane < RW) rows[x * RS + w * 64 + lane] = 0u;
+          }
+          if (lane < nr) freel[nfree + lane] = (uint16_t)(ent & ~(uint32_t)kRetClear);
+          nfree += nr;
+        }
         wave_sync();
         // rows whose top vertex is in this word (segment, below 32 vertices)
         uint32_t rb = 0, re = 0;
@@ -1016,10 +1044,10 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
         if (!published) publish();
       } else {
         if (it == 0) {
-          if (lane == 0) ctl->nret[cur] = 0;
+          if (lane == 0) ctl->nret[cur][em] = 0;
         } else if (!emit(prev, cur)) {
           if (lane == 0) {
-            ctl->nret[cur] = 0;
+            ctl->nret[cur][em] = 0;
             atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
           }
         }
@@ -1027,16 +1055,16 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
         const uint32_t want = it + 1;
         wait_for(pc, A.work, [&] { return lds_load(&ctl->bseq) >= want; });
         acquire_wg();
-        // 2. whole rows, wavefront 1's share: rows whose padding word holds
-        //    a mask
+        // 2. whole rows, the emitters' share: rows whose padding word holds
+        //    a mask, this emitter's slot parity
         if (const uint32_t kc = uniform(ctl->k[cur])) {
           const uint32_t ptab = lane < kc ? ctl->slot[cur][lane] : 0u;
           const uint32_t nq = uniform(ctl->nq[cur]);
-          uint32_t nr = uniform(ctl->nret[cur]);
+          uint32_t nr = uniform(ctl->nret[cur][em]);
           for (uint32_t q = 0; q < nq; q++) {
             const uint32_t slot = q * 64 + lane;
             const uint32_t cmv = slot < W ? rows[(uint64_t)slot * RS + RW] : 0u;
-            uint64_t m = __ballot(cmv != 0);
+            uint64_t m = __ballot(cmv != 0 && (slot & 1u) == em);
             while (m) {
               const uint32_t xl = (uint32_t)(__ffsll((long long)m) - 1);
               m &= m - 1;
@@ -1046,13 +1074,13 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
                 incons |= rset;
                 if (lane == 0) {
                   rpop[x] = 0;
-                  if (nr < 64) ctl->ret[cur][nr] = (uint16_t)x;
+                  if (nr < 64) ctl->ret[cur][em][nr] = (uint16_t)x;
                 }
                 nr = nr < 64 ? nr + 1 : nr;  // beyond 64 a dead slot stays taken
               }
             }
           }
-          if (lane == 0) ctl->nret[cur] = nr;
+          if (lane == 0) ctl->nret[cur][em] = nr;
         }
       }
       if (incons && lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveInconsistent);
@@ -1074,10 +1102,10 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   } else {
     // the pivots of the last word
     const uint32_t cur = it & 1u, prev = cur ^ 1u;
-    if (wid == 1) {
+    if (wid != 0) {
       if (it > 0 && !emit(prev, cur) && lane == 0)
         atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
-      if (lane == 0) ctl->np = np;
+      if (wid == 1 && lane == 0) ctl->np = np;
     }
     psync();
     fl = uniform(ctl->flag[cur]);
@@ -1177,14 +1205,14 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
   return (uint64_t)uniform((uint32_t)x) | ((uint64_t)uniform((uint32_t)(x >> 32)) << 32);
 }
 
-// A grid of workgroups of four wavefronts takes work items (shards, or
+// A grid of workgroups of five wavefronts takes work items (shards, or
 // instances of a batch) from a shared counter until none is left.  Within a
 // workgroup the items flow through three stages, each on its own records:
 //  - wavefront 2 takes an item, computes its right sides, then per attempt
 //    its edges, peeling order and 2-core; it retries failed attempts with
 //    the next local seed and clears the cells of items that fail them all;
-//  - wavefronts 0 and 1 eliminate the 2-core of the oldest ready record
-//    (wavefront 1 emitting the pivot rows);
+//  - wavefronts 0, 1 and 4 eliminate the 2-core of the oldest ready record
+//    (0 searches the pivots, 1 and 4 emit the pivot rows);
 //  - wavefront 3 assigns the cells of solved records.
 // Peeling, elimination and assignment of consecutive items thus overlap.
 template <typename T, int QM>
@@ -1207,7 +1235,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   if (threadIdx.x == 0) {
     pc->quit = 0;
     pc->abort = 0;
-    pc->pair[0] = pc->pair[1] = 0;
+    pc->bar[0] = pc->bar[1] = pc->bar[2] = 0;
     pc->pick = kSlots;
   }
   // the only workgroup barrier: from here on the stages meet through records
@@ -1533,11 +1561,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       }
       attempts(s, t0);
     }
-  } else if (wid < 2) {
-    // ------------------------------------------ elimination (wavefronts 0, 1)
+  } else if (wid != 3) {
+    // -------------------------------------- elimination (wavefronts 0, 1, 4)
+    const uint32_t bw = wid == 4 ? 2u : wid;  // 0: search, 1 and 2: emit
     uint32_t gen = 0;
     for (;;) {
-      if (wid == 0) {
+      if (bw == 0) {
         uint32_t s = kSlots;
         wait_for(pc, A.work, [&] {
           uint32_t best = 0xFFFFFFFFu;
@@ -1558,15 +1587,15 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
           pc->pick = s;
         }
       }
-      pair_sync(pc, A.work, wid, gen);
+      band_sync(pc, A.work, bw, gen);
       const uint32_t s = lds_load(&pc->pick);
       if (s >= kSlots) break;
       const ShardBufs sb = bufs(s);
       const Geo G = geo(s);
       const uint32_t W = min(A.wmax, window_slots_for(G.sigma, A.lds_bytes));
       uint32_t np = 0;
-      const int st = band_solve<QM>(A, G, W, sb, lds, ctl, wid, &np, pc, gen);
-      if (wid == 0) {
+      const int st = band_solve<QM>(A, G, W, sb, lds, ctl, bw, &np, pc, gen);
+      if (bw == 0) {
         const uint32_t j = uniform(rec[s].shard), t = uniform(rec[s].t);
         uint32_t next = kRecSolved;
         if (st == kSolveCapacity) {

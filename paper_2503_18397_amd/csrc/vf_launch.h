@@ -95,10 +95,10 @@ constexpr uint32_t kLdsBudget = 160 * 1024;  // LDS of one CU
 // Bytes at the end of a build workgroup's dynamic LDS that hold the control
 // blocks shared by its wavefronts and the back-substitution columns.
 constexpr uint32_t kLdsTail = 2048;
-// Threads of a build workgroup: two wavefronts eliminate (one searches the
-// pivots, the other emits the pivot rows), one peels the next item and one
+// Threads of a build workgroup: three wavefronts eliminate (one searches
+// the pivots, two emit the pivot rows), one peels the next item and one
 // assigns the cells of solved items.
-constexpr uint32_t kBuildThreads = 256;
+constexpr uint32_t kBuildThreads = 320;
 
 uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap);
 uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes);

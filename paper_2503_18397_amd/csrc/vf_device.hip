@@ -896,6 +896,10 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
                 best = min(best, has[g] ? key : 0xFFFFFFFFu);
               }
               best = wave_min(best);
+              if (best == 0xFFFFFFFFu) {  // every row that held this column lost it
+                colmask &= bit - 1u;
+                continue;
+              }
               const uint32_t p = best & 0xFFFFu, pg = p >> 6, pl = p & 63u;
               const uint32_t dpop = (best >> 16) - 2u;
               uint32_t pw = 0, pcm = 0, ps = 0;
@@ -914,7 +918,6 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
               }
               if (lane == pl) cpiv |= 1u << pg;
               const uint32_t kbit = pcm | (1u << k);
-              orv = 0;
 #pragma unroll
               for (int g = 0; g < NC; g++) {
                 if (has[g]) {
@@ -922,10 +925,12 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
                   ccm[g] ^= kbit;
                   cpop[g] = min(cpop[g] + dpop, 0xFFFFu);
                 }
-                orv |= ccw[g];
               }
               k++;
-              colmask = wave_or(orv) & (bit - 1u);
+              // columns below b that may still have rows: the earlier ones
+              // and those of the pivot word (a column whose rows all lost
+              // it is skipped when visited)
+              colmask = (colmask | pw) & (bit - 1u);
             }
             if (k) {
               // popcount estimates back to LDS (zero marks a pivot row, no

@@ -483,6 +483,8 @@ struct ShardRec {
 };
 struct PipeCtl {
   ShardRec rec[kSlots];
+  uint32_t fcnt[7];  // list counts of a peel (see the peeling stage)
+  uint32_t first[2]; // the workgroup's first work item and its first seed
   uint32_t quit;     // no work is left and every record is free
   uint32_t abort;    // a wait ran out: every wavefront of the workgroup ends
   uint32_t bar[3];   // barriers reached by each eliminating wavefront
@@ -1257,206 +1259,322 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
     return G;
   };
 
-  if (wid == 2) {
-    // ------------------------------------------------ peeling (wavefront 2)
+  // ------------------------------------------------------------ peeling
+  // Peeling of an item is done by wavefront 2, except for the workgroup's
+  // first item, which all five wavefronts peel together (nothing else can
+  // run before it).  The helpers below take the calling threads' index tid
+  // in [0, nthr) and sync(), which orders their memory operations (the
+  // workgroup barrier, or a wavefront fence when one wavefront calls).
+  uint32_t *f_deg, *f_xr, *f_F0, *f_F1, *f_cc;
+  uint8_t *f_pe;
+  {
     FrontBufs fb;
     front_layout(wbase + (uint64_t)kSlots * slot_bytes, A.M, A.scr_V, A.scr_l, &fb);
+    f_deg = fb.deg;
+    f_xr = fb.xr;
+    f_F0 = fb.F0;
+    f_F1 = fb.F1;
+    f_cc = fb.cc;
+    f_pe = fb.pe;
+  }
+  uint32_t *const fcnt = pc->fcnt;
 
-    // edges, peeling order and grouped 2-core of attempt t; early = 1: two
-    // 2-core rows contradict each other, 2: an MWHC hypergraph did not peel
-    auto front = [&](const Geo &G, const ShardBufs &sb, uint32_t m, uint64_t base, uint32_t t,
-                     uint32_t &k_out, uint32_t &rounds_out, uint32_t &early_out) {
-      const uint64_t V = G.V;
-      uint64_t *const E = sb.E;
-      const uint64_t *const R = sb.R;
-      uint32_t *const stk = sb.stack, *const rst = sb.rst;
-      uint32_t nrounds = 0;
-      // edges of this attempt, cleared vertex state
-      for (uint32_t i = lane; i < m; i += 64) {
-        const uint64_t key = A.bkeys[base + i];
-        uint32_t v0, v1, v2;
-        edge3(G, fin64(key ^ G.khi), fin64(key ^ G.klo), t, v0, v1, v2);
-        E[i] = pack3(v0, v1, v2);
-        fb.pe[i] = 0;
+  // edges, peeling order and grouped 2-core of attempt t; early = 1: two
+  // 2-core rows contradict each other, 2: an MWHC hypergraph did not peel.
+  // List appends count in LDS: fcnt[0] the degree-one vertices, fcnt[1]
+  // the peeled edges, fcnt[2 + r mod 3] the vertices freed by round r (a
+  // count is reset a round before its use, after everyone has read its
+  // previous value), fcnt[5] the 2-core size, fcnt[6] a contradiction.
+  auto front = [&](const Geo &G, const ShardBufs &sb, uint32_t m, uint64_t base, uint32_t t,
+                   uint32_t tid, uint32_t nthr, auto &&sync, uint32_t &k_out,
+                   uint32_t &rounds_out, uint32_t &early_out) {
+    const uint64_t V = G.V;
+    uint64_t *const E = sb.E;
+    const uint64_t *const R = sb.R;
+    uint32_t *const stk = sb.stack, *const rst = sb.rst;
+    const uint32_t w0t = tid - lane;  // this wavefront's first thread
+    const FrontBufs fb{f_deg, f_xr, f_pe, f_F0, f_F1, f_cc};
+    uint32_t nrounds = 0;
+    if (tid == 0)
+      for (int i = 0; i < 7; i++) fcnt[i] = 0;
+    // edges of this attempt, cleared vertex state
+    for (uint32_t i = tid; i < m; i += nthr) {
+      const uint64_t key = A.bkeys[base + i];
+      uint32_t v0, v1, v2;
+      edge3(G, fin64(key ^ G.khi), fin64(key ^ G.klo), t, v0, v1, v2);
+      E[i] = pack3(v0, v1, v2);
+      fb.pe[i] = 0;
+    }
+    for (uint64_t v = tid; v < V; v += nthr) {
+      fb.deg[v] = 0;
+      fb.xr[v] = 0;
+    }
+    sync();
+    // incidence: degree and xor of incident edges
+    for (uint32_t i = tid; i < m; i += nthr) {
+      uint32_t v[3];
+      unpack3(E[i], v);
+      for (int k = 0; k < 3; k++) {
+        atomicAdd(&fb.deg[v[k]], 1u);
+        atomicXor(&fb.xr[v[k]], i);
       }
-      for (uint64_t v = lane; v < V; v += 64) {
-        fb.deg[v] = 0;
-        fb.xr[v] = 0;
-      }
-      wave_sync_global();
-      // incidence: degree and xor of incident edges
-      for (uint32_t i = lane; i < m; i += 64) {
-        uint32_t v[3];
-        unpack3(E[i], v);
-        for (int k = 0; k < 3; k++) {
-          atomicAdd(&fb.deg[v[k]], 1u);
-          atomicXor(&fb.xr[v[k]], i);
-        }
-      }
-      wave_sync_global();
-      // round-synchronous peeling; list appends are counted by ballot
-      uint32_t nf = 0;
-      for (uint64_t v0 = 0; v0 < V; v0 += 64) {
-        const uint64_t v = v0 + lane;
-        const bool one = v < V && fb.deg[v] == 1;
-        const uint64_t bm = __ballot(one);
-        if (one) fb.F0[nf + lanes_below(bm)] = (uint32_t)v;
-        nf += (uint32_t)__popcll(bm);
-      }
-      wave_sync_global();
-      uint32_t nst = 0;
-      uint32_t *cur = fb.F0, *nxt = fb.F1;
-      if (lane == 0) rst[0] = 0;
-      while (nf) {
-        const uint32_t r0 = nst;
-        // select with the degrees of the start of the round
-        for (uint32_t i0 = 0; i0 < nf; i0 += 64) {
-          const uint32_t i = i0 + lane;
-          bool take = false;
-          uint32_t e = 0, side = 0;
-          if (i < nf) {
-            const uint32_t v = cur[i];
-            if (fb.deg[v] == 1) {
-              e = fb.xr[v];
-              uint32_t a[3];
-              unpack3(E[e], a);
-              side = a[0] == v ? 0u : (a[1] == v ? 1u : 2u);
-              take = true;
-              for (uint32_t k = 0; k < side; k++)
-                if (fb.deg[a[k]] == 1) take = false;
-            }
-          }
-          const uint64_t bm = __ballot(take);
-          if (take) {
-            stk[nst + lanes_below(bm)] = e | (side << 30);
-            fb.pe[e] = 1;
-          }
-          nst += (uint32_t)__popcll(bm);
-        }
-        wave_sync_global();
-        // remove the selected edges
-        uint32_t nn = 0;
-        for (uint32_t i0 = r0; i0 < nst; i0 += 64) {
-          const uint32_t i = i0 + lane;
-          bool push[3] = {false, false, false};
-          uint32_t a[3] = {0, 0, 0};
-          if (i < nst) {
-            const uint32_t e = stk[i] & 0x3FFFFFFFu;
+    }
+    sync();
+    // round-synchronous peeling
+    for (uint64_t v0 = w0t; v0 < V; v0 += nthr) {
+      const uint64_t v = v0 + lane;
+      const bool one = v < V && fb.deg[v] == 1;
+      const uint32_t at = wave_append(one, &fcnt[0]);
+      if (one) fb.F0[at] = (uint32_t)v;
+    }
+    sync();
+    uint32_t nf = lds_load(&fcnt[0]), nst = 0;
+    uint32_t *cur = fb.F0, *nxt = fb.F1;
+    if (tid == 0) rst[0] = 0;
+    while (nf) {
+      const uint32_t r0 = nst;
+      uint32_t *const ncnt = &fcnt[2 + nrounds % 3];
+      if (tid == 0) fcnt[2 + (nrounds + 1) % 3] = 0;
+      // select with the degrees of the start of the round
+      for (uint32_t i0 = w0t; i0 < nf; i0 += nthr) {
+        const uint32_t i = i0 + lane;
+        bool take = false;
+        uint32_t e = 0, side = 0;
+        if (i < nf) {
+          const uint32_t v = cur[i];
+          if (fb.deg[v] == 1) {
+            e = fb.xr[v];
+            uint32_t a[3];
             unpack3(E[e], a);
-            for (int k = 0; k < 3; k++) {
-              const uint32_t old = atomicSub(&fb.deg[a[k]], 1u);
-              atomicXor(&fb.xr[a[k]], e);
-              push[k] = old == 2;
-            }
+            side = a[0] == v ? 0u : (a[1] == v ? 1u : 2u);
+            take = true;
+            for (uint32_t k = 0; k < side; k++)
+              if (fb.deg[a[k]] == 1) take = false;
           }
+        }
+        const uint32_t at = wave_append(take, &fcnt[1]);
+        if (take) {
+          stk[at] = e | (side << 30);
+          fb.pe[e] = 1;
+        }
+      }
+      sync();
+      nst = lds_load(&fcnt[1]);
+      // remove the selected edges
+      for (uint32_t i0 = r0 + w0t; i0 < nst; i0 += nthr) {
+        const uint32_t i = i0 + lane;
+        bool push[3] = {false, false, false};
+        uint32_t a[3] = {0, 0, 0};
+        if (i < nst) {
+          const uint32_t e = stk[i] & 0x3FFFFFFFu;
+          unpack3(E[e], a);
           for (int k = 0; k < 3; k++) {
-            const uint64_t bm = __ballot(push[k]);
-            if (push[k]) nxt[nn + lanes_below(bm)] = a[k];
-            nn += (uint32_t)__popcll(bm);
+            const uint32_t old = atomicSub(&fb.deg[a[k]], 1u);
+            atomicXor(&fb.xr[a[k]], e);
+            push[k] = old == 2;
           }
         }
-        nrounds++;
-        if (lane == 0) rst[nrounds] = nst;
-        wave_sync_global();
-        nf = nn;
-        uint32_t *tmp = cur;
-        cur = nxt;
-        nxt = tmp;
+        for (int k = 0; k < 3; k++) {
+          const uint32_t at = wave_append(push[k], ncnt);
+          if (push[k]) nxt[at] = a[k];
+        }
       }
+      nrounds++;
+      if (tid == 0) rst[nrounds] = nst;
+      sync();
+      nf = lds_load(ncnt);
+      uint32_t *tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+    }
 
-      // 2-core edges, grouped by the entry group of their top vertex (an
-      // MWHC hypergraph is peel-only: only its unpeeled edges are counted)
-      uint32_t k;
-      if (G.mwhc) {
-        uint32_t left = 0;
-        for (uint32_t i = lane; i < m; i += 64) left += fb.pe[i] ? 0u : 1u;
-        k = wave_sum(left);
+    // 2-core edges, grouped by the entry group of their top vertex (an
+    // MWHC hypergraph is peel-only: only its unpeeled edges are counted)
+    uint32_t k;
+    if (G.mwhc) {
+      uint32_t left = 0;
+      for (uint32_t i = tid; i < m; i += nthr) left += fb.pe[i] ? 0u : 1u;
+      left = wave_sum(left);
+      if (lane == 0 && left) atomicAdd(&fcnt[5], left);
+      sync();
+      k = lds_load(&fcnt[5]);
+    } else {
+      const uint32_t gsh = entry_shift(G.sigma);
+      const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
+      for (uint32_t g = tid; g < ngroups; g += nthr) fb.cc[g] = 0;
+      sync();
+      for (uint32_t i = tid; i < m; i += nthr)
+        if (!fb.pe[i]) atomicAdd(&fb.cc[(uint32_t)(E[i] >> 42) >> gsh], 1u);
+      sync();
+      if (tid < 64) {  // one wavefront scans the group counts
+        const uint32_t kk = wave_scan_array(fb.cc, sb.cb, ngroups);
+        if (tid == 0) fcnt[5] = kk;
+      }
+      sync();
+      k = lds_load(&fcnt[5]);
+      for (uint32_t i = tid; i < m; i += nthr)
+        if (!fb.pe[i]) {
+          const uint64_t e = E[i];
+          const uint32_t pos = atomicAdd(&fb.cc[(uint32_t)(e >> 42) >> gsh], 1u);
+          sb.cE[pos] = e;
+          sb.cR[pos] = R[i];
+        }
+      sync();
+    }
+    // MWHC is peel-only: any unpeeled edge ends the attempt (kind 2).
+    // Otherwise two 2-core rows with the same vertices and different right
+    // sides (the usual reason for an inconsistent system) end the attempt
+    // before the elimination: rows are listed by top vertex in the degree
+    // array, which peeling no longer needs
+    const uint32_t kl = G.mwhc ? 0u : k;
+    uint32_t *const head = fb.deg, *const next = fb.F0;
+    if (kl)
+      for (uint64_t v = tid; v < V; v += nthr) head[v] = 0xFFFFFFFFu;
+    sync();
+    for (uint32_t i = tid; i < kl; i += nthr)
+      next[i] = atomicExch(&head[(uint32_t)(sb.cE[i] >> 42)], i);
+    sync();
+    bool clash = false;
+    for (uint32_t i = tid; i < kl; i += nthr) {
+      const uint64_t e = sb.cE[i], r = sb.cR[i];
+      for (uint32_t x = next[i]; x != 0xFFFFFFFFu; x = next[x])
+        clash |= sb.cE[x] == e && sb.cR[x] != r;
+    }
+    if (__ballot(clash) != 0 && lane == 0) atomicOr(&fcnt[6], 1u);
+    sync();
+    const bool dup = lds_load(&fcnt[6]) != 0;
+    k_out = k;
+    rounds_out = nrounds;
+    early_out = G.mwhc && k ? 2u : (dup ? 1u : 0u);
+  };
+
+  // cells of a failed item are zero, its local seed 255
+  auto clear = [&](uint32_t s, uint32_t tid, uint32_t nthr) {
+    const uint64_t V = uniform64(rec[s].V);
+    T *const wg = (T *)uniform64(rec[s].cells);
+    for (uint64_t v = tid; v < V; v += nthr) wg[v] = (T)0;
+    if (tid == 0) A.tseed[uniform(rec[s].shard)] = 255;
+  };
+
+  uint32_t order = 0;  // peeling wavefront: records made ready so far
+  // attempts t, t + 1, ... of record s until one leaves a 2-core for the
+  // elimination (ready) or none (solved); every attempt failing clears the
+  // cells (free)
+  auto attempts = [&](uint32_t s, uint32_t t, uint32_t tid, uint32_t nthr, auto &&sync) {
+    const uint32_t j = uniform(rec[s].shard), m = uniform(rec[s].m);
+    const uint64_t base = uniform64(rec[s].base);
+    const ShardBufs sb = bufs(s);
+    const Geo G = geo(s);
+    for (; t < A.tmax; t++) {
+      uint32_t k, nrounds, early;
+      front(G, sb, m, base, t, tid, nthr, sync, k, nrounds, early);
+      if (early) {
+        if (tid == 0) {
+          const uint32_t idx = atomicAdd(&A.work[kWorkFails], 1u);
+          if (idx < A.fail_cap) A.fails[idx] = FailRec{j, t, early, k};
+        }
+        continue;
+      }
+      if (tid == 0) {
+        rec[s].t = t;
+        rec[s].core = k;
+        rec[s].rounds = nrounds;
+        rec[s].np = 0;
+        rec[s].order = order;
+      }
+      order += k ? 1u : 0u;
+      sync();
+      if (tid < 64) lds_publish(&rec[s].state, k ? kRecReady : kRecSolved);
+      return;
+    }
+    clear(s, tid, nthr);
+    sync();
+    if (tid < 64) lds_publish(&rec[s].state, kRecFree);
+  };
+
+  // the next work item and its first local seed (one lane); j = ~0: none
+  auto next_item = [&](uint32_t &j, uint32_t &t0) {
+    j = atomicAdd(&A.work[kWorkNext], 1u);
+    t0 = 0;
+    if (A.list) {
+      if (j < (A.nlist_dev ? *A.nlist_dev : A.nlist)) {
+        t0 = A.list[2 * j + 1];
+        j = A.list[2 * j];
       } else {
-        const uint32_t gsh = entry_shift(G.sigma);
-        const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
-        for (uint32_t g = lane; g < ngroups; g += 64) fb.cc[g] = 0;
-        wave_sync_global();
-        for (uint32_t i = lane; i < m; i += 64)
-          if (!fb.pe[i]) atomicAdd(&fb.cc[(uint32_t)(E[i] >> 42) >> gsh], 1u);
-        wave_sync_global();
-        k = wave_scan_array(fb.cc, sb.cb, ngroups);
-        wave_sync_global();
-        for (uint32_t i = lane; i < m; i += 64)
-          if (!fb.pe[i]) {
-            const uint64_t e = E[i];
-            const uint32_t pos = atomicAdd(&fb.cc[(uint32_t)(e >> 42) >> gsh], 1u);
-            sb.cE[pos] = e;
-            sb.cR[pos] = R[i];
-          }
-        wave_sync_global();
+        j = 0xFFFFFFFFu;
       }
-      // MWHC is peel-only: any unpeeled edge ends the attempt (kind 2).
-      // Otherwise two 2-core rows with the same vertices and different
-      // right sides (the usual reason for an inconsistent system) end the
-      // attempt before the elimination: rows are listed by top vertex in
-      // the degree array, which peeling no longer needs
-      const uint32_t kl = G.mwhc ? 0u : k;
-      uint32_t *const head = fb.deg, *const next = fb.F0;
-      if (kl)
-        for (uint64_t v = lane; v < V; v += 64) head[v] = 0xFFFFFFFFu;
-      wave_sync_global();
-      for (uint32_t i = lane; i < kl; i += 64)
-        next[i] = atomicExch(&head[(uint32_t)(sb.cE[i] >> 42)], i);
-      wave_sync_global();
-      bool clash = false;
-      for (uint32_t i = lane; i < kl; i += 64) {
-        const uint64_t e = sb.cE[i], r = sb.cR[i];
-        for (uint32_t x = next[i]; x != 0xFFFFFFFFu; x = next[x])
-          clash |= sb.cE[x] == e && sb.cR[x] != r;
+    } else if (j >= A.G.S) {
+      j = 0xFFFFFFFFu;
+    }
+  };
+  // record s takes item j (one lane)
+  auto fill = [&](uint32_t s, uint32_t j, uint32_t t0) {
+    ShardRec &r = rec[s];
+    r.state = kRecFront;
+    r.shard = j;
+    r.t = t0;
+    if (A.items) {
+      const BatchItem it = A.items[j];
+      r.V = it.V;
+      r.vmask = it.vmask;
+      r.l = it.l;
+      r.sigma = it.sigma;
+      r.b = it.b;
+      r.base = it.key_off;
+      r.m = it.n;
+      r.cells = (uint64_t)((uint8_t *)A.cells + it.cell_off);
+    } else {
+      r.V = A.G.V;
+      r.vmask = A.G.vmask;
+      r.l = A.G.l;
+      r.sigma = A.G.sigma;
+      r.b = A.G.b;
+      r.base = A.offsets[j];
+      r.m = (uint32_t)(A.offsets[j + 1] - A.offsets[j]);
+      r.cells = (uint64_t)((T *)A.cells + (uint64_t)j * A.G.V);
+    }
+  };
+  // right sides of record s: values (Problem 1) or fingerprints (Problem 2)
+  auto rights = [&](uint32_t s, uint32_t tid, uint32_t nthr) {
+    const Geo G = geo(s);
+    const ShardBufs sb = bufs(s);
+    const uint32_t m = uniform(rec[s].m);
+    const uint64_t base = uniform64(rec[s].base);
+    for (uint32_t i = tid; i < m; i += nthr) {
+      const uint64_t key = A.bkeys[base + i];
+      if (G.is_filter) {
+        sb.R[i] = fingerprint(G, fin64(key ^ G.khi), fin64(key ^ G.klo));
+      } else {
+        sb.R[i] = A.bvals[base + i] & G.vmask;
       }
-      const bool dup = __ballot(clash) != 0;
-      k_out = k;
-      rounds_out = nrounds;
-      early_out = G.mwhc && k ? 2u : (dup ? 1u : 0u);
-    };
+    }
+  };
 
-    // cells of a failed item are zero, its local seed 255
-    auto clear = [&](uint32_t s) {
-      const uint64_t V = uniform64(rec[s].V);
-      T *const wg = (T *)uniform64(rec[s].cells);
-      for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
-      if (lane == 0) A.tseed[uniform(rec[s].shard)] = 255;
-    };
+  // the workgroup's first item, peeled by all five wavefronts into record 0
+  bool exhausted;
+  {
+    auto bar = [] { __syncthreads(); };
+    if (threadIdx.x == 0) {
+      uint32_t j, t0;
+      next_item(j, t0);
+      pc->first[0] = j;
+      pc->first[1] = t0;
+      if (j != 0xFFFFFFFFu) fill(0, j, t0);
+    }
+    __syncthreads();
+    const uint32_t j = lds_load(&pc->first[0]), t0 = lds_load(&pc->first[1]);
+    exhausted = j == 0xFFFFFFFFu;
+    if (!exhausted) {
+      rights(0, threadIdx.x, kBuildThreads);
+      __syncthreads();
+      attempts(0, t0, threadIdx.x, kBuildThreads, bar);
+    }
+    __syncthreads();
+  }
 
-    uint32_t order = 0;
-    // attempts t, t + 1, ... of record s until one leaves a 2-core for the
-    // elimination (ready) or none (solved)
-    auto attempts = [&](uint32_t s, uint32_t t) {
-      const uint32_t j = uniform(rec[s].shard), m = uniform(rec[s].m);
-      const uint64_t base = uniform64(rec[s].base);
-      const ShardBufs sb = bufs(s);
-      const Geo G = geo(s);
-      for (; t < A.tmax; t++) {
-        uint32_t k, nrounds, early;
-        front(G, sb, m, base, t, k, nrounds, early);
-        if (early) {
-          if (lane == 0) {
-            const uint32_t idx = atomicAdd(&A.work[kWorkFails], 1u);
-            if (idx < A.fail_cap) A.fails[idx] = FailRec{j, t, early, k};
-          }
-          continue;
-        }
-        if (lane == 0) {
-          rec[s].t = t;
-          rec[s].core = k;
-          rec[s].rounds = nrounds;
-          rec[s].np = 0;
-          rec[s].order = order;
-        }
-        order += k ? 1u : 0u;
-        lds_publish(&rec[s].state, k ? kRecReady : kRecSolved);
-        return;
-      }
-      clear(s);
-      lds_publish(&rec[s].state, kRecFree);
-    };
-
-    bool exhausted = false;
+  if (wid == 2) {
+    // ------------------------------------------------ peeling (wavefront 2)
+    auto wsync = [] { wave_sync_global(); };
     for (;;) {
       // failed eliminations first, then a new item into a free record once
       // no record waits for the elimination (taking items further ahead
@@ -1492,79 +1610,29 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         break;
       }
       if (what == kRecGiveUp) {
-        clear(s);
+        clear(s, lane, 64);
+        wave_sync_global();
         lds_publish(&rec[s].state, kRecFree);
         continue;
       }
       if (what == kRecRetry) {
         if (lane == 0) rec[s].state = kRecFront;
-        attempts(s, uniform(rec[s].t) + 1u);
+        attempts(s, uniform(rec[s].t) + 1u, lane, 64, wsync);
         continue;
       }
       // the next work item
       uint32_t j = 0xFFFFFFFFu, t0 = 0;
-      if (lane == 0) {
-        j = atomicAdd(&A.work[kWorkNext], 1u);
-        if (A.list) {
-          if (j < (A.nlist_dev ? *A.nlist_dev : A.nlist)) {
-            t0 = A.list[2 * j + 1];
-            j = A.list[2 * j];
-          } else {
-            j = 0xFFFFFFFFu;
-          }
-        } else if (j >= A.G.S) {
-          j = 0xFFFFFFFFu;
-        }
-      }
+      if (lane == 0) next_item(j, t0);
       j = uniform(j);
       t0 = uniform(t0);
       if (j == 0xFFFFFFFFu) {
         exhausted = true;
         continue;
       }
-      if (lane == 0) {
-        ShardRec &r = rec[s];
-        r.state = kRecFront;
-        r.shard = j;
-        r.t = t0;
-        if (A.items) {
-          const BatchItem it = A.items[j];
-          r.V = it.V;
-          r.vmask = it.vmask;
-          r.l = it.l;
-          r.sigma = it.sigma;
-          r.b = it.b;
-          r.base = it.key_off;
-          r.m = it.n;
-          r.cells = (uint64_t)((uint8_t *)A.cells + it.cell_off);
-        } else {
-          r.V = A.G.V;
-          r.vmask = A.G.vmask;
-          r.l = A.G.l;
-          r.sigma = A.G.sigma;
-          r.b = A.G.b;
-          r.base = A.offsets[j];
-          r.m = (uint32_t)(A.offsets[j + 1] - A.offsets[j]);
-          r.cells = (uint64_t)((T *)A.cells + (uint64_t)j * A.G.V);
-        }
-      }
+      if (lane == 0) fill(s, j, t0);
       wave_sync();
-      {
-        // right sides: values (Problem 1) or fingerprints (Problem 2)
-        const Geo G = geo(s);
-        const ShardBufs sb = bufs(s);
-        const uint32_t m = uniform(rec[s].m);
-        const uint64_t base = uniform64(rec[s].base);
-        for (uint32_t i = lane; i < m; i += 64) {
-          const uint64_t key = A.bkeys[base + i];
-          if (G.is_filter) {
-            sb.R[i] = fingerprint(G, fin64(key ^ G.khi), fin64(key ^ G.klo));
-          } else {
-            sb.R[i] = A.bvals[base + i] & G.vmask;
-          }
-        }
-      }
-      attempts(s, t0);
+      rights(s, lane, 64);
+      attempts(s, t0, lane, 64, wsync);
     }
   } else if (wid != 3) {
     // -------------------------------------- elimination (wavefronts 0, 1, 4)

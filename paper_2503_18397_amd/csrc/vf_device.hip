@@ -652,12 +652,17 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   const uint32_t gsh = entry_shift(G.sigma);
 
   // core rows [rb, re) join the window (wavefront 0; re - rb <= nfree)
+  // The rows of the next word are loaded while the current word is
+  // searched (pre_rb: the first row they hold, ~0: none).
+  uint64_t pre_e = 0, pre_r = 0;
+  uint32_t pre_rb = 0xFFFFFFFFu;
   auto enter = [&](uint32_t rb, uint32_t re) {
     for (uint32_t r0 = rb; r0 < re; r0 += 64) {
       const uint32_t cnt = min(64u, re - r0);
+      const bool pre = r0 == pre_rb;
       if (lane < cnt) {
-        const uint64_t e = cE[r0 + lane];
-        const uint64_t rhs = cR[r0 + lane];
+        const uint64_t e = pre ? pre_e : cE[r0 + lane];
+        const uint64_t rhs = pre ? pre_r : cR[r0 + lane];
         const uint32_t slot = freel[nfree - 1 - lane];
         uint32_t v[3];
         unpack3(e, v);
@@ -860,6 +865,18 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           else if (lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
         } else {
           enter(rb, re);
+          // rows of the next word of the segment, loaded ahead
+          if (gsh == 5 && wlo_col != segbot) {
+            const uint32_t wi2 = ((wlo_col - 1) >> 5) - g0;
+            const uint32_t rb2 = cbv(wi2), re2 = cbv(wi2 + 1);
+            if (rb2 < re2) {
+              pre_rb = rb2;
+              if (lane < min(64u, re2 - rb2)) {
+                pre_e = cE[rb2 + lane];
+                pre_r = cR[rb2 + lane];
+              }
+            }
+          }
           const uint32_t lowbit = wlo_col - wbase, hibit = cpos & 31;
           const uint32_t range = (hibit >= 31 ? 0xFFFFFFFFu : ((2u << hibit) - 1u)) &
                                  ~((1u << lowbit) - 1u);

@@ -51,6 +51,11 @@ def parse():
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--data-seed", type=int, default=2027)
     p.add_argument("--sigma", type=int, default=None, help="override lg segment size")
+    p.add_argument("--query", choices=("grouped", "plain"), default="grouped",
+                   help="grouped: queries grouped by shard first (vfilter_contains_grouped, "
+                        "its workspace is the build's); plain: one gather per probe")
+    p.add_argument("--group-chunk-log2", type=int, default=None,
+                   help="grouped queries: chunks of 2^k keys (default: the library's largest)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-shards", type=int, default=16)
     p.add_argument("--workload", choices=("vfilter", "batch", "serve", "stream", "mwhc"),
@@ -381,13 +386,21 @@ def main():
     st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    qws = ws if args.group_chunk_log2 is None else None
 
     def step(timed: bool):
+        nonlocal qws
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         e[0].record(stream)
         rc, h = vf.vfilter_build(keys, args.b, args.eps, args.seed, opts, ws, st, stream)
+        if qws is None:
+            qws = ws[:vf.vf_query_grouped_bytes(h, 1 << args.group_chunk_log2)]
         e[1].record(stream)
-        vf.vfilter_contains(h, queries, out, stream)
+        if args.query == "grouped":
+            # the build's workspace is free once vfilter_build has returned
+            vf.vfilter_contains_grouped(h, queries, out, qws, stream)
+        else:
+            vf.vfilter_contains(h, queries, out, stream)
         e[2].record(stream)
         e[2].synchronize()
         info = vf.vf_info(h)
@@ -421,7 +434,7 @@ def main():
     # algorithmic bytes per launch (measurement)
     kern = {
         "k_build": {"ms": k_build_ms, "bytes": 8 * n + S_ * V * cb + S_},
-        "k_query": {"ms": query_ms, "bytes": Q * (8 + 3 * cb + 1)},
+        "k_query": {"ms": query_ms, "bytes": Q * (8 + 3 * cb + 1), "path": args.query},
         "k_count+k_scan": {"ms": k_count_ms, "bytes": 8 * n},
         "k_scatter": {"ms": k_scatter_ms, "bytes": 8 * n + 8 * n},
     }
@@ -454,7 +467,8 @@ def main():
                                 "(50% members)"),
                    "n": n, "queries": Q, "b": args.b, "eps": args.eps, "h": info["h"],
                    "M": info["M"], "sigma": info["sigma"], "l": info["l"], "V": V,
-                   "c": f"{info['c_num']}/{info['c_den']}", "parallelism": "1 GPU"},
+                   "c": f"{info['c_num']}/{info['c_den']}", "query_path": args.query,
+                   "parallelism": "1 GPU"},
         "check": {"rc": rc, "members_all_true": members_ok, "negatives": n_neg,
                   "false_positives": fp, "fpr_x256": round(256 * fp / max(n_neg, 1), 4),
                   "failed_attempts": info["n_failures"],

@@ -182,6 +182,40 @@ int vfilter_build_host(const uint64_t *keys, uint64_t n, int32_t b, double eps,
 int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n,
                      uint8_t *out, hipStream_t stream);
 
+/* ---- Queries grouped by shard --------------------------------------
+ * The same answers as vf_query / vfilter_contains, computed another way: a
+ * key's shard is a function of its signature alone (section 4, no offsets
+ * are stored), so the queries can first be grouped by shard with a
+ * counting sort, and each shard's queries answered together while its
+ * cells sit on chip.  The three probes of a query then cost no memory
+ * traffic; the grouping costs a streaming pass over the keys.  Queries are
+ * taken in chunks of up to 2^26 keys; each chunk is counted, scattered
+ * into the workspace as (key, index) pairs grouped by shard and answered,
+ * and every answer is written to the key's own position in out. */
+
+/* Workspace that answers n keys of handle h in one chunk: per-shard
+ * counters and offsets plus 12 bytes per key of a chunk (up to 2^26 keys).
+ * Errors: VF_EINVAL (null or batch handle, bytes NULL). */
+int vf_query_grouped_bytes(const vf_handle *h, uint64_t n, uint64_t *bytes);
+
+/* vf_query with the queries grouped by shard.
+ *   keys       device, n uint64 keys (read only)
+ *   out        device, n answers of cell_bytes each, as vf_query writes them
+ *   workspace  device scratch of workspace_bytes; any size from the
+ *              per-shard part plus one key works (smaller chunks are
+ *              slower), vf_query_grouped_bytes(h, n) gives a single chunk.
+ *              Its contents are dead once the stream passes the call; two
+ *              calls in flight at once need two workspaces.
+ * Errors: VF_EINVAL (null handle/pointers, a filter or batch handle),
+ * VF_ENOSPC (workspace below the per-shard part plus one key), VF_EHIP. */
+int vf_query_grouped(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
+                     void *workspace, uint64_t workspace_bytes, hipStream_t stream);
+
+/* vfilter_contains with the queries grouped by shard; arguments and errors
+ * as vf_query_grouped, out is n bytes (1 = may be in the set). */
+int vfilter_contains_grouped(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8_t *out,
+                             void *workspace, uint64_t workspace_bytes, hipStream_t stream);
+
 /* Describe a handle.  Errors: VF_EINVAL. */
 int vf_info(const vf_handle *h, vf_info_t *out);
 

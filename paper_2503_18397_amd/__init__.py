@@ -89,6 +89,9 @@ _lib.vfilter_build_host.argtypes = [_vp, _u64, _i32, _dbl, _u64, C.POINTER(Opts)
                                     _u64, _vp, _u64, _vp, C.POINTER(_vp)]
 _lib.vf_query.argtypes = [_vp, _vp, _u64, _vp, _vp]
 _lib.vfilter_contains.argtypes = [_vp, _vp, _u64, _vp, _vp]
+_lib.vf_query_grouped_bytes.argtypes = [_vp, _u64, C.POINTER(_u64)]
+_lib.vf_query_grouped.argtypes = [_vp, _vp, _u64, _vp, _vp, _u64, _vp]
+_lib.vfilter_contains_grouped.argtypes = [_vp, _vp, _u64, _vp, _vp, _u64, _vp]
 _lib.vf_info.argtypes = [_vp, C.POINTER(Info)]
 _lib.vf_failures.argtypes = [_vp, C.POINTER(Failure), C.c_uint32, C.POINTER(C.c_uint32)]
 _lib.vf_free.argtypes = [_vp]
@@ -100,12 +103,14 @@ _lib.vf_batch_query.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp]
 _lib.vf_batch_item.argtypes = [_vp, _u64, C.POINTER(BatchItem)]
 for _f in ("vf_plan", "vf_build", "vfilter_build", "vf_query", "vfilter_contains", "vf_info",
            "vf_failures", "vf_batch_plan", "vf_batch_build", "vf_batch_query", "vf_batch_item",
-           "vfilter_build_host"):
+           "vfilter_build_host", "vf_query_grouped_bytes", "vf_query_grouped",
+           "vfilter_contains_grouped"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build",
            "vfilter_contains", "vf_info", "vf_failures", "vf_free", "vf_batch_plan",
-           "vf_batch_build", "vf_batch_query", "vf_batch_item", "vfilter_build_host")
+           "vf_batch_build", "vf_batch_query", "vf_batch_item", "vfilter_build_host",
+           "vf_query_grouped_bytes", "vf_query_grouped", "vfilter_contains_grouped")
 
 
 def _check(rc: int, where: str) -> None:
@@ -191,6 +196,27 @@ def vf_query(handle, keys, out, stream=None) -> None:
 def vfilter_contains(handle, keys, out, stream=None) -> None:
     _check(_lib.vfilter_contains(handle, _dev_ptr(keys, "keys"), keys.numel(),
                                  _dev_ptr(out, "out"), _stream(stream)), "vfilter_contains")
+
+
+def vf_query_grouped_bytes(handle, n: int) -> int:
+    b = C.c_uint64(0)
+    _check(_lib.vf_query_grouped_bytes(handle, n, C.byref(b)), "vf_query_grouped_bytes")
+    return b.value
+
+
+def vf_query_grouped(handle, keys, out, workspace, stream=None) -> None:
+    _check(_lib.vf_query_grouped(handle, _dev_ptr(keys, "keys"), keys.numel(),
+                                 _dev_ptr(out, "out"), _dev_ptr(workspace, "workspace"),
+                                 workspace.numel() * workspace.element_size(), _stream(stream)),
+           "vf_query_grouped")
+
+
+def vfilter_contains_grouped(handle, keys, out, workspace, stream=None) -> None:
+    _check(_lib.vfilter_contains_grouped(handle, _dev_ptr(keys, "keys"), keys.numel(),
+                                         _dev_ptr(out, "out"), _dev_ptr(workspace, "workspace"),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream(stream)),
+           "vfilter_contains_grouped")
 
 
 def vf_info(handle) -> dict:
@@ -321,6 +347,24 @@ class Structure:
                 out = torch.empty(keys.numel(), dtype=_CELL_DTYPE[self.info["cell_bytes"]],
                                   device=keys.device)
             vf_query(self.handle, keys, out, stream)
+        return out
+
+    def query_grouped(self, keys: torch.Tensor, out: torch.Tensor | None = None,
+                      workspace: torch.Tensor | None = None, stream=None):
+        """As query, with the keys grouped by shard first; workspace is a
+        uint8 device tensor (default: one chunk for all keys)."""
+        if workspace is None:
+            workspace = torch.empty(vf_query_grouped_bytes(self.handle, keys.numel()),
+                                    dtype=torch.uint8, device=keys.device)
+        if self.is_filter:
+            if out is None:
+                out = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+            vfilter_contains_grouped(self.handle, keys, out, workspace, stream)
+        else:
+            if out is None:
+                out = torch.empty(keys.numel(), dtype=_CELL_DTYPE[self.info["cell_bytes"]],
+                                  device=keys.device)
+            vf_query_grouped(self.handle, keys, out, workspace, stream)
         return out
 
     def free(self) -> None:

@@ -519,7 +519,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   // 2. group keys by shard; build order (largest shards first)
   HIPCHK(vfk::launch_order(counts, L.S, M, order, stream));
   HIPCHK(vfk::launch_scatter(keys, values, n, sw[0], (uint32_t)L.h, L.S, cursor, bkeys, bvals,
-                             ncu, stream));
+                             nullptr, ncu, stream));
   pe.record(2, stream);
 
   // 3. build every shard
@@ -671,6 +671,68 @@ int vf_query(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
 int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8_t *out,
                      hipStream_t stream) {
   return query_common(h, keys, n, out, stream, 1);
+}
+
+// Grouped queries: workspace = counts, offsets, cursor and a few words per
+// shard, then the keys of one chunk and their indices grouped by shard.
+constexpr uint64_t kGroupChunkMax = 1ull << 26;
+
+static uint64_t group_fixed_bytes(uint32_t S) {
+  return align256(4ull * S) + align256(8ull * (S + 1)) + align256(8ull * S) + 256;
+}
+
+static uint64_t group_bytes(uint32_t S, uint64_t chunk) {
+  return group_fixed_bytes(S) + align256(8 * chunk) + align256(4 * chunk);
+}
+
+int vf_query_grouped_bytes(const vf_handle *h, uint64_t n, uint64_t *bytes) {
+  if (!h || h->magic != kMagic || h->kind != 0 || !bytes) return VF_EINVAL;
+  *bytes = group_bytes(h->G.S, std::max<uint64_t>(1, std::min(n, kGroupChunkMax)));
+  return VF_OK;
+}
+
+static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
+                                void *workspace, uint64_t workspace_bytes, hipStream_t stream,
+                                int32_t want_filter) {
+  if (!h || h->magic != kMagic || h->kind != 0 || h->is_filter != want_filter) return VF_EINVAL;
+  if (n && (!keys || !out || !workspace)) return VF_EINVAL;
+  if (!n) return VF_OK;
+  const uint32_t S = h->G.S;
+  const uint64_t fixed = group_fixed_bytes(S);
+  if (workspace_bytes < fixed + 512 + 12) return VF_ENOSPC;
+  uint64_t chunk = (workspace_bytes - fixed - 512) / 12;
+  chunk = std::min(chunk, std::min(n, kGroupChunkMax));
+  uint8_t *W = (uint8_t *)workspace;
+  uint32_t *counts = (uint32_t *)W;
+  uint64_t *offsets = (uint64_t *)(W + align256(4ull * S));
+  uint64_t *cursor = (uint64_t *)((uint8_t *)offsets + align256(8ull * (S + 1)));
+  uint32_t *meta = (uint32_t *)((uint8_t *)cursor + align256(8ull * S));
+  uint64_t *bkeys = (uint64_t *)((uint8_t *)meta + 256);
+  uint32_t *bidx = (uint32_t *)((uint8_t *)bkeys + align256(8 * chunk));
+  const uint32_t ob = want_filter ? 1 : h->cell_bytes;
+  for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
+    const uint64_t cnt = std::min(chunk, n - c0);
+    const uint64_t *k = keys + c0;
+    if (vfk::launch_fill_u32(counts, S, 0, stream) != hipSuccess ||
+        vfk::launch_count(k, cnt, h->G.khi, h->G.h, S, counts, h->ncu, stream) != hipSuccess ||
+        vfk::launch_scan(counts, S, offsets, cursor, meta, stream) != hipSuccess ||
+        vfk::launch_scatter(k, nullptr, cnt, h->G.khi, h->G.h, S, cursor, bkeys, nullptr, bidx,
+                            h->ncu, stream) != hipSuccess ||
+        vfk::launch_query_grouped(h->G, h->cells, h->cell_bytes, h->tseed, offsets, bkeys, bidx,
+                                  (uint8_t *)out + c0 * ob, h->ncu, stream) != hipSuccess)
+      return VF_EHIP;
+  }
+  return VF_OK;
+}
+
+int vf_query_grouped(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
+                     void *workspace, uint64_t workspace_bytes, hipStream_t stream) {
+  return query_grouped_common(h, keys, n, out, workspace, workspace_bytes, stream, 0);
+}
+
+int vfilter_contains_grouped(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8_t *out,
+                             void *workspace, uint64_t workspace_bytes, hipStream_t stream) {
+  return query_grouped_common(h, keys, n, out, workspace, workspace_bytes, stream, 1);
 }
 
 int vf_batch_plan(uint64_t count, const uint64_t *n, const int32_t *b, const vf_opts *o,

@@ -243,12 +243,14 @@ constexpr int kScatterThreads = 256;
 constexpr int kScatterPer = 16;
 constexpr uint32_t kScatterLdsMax = 8192;
 
-// Group keys (and values) by shard: a counting sort whose per-workgroup
-// counts reserve each shard's range with one atomic per shard.
+// Group keys (and values, or each key's index) by shard: a counting sort
+// whose per-workgroup counts reserve each shard's range with one atomic per
+// shard.
 __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ vals,
                           uint64_t n, uint64_t khi, uint32_t h, uint32_t S,
                           unsigned long long *__restrict__ cursor,
-                          uint64_t *__restrict__ bkeys, uint64_t *__restrict__ bvals) {
+                          uint64_t *__restrict__ bkeys, uint64_t *__restrict__ bvals,
+                          uint32_t *__restrict__ bidx) {
   extern __shared__ uint64_t sbase[];
   uint32_t *cnt = (uint32_t *)(sbase + (S <= kScatterLdsMax ? S : 0));
   const bool lds = S <= kScatterLdsMax;
@@ -282,6 +284,7 @@ __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__r
         uint64_t pos = lds ? sbase[js[q]] + rk[q] : atomicAdd(&cursor[js[q]], 1ull);
         bkeys[pos] = keys[i];
         if (vals) bvals[pos] = vals[i];
+        if (bidx) bidx[pos] = (uint32_t)i;
       }
     }
     if (lds) __syncthreads();
@@ -1807,6 +1810,66 @@ __global__ void __launch_bounds__(256) k_query(Geo G, const T *__restrict__ cell
   }
 }
 
+// Query of keys grouped by shard (section 4: a key's shard is fixed by its
+// signature, so the queries of one shard need only that shard's cells).  A
+// workgroup takes whole shards: it copies the shard's cells to LDS when
+// they fit (lds_cells), then answers the shard's keys bkeys[off[j] ..
+// off[j+1]) with three LDS probes each and writes each answer to its
+// original position out[bidx[p]].
+constexpr uint32_t kGroupThreads = 256;
+constexpr int kGroupQP = 4;
+constexpr uint64_t kGroupLdsMax = kLdsBudget - 256;
+
+template <typename T>
+__global__ void __launch_bounds__(kGroupThreads) k_query_grouped(
+    Geo G, const T *__restrict__ cells, const uint8_t *__restrict__ tseed,
+    const uint64_t *__restrict__ off, const uint64_t *__restrict__ bkeys,
+    const uint32_t *__restrict__ bidx, uint32_t lds_cells, void *__restrict__ out) {
+  extern __shared__ uint4 cells_lds[];
+  const uint64_t vbytes = G.V * sizeof(T);
+  for (uint32_t j = blockIdx.x; j < G.S; j += gridDim.x) {
+    const uint64_t p0 = off[j], p1 = off[j + 1];
+    if (p0 == p1) continue;
+    const T *w = cells + (uint64_t)j * G.V;
+    if (lds_cells) {
+      // the shard's V cells start 16-byte aligned (checked by the launcher)
+      const uint4 *src = (const uint4 *)w;
+      const uint32_t n16 = (uint32_t)(vbytes >> 4);
+      for (uint32_t i = threadIdx.x; i < n16; i += kGroupThreads) cells_lds[i] = src[i];
+      uint8_t *lb = (uint8_t *)cells_lds;
+      for (uint32_t i = (n16 << 4) + threadIdx.x; i < vbytes; i += kGroupThreads)
+        lb[i] = ((const uint8_t *)w)[i];
+      __syncthreads();
+      w = (const T *)cells_lds;
+    }
+    const uint32_t t = tseed[j];
+    for (uint64_t q0 = p0 + threadIdx.x; q0 < p1; q0 += (uint64_t)kGroupThreads * kGroupQP) {
+      uint64_t hi[kGroupQP], lo[kGroupQP];
+      uint32_t dst[kGroupQP];
+#pragma unroll
+      for (int k = 0; k < kGroupQP; k++) {
+        const uint64_t q = q0 + (uint64_t)k * kGroupThreads;
+        const uint64_t key = q < p1 ? bkeys[q] : 0ull;
+        dst[k] = q < p1 ? bidx[q] : 0u;
+        hi[k] = fin64(key ^ G.khi);
+        lo[k] = fin64(key ^ G.klo);
+      }
+#pragma unroll
+      for (int k = 0; k < kGroupQP; k++) {
+        const uint64_t q = q0 + (uint64_t)k * kGroupThreads;
+        if (q < p1) {
+          uint32_t v0, v1, v2;
+          edge3(G, hi[k], lo[k], t, v0, v1, v2);
+          const T x = w[v0] ^ w[v1] ^ w[v2];
+          if (G.is_filter) ((uint8_t *)out)[dst[k]] = (uint64_t)x == fingerprint(G, hi[k], lo[k]);
+          else ((T *)out)[dst[k]] = x;
+        }
+      }
+    }
+    if (lds_cells) __syncthreads();
+  }
+}
+
 // Query of a batch of unsharded functions: instance inst[i]'s geometry
 // comes from its descriptor; the answer is widened to 64 bits.
 __global__ void __launch_bounds__(256) k_query_batch(Geo G, const BatchItem *__restrict__ items,
@@ -1926,7 +1989,8 @@ hipError_t launch_order(const uint32_t *counts, uint32_t S, uint32_t M, uint32_t
 
 hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n,
                           uint64_t khi, uint32_t h, uint32_t S, uint64_t *cursor,
-                          uint64_t *bkeys, uint64_t *bvals, int ncu, hipStream_t s) {
+                          uint64_t *bkeys, uint64_t *bvals, uint32_t *bidx, int ncu,
+                          hipStream_t s) {
   if (!n) return hipSuccess;
   const uint64_t chunk = (uint64_t)kScatterThreads * kScatterPer;
   uint64_t blocks = (n + chunk - 1) / chunk;
@@ -1934,7 +1998,7 @@ hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n
   if (blocks > cap) blocks = cap;
   size_t shm = S <= kScatterLdsMax ? (size_t)S * 12 : 0;
   hipLaunchKernelGGL(k_scatter, dim3((uint32_t)blocks), dim3(kScatterThreads), shm, s, keys, vals,
-                     n, khi, h, S, (unsigned long long *)cursor, bkeys, bvals);
+                     n, khi, h, S, (unsigned long long *)cursor, bkeys, bvals, bidx);
   return hipGetLastError();
 }
 
@@ -1993,6 +2057,36 @@ hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
     case 2: hipLaunchKernelGGL((k_query<uint16_t, QP>), g, b, shm, s, G, (const uint16_t *)cells, tseed, keys, n, out); break;
     case 4: hipLaunchKernelGGL((k_query<uint32_t, QP>), g, b, shm, s, G, (const uint32_t *)cells, tseed, keys, n, out); break;
     default: hipLaunchKernelGGL((k_query<uint64_t, QP>), g, b, shm, s, G, (const uint64_t *)cells, tseed, keys, n, out); break;
+  }
+  return hipGetLastError();
+}
+
+uint32_t query_grouped_lds_bytes(const Geo &G, uint32_t cell_bytes) {
+  const uint64_t vb = G.V * cell_bytes;
+  return vb <= kGroupLdsMax && (vb & 15) == 0 ? (uint32_t)vb : 0;
+}
+
+hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_bytes,
+                                const uint8_t *tseed, const uint64_t *off, const uint64_t *bkeys,
+                                const uint32_t *bidx, void *out, int ncu, hipStream_t s) {
+  const uint32_t lds = ((uintptr_t)cells & 15) ? 0 : query_grouped_lds_bytes(G, cell_bytes);
+  uint64_t blocks = G.S;
+  const uint64_t cap = (uint64_t)ncu * 8;
+  if (blocks > cap) blocks = cap;
+  dim3 g((uint32_t)blocks), b(kGroupThreads);
+  if (lds) {
+    const void *f = cell_bytes == 1   ? (const void *)k_query_grouped<uint8_t>
+                    : cell_bytes == 2 ? (const void *)k_query_grouped<uint16_t>
+                    : cell_bytes == 4 ? (const void *)k_query_grouped<uint32_t>
+                                      : (const void *)k_query_grouped<uint64_t>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  switch (cell_bytes) {
+    case 1: hipLaunchKernelGGL((k_query_grouped<uint8_t>), g, b, lds, s, G, (const uint8_t *)cells, tseed, off, bkeys, bidx, lds, out); break;
+    case 2: hipLaunchKernelGGL((k_query_grouped<uint16_t>), g, b, lds, s, G, (const uint16_t *)cells, tseed, off, bkeys, bidx, lds, out); break;
+    case 4: hipLaunchKernelGGL((k_query_grouped<uint32_t>), g, b, lds, s, G, (const uint32_t *)cells, tseed, off, bkeys, bidx, lds, out); break;
+    default: hipLaunchKernelGGL((k_query_grouped<uint64_t>), g, b, lds, s, G, (const uint64_t *)cells, tseed, off, bkeys, bidx, lds, out); break;
   }
   return hipGetLastError();
 }

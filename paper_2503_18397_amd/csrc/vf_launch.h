@@ -112,7 +112,8 @@ hipError_t launch_order(const uint32_t *counts, uint32_t S, uint32_t M, uint32_t
                         hipStream_t s);
 hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n,
                           uint64_t khi, uint32_t h, uint32_t S, uint64_t *cursor,
-                          uint64_t *bkeys, uint64_t *bvals, int ncu, hipStream_t s);
+                          uint64_t *bkeys, uint64_t *bvals, uint32_t *bidx, int ncu,
+                          hipStream_t s);
 hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s);
 hipError_t launch_query_batch(const Geo &G, const BatchItem *items, uint64_t count,
                               const uint8_t *cells, const uint8_t *tseed, const uint32_t *inst,
@@ -121,5 +122,10 @@ hipError_t launch_query_batch(const Geo &G, const BatchItem *items, uint64_t cou
 hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
                         const uint8_t *tseed, const uint64_t *keys, uint64_t n,
                         void *out, int ncu, hipStream_t s);
+// Grouped query: off (S + 1 offsets), bkeys and bidx from launch_scatter.
+uint32_t query_grouped_lds_bytes(const Geo &G, uint32_t cell_bytes);
+hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_bytes,
+                                const uint8_t *tseed, const uint64_t *off, const uint64_t *bkeys,
+                                const uint32_t *bidx, void *out, int ncu, hipStream_t s);
 
 }  // namespace vfk

@@ -66,3 +66,11 @@ def test_benchmark_workload_sampled_shards_bit_exact():
     built = want != np.uint64(0xFFFFFFFFFFFFFFFF)  # queries falling in sampled shards
     assert built.sum() > 1000
     assert np.array_equal(ans[built].astype(np.uint64), want[built])
+
+    print("[fullsize] grouped queries", flush=True)
+    assert st.query_grouped(keys).min().item() == 1
+    assert np.array_equal(st.query_grouped(q).cpu().numpy(), ans)
+    # chunks of 2^22 queries, as in a workspace of a quarter of the queries
+    ws = torch.empty(vf.vf_query_grouped_bytes(st.handle, 1 << 22), dtype=torch.uint8,
+                     device=DEV)
+    assert np.array_equal(st.query_grouped(q, workspace=ws).cpu().numpy(), ans)

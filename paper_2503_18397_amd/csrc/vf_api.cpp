@@ -677,8 +677,14 @@ int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8
 // shard, then the keys of one chunk and their indices grouped by shard.
 constexpr uint64_t kGroupChunkMax = 1ull << 26;
 
+// counts, per-segment rows of launch_group_rows, offsets, cursor, meta
+static uint64_t group_rows_bytes(uint32_t S) {
+  return vfk::group_rows_fit(S) ? align256(4 * vfk::group_rows_words(S)) : 0;
+}
+
 static uint64_t group_fixed_bytes(uint32_t S) {
-  return align256(4ull * S) + align256(8ull * (S + 1)) + align256(8ull * S) + 256;
+  return align256(4ull * S) + group_rows_bytes(S) + align256(8ull * (S + 1)) +
+         align256(8ull * S) + 256;
 }
 
 static uint64_t group_bytes(uint32_t S, uint64_t chunk) {
@@ -699,12 +705,14 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
   if (!n) return VF_OK;
   const uint32_t S = h->G.S;
   const uint64_t fixed = group_fixed_bytes(S);
-  if (workspace_bytes < fixed + 512 + 12) return VF_ENOSPC;
-  uint64_t chunk = (workspace_bytes - fixed - 512) / 12;
-  chunk = std::min(chunk, std::min(n, kGroupChunkMax));
+  if (workspace_bytes < group_bytes(S, 1)) return VF_ENOSPC;
+  // the largest chunk the workspace holds (the alignment costs < 43 keys)
+  uint64_t chunk = std::min((workspace_bytes - fixed) / 12, std::min(n, kGroupChunkMax));
+  while (group_bytes(S, chunk) > workspace_bytes) chunk--;
   uint8_t *W = (uint8_t *)workspace;
   uint32_t *counts = (uint32_t *)W;
-  uint64_t *offsets = (uint64_t *)(W + align256(4ull * S));
+  uint32_t *rows = (uint32_t *)(W + align256(4ull * S));
+  uint64_t *offsets = (uint64_t *)((uint8_t *)rows + group_rows_bytes(S));
   uint64_t *cursor = (uint64_t *)((uint8_t *)offsets + align256(8ull * (S + 1)));
   uint32_t *meta = (uint32_t *)((uint8_t *)cursor + align256(8ull * S));
   uint64_t *bkeys = (uint64_t *)((uint8_t *)meta + 256);
@@ -713,6 +721,14 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
   for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
     const uint64_t cnt = std::min(chunk, n - c0);
     const uint64_t *k = keys + c0;
+    if (vfk::group_rows_fit(S)) {
+      if (vfk::launch_group_rows(k, cnt, h->G.khi, h->G.h, S, rows, counts, offsets, cursor,
+                                 meta, bkeys, bidx, stream) != hipSuccess ||
+          vfk::launch_query_grouped(h->G, h->cells, h->cell_bytes, h->tseed, offsets, bkeys,
+                                    bidx, (uint8_t *)out + c0 * ob, h->ncu, stream) != hipSuccess)
+        return VF_EHIP;
+      continue;
+    }
     if (vfk::launch_fill_u32(counts, S, 0, stream) != hipSuccess ||
         vfk::launch_count(k, cnt, h->G.khi, h->G.h, S, counts, h->ncu, stream) != hipSuccess ||
         vfk::launch_scan(counts, S, offsets, cursor, meta, stream) != hipSuccess ||

@@ -291,6 +291,129 @@ __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__r
   }
 }
 
+// Grouping of query keys by shard with one global atomic per shard and
+// segment.  A chunk of keys is cut into contiguous segments, one per
+// workgroup.  k_count_rows writes each segment's shard histogram as a row
+// and adds it to the shard totals; k_scan turns the totals into shard
+// starts; k_scatter_rows reserves its segment's range in every shard (one
+// atomic per shard), sorts sub-chunks of the segment by shard in LDS, then
+// writes every shard's run of the sub-chunk with consecutive lanes
+// (coalesced), continuing where the previous sub-chunk's run ended.  The
+// order of keys within a shard depends on the order of the reservations;
+// every key carries its index.
+constexpr uint32_t kRowThreads = 1024;
+constexpr uint32_t kRowBlocksMax = 256;
+constexpr uint32_t kRowSub = 8192;  // keys per sub-chunk staged in LDS
+constexpr uint32_t kRowMaxS = 4096;
+
+// Exclusive prefix sum over the workgroup (threads in order); *total gets
+// the sum.  wsum: one LDS word per wavefront.  Every thread must call it.
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *wsum, uint32_t *total) {
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t inc = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d);
+    if (lane >= (uint32_t)d) inc += y;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (uint32_t i = 0; i < nw; i++) {
+    const uint32_t x = wsum[i];
+    base += i < w ? x : 0u;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
+}
+
+__global__ void __launch_bounds__(kRowThreads) k_count_rows(const uint64_t *__restrict__ keys,
+                                                            uint64_t n, uint64_t seg,
+                                                            uint64_t khi, uint32_t h, uint32_t S,
+                                                            uint32_t *__restrict__ rows,
+                                                            uint32_t *__restrict__ totals) {
+  extern __shared__ uint32_t hist[];
+  for (uint32_t j = threadIdx.x; j < S; j += kRowThreads) hist[j] = 0;
+  __syncthreads();
+  const uint64_t lo = blockIdx.x * seg, hi = lo < n ? min(n, lo + seg) : lo;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kRowThreads)
+    atomicAdd(&hist[shard_of(fin64(keys[i] ^ khi), h)], 1u);
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < S; j += kRowThreads) {
+    const uint32_t c = hist[j];
+    rows[(uint64_t)blockIdx.x * S + j] = c;
+    if (c) atomicAdd(&totals[j], c);
+  }
+}
+
+__global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
+    const uint64_t *__restrict__ keys, uint64_t n, uint64_t seg, uint64_t khi, uint32_t h,
+    uint32_t S, const uint32_t *__restrict__ rows, unsigned long long *__restrict__ cursor,
+    uint64_t *__restrict__ bkeys, uint32_t *__restrict__ bidx) {
+  extern __shared__ uint64_t skey[];                      // kRowSub keys
+  uint32_t *const sidx = (uint32_t *)(skey + kRowSub);    // their indices
+  uint32_t *const cnt = sidx + kRowSub;                   // S: keys per shard
+  uint32_t *const lofs = cnt + S;                         // S: first staged slot
+  uint32_t *const wptr = lofs + S;                        // S: next output position
+  __shared__ uint32_t wsum[kRowThreads / 64];
+  constexpr int KPT = kRowSub / kRowThreads;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t lo = blockIdx.x * seg, hi = lo < n ? min(n, lo + seg) : lo;
+  for (uint32_t j = tid; j < S; j += kRowThreads) {
+    const uint32_t c = rows[(uint64_t)blockIdx.x * S + j];
+    wptr[j] = c ? (uint32_t)atomicAdd(&cursor[j], (unsigned long long)c) : 0u;
+  }
+  const uint32_t per = (S + kRowThreads - 1) / kRowThreads;
+  const uint32_t j0 = min(S, tid * per), j1 = min(S, j0 + per);
+  for (uint64_t c = lo; c < hi; c += kRowSub) {
+    for (uint32_t j = tid; j < S; j += kRowThreads) cnt[j] = 0;
+    __syncthreads();
+    uint64_t key[KPT];
+    uint32_t js[KPT], rk[KPT];
+#pragma unroll
+    for (int k = 0; k < KPT; k++) {
+      const uint64_t i = c + (uint64_t)k * kRowThreads + tid;
+      js[k] = 0xFFFFFFFFu;
+      key[k] = 0;
+      rk[k] = 0;
+      if (i < hi) {
+        key[k] = keys[i];
+        js[k] = shard_of(fin64(key[k] ^ khi), h);
+        rk[k] = atomicAdd(&cnt[js[k]], 1u);
+      }
+    }
+    __syncthreads();
+    uint32_t s = 0;
+    for (uint32_t j = j0; j < j1; j++) s += cnt[j];
+    uint32_t tot;
+    uint32_t run = block_scan(s, wsum, &tot);
+    for (uint32_t j = j0; j < j1; j++) {
+      lofs[j] = run;
+      run += cnt[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KPT; k++)
+      if (js[k] != 0xFFFFFFFFu) {
+        const uint32_t p = lofs[js[k]] + rk[k];
+        skey[p] = key[k];
+        sidx[p] = (uint32_t)(c + (uint64_t)k * kRowThreads + tid);
+      }
+    __syncthreads();
+    for (uint32_t e = tid; e < tot; e += kRowThreads) {
+      const uint64_t x = skey[e];
+      const uint32_t j = shard_of(fin64(x ^ khi), h);
+      const uint32_t d = wptr[j] + (e - lofs[j]);
+      bkeys[d] = x;
+      bidx[d] = sidx[e];
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < S; j += kRowThreads) wptr[j] += cnt[j];
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------- shard build
 //
 // A workgroup of four wavefronts builds shards as a pipeline: wavefront 2
@@ -2058,6 +2181,32 @@ hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
     case 4: hipLaunchKernelGGL((k_query<uint32_t, QP>), g, b, shm, s, G, (const uint32_t *)cells, tseed, keys, n, out); break;
     default: hipLaunchKernelGGL((k_query<uint64_t, QP>), g, b, shm, s, G, (const uint64_t *)cells, tseed, keys, n, out); break;
   }
+  return hipGetLastError();
+}
+
+bool group_rows_fit(uint32_t S) { return S <= kRowMaxS; }
+uint64_t group_rows_words(uint32_t S) { return (uint64_t)kRowBlocksMax * S; }
+
+hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
+                             uint32_t S, uint32_t *rows, uint32_t *totals, uint64_t *offsets,
+                             uint64_t *cursor, uint32_t *meta, uint64_t *bkeys, uint32_t *bidx,
+                             hipStream_t s) {
+  if (!n || S > kRowMaxS || n > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  uint64_t nblk = (n + kRowSub - 1) / kRowSub;
+  if (nblk > kRowBlocksMax) nblk = kRowBlocksMax;
+  const uint64_t seg = (n + nblk - 1) / nblk;
+  hipError_t e = launch_fill_u32(totals, S, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_count_rows, dim3((uint32_t)nblk), dim3(kRowThreads), (size_t)S * 4, s,
+                     keys, n, seg, khi, h, S, rows, totals);
+  e = launch_scan(totals, S, offsets, cursor, meta, s);
+  if (e != hipSuccess) return e;
+  const size_t shm = (size_t)kRowSub * 12 + (size_t)S * 12;
+  e = hipFuncSetAttribute((const void *)k_scatter_rows,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((uint32_t)nblk), dim3(kRowThreads), shm, s, keys, n,
+                     seg, khi, h, S, rows, (unsigned long long *)cursor, bkeys, bidx);
   return hipGetLastError();
 }
 

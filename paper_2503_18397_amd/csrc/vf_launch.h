@@ -122,7 +122,18 @@ hipError_t launch_query_batch(const Geo &G, const BatchItem *items, uint64_t cou
 hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
                         const uint8_t *tseed, const uint64_t *keys, uint64_t n,
                         void *out, int ncu, hipStream_t s);
-// Grouped query: off (S + 1 offsets), bkeys and bidx from launch_scatter.
+// Keys of a query chunk (n < 2^32) grouped by shard, one reservation per
+// shard and segment (S <= 4096): rows is scratch of group_rows_words(S)
+// words, totals / cursor of S words, meta of 4; offsets gets S + 1 shard
+// starts, bkeys / bidx the keys and their indices.
+bool group_rows_fit(uint32_t S);
+uint64_t group_rows_words(uint32_t S);
+hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
+                             uint32_t S, uint32_t *rows, uint32_t *totals, uint64_t *offsets,
+                             uint64_t *cursor, uint32_t *meta, uint64_t *bkeys, uint32_t *bidx,
+                             hipStream_t s);
+// Grouped query: off (S + 1 offsets), bkeys and bidx from launch_scatter or
+// launch_group_rows.
 uint32_t query_grouped_lds_bytes(const Geo &G, uint32_t cell_bytes);
 hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_bytes,
                                 const uint8_t *tseed, const uint64_t *off, const uint64_t *bkeys,

@@ -32,8 +32,9 @@ def _queries(keys, n_neg, seed):
 def _check(st, ob, q, workspace=None):
     """Grouped answers == plain answers == oracle answers on q."""
     qd = q.to(DEV)
-    got = st.query_grouped(qd, workspace=workspace).cpu().numpy()
-    plain = st.query(qd).cpu().numpy()
+    dt = np.uint8 if st.is_filter else _NP[st.info["cell_bytes"]]
+    got = st.query_grouped(qd, workspace=workspace).cpu().numpy().view(dt)
+    plain = st.query(qd).cpu().numpy().view(dt)
     assert np.array_equal(got, plain)
     want = O.query(ob, _u64(q))
     assert np.array_equal(got.astype(np.uint64), want)
@@ -81,8 +82,9 @@ def test_mwhc_grouped_matches_oracle():
 
 @pytest.mark.parametrize("chunk", [1, 999, 4096])
 def test_many_chunks_give_the_same_answers(chunk):
-    """A workspace of the per-shard part plus `chunk` keys: the queries are
-    answered chunk by chunk (chunk = 1 is one key per chunk)."""
+    """A workspace of the per-shard part plus room for `chunk` keys (a few
+    dozen more where the alignment leaves room): the queries are answered
+    chunk by chunk."""
     n, b, h, seed = 30000, 8, 3, 31
     print(f"[grouped] chunk={chunk}", flush=True)
     keys = S.member_keys(n, 800)

@@ -337,8 +337,18 @@ __global__ void __launch_bounds__(kRowThreads) k_count_rows(const uint64_t *__re
   for (uint32_t j = threadIdx.x; j < S; j += kRowThreads) hist[j] = 0;
   __syncthreads();
   const uint64_t lo = blockIdx.x * seg, hi = lo < n ? min(n, lo + seg) : lo;
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += kRowThreads)
-    atomicAdd(&hist[shard_of(fin64(keys[i] ^ khi), h)], 1u);
+  constexpr int U = 8;  // independent loads in flight per thread
+  for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)U * kRowThreads) {
+    uint64_t k[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint64_t i = i0 + (uint64_t)u * kRowThreads;
+      k[u] = i < hi ? keys[i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (i0 + (uint64_t)u * kRowThreads < hi) atomicAdd(&hist[shard_of(fin64(k[u] ^ khi), h)], 1u);
+  }
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < S; j += kRowThreads) {
     const uint32_t c = hist[j];
@@ -366,19 +376,30 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
   }
   const uint32_t per = (S + kRowThreads - 1) / kRowThreads;
   const uint32_t j0 = min(S, tid * per), j1 = min(S, j0 + per);
+  // the keys of the next sub-chunk are loaded while this one is sorted
+  uint64_t nkey[KPT];
+#pragma unroll
+  for (int k = 0; k < KPT; k++) {
+    const uint64_t i = lo + (uint64_t)k * kRowThreads + tid;
+    nkey[k] = i < hi ? keys[i] : 0ull;
+  }
   for (uint64_t c = lo; c < hi; c += kRowSub) {
     for (uint32_t j = tid; j < S; j += kRowThreads) cnt[j] = 0;
-    __syncthreads();
     uint64_t key[KPT];
+#pragma unroll
+    for (int k = 0; k < KPT; k++) {
+      key[k] = nkey[k];
+      const uint64_t i = c + kRowSub + (uint64_t)k * kRowThreads + tid;
+      nkey[k] = i < hi ? keys[i] : 0ull;
+    }
+    __syncthreads();
     uint32_t js[KPT], rk[KPT];
 #pragma unroll
     for (int k = 0; k < KPT; k++) {
       const uint64_t i = c + (uint64_t)k * kRowThreads + tid;
       js[k] = 0xFFFFFFFFu;
-      key[k] = 0;
       rk[k] = 0;
       if (i < hi) {
-        key[k] = keys[i];
         js[k] = shard_of(fin64(key[k] ^ khi), h);
         rk[k] = atomicAdd(&cnt[js[k]], 1u);
       }

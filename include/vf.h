@@ -189,12 +189,12 @@ int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n,
  * counting sort, and each shard's queries answered together while its
  * cells sit on chip.  The three probes of a query then cost no memory
  * traffic; the grouping costs a streaming pass over the keys.  Queries are
- * taken in chunks of up to 2^24 keys; each chunk is counted, scattered
+ * taken in chunks of up to 2^23 keys; each chunk is counted, scattered
  * into the workspace as (key, index) pairs grouped by shard and answered,
  * and every answer is written to the key's own position in out. */
 
 /* Workspace that answers n keys of handle h in one chunk: per-shard
- * counters and offsets plus 12 bytes per key of a chunk (up to 2^24 keys).
+ * counters and offsets plus 12 bytes per key of a chunk (up to 2^23 keys).
  * Errors: VF_EINVAL (null or batch handle, bytes NULL). */
 int vf_query_grouped_bytes(const vf_handle *h, uint64_t n, uint64_t *bytes);
 

@@ -1960,7 +1960,7 @@ __global__ void __launch_bounds__(256) k_query(Geo G, const T *__restrict__ cell
 // they fit (lds_cells), then answers the shard's keys bkeys[off[j] ..
 // off[j+1]) with three LDS probes each and writes each answer to its
 // original position out[bidx[p]].
-constexpr uint32_t kGroupThreads = 256;
+constexpr uint32_t kGroupThreads = 1024;
 constexpr int kGroupQP = 4;
 constexpr uint64_t kGroupLdsMax = kLdsBudget - 256;
 

@@ -439,7 +439,8 @@ def main():
         "k_scatter": {"ms": k_scatter_ms, "bytes": 8 * n + 8 * n},
     }
     for name, k in kern.items():
-        k["traffic"] = None if mwhc else pmc_traffic(name)
+        k["traffic"] = None if mwhc else pmc_traffic(
+            "query_grouped" if name == "k_query" and args.query == "grouped" else name)
         k["GB/s"] = round(k["bytes"] / (k["ms"] * 1e-3) / 1e9, 2) if k["ms"] > 0 else None
         k["frac"] = round(k["GB/s"] / HBM_PEAK_GBS, 5) if k["GB/s"] else None
     dom = "k_build" if k_build_ms >= query_ms else "k_query"
@@ -477,7 +478,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5) if achieved else None,
-                     "traffic": None if mwhc else pmc_traffic(dom)},
+                     "traffic": kern[dom]["traffic"]},
         "kernels": kern,
     }
     if not args.no_cpu_baseline:

@@ -22,13 +22,14 @@ sys.path.insert(0, ROOT)
 METRIC = "build Mkeys/s + query Gq/s (VFilter b=8, 2^27 keys); serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of this workload measured with rocprofv3 PMC counters
+# HBM bytes per launch (per query pass for the grouped query, whose kernels
+# run once per chunk) of this workload measured with rocprofv3 PMC counters
 # (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy); see
 # profiles/vfilter_b8_n2p27_hbm_traffic_pmc.md.  They hold for the kernel
 # source with this SHA-256 prefix only and are reported as null otherwise.
-PMC_SOURCE_SHA = "67a02e6ec5e82d17"
-PMC_TRAFFIC_BYTES = {"k_build": 112.91e9, "k_query": 410.87e9, "k_scatter": 7.06e9,
-                     "k_count+k_scan": 1.08e9}
+PMC_SOURCE_SHA = "5b7271e827a510de"
+PMC_TRAFFIC_BYTES = {"k_build": 115.54e9, "k_query": 410.87e9, "query_grouped": 116.0e9,
+                     "k_scatter": 7.05e9, "k_count+k_scan": 1.08e9}
 
 
 def pmc_traffic(kernel: str):

@@ -191,7 +191,11 @@ int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n,
  * traffic; the grouping costs a streaming pass over the keys.  Queries are
  * taken in chunks of up to 2^23 keys; each chunk is counted, scattered
  * into the workspace as (key, index) pairs grouped by shard and answered,
- * and every answer is written to the key's own position in out. */
+ * and every answer is written to the key's own position in out.  A
+ * structure whose shards' cells do not fit in LDS (more than about 160 KB
+ * per shard) is answered by the plain gathers of vf_query instead.
+ * Grouping pays when a chunk holds many queries per shard (thousands at
+ * 2^16-key shards); with very many shards the plain query is faster. */
 
 /* Workspace that answers n keys of handle h in one chunk: per-shard
  * counters and offsets plus 12 bytes per key of a chunk (up to 2^23 keys).

@@ -706,6 +706,13 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
   const uint32_t S = h->G.S;
   const uint64_t fixed = group_fixed_bytes(S);
   if (workspace_bytes < group_bytes(S, 1)) return VF_ENOSPC;
+  // a shard whose cells do not fit in LDS gains nothing from grouping: its
+  // probes would miss the L2 as the plain gathers do
+  if (!vfk::query_grouped_lds_bytes(h->G, h->cells, h->cell_bytes))
+    return vfk::launch_query(h->G, h->cells, h->cell_bytes, h->tseed, keys, n, out, h->ncu,
+                             stream) == hipSuccess
+               ? VF_OK
+               : VF_EHIP;
   // the largest chunk the workspace holds (the alignment costs < 43 keys)
   uint64_t chunk = std::min((workspace_bytes - fixed) / 12, std::min(n, kGroupChunkMax));
   while (group_bytes(S, chunk) > workspace_bytes) chunk--;

@@ -1956,10 +1956,10 @@ __global__ void __launch_bounds__(256) k_query(Geo G, const T *__restrict__ cell
 
 // Query of keys grouped by shard (section 4: a key's shard is fixed by its
 // signature, so the queries of one shard need only that shard's cells).  A
-// workgroup takes whole shards: it copies the shard's cells to LDS when
-// they fit (lds_cells), then answers the shard's keys bkeys[off[j] ..
-// off[j+1]) with three LDS probes each and writes each answer to its
-// original position out[bidx[p]].
+// workgroup takes whole shards: it copies the shard's cells to LDS (the
+// launcher only runs when they fit), then answers the shard's keys
+// bkeys[off[j] .. off[j+1]) with three LDS probes each and writes each
+// answer to its original position out[bidx[p]].
 constexpr uint32_t kGroupThreads = 1024;
 constexpr int kGroupQP = 4;
 constexpr uint64_t kGroupLdsMax = kLdsBudget - 256;
@@ -1968,24 +1968,18 @@ template <typename T>
 __global__ void __launch_bounds__(kGroupThreads) k_query_grouped(
     Geo G, const T *__restrict__ cells, const uint8_t *__restrict__ tseed,
     const uint64_t *__restrict__ off, const uint64_t *__restrict__ bkeys,
-    const uint32_t *__restrict__ bidx, uint32_t lds_cells, void *__restrict__ out) {
+    const uint32_t *__restrict__ bidx, void *__restrict__ out) {
   extern __shared__ uint4 cells_lds[];
-  const uint64_t vbytes = G.V * sizeof(T);
+  // V cells of a shard are a whole number of 16-byte words and start
+  // 16-byte aligned (checked by the launcher)
+  const uint32_t n16 = (uint32_t)((G.V * sizeof(T)) >> 4);
+  const T *const w = (const T *)cells_lds;
   for (uint32_t j = blockIdx.x; j < G.S; j += gridDim.x) {
     const uint64_t p0 = off[j], p1 = off[j + 1];
     if (p0 == p1) continue;
-    const T *w = cells + (uint64_t)j * G.V;
-    if (lds_cells) {
-      // the shard's V cells start 16-byte aligned (checked by the launcher)
-      const uint4 *src = (const uint4 *)w;
-      const uint32_t n16 = (uint32_t)(vbytes >> 4);
-      for (uint32_t i = threadIdx.x; i < n16; i += kGroupThreads) cells_lds[i] = src[i];
-      uint8_t *lb = (uint8_t *)cells_lds;
-      for (uint32_t i = (n16 << 4) + threadIdx.x; i < vbytes; i += kGroupThreads)
-        lb[i] = ((const uint8_t *)w)[i];
-      __syncthreads();
-      w = (const T *)cells_lds;
-    }
+    const uint4 *src = (const uint4 *)(cells + (uint64_t)j * G.V);
+    for (uint32_t i = threadIdx.x; i < n16; i += kGroupThreads) cells_lds[i] = src[i];
+    __syncthreads();
     const uint32_t t = tseed[j];
     for (uint64_t q0 = p0 + threadIdx.x; q0 < p1; q0 += (uint64_t)kGroupThreads * kGroupQP) {
       uint64_t hi[kGroupQP], lo[kGroupQP];
@@ -2010,7 +2004,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_query_grouped(
         }
       }
     }
-    if (lds_cells) __syncthreads();
+    __syncthreads();
   }
 }
 
@@ -2231,20 +2225,22 @@ hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uin
   return hipGetLastError();
 }
 
-uint32_t query_grouped_lds_bytes(const Geo &G, uint32_t cell_bytes) {
+uint32_t query_grouped_lds_bytes(const Geo &G, const void *cells, uint32_t cell_bytes) {
   const uint64_t vb = G.V * cell_bytes;
-  return vb <= kGroupLdsMax && (vb & 15) == 0 ? (uint32_t)vb : 0;
+  return vb <= kGroupLdsMax && (vb & 15) == 0 && ((uintptr_t)cells & 15) == 0 ? (uint32_t)vb
+                                                                              : 0;
 }
 
 hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_bytes,
                                 const uint8_t *tseed, const uint64_t *off, const uint64_t *bkeys,
                                 const uint32_t *bidx, void *out, int ncu, hipStream_t s) {
-  const uint32_t lds = ((uintptr_t)cells & 15) ? 0 : query_grouped_lds_bytes(G, cell_bytes);
+  const uint32_t lds = query_grouped_lds_bytes(G, cells, cell_bytes);
+  if (!lds) return hipErrorInvalidValue;
   uint64_t blocks = G.S;
   const uint64_t cap = (uint64_t)ncu * 8;
   if (blocks > cap) blocks = cap;
   dim3 g((uint32_t)blocks), b(kGroupThreads);
-  if (lds) {
+  {
     const void *f = cell_bytes == 1   ? (const void *)k_query_grouped<uint8_t>
                     : cell_bytes == 2 ? (const void *)k_query_grouped<uint16_t>
                     : cell_bytes == 4 ? (const void *)k_query_grouped<uint32_t>
@@ -2253,10 +2249,10 @@ hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_b
     if (e != hipSuccess) return e;
   }
   switch (cell_bytes) {
-    case 1: hipLaunchKernelGGL((k_query_grouped<uint8_t>), g, b, lds, s, G, (const uint8_t *)cells, tseed, off, bkeys, bidx, lds, out); break;
-    case 2: hipLaunchKernelGGL((k_query_grouped<uint16_t>), g, b, lds, s, G, (const uint16_t *)cells, tseed, off, bkeys, bidx, lds, out); break;
-    case 4: hipLaunchKernelGGL((k_query_grouped<uint32_t>), g, b, lds, s, G, (const uint32_t *)cells, tseed, off, bkeys, bidx, lds, out); break;
-    default: hipLaunchKernelGGL((k_query_grouped<uint64_t>), g, b, lds, s, G, (const uint64_t *)cells, tseed, off, bkeys, bidx, lds, out); break;
+    case 1: hipLaunchKernelGGL((k_query_grouped<uint8_t>), g, b, lds, s, G, (const uint8_t *)cells, tseed, off, bkeys, bidx, out); break;
+    case 2: hipLaunchKernelGGL((k_query_grouped<uint16_t>), g, b, lds, s, G, (const uint16_t *)cells, tseed, off, bkeys, bidx, out); break;
+    case 4: hipLaunchKernelGGL((k_query_grouped<uint32_t>), g, b, lds, s, G, (const uint32_t *)cells, tseed, off, bkeys, bidx, out); break;
+    default: hipLaunchKernelGGL((k_query_grouped<uint64_t>), g, b, lds, s, G, (const uint64_t *)cells, tseed, off, bkeys, bidx, out); break;
   }
   return hipGetLastError();
 }

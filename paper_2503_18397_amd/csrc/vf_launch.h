@@ -134,7 +134,9 @@ hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uin
                              hipStream_t s);
 // Grouped query: off (S + 1 offsets), bkeys and bidx from launch_scatter or
 // launch_group_rows.
-uint32_t query_grouped_lds_bytes(const Geo &G, uint32_t cell_bytes);
+// LDS bytes of one shard's cells, 0 when they do not fit (or are not
+// 16-byte aligned): then the grouped query is not launched.
+uint32_t query_grouped_lds_bytes(const Geo &G, const void *cells, uint32_t cell_bytes);
 hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_bytes,
                                 const uint8_t *tseed, const uint64_t *off, const uint64_t *bkeys,
                                 const uint32_t *bidx, void *out, int ncu, hipStream_t s);

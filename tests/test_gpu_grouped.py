@@ -46,7 +46,8 @@ def _check(st, ob, q, workspace=None):
 ])
 def test_vfunc_grouped_matches_oracle(n, b, h, seed):
     """Cell widths 1, 2, 4 and 8 bytes; (200000, h = 0) has 225K cells,
-    more than LDS holds, so its probes read global memory."""
+    more than LDS holds, which the grouped entry point answers with the
+    plain gathers."""
     print(f"[grouped] vfunc n={n} b={b} h={h} seed={seed}", flush=True)
     keys = S.member_keys(n, 500 + seed)
     vals = S.values(n, b, 500 + seed)

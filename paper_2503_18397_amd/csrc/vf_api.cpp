@@ -725,6 +725,9 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
   uint64_t *bkeys = (uint64_t *)((uint8_t *)meta + 256);
   uint32_t *bidx = (uint32_t *)((uint8_t *)bkeys + align256(8 * chunk));
   const uint32_t ob = want_filter ? 1 : h->cell_bytes;
+  // the per-chunk scan clears the shard totals for the next chunk
+  if (vfk::group_rows_fit(S) && vfk::launch_fill_u32(counts, S, 0, stream) != hipSuccess)
+    return VF_EHIP;
   for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
     const uint64_t cnt = std::min(chunk, n - c0);
     const uint64_t *k = keys + c0;

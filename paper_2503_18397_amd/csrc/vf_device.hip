@@ -201,10 +201,11 @@ __global__ void k_count(const uint64_t *__restrict__ keys, uint64_t n, uint64_t 
   }
 }
 
-// Exclusive scan of the shard counts (one workgroup) and the largest shard.
-__global__ void k_scan(const uint32_t *__restrict__ counts, uint32_t S,
-                       uint64_t *__restrict__ offsets, uint64_t *__restrict__ cursor,
-                       uint32_t *__restrict__ max_out) {
+// Exclusive scan of the shard counts (one workgroup) and the largest shard;
+// clear (the counts themselves, or null) is zeroed after the scan read it.
+__global__ void k_scan(const uint32_t *counts, uint32_t S, uint64_t *__restrict__ offsets,
+                       uint64_t *__restrict__ cursor, uint32_t *__restrict__ max_out,
+                       uint32_t *clear) {
   __shared__ uint64_t part[1024];
   __shared__ uint32_t mx[1024];
   const uint32_t T = blockDim.x, tid = threadIdx.x;
@@ -232,6 +233,7 @@ __global__ void k_scan(const uint32_t *__restrict__ counts, uint32_t S,
     offsets[i] = run;
     cursor[i] = run;
     run += counts[i];
+    if (clear) clear[i] = 0;
   }
   if (tid == T - 1) {
     offsets[S] = part[tid];
@@ -2114,8 +2116,10 @@ hipError_t launch_count(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t
 }
 
 hipError_t launch_scan(const uint32_t *counts, uint32_t S, uint64_t *offsets,
-                       uint64_t *cursor, uint32_t *max_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, S, offsets, cursor, max_out);
+                       uint64_t *cursor, uint32_t *max_out, hipStream_t s,
+                       uint32_t *clear) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, S, offsets, cursor, max_out,
+                     clear);
   return hipGetLastError();
 }
 
@@ -2210,11 +2214,9 @@ hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uin
   uint64_t nblk = (n + kRowSub - 1) / kRowSub;
   if (nblk > kRowBlocksMax) nblk = kRowBlocksMax;
   const uint64_t seg = (n + nblk - 1) / nblk;
-  hipError_t e = launch_fill_u32(totals, S, 0, s);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_count_rows, dim3((uint32_t)nblk), dim3(kRowThreads), (size_t)S * 4, s,
                      keys, n, seg, khi, h, S, rows, totals);
-  e = launch_scan(totals, S, offsets, cursor, meta, s);
+  hipError_t e = launch_scan(totals, S, offsets, cursor, meta, s, totals);
   if (e != hipSuccess) return e;
   const size_t shm = (size_t)kRowSub * 12 + (size_t)S * 12;
   e = hipFuncSetAttribute((const void *)k_scatter_rows,

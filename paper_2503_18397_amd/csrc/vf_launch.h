@@ -107,7 +107,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_count(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                         uint32_t S, uint32_t *counts, int ncu, hipStream_t s);
 hipError_t launch_scan(const uint32_t *counts, uint32_t S, uint64_t *offsets,
-                       uint64_t *cursor, uint32_t *max_out, hipStream_t s);
+                       uint64_t *cursor, uint32_t *max_out, hipStream_t s,
+                       uint32_t *clear = nullptr);
 hipError_t launch_order(const uint32_t *counts, uint32_t S, uint32_t M, uint32_t *list,
                         hipStream_t s);
 hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n,
@@ -124,8 +125,9 @@ hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
                         void *out, int ncu, hipStream_t s);
 // Keys of a query chunk (n < 2^32) grouped by shard, one reservation per
 // shard and segment (S <= 4096): rows is scratch of group_rows_words(S)
-// words, totals / cursor of S words, meta of 4; offsets gets S + 1 shard
-// starts, bkeys / bidx the keys and their indices.
+// words, totals (zero on entry, zero again on return) and cursor of S
+// words, meta of 4; offsets gets S + 1 shard starts, bkeys / bidx the keys
+// and their indices.
 bool group_rows_fit(uint32_t S);
 uint64_t group_rows_words(uint32_t S);
 hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,

@@ -205,13 +205,15 @@ int vf_query_grouped_bytes(const vf_handle *h, uint64_t n, uint64_t *bytes);
 /* vf_query with the queries grouped by shard.
  *   keys       device, n uint64 keys (read only)
  *   out        device, n answers of cell_bytes each, as vf_query writes them
- *   workspace  device scratch of workspace_bytes; any size from the
- *              per-shard part plus one key works (smaller chunks are
- *              slower), vf_query_grouped_bytes(h, n) gives a single chunk.
+ *   workspace  device scratch of workspace_bytes, 8-byte aligned (keys
+ *              too); any size from the per-shard part plus one key works
+ *              (smaller chunks are slower), vf_query_grouped_bytes(h, n)
+ *              gives a single chunk.
  *              Its contents are dead once the stream passes the call; two
  *              calls in flight at once need two workspaces.
- * Errors: VF_EINVAL (null handle/pointers, a filter or batch handle),
- * VF_ENOSPC (workspace below the per-shard part plus one key), VF_EHIP. */
+ * Errors: VF_EINVAL (null handle/pointers, a filter or batch handle, keys
+ * or workspace not 8-byte aligned), VF_ENOSPC (workspace below the
+ * per-shard part plus one key), VF_EHIP. */
 int vf_query_grouped(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
                      void *workspace, uint64_t workspace_bytes, hipStream_t stream);
 

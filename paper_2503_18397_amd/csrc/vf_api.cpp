@@ -703,6 +703,7 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
   if (!h || h->magic != kMagic || h->kind != 0 || h->is_filter != want_filter) return VF_EINVAL;
   if (n && (!keys || !out || !workspace)) return VF_EINVAL;
   if (!n) return VF_OK;
+  if (((uintptr_t)keys | (uintptr_t)workspace) & 7) return VF_EINVAL;
   const uint32_t S = h->G.S;
   const uint64_t fixed = group_fixed_bytes(S);
   if (workspace_bytes < group_bytes(S, 1)) return VF_ENOSPC;

@@ -123,6 +123,9 @@ def test_grouped_argument_errors():
     assert lib.vf_query_grouped(st.handle, k, n, o, None, need, None) == vf.VF_EINVAL
     assert lib.vf_query_grouped(st.handle, None, n, o, w, need, None) == vf.VF_EINVAL
     assert lib.vf_query_grouped(st.handle, k, n, o, w, 64, None) == vf.VF_ENOSPC
+    # a workspace or keys not 8-byte aligned
+    assert lib.vf_query_grouped(st.handle, k, n, o, w + 4, need - 4, None) == vf.VF_EINVAL
+    assert lib.vf_query_grouped(st.handle, k + 4, n - 1, o, w, need, None) == vf.VF_EINVAL
     b = C.c_uint64(0)
     assert lib.vf_query_grouped_bytes(None, n, C.byref(b)) == vf.VF_EINVAL
     assert lib.vf_query_grouped_bytes(st.handle, n, None) == vf.VF_EINVAL

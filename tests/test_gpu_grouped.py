@@ -59,10 +59,11 @@ def test_vfunc_grouped_matches_oracle(n, b, h, seed):
 
 
 @pytest.mark.parametrize("n,b,h,seed", [(1 << 17, 8, 3, 11), (100000, 4, 4, 12),
-                                        (100000, 8, 13, 13)])
+                                        (1 << 17, 8, 12, 14), (100000, 8, 13, 13)])
 def test_vfilter_grouped_matches_oracle(n, b, h, seed):
-    """h = 13 (8192 shards) takes the grouping for more than 4096 shards:
-    one shard counter per key instead of per-segment histograms."""
+    """h = 12 (4096 shards) is the largest shard count of the per-segment
+    histograms (the scatter's LDS at its largest); h = 13 (8192 shards)
+    takes the grouping for more shards: one shard counter per key."""
     print(f"[grouped] vfilter n={n} b={b} h={h} seed={seed}", flush=True)
     keys = S.member_keys(n, 600 + seed)
     st = vf.Structure.build(keys.to(DEV), None, b=b, h=h, seed=seed)

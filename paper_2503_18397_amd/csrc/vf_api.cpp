@@ -682,18 +682,21 @@ static uint64_t group_rows_bytes(uint32_t S) {
   return vfk::group_rows_fit(S) ? align256(4 * vfk::group_rows_words(S)) : 0;
 }
 
+// totals, rows, starts, offsets, cursor, meta; then per key of a chunk its
+// key, index and answer (ob bytes)
 static uint64_t group_fixed_bytes(uint32_t S) {
-  return align256(4ull * S) + group_rows_bytes(S) + align256(8ull * (S + 1)) +
+  return align256(4ull * S) + 2 * group_rows_bytes(S) + align256(8ull * (S + 1)) +
          align256(8ull * S) + 256;
 }
 
-static uint64_t group_bytes(uint32_t S, uint64_t chunk) {
-  return group_fixed_bytes(S) + align256(8 * chunk) + align256(4 * chunk);
+static uint64_t group_bytes(uint32_t S, uint64_t chunk, uint32_t ob) {
+  return group_fixed_bytes(S) + align256(8 * chunk) + align256(4 * chunk) + align256(ob * chunk);
 }
 
 int vf_query_grouped_bytes(const vf_handle *h, uint64_t n, uint64_t *bytes) {
   if (!h || h->magic != kMagic || h->kind != 0 || !bytes) return VF_EINVAL;
-  *bytes = group_bytes(h->G.S, std::max<uint64_t>(1, std::min(n, kGroupChunkMax)));
+  *bytes = group_bytes(h->G.S, std::max<uint64_t>(1, std::min(n, kGroupChunkMax)),
+                       h->is_filter ? 1 : h->cell_bytes);
   return VF_OK;
 }
 
@@ -705,8 +708,9 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
   if (!n) return VF_OK;
   if (((uintptr_t)keys | (uintptr_t)workspace) & 7) return VF_EINVAL;
   const uint32_t S = h->G.S;
+  const uint32_t ob = want_filter ? 1 : h->cell_bytes;
   const uint64_t fixed = group_fixed_bytes(S);
-  if (workspace_bytes < group_bytes(S, 1)) return VF_ENOSPC;
+  if (workspace_bytes < group_bytes(S, 1, ob)) return VF_ENOSPC;
   // a shard whose cells do not fit in LDS gains nothing from grouping: its
   // probes would miss the L2 as the plain gathers do
   if (!vfk::query_grouped_lds_bytes(h->G, h->cells, h->cell_bytes))
@@ -714,29 +718,38 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
                              stream) == hipSuccess
                ? VF_OK
                : VF_EHIP;
-  // the largest chunk the workspace holds (the alignment costs < 43 keys)
-  uint64_t chunk = std::min((workspace_bytes - fixed) / 12, std::min(n, kGroupChunkMax));
-  while (group_bytes(S, chunk) > workspace_bytes) chunk--;
+  // the largest chunk the workspace holds (the alignment costs < 64 keys)
+  uint64_t chunk = std::min((workspace_bytes - fixed) / (12 + ob), std::min(n, kGroupChunkMax));
+  while (group_bytes(S, chunk, ob) > workspace_bytes) chunk--;
   uint8_t *W = (uint8_t *)workspace;
   uint32_t *counts = (uint32_t *)W;
   uint32_t *rows = (uint32_t *)(W + align256(4ull * S));
-  uint64_t *offsets = (uint64_t *)((uint8_t *)rows + group_rows_bytes(S));
+  uint32_t *starts = (uint32_t *)((uint8_t *)rows + group_rows_bytes(S));
+  uint64_t *offsets = (uint64_t *)((uint8_t *)starts + group_rows_bytes(S));
   uint64_t *cursor = (uint64_t *)((uint8_t *)offsets + align256(8ull * (S + 1)));
   uint32_t *meta = (uint32_t *)((uint8_t *)cursor + align256(8ull * S));
   uint64_t *bkeys = (uint64_t *)((uint8_t *)meta + 256);
   uint32_t *bidx = (uint32_t *)((uint8_t *)bkeys + align256(8 * chunk));
-  const uint32_t ob = want_filter ? 1 : h->cell_bytes;
+  uint8_t *ans = (uint8_t *)bidx + align256(4 * chunk);
   // the per-chunk scan clears the shard totals for the next chunk
   if (vfk::group_rows_fit(S) && vfk::launch_fill_u32(counts, S, 0, stream) != hipSuccess)
     return VF_EHIP;
   for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
     const uint64_t cnt = std::min(chunk, n - c0);
     const uint64_t *k = keys + c0;
+    uint8_t *o = (uint8_t *)out + c0 * ob;
     if (vfk::group_rows_fit(S)) {
+      // answers in grouped order, then moved through LDS windows; or each
+      // written straight to its position when a segment's window is too big
+      const bool place = vfk::place_fits(S, cnt, ob);
       if (vfk::launch_group_rows(k, cnt, h->G.khi, h->G.h, S, rows, counts, offsets, cursor,
-                                 meta, bkeys, bidx, stream) != hipSuccess ||
+                                 meta, bkeys, bidx, place ? starts : nullptr,
+                                 stream) != hipSuccess ||
           vfk::launch_query_grouped(h->G, h->cells, h->cell_bytes, h->tseed, offsets, bkeys,
-                                    bidx, (uint8_t *)out + c0 * ob, h->ncu, stream) != hipSuccess)
+                                    bidx, o, place ? ans : nullptr, h->ncu,
+                                    stream) != hipSuccess ||
+          (place && vfk::launch_place_rows(rows, starts, S, cnt, ob, ans, bidx, o, stream) !=
+                        hipSuccess))
         return VF_EHIP;
       continue;
     }
@@ -746,7 +759,7 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
         vfk::launch_scatter(k, nullptr, cnt, h->G.khi, h->G.h, S, cursor, bkeys, nullptr, bidx,
                             h->ncu, stream) != hipSuccess ||
         vfk::launch_query_grouped(h->G, h->cells, h->cell_bytes, h->tseed, offsets, bkeys, bidx,
-                                  (uint8_t *)out + c0 * ob, h->ncu, stream) != hipSuccess)
+                                  o, nullptr, h->ncu, stream) != hipSuccess)
       return VF_EHIP;
   }
   return VF_OK;

@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(kRowThreads) k_count_rows(const uint64_t *__re
 __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
     const uint64_t *__restrict__ keys, uint64_t n, uint64_t seg, uint64_t khi, uint32_t h,
     uint32_t S, const uint32_t *__restrict__ rows, unsigned long long *__restrict__ cursor,
-    uint64_t *__restrict__ bkeys, uint32_t *__restrict__ bidx) {
+    uint64_t *__restrict__ bkeys, uint32_t *__restrict__ bidx, uint32_t *__restrict__ starts) {
   extern __shared__ uint64_t skey[];                      // kRowSub keys
   uint32_t *const sidx = (uint32_t *)(skey + kRowSub);    // their indices
   uint32_t *const cnt = sidx + kRowSub;                   // S: keys per shard
@@ -375,6 +375,7 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
   for (uint32_t j = tid; j < S; j += kRowThreads) {
     const uint32_t c = rows[(uint64_t)blockIdx.x * S + j];
     wptr[j] = c ? (uint32_t)atomicAdd(&cursor[j], (unsigned long long)c) : 0u;
+    if (starts) starts[(uint64_t)blockIdx.x * S + j] = wptr[j];
   }
   const uint32_t per = (S + kRowThreads - 1) / kRowThreads;
   const uint32_t j0 = min(S, tid * per), j1 = min(S, j0 + per);
@@ -435,6 +436,90 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
     for (uint32_t j = tid; j < S; j += kRowThreads) wptr[j] += cnt[j];
     __syncthreads();
   }
+}
+
+// Answers of a chunk grouped by shard (ans, in the order of bkeys) moved to
+// their positions.  Workgroup b owns segment b of the chunk, whose keys
+// occupy one run in every shard (starts[b][j], rows[b][j] long): its
+// wavefronts read the runs of their share of the shards, place each answer
+// in an LDS window over the segment's part of out, and the window is
+// written out contiguously.
+constexpr uint32_t kPlaceLdsMax = 150 * 1024;
+
+__host__ __device__ inline uint32_t place_lds_bytes(uint32_t S, uint64_t seg, uint32_t ob) {
+  const uint64_t win = (seg * ob + 15) & ~15ull;
+  const uint32_t per_w = (S + kRowThreads / 64 - 1) / (kRowThreads / 64);
+  const uint64_t b = win + (uint64_t)(kRowThreads / 64) * 2 * per_w * 4;
+  return b <= kPlaceLdsMax ? (uint32_t)b : 0u;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRowThreads) k_place_rows(
+    const uint32_t *__restrict__ rows, const uint32_t *__restrict__ starts, uint32_t S,
+    uint64_t n, uint64_t seg, const T *__restrict__ ans, const uint32_t *__restrict__ bidx,
+    T *__restrict__ out) {
+  extern __shared__ uint4 place_lds[];
+  constexpr uint32_t nw = kRowThreads / 64;
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t per_w = (S + nw - 1) / nw;
+  T *const win = (T *)place_lds;
+  uint32_t *const pre = (uint32_t *)((uint8_t *)place_lds + ((seg * sizeof(T) + 15) & ~15ull)) +
+                        w * 2 * per_w;
+  uint32_t *const beg = pre + per_w;
+  const uint64_t lo = blockIdx.x * seg, hi = lo < n ? min(n, lo + seg) : lo;
+  const uint32_t j0 = min(S, w * per_w), nj = min(S, j0 + per_w) - j0;
+  const uint64_t rb = (uint64_t)blockIdx.x * S + j0;
+  // run lengths of this wavefront's shards -> exclusive prefix in LDS
+  const uint32_t per_l = (nj + 63) / 64, k0 = min(nj, lane * per_l), k1 = min(nj, k0 + per_l);
+  uint32_t sum = 0;
+  for (uint32_t k = k0; k < k1; k++) sum += rows[rb + k];
+  uint32_t inc = sum;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d);
+    if (lane >= (uint32_t)d) inc += y;
+  }
+  const uint32_t total = __shfl(inc, 63);
+  uint32_t run = inc - sum;
+  for (uint32_t k = k0; k < k1; k++) {
+    pre[k] = run;
+    beg[k] = starts[rb + k];
+    run += rows[rb + k];
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  constexpr int U = 4;  // elements in flight per lane
+  for (uint32_t e0 = lane; e0 < total; e0 += 64 * U) {
+    uint32_t p[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t e = e0 + 64 * u;
+      p[u] = 0xFFFFFFFFu;
+      if (e < total) {
+        // last shard k with pre[k] <= e (runs of length 0 share a prefix)
+        uint32_t a = 0, b = nj - 1;
+        while (a < b) {
+          const uint32_t m = (a + b + 1) >> 1;
+          if (pre[m] <= e) a = m;
+          else b = m - 1;
+        }
+        p[u] = beg[a] + (e - pre[a]);
+      }
+    }
+    T v[U];
+    uint32_t i[U];
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (p[u] != 0xFFFFFFFFu) {
+        v[u] = ans[p[u]];
+        i[u] = bidx[p[u]];
+      }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (p[u] != 0xFFFFFFFFu) win[i[u] - lo] = v[u];
+  }
+  __syncthreads();
+  for (uint64_t i = threadIdx.x; i < hi - lo; i += kRowThreads) out[lo + i] = win[i];
 }
 
 // ------------------------------------------------------------- shard build
@@ -1961,7 +2046,8 @@ __global__ void __launch_bounds__(256) k_query(Geo G, const T *__restrict__ cell
 // workgroup takes whole shards: it copies the shard's cells to LDS (the
 // launcher only runs when they fit), then answers the shard's keys
 // bkeys[off[j] .. off[j+1]) with three LDS probes each and writes each
-// answer to its original position out[bidx[p]].
+// answer to its original position out[bidx[p]], or, with ans, in grouped
+// order to ans[p] for k_place_rows to move.
 constexpr uint32_t kGroupThreads = 1024;
 constexpr int kGroupQP = 4;
 constexpr uint64_t kGroupLdsMax = kLdsBudget - 256;
@@ -1970,7 +2056,7 @@ template <typename T>
 __global__ void __launch_bounds__(kGroupThreads) k_query_grouped(
     Geo G, const T *__restrict__ cells, const uint8_t *__restrict__ tseed,
     const uint64_t *__restrict__ off, const uint64_t *__restrict__ bkeys,
-    const uint32_t *__restrict__ bidx, void *__restrict__ out) {
+    const uint32_t *__restrict__ bidx, void *__restrict__ out, void *__restrict__ ans) {
   extern __shared__ uint4 cells_lds[];
   // V cells of a shard are a whole number of 16-byte words and start
   // 16-byte aligned (checked by the launcher)
@@ -1990,7 +2076,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_query_grouped(
       for (int k = 0; k < kGroupQP; k++) {
         const uint64_t q = q0 + (uint64_t)k * kGroupThreads;
         const uint64_t key = q < p1 ? bkeys[q] : 0ull;
-        dst[k] = q < p1 ? bidx[q] : 0u;
+        dst[k] = q < p1 && !ans ? bidx[q] : 0u;
         hi[k] = fin64(key ^ G.khi);
         lo[k] = fin64(key ^ G.klo);
       }
@@ -2001,8 +2087,13 @@ __global__ void __launch_bounds__(kGroupThreads) k_query_grouped(
           uint32_t v0, v1, v2;
           edge3(G, hi[k], lo[k], t, v0, v1, v2);
           const T x = w[v0] ^ w[v1] ^ w[v2];
-          if (G.is_filter) ((uint8_t *)out)[dst[k]] = (uint64_t)x == fingerprint(G, hi[k], lo[k]);
-          else ((T *)out)[dst[k]] = x;
+          if (ans) {
+            if (G.is_filter) ((uint8_t *)ans)[q] = (uint64_t)x == fingerprint(G, hi[k], lo[k]);
+            else ((T *)ans)[q] = x;
+          } else {
+            if (G.is_filter) ((uint8_t *)out)[dst[k]] = (uint64_t)x == fingerprint(G, hi[k], lo[k]);
+            else ((T *)out)[dst[k]] = x;
+          }
         }
       }
     }
@@ -2206,14 +2297,26 @@ hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
 bool group_rows_fit(uint32_t S) { return S <= kRowMaxS; }
 uint64_t group_rows_words(uint32_t S) { return (uint64_t)kRowBlocksMax * S; }
 
+static void group_rows_split(uint64_t n, uint64_t *nblk, uint64_t *seg) {
+  uint64_t b = (n + kRowSub - 1) / kRowSub;
+  if (b > kRowBlocksMax) b = kRowBlocksMax;
+  *nblk = b;
+  *seg = (n + b - 1) / b;
+}
+
+bool place_fits(uint32_t S, uint64_t n, uint32_t ob) {
+  uint64_t nblk, seg;
+  group_rows_split(n, &nblk, &seg);
+  return S <= kRowMaxS && place_lds_bytes(S, seg, ob) != 0;
+}
+
 hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                              uint32_t S, uint32_t *rows, uint32_t *totals, uint64_t *offsets,
                              uint64_t *cursor, uint32_t *meta, uint64_t *bkeys, uint32_t *bidx,
-                             hipStream_t s) {
+                             uint32_t *starts, hipStream_t s) {
   if (!n || S > kRowMaxS || n > 0xFFFFFFFFull) return hipErrorInvalidValue;
-  uint64_t nblk = (n + kRowSub - 1) / kRowSub;
-  if (nblk > kRowBlocksMax) nblk = kRowBlocksMax;
-  const uint64_t seg = (n + nblk - 1) / nblk;
+  uint64_t nblk, seg;
+  group_rows_split(n, &nblk, &seg);
   hipLaunchKernelGGL(k_count_rows, dim3((uint32_t)nblk), dim3(kRowThreads), (size_t)S * 4, s,
                      keys, n, seg, khi, h, S, rows, totals);
   hipError_t e = launch_scan(totals, S, offsets, cursor, meta, s, totals);
@@ -2223,8 +2326,35 @@ hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uin
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_scatter_rows, dim3((uint32_t)nblk), dim3(kRowThreads), shm, s, keys, n,
-                     seg, khi, h, S, rows, (unsigned long long *)cursor, bkeys, bidx);
+                     seg, khi, h, S, rows, (unsigned long long *)cursor, bkeys, bidx, starts);
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_place_t(const uint32_t *rows, const uint32_t *starts, uint32_t S,
+                                 uint64_t n, uint64_t nblk, uint64_t seg, uint32_t lds,
+                                 const void *ans, const uint32_t *bidx, void *out, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_place_rows<T>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_place_rows<T>, dim3((uint32_t)nblk), dim3(kRowThreads), lds, s, rows,
+                     starts, S, n, seg, (const T *)ans, bidx, (T *)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_place_rows(const uint32_t *rows, const uint32_t *starts, uint32_t S,
+                             uint64_t n, uint32_t ob, const void *ans, const uint32_t *bidx,
+                             void *out, hipStream_t s) {
+  uint64_t nblk, seg;
+  group_rows_split(n, &nblk, &seg);
+  const uint32_t lds = place_lds_bytes(S, seg, ob);
+  if (!n || S > kRowMaxS || !lds) return hipErrorInvalidValue;
+  switch (ob) {
+    case 1: return launch_place_t<uint8_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, out, s);
+    case 2: return launch_place_t<uint16_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, out, s);
+    case 4: return launch_place_t<uint32_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, out, s);
+    default: return launch_place_t<uint64_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, out, s);
+  }
 }
 
 uint32_t query_grouped_lds_bytes(const Geo &G, const void *cells, uint32_t cell_bytes) {
@@ -2235,7 +2365,8 @@ uint32_t query_grouped_lds_bytes(const Geo &G, const void *cells, uint32_t cell_
 
 hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_bytes,
                                 const uint8_t *tseed, const uint64_t *off, const uint64_t *bkeys,
-                                const uint32_t *bidx, void *out, int ncu, hipStream_t s) {
+                                const uint32_t *bidx, void *out, void *ans, int ncu,
+                                hipStream_t s) {
   const uint32_t lds = query_grouped_lds_bytes(G, cells, cell_bytes);
   if (!lds) return hipErrorInvalidValue;
   uint64_t blocks = G.S;
@@ -2251,10 +2382,10 @@ hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_b
     if (e != hipSuccess) return e;
   }
   switch (cell_bytes) {
-    case 1: hipLaunchKernelGGL((k_query_grouped<uint8_t>), g, b, lds, s, G, (const uint8_t *)cells, tseed, off, bkeys, bidx, out); break;
-    case 2: hipLaunchKernelGGL((k_query_grouped<uint16_t>), g, b, lds, s, G, (const uint16_t *)cells, tseed, off, bkeys, bidx, out); break;
-    case 4: hipLaunchKernelGGL((k_query_grouped<uint32_t>), g, b, lds, s, G, (const uint32_t *)cells, tseed, off, bkeys, bidx, out); break;
-    default: hipLaunchKernelGGL((k_query_grouped<uint64_t>), g, b, lds, s, G, (const uint64_t *)cells, tseed, off, bkeys, bidx, out); break;
+    case 1: hipLaunchKernelGGL((k_query_grouped<uint8_t>), g, b, lds, s, G, (const uint8_t *)cells, tseed, off, bkeys, bidx, out, ans); break;
+    case 2: hipLaunchKernelGGL((k_query_grouped<uint16_t>), g, b, lds, s, G, (const uint16_t *)cells, tseed, off, bkeys, bidx, out, ans); break;
+    case 4: hipLaunchKernelGGL((k_query_grouped<uint32_t>), g, b, lds, s, G, (const uint32_t *)cells, tseed, off, bkeys, bidx, out, ans); break;
+    default: hipLaunchKernelGGL((k_query_grouped<uint64_t>), g, b, lds, s, G, (const uint64_t *)cells, tseed, off, bkeys, bidx, out, ans); break;
   }
   return hipGetLastError();
 }

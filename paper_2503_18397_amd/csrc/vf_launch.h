@@ -133,14 +133,23 @@ uint64_t group_rows_words(uint32_t S);
 hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                              uint32_t S, uint32_t *rows, uint32_t *totals, uint64_t *offsets,
                              uint64_t *cursor, uint32_t *meta, uint64_t *bkeys, uint32_t *bidx,
-                             hipStream_t s);
+                             uint32_t *starts, hipStream_t s);
+// Answers of a chunk of n keys in grouped order (ans, ob bytes each) moved
+// to out[bidx]: rows and starts (group_rows_words(S) words each) from
+// launch_group_rows.  place_fits tells whether a segment's window fits LDS.
+bool place_fits(uint32_t S, uint64_t n, uint32_t ob);
+hipError_t launch_place_rows(const uint32_t *rows, const uint32_t *starts, uint32_t S,
+                             uint64_t n, uint32_t ob, const void *ans, const uint32_t *bidx,
+                             void *out, hipStream_t s);
 // Grouped query: off (S + 1 offsets), bkeys and bidx from launch_scatter or
-// launch_group_rows.
+// launch_group_rows; answers go to out[bidx], or with ans to ans in grouped
+// order (then bidx is not read).
 // LDS bytes of one shard's cells, 0 when they do not fit (or are not
 // 16-byte aligned): then the grouped query is not launched.
 uint32_t query_grouped_lds_bytes(const Geo &G, const void *cells, uint32_t cell_bytes);
 hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_bytes,
                                 const uint8_t *tseed, const uint64_t *off, const uint64_t *bkeys,
-                                const uint32_t *bidx, void *out, int ncu, hipStream_t s);
+                                const uint32_t *bidx, void *out, void *ans, int ncu,
+                                hipStream_t s);
 
 }  // namespace vfk

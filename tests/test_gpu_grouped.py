@@ -98,9 +98,32 @@ def test_many_chunks_give_the_same_answers(chunk):
     ob = O.build(_u64(keys), b=b, is_filter=True, h=h, seed=seed)
     nq = 5000 if chunk == 1 else 100000
     q = _queries(keys[:nq // 2], nq - nq // 2, 800)
-    fixed = vf.vf_query_grouped_bytes(st.handle, 1) - 512  # per-shard part
-    ws = torch.empty(fixed + 512 + 12 * chunk, dtype=torch.uint8, device=DEV)
+    # per-shard part + one key (8 B key, 4 B index, 1 B answer, each 256-aligned)
+    fixed = vf.vf_query_grouped_bytes(st.handle, 1) - 768
+    ws = torch.empty(fixed + 768 + 13 * chunk, dtype=torch.uint8, device=DEV)
     _check(st, ob, q, workspace=ws)
+
+
+@pytest.mark.parametrize("b", [8, 64])
+def test_large_chunk_matches_plain(b):
+    """5.5 million queries in one chunk: the segments of the grouping are
+    22 000 keys long, so b = 8 answers are placed through LDS windows and
+    b = 64 answers (176 KB windows) are written straight to their places."""
+    n, h, seed = 1 << 16, 2, 41
+    print(f"[grouped] large chunk b={b}", flush=True)
+    keys = S.member_keys(n, 1000)
+    vals = S.values(n, b, 1000)
+    st = vf.Structure.build(keys.to(DEV), vals.to(DEV), b=b, h=h, seed=seed)
+    assert st.rc == vf.VF_OK
+    q = torch.cat([keys.repeat(40), S.negative_keys(n, 3_000_000, 1000)]).to(DEV)
+    dt = _NP[st.info["cell_bytes"]]
+    got = st.query_grouped(q).cpu().numpy().view(dt)
+    assert np.array_equal(got, st.query(q).cpu().numpy().view(dt))
+    assert np.array_equal(got[:n].astype(np.uint64), _u64(vals) & np.uint64(
+        (1 << b) - 1 if b < 64 else 0xFFFFFFFFFFFFFFFF))
+    ob = O.build(_u64(keys), _u64(vals), b=b, is_filter=False, h=h, seed=seed)
+    tail = q[-20000:].cpu()
+    assert np.array_equal(got[-20000:].astype(np.uint64), O.query(ob, _u64(tail)))
 
 
 def test_grouped_argument_errors():

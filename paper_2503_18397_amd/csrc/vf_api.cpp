@@ -675,7 +675,7 @@ int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8
 
 // Grouped queries: workspace = counts, offsets, cursor and a few words per
 // shard, then the keys of one chunk and their indices grouped by shard.
-constexpr uint64_t kGroupChunkMax = 1ull << 23;
+constexpr uint64_t kGroupChunkMax = 1ull << 25;
 
 // counts, per-segment rows of launch_group_rows, offsets, cursor, meta
 static uint64_t group_rows_bytes(uint32_t S) {

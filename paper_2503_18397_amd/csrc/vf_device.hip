@@ -304,7 +304,7 @@ __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__r
 // order of keys within a shard depends on the order of the reservations;
 // every key carries its index.
 constexpr uint32_t kRowThreads = 1024;
-constexpr uint32_t kRowBlocksMax = 256;
+constexpr uint32_t kRowBlocksMax = 512;
 constexpr uint32_t kRowSub = 8192;  // keys per sub-chunk staged in LDS
 constexpr uint32_t kRowMaxS = 4096;
 

@@ -27,8 +27,8 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy); see
 # profiles/vfilter_b8_n2p27_hbm_traffic_pmc.md.  They hold for the kernel
 # source with this SHA-256 prefix only and are reported as null otherwise.
-PMC_SOURCE_SHA = "1aa9c2a9e3df3da1"
-PMC_TRAFFIC_BYTES = {"k_build": 115.53e9, "k_query": 410.87e9, "query_grouped": 116.3e9,
+PMC_SOURCE_SHA = "b1f4860c2e79b8ea"
+PMC_TRAFFIC_BYTES = {"k_build": 115.59e9, "k_query": 410.87e9, "query_grouped": 69.7e9,
                      "k_scatter": 7.05e9, "k_count+k_scan": 1.08e9}
 
 

@@ -178,7 +178,8 @@ struct Layout {
   uint64_t cells_bytes;
   // workspace offsets
   uint64_t o_counts, o_offsets, o_cursor, o_meta, o_work, o_fails, o_overflow, o_order, o_bkeys,
-      o_bvals, o_scratch;
+      o_bvals, o_scratch, o_rows;
+  bool rows;  // keys grouped by per-segment histograms (filters, S <= 4096)
   uint32_t fail_cap;
 };
 
@@ -254,6 +255,8 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   l.o_bkeys = take(8ull * std::max<uint64_t>(n, 1));
   l.o_bvals = is_filter ? 0 : take(8ull * std::max<uint64_t>(n, 1));
   l.o_scratch = take(l.scratch_stride * l.nwg);
+  l.rows = is_filter && vfk::group_rows_fit(l.S) && n >= 1 && n <= 0xFFFFFFFFull;
+  l.o_rows = l.rows ? take(4 * vfk::group_rows_words(l.S)) : 0;
   l.ws_bytes = o_;
   l.cells_bytes = align256((uint64_t)l.S * l.gcap.V * l.cell_bytes);
   l.st_bytes = l.cells_bytes + align256(l.S);
@@ -458,6 +461,10 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   uint64_t *bkeys = (uint64_t *)(W + L.o_bkeys);
   uint64_t *bvals = is_filter ? nullptr : (uint64_t *)(W + L.o_bvals);
   uint8_t *scratch = W + L.o_scratch;
+  // keys grouped through per-segment histograms (not for keys copied from
+  // the host chunk by chunk)
+  const bool rows = L.rows && !hk;
+  uint32_t *row_counts = rows ? (uint32_t *)(W + L.o_rows) : nullptr;
   uint8_t *cells = (uint8_t *)st;
   uint8_t *tseed = cells + L.cells_bytes;
 
@@ -499,6 +506,8 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
     if (cs) (void)hipStreamDestroy(cs);
     if (!ok) return VF_EHIP;
     keys = dk;
+  } else if (rows) {
+    HIPCHK(vfk::launch_count_rows(keys, n, sw[0], (uint32_t)L.h, L.S, row_counts, counts, stream));
   } else {
     HIPCHK(vfk::launch_count(keys, n, sw[0], (uint32_t)L.h, L.S, counts, ncu, stream));
   }
@@ -518,8 +527,12 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
 
   // 2. group keys by shard; build order (largest shards first)
   HIPCHK(vfk::launch_order(counts, L.S, M, order, stream));
-  HIPCHK(vfk::launch_scatter(keys, values, n, sw[0], (uint32_t)L.h, L.S, cursor, bkeys, bvals,
-                             nullptr, ncu, stream));
+  if (rows)
+    HIPCHK(vfk::launch_scatter_rows(keys, n, sw[0], (uint32_t)L.h, L.S, row_counts, cursor, bkeys,
+                                    nullptr, nullptr, stream));
+  else
+    HIPCHK(vfk::launch_scatter(keys, values, n, sw[0], (uint32_t)L.h, L.S, cursor, bkeys, bvals,
+                               nullptr, ncu, stream));
   pe.record(2, stream);
 
   // 3. build every shard

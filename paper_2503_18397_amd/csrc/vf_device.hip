@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
       const uint32_t j = shard_of(fin64(x ^ khi), h);
       const uint32_t d = wptr[j] + (e - lofs[j]);
       bkeys[d] = x;
-      bidx[d] = sidx[e];
+      if (bidx) bidx[d] = sidx[e];
     }
     __syncthreads();
     for (uint32_t j = tid; j < S; j += kRowThreads) wptr[j] += cnt[j];
@@ -2310,24 +2310,40 @@ bool place_fits(uint32_t S, uint64_t n, uint32_t ob) {
   return S <= kRowMaxS && place_lds_bytes(S, seg, ob) != 0;
 }
 
-hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
-                             uint32_t S, uint32_t *rows, uint32_t *totals, uint64_t *offsets,
-                             uint64_t *cursor, uint32_t *meta, uint64_t *bkeys, uint32_t *bidx,
-                             uint32_t *starts, hipStream_t s) {
+hipError_t launch_count_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
+                             uint32_t S, uint32_t *rows, uint32_t *totals, hipStream_t s) {
   if (!n || S > kRowMaxS || n > 0xFFFFFFFFull) return hipErrorInvalidValue;
   uint64_t nblk, seg;
   group_rows_split(n, &nblk, &seg);
   hipLaunchKernelGGL(k_count_rows, dim3((uint32_t)nblk), dim3(kRowThreads), (size_t)S * 4, s,
                      keys, n, seg, khi, h, S, rows, totals);
-  hipError_t e = launch_scan(totals, S, offsets, cursor, meta, s, totals);
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
+                               uint32_t S, const uint32_t *rows, uint64_t *cursor,
+                               uint64_t *bkeys, uint32_t *bidx, uint32_t *starts, hipStream_t s) {
+  if (!n || S > kRowMaxS || n > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  uint64_t nblk, seg;
+  group_rows_split(n, &nblk, &seg);
   const size_t shm = (size_t)kRowSub * 12 + (size_t)S * 12;
-  e = hipFuncSetAttribute((const void *)k_scatter_rows,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipError_t e = hipFuncSetAttribute((const void *)k_scatter_rows,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_scatter_rows, dim3((uint32_t)nblk), dim3(kRowThreads), shm, s, keys, n,
                      seg, khi, h, S, rows, (unsigned long long *)cursor, bkeys, bidx, starts);
   return hipGetLastError();
+}
+
+hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
+                             uint32_t S, uint32_t *rows, uint32_t *totals, uint64_t *offsets,
+                             uint64_t *cursor, uint32_t *meta, uint64_t *bkeys, uint32_t *bidx,
+                             uint32_t *starts, hipStream_t s) {
+  hipError_t e = launch_count_rows(keys, n, khi, h, S, rows, totals, s);
+  if (e != hipSuccess) return e;
+  e = launch_scan(totals, S, offsets, cursor, meta, s, totals);
+  if (e != hipSuccess) return e;
+  return launch_scatter_rows(keys, n, khi, h, S, rows, cursor, bkeys, bidx, starts, s);
 }
 
 template <typename T>

@@ -130,6 +130,13 @@ hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
 // and their indices.
 bool group_rows_fit(uint32_t S);
 uint64_t group_rows_words(uint32_t S);
+// The two passes of launch_group_rows on their own (a build scans in
+// between and reads the largest shard); bidx and starts may be null.
+hipError_t launch_count_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
+                             uint32_t S, uint32_t *rows, uint32_t *totals, hipStream_t s);
+hipError_t launch_scatter_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
+                               uint32_t S, const uint32_t *rows, uint64_t *cursor,
+                               uint64_t *bkeys, uint32_t *bidx, uint32_t *starts, hipStream_t s);
 hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                              uint32_t S, uint32_t *rows, uint32_t *totals, uint64_t *offsets,
                              uint64_t *cursor, uint32_t *meta, uint64_t *bkeys, uint32_t *bidx,

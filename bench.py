@@ -334,12 +334,31 @@ def cpu_baseline(args) -> dict:
     q, _ = S.queries(keys, 1 << 21, args.data_seed)
     k_np = keys.numpy().view(np.uint64)
     q_np = q.numpy().view(np.uint64)
+    mwhc = args.workload == "mwhc"
     t0 = time.perf_counter()
-    built = O.build(k_np, b=args.b, is_filter=True, h=h_s, seed=args.seed,
-                    mwhc=args.workload == "mwhc")
+    built = O.build(k_np, b=args.b, is_filter=True, h=h_s, seed=args.seed, mwhc=mwhc)
     t1 = time.perf_counter()
     O.query(built, q_np)
     t2 = time.perf_counter()
+    # the same oracle calls spread over host threads (the C oracle runs with
+    # the interpreter lock released): shards split between threads, then the
+    # queries in chunks
+    import concurrent.futures as cf
+    threads = max(1, min(16, os.cpu_count() or 1, args.cpu_sample_shards))
+    sets = [np.arange(i, 1 << h_s, threads, dtype=np.uint32) for i in range(threads)]
+    with cf.ThreadPoolExecutor(threads) as ex:
+        t3 = time.perf_counter()
+        list(ex.map(lambda sh: O.build(k_np, b=args.b, is_filter=True, h=h_s, seed=args.seed,
+                                        shards=sh, mwhc=mwhc), sets))
+        t4 = time.perf_counter()
+        list(ex.map(lambda qc: O.query(built, qc), np.array_split(q_np, threads)))
+        t5 = time.perf_counter()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": round(n_s / (t1 - t0) / 1e6, 4),
         "unit": "Mkeys/s",
@@ -349,7 +368,30 @@ def cpu_baseline(args) -> dict:
         "kind": "oracle",
         "sample": f"{args.cpu_sample_shards} shards x ~2^16 keys (n={n_s}, h={h_s}, b={args.b}) "
                   f"build; 2^21 mixed queries",
+        "parallel": {"value": round(n_s / (t4 - t3) / 1e6, 4), "unit": "Mkeys/s",
+                     "query_value": round(q_np.size / (t5 - t4) / 1e9, 6), "query_unit": "Gq/s",
+                     "threads": threads, "nproc": os.cpu_count(), "cpu": model},
     }
+
+
+def copy_bandwidth(torch, dev) -> float:
+    """Device-to-device copy of 2 GiB (reads 2 GiB, writes 2 GiB), best of
+    five, in GB/s: the measured ceiling beside the 8 TB/s specification."""
+    x = torch.empty(1 << 28, dtype=torch.int64, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(5):
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * 2.0 ** 31 / (best * 1e-3) / 1e9
 
 
 def main():
@@ -387,6 +429,7 @@ def main():
     st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    copy_gbs = copy_bandwidth(torch, dev)
     qws = ws if args.group_chunk_log2 is None else None
 
     def step(timed: bool):
@@ -479,7 +522,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5) if achieved else None,
-                     "traffic": kern[dom]["traffic"]},
+                     "traffic": kern[dom]["traffic"],
+                     "copy_GBps": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 5) if achieved else None},
         "kernels": kern,
     }
     if not args.no_cpu_baseline:

@@ -686,11 +686,12 @@ int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8
   return query_common(h, keys, n, out, stream, 1);
 }
 
-// Grouped queries: workspace = counts, offsets, cursor and a few words per
-// shard, then the keys of one chunk and their indices grouped by shard.
+// Grouped queries: workspace = shard totals, per-segment histograms and
+// run starts, shard offsets and cursors, then for one chunk the keys grouped
+// by shard, their indices and their answers in grouped order.
 constexpr uint64_t kGroupChunkMax = 1ull << 25;
 
-// counts, per-segment rows of launch_group_rows, offsets, cursor, meta
+// one per-segment table (histogram rows, or run starts) of launch_group_rows
 static uint64_t group_rows_bytes(uint32_t S) {
   return vfk::group_rows_fit(S) ? align256(4 * vfk::group_rows_words(S)) : 0;
 }

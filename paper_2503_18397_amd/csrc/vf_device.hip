@@ -293,16 +293,17 @@ __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__r
   }
 }
 
-// Grouping of query keys by shard with one global atomic per shard and
-// segment.  A chunk of keys is cut into contiguous segments, one per
-// workgroup.  k_count_rows writes each segment's shard histogram as a row
-// and adds it to the shard totals; k_scan turns the totals into shard
-// starts; k_scatter_rows reserves its segment's range in every shard (one
-// atomic per shard), sorts sub-chunks of the segment by shard in LDS, then
-// writes every shard's run of the sub-chunk with consecutive lanes
-// (coalesced), continuing where the previous sub-chunk's run ended.  The
-// order of keys within a shard depends on the order of the reservations;
-// every key carries its index.
+// Grouping of keys by shard (a filter's keys before the build, a chunk of
+// queries before answering them) with one global atomic per shard and
+// segment.  The keys are cut into contiguous segments, one per workgroup.
+// k_count_rows writes each segment's shard histogram as a row and adds it
+// to the shard totals; k_scan turns the totals into shard starts;
+// k_scatter_rows reserves its segment's run in every shard (one atomic per
+// shard), sorts sub-chunks of the segment by shard in LDS, then writes
+// every shard's part of the sub-chunk with consecutive lanes (coalesced),
+// continuing where the previous sub-chunk's part ended.  The order of keys
+// within a shard depends on the order of the reservations; a query key
+// carries its index.
 constexpr uint32_t kRowThreads = 1024;
 constexpr uint32_t kRowBlocksMax = 512;
 constexpr uint32_t kRowSub = 8192;  // keys per sub-chunk staged in LDS

@@ -748,6 +748,10 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
   // the per-chunk scan clears the shard totals for the next chunk
   if (vfk::group_rows_fit(S) && vfk::launch_fill_u32(counts, S, 0, stream) != hipSuccess)
     return VF_EHIP;
+  // keys hashed once, while they are grouped: the grouped copy holds each
+  // query's edge and fingerprint when they fit a word
+  uint32_t vb = 0;
+  const bool pack = vfk::pack_fits(h->G, S, &vb);
   for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
     const uint64_t cnt = std::min(chunk, n - c0);
     const uint64_t *k = keys + c0;
@@ -757,10 +761,10 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
       // written straight to its position when a segment's window is too big
       const bool place = vfk::place_fits(S, cnt, ob);
       if (vfk::launch_group_rows(k, cnt, h->G.khi, h->G.h, S, rows, counts, offsets, cursor,
-                                 meta, bkeys, bidx, place ? starts : nullptr,
-                                 stream) != hipSuccess ||
+                                 meta, bkeys, bidx, place ? starts : nullptr, stream,
+                                 pack ? &h->G : nullptr, h->tseed, vb) != hipSuccess ||
           vfk::launch_query_grouped(h->G, h->cells, h->cell_bytes, h->tseed, offsets, bkeys,
-                                    bidx, o, place ? ans : nullptr, h->ncu,
+                                    bidx, o, place ? ans : nullptr, pack ? vb : 0u, h->ncu,
                                     stream) != hipSuccess ||
           (place && vfk::launch_place_rows(rows, starts, S, cnt, ob, ans, bidx, o, stream) !=
                         hipSuccess))
@@ -773,7 +777,7 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
         vfk::launch_scatter(k, nullptr, cnt, h->G.khi, h->G.h, S, cursor, bkeys, nullptr, bidx,
                             h->ncu, stream) != hipSuccess ||
         vfk::launch_query_grouped(h->G, h->cells, h->cell_bytes, h->tseed, offsets, bkeys, bidx,
-                                  o, nullptr, h->ncu, stream) != hipSuccess)
+                                  o, nullptr, 0u, h->ncu, stream) != hipSuccess)
       return VF_EHIP;
   }
   return VF_OK;

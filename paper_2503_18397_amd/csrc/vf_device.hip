@@ -308,6 +308,7 @@ constexpr uint32_t kRowThreads = 1024;
 constexpr uint32_t kRowBlocksMax = 512;
 constexpr uint32_t kRowSub = 8192;  // keys per sub-chunk staged in LDS
 constexpr uint32_t kRowMaxS = 4096;
+constexpr uint32_t kPackMaxS = 2048;  // packed edges stage their shard ids too
 
 // Exclusive prefix sum over the workgroup (threads in order); *total gets
 // the sum.  wsum: one LDS word per wavefront.  Every thread must call it.
@@ -360,13 +361,20 @@ __global__ void __launch_bounds__(kRowThreads) k_count_rows(const uint64_t *__re
   }
 }
 
+// With PACK (queries of a structure with geometry G and local seeds tseed)
+// a key is written as its edge and fingerprint instead, vb bits per vertex:
+// v0 | v1 << vb | v2 << 2 vb | fingerprint << 3 vb (3 vb + b <= 64), which
+// leaves the answering kernel no hashing to do.
+template <bool PACK>
 __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
     const uint64_t *__restrict__ keys, uint64_t n, uint64_t seg, uint64_t khi, uint32_t h,
     uint32_t S, const uint32_t *__restrict__ rows, unsigned long long *__restrict__ cursor,
-    uint64_t *__restrict__ bkeys, uint32_t *__restrict__ bidx, uint32_t *__restrict__ starts) {
-  extern __shared__ uint64_t skey[];                      // kRowSub keys
+    uint64_t *__restrict__ bkeys, uint32_t *__restrict__ bidx, uint32_t *__restrict__ starts,
+    Geo G, const uint8_t *__restrict__ tseed, uint32_t vb) {
+  extern __shared__ uint64_t skey[];                      // kRowSub keys (or packed edges)
   uint32_t *const sidx = (uint32_t *)(skey + kRowSub);    // their indices
-  uint32_t *const cnt = sidx + kRowSub;                   // S: keys per shard
+  uint16_t *const ssh = (uint16_t *)(sidx + kRowSub);     // PACK: their shards
+  uint32_t *const cnt = PACK ? (uint32_t *)(ssh + kRowSub) : sidx + kRowSub;  // S: per shard
   uint32_t *const lofs = cnt + S;                         // S: first staged slot
   uint32_t *const wptr = lofs + S;                        // S: next output position
   __shared__ uint32_t wsum[kRowThreads / 64];
@@ -404,8 +412,17 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
       js[k] = 0xFFFFFFFFu;
       rk[k] = 0;
       if (i < hi) {
-        js[k] = shard_of(fin64(key[k] ^ khi), h);
+        const uint64_t hk = fin64(key[k] ^ khi);
+        js[k] = shard_of(hk, h);
         rk[k] = atomicAdd(&cnt[js[k]], 1u);
+        if (PACK) {
+          const uint64_t lk = fin64(key[k] ^ G.klo);
+          uint32_t v0, v1, v2;
+          edge3(G, hk, lk, tseed[js[k]], v0, v1, v2);
+          const uint64_t fp = G.is_filter ? fingerprint(G, hk, lk) : 0ull;
+          key[k] = (uint64_t)v0 | ((uint64_t)v1 << vb) | ((uint64_t)v2 << (2 * vb)) |
+                   (fp << (3 * vb));
+        }
       }
     }
     __syncthreads();
@@ -424,11 +441,12 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
         const uint32_t p = lofs[js[k]] + rk[k];
         skey[p] = key[k];
         sidx[p] = (uint32_t)(c + (uint64_t)k * kRowThreads + tid);
+        if (PACK) ssh[p] = (uint16_t)js[k];
       }
     __syncthreads();
     for (uint32_t e = tid; e < tot; e += kRowThreads) {
       const uint64_t x = skey[e];
-      const uint32_t j = shard_of(fin64(x ^ khi), h);
+      const uint32_t j = PACK ? (uint32_t)ssh[e] : shard_of(fin64(x ^ khi), h);
       const uint32_t d = wptr[j] + (e - lofs[j]);
       bkeys[d] = x;
       if (bidx) bidx[d] = sidx[e];
@@ -2053,11 +2071,12 @@ constexpr uint32_t kGroupThreads = 1024;
 constexpr int kGroupQP = 4;
 constexpr uint64_t kGroupLdsMax = kLdsBudget - 256;
 
-template <typename T>
+template <typename T, bool PACK>
 __global__ void __launch_bounds__(kGroupThreads) k_query_grouped(
     Geo G, const T *__restrict__ cells, const uint8_t *__restrict__ tseed,
     const uint64_t *__restrict__ off, const uint64_t *__restrict__ bkeys,
-    const uint32_t *__restrict__ bidx, void *__restrict__ out, void *__restrict__ ans) {
+    const uint32_t *__restrict__ bidx, void *__restrict__ out, void *__restrict__ ans,
+    uint32_t vb) {
   extern __shared__ uint4 cells_lds[];
   // V cells of a shard are a whole number of 16-byte words and start
   // 16-byte aligned (checked by the launcher)
@@ -2069,6 +2088,37 @@ __global__ void __launch_bounds__(kGroupThreads) k_query_grouped(
     const uint4 *src = (const uint4 *)(cells + (uint64_t)j * G.V);
     for (uint32_t i = threadIdx.x; i < n16; i += kGroupThreads) cells_lds[i] = src[i];
     __syncthreads();
+    if (PACK) {
+      // packed edges (k_scatter_rows<true>): no hashing here
+      const uint64_t vm = (1ull << vb) - 1;
+      for (uint64_t q0 = p0 + threadIdx.x; q0 < p1; q0 += (uint64_t)kGroupThreads * kGroupQP) {
+        uint64_t pk[kGroupQP];
+        uint32_t dst[kGroupQP];
+#pragma unroll
+        for (int k = 0; k < kGroupQP; k++) {
+          const uint64_t q = q0 + (uint64_t)k * kGroupThreads;
+          pk[k] = q < p1 ? bkeys[q] : 0ull;
+          dst[k] = q < p1 && !ans ? bidx[q] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kGroupQP; k++) {
+          const uint64_t q = q0 + (uint64_t)k * kGroupThreads;
+          if (q < p1) {
+            const T x = w[pk[k] & vm] ^ w[(pk[k] >> vb) & vm] ^ w[(pk[k] >> (2 * vb)) & vm];
+            if (G.is_filter) {
+              const uint8_t a = (uint64_t)x == (pk[k] >> (3 * vb));
+              if (ans) ((uint8_t *)ans)[q] = a;
+              else ((uint8_t *)out)[dst[k]] = a;
+            } else {
+              if (ans) ((T *)ans)[q] = x;
+              else ((T *)out)[dst[k]] = x;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     const uint32_t t = tseed[j];
     for (uint64_t q0 = p0 + threadIdx.x; q0 < p1; q0 += (uint64_t)kGroupThreads * kGroupQP) {
       uint64_t hi[kGroupQP], lo[kGroupQP];
@@ -2321,30 +2371,48 @@ hipError_t launch_count_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uin
   return hipGetLastError();
 }
 
+bool pack_fits(const Geo &G, uint32_t S, uint32_t *vb) {
+  uint32_t w = 1;
+  while (w < 21 && (1ull << w) < G.V) w++;
+  *vb = w;
+  return S <= kPackMaxS && (1ull << w) >= G.V && 3 * w + (G.is_filter ? G.b : 0u) <= 64;
+}
+
 hipError_t launch_scatter_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                                uint32_t S, const uint32_t *rows, uint64_t *cursor,
-                               uint64_t *bkeys, uint32_t *bidx, uint32_t *starts, hipStream_t s) {
+                               uint64_t *bkeys, uint32_t *bidx, uint32_t *starts, hipStream_t s,
+                               const Geo *pack, const uint8_t *tseed, uint32_t vb) {
   if (!n || S > kRowMaxS || n > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  if (pack && S > kPackMaxS) return hipErrorInvalidValue;
   uint64_t nblk, seg;
   group_rows_split(n, &nblk, &seg);
-  const size_t shm = (size_t)kRowSub * 12 + (size_t)S * 12;
-  hipError_t e = hipFuncSetAttribute((const void *)k_scatter_rows,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  const size_t shm = (size_t)kRowSub * (pack ? 14 : 12) + (size_t)S * 12;
+  const void *f = pack ? (const void *)k_scatter_rows<true> : (const void *)k_scatter_rows<false>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scatter_rows, dim3((uint32_t)nblk), dim3(kRowThreads), shm, s, keys, n,
-                     seg, khi, h, S, rows, (unsigned long long *)cursor, bkeys, bidx, starts);
+  const Geo G = pack ? *pack : Geo{};
+  if (pack)
+    hipLaunchKernelGGL(k_scatter_rows<true>, dim3((uint32_t)nblk), dim3(kRowThreads), shm, s,
+                       keys, n, seg, khi, h, S, rows, (unsigned long long *)cursor, bkeys, bidx,
+                       starts, G, tseed, vb);
+  else
+    hipLaunchKernelGGL(k_scatter_rows<false>, dim3((uint32_t)nblk), dim3(kRowThreads), shm, s,
+                       keys, n, seg, khi, h, S, rows, (unsigned long long *)cursor, bkeys, bidx,
+                       starts, G, tseed, 0u);
   return hipGetLastError();
 }
 
 hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                              uint32_t S, uint32_t *rows, uint32_t *totals, uint64_t *offsets,
                              uint64_t *cursor, uint32_t *meta, uint64_t *bkeys, uint32_t *bidx,
-                             uint32_t *starts, hipStream_t s) {
+                             uint32_t *starts, hipStream_t s, const Geo *pack,
+                             const uint8_t *tseed, uint32_t vb) {
   hipError_t e = launch_count_rows(keys, n, khi, h, S, rows, totals, s);
   if (e != hipSuccess) return e;
   e = launch_scan(totals, S, offsets, cursor, meta, s, totals);
   if (e != hipSuccess) return e;
-  return launch_scatter_rows(keys, n, khi, h, S, rows, cursor, bkeys, bidx, starts, s);
+  return launch_scatter_rows(keys, n, khi, h, S, rows, cursor, bkeys, bidx, starts, s, pack,
+                             tseed, vb);
 }
 
 template <typename T>
@@ -2380,31 +2448,46 @@ uint32_t query_grouped_lds_bytes(const Geo &G, const void *cells, uint32_t cell_
                                                                               : 0;
 }
 
+template <typename T, bool PACK>
+static hipError_t launch_query_grouped_t(const Geo &G, const void *cells, const uint8_t *tseed,
+                                         const uint64_t *off, const uint64_t *bkeys,
+                                         const uint32_t *bidx, void *out, void *ans,
+                                         uint32_t vb, uint32_t lds, dim3 g, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_query_grouped<T, PACK>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_query_grouped<T, PACK>), g, dim3(kGroupThreads), lds, s, G,
+                     (const T *)cells, tseed, off, bkeys, bidx, out, ans, vb);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_query_grouped_p(const Geo &G, const void *cells, const uint8_t *tseed,
+                                         const uint64_t *off, const uint64_t *bkeys,
+                                         const uint32_t *bidx, void *out, void *ans,
+                                         uint32_t vb, uint32_t lds, dim3 g, hipStream_t s) {
+  return vb ? launch_query_grouped_t<T, true>(G, cells, tseed, off, bkeys, bidx, out, ans, vb,
+                                              lds, g, s)
+            : launch_query_grouped_t<T, false>(G, cells, tseed, off, bkeys, bidx, out, ans, 0,
+                                               lds, g, s);
+}
+
 hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_bytes,
                                 const uint8_t *tseed, const uint64_t *off, const uint64_t *bkeys,
-                                const uint32_t *bidx, void *out, void *ans, int ncu,
-                                hipStream_t s) {
+                                const uint32_t *bidx, void *out, void *ans, uint32_t vb,
+                                int ncu, hipStream_t s) {
   const uint32_t lds = query_grouped_lds_bytes(G, cells, cell_bytes);
   if (!lds) return hipErrorInvalidValue;
   uint64_t blocks = G.S;
   const uint64_t cap = (uint64_t)ncu * 8;
   if (blocks > cap) blocks = cap;
-  dim3 g((uint32_t)blocks), b(kGroupThreads);
-  {
-    const void *f = cell_bytes == 1   ? (const void *)k_query_grouped<uint8_t>
-                    : cell_bytes == 2 ? (const void *)k_query_grouped<uint16_t>
-                    : cell_bytes == 4 ? (const void *)k_query_grouped<uint32_t>
-                                      : (const void *)k_query_grouped<uint64_t>;
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
+  const dim3 g((uint32_t)blocks);
   switch (cell_bytes) {
-    case 1: hipLaunchKernelGGL((k_query_grouped<uint8_t>), g, b, lds, s, G, (const uint8_t *)cells, tseed, off, bkeys, bidx, out, ans); break;
-    case 2: hipLaunchKernelGGL((k_query_grouped<uint16_t>), g, b, lds, s, G, (const uint16_t *)cells, tseed, off, bkeys, bidx, out, ans); break;
-    case 4: hipLaunchKernelGGL((k_query_grouped<uint32_t>), g, b, lds, s, G, (const uint32_t *)cells, tseed, off, bkeys, bidx, out, ans); break;
-    default: hipLaunchKernelGGL((k_query_grouped<uint64_t>), g, b, lds, s, G, (const uint64_t *)cells, tseed, off, bkeys, bidx, out, ans); break;
+    case 1: return launch_query_grouped_p<uint8_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, lds, g, s);
+    case 2: return launch_query_grouped_p<uint16_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, lds, g, s);
+    case 4: return launch_query_grouped_p<uint32_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, lds, g, s);
+    default: return launch_query_grouped_p<uint64_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, lds, g, s);
   }
-  return hipGetLastError();
 }
 
 }  // namespace vfk

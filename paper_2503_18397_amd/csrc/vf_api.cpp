@@ -749,8 +749,9 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
   if (vfk::group_rows_fit(S) && vfk::launch_fill_u32(counts, S, 0, stream) != hipSuccess)
     return VF_EHIP;
   // keys hashed once, while they are grouped: the grouped copy holds each
-  // query's edge and fingerprint when they fit a word
-  uint32_t vb = 0;
+  // query's edge and fingerprint (and, in mode 2, its position) when they fit
+  // a word
+  uint32_t vb = 0, gb = 0;
   const bool pack = vfk::pack_fits(h->G, S, &vb);
   for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
     const uint64_t cnt = std::min(chunk, n - c0);
@@ -760,14 +761,17 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
       // answers in grouped order, then moved through LDS windows; or each
       // written straight to its position when a segment's window is too big
       const bool place = vfk::place_fits(S, cnt, ob);
+      const int mode = place && vfk::pack_compact_fits(h->G, S, cnt, &gb) ? 2 : pack ? 1 : 0;
+      const uint32_t w = mode == 2 ? gb : vb;
       if (vfk::launch_group_rows(k, cnt, h->G.khi, h->G.h, S, rows, counts, offsets, cursor,
-                                 meta, bkeys, bidx, place ? starts : nullptr, stream,
-                                 pack ? &h->G : nullptr, h->tseed, vb) != hipSuccess ||
+                                 meta, bkeys, mode == 2 ? nullptr : bidx,
+                                 place ? starts : nullptr, stream, mode, &h->G, h->tseed,
+                                 w) != hipSuccess ||
           vfk::launch_query_grouped(h->G, h->cells, h->cell_bytes, h->tseed, offsets, bkeys,
-                                    bidx, o, place ? ans : nullptr, pack ? vb : 0u, h->ncu,
+                                    bidx, o, place ? ans : nullptr, w, mode, h->ncu,
                                     stream) != hipSuccess ||
-          (place && vfk::launch_place_rows(rows, starts, S, cnt, ob, ans, bidx, o, stream) !=
-                        hipSuccess))
+          (place && vfk::launch_place_rows(rows, starts, S, cnt, ob, ans, bidx,
+                                           mode == 2 ? bkeys : nullptr, o, stream) != hipSuccess))
         return VF_EHIP;
       continue;
     }
@@ -777,7 +781,7 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
         vfk::launch_scatter(k, nullptr, cnt, h->G.khi, h->G.h, S, cursor, bkeys, nullptr, bidx,
                             h->ncu, stream) != hipSuccess ||
         vfk::launch_query_grouped(h->G, h->cells, h->cell_bytes, h->tseed, offsets, bkeys, bidx,
-                                  o, nullptr, 0u, h->ncu, stream) != hipSuccess)
+                                  o, nullptr, 0u, 0, h->ncu, stream) != hipSuccess)
       return VF_EHIP;
   }
   return VF_OK;

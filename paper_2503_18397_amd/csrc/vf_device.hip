@@ -361,11 +361,28 @@ __global__ void __launch_bounds__(kRowThreads) k_count_rows(const uint64_t *__re
   }
 }
 
-// With PACK (queries of a structure with geometry G and local seeds tseed)
-// a key is written as its edge and fingerprint instead, vb bits per vertex:
-// v0 | v1 << vb | v2 << 2 vb | fingerprint << 3 vb (3 vb + b <= 64), which
-// leaves the answering kernel no hashing to do.
-template <bool PACK>
+// Queries of a structure with geometry G and local seeds tseed may be
+// written hashed, which leaves the answering kernel no hashing to do:
+//   MODE 1: the edge and fingerprint, vb bits per vertex:
+//           v0 | v1 << vb | v2 << 2 vb | fingerprint << 3 vb (3 vb + b <= 64);
+//   MODE 2 (fuse graphs): first segment g (vb bits), the three offsets in
+//           segments g, g + 1, g + 2 (sigma bits each), the fingerprint, and
+//           in bits 48..63 the key's position in its segment, which then
+//           needs no index array (vb + 3 sigma + b <= 48).
+__device__ __forceinline__ uint64_t pack_compact(const Geo &G, uint64_t hi, uint64_t lo,
+                                                 uint32_t t, uint32_t gb) {
+  const uint32_t F = (uint32_t)((hi << G.h) >> 32);
+  const uint64_t g = __umulhi(F, G.l);
+  const uint64_t L = t ? fin64(lo + (uint64_t)t * kGamma) : lo;
+  const uint32_t sg = G.sigma;
+  const uint64_t m = (1ull << sg) - 1;
+  uint64_t w = g | ((L & m) << gb) | (((L >> sg) & m) << (gb + sg)) |
+               (((L >> (2 * sg)) & m) << (gb + 2 * sg));
+  if (G.is_filter) w |= fingerprint(G, hi, lo) << (gb + 3 * sg);
+  return w;
+}
+
+template <int MODE>
 __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
     const uint64_t *__restrict__ keys, uint64_t n, uint64_t seg, uint64_t khi, uint32_t h,
     uint32_t S, const uint32_t *__restrict__ rows, unsigned long long *__restrict__ cursor,
@@ -373,8 +390,8 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
     Geo G, const uint8_t *__restrict__ tseed, uint32_t vb) {
   extern __shared__ uint64_t skey[];                      // kRowSub keys (or packed edges)
   uint32_t *const sidx = (uint32_t *)(skey + kRowSub);    // their indices
-  uint16_t *const ssh = (uint16_t *)(sidx + kRowSub);     // PACK: their shards
-  uint32_t *const cnt = PACK ? (uint32_t *)(ssh + kRowSub) : sidx + kRowSub;  // S: per shard
+  uint16_t *const ssh = (uint16_t *)(sidx + kRowSub);     // MODE 1, 2: their shards
+  uint32_t *const cnt = MODE ? (uint32_t *)(ssh + kRowSub) : sidx + kRowSub;  // S: per shard
   uint32_t *const lofs = cnt + S;                         // S: first staged slot
   uint32_t *const wptr = lofs + S;                        // S: next output position
   __shared__ uint32_t wsum[kRowThreads / 64];
@@ -415,13 +432,16 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
         const uint64_t hk = fin64(key[k] ^ khi);
         js[k] = shard_of(hk, h);
         rk[k] = atomicAdd(&cnt[js[k]], 1u);
-        if (PACK) {
+        if (MODE == 1) {
           const uint64_t lk = fin64(key[k] ^ G.klo);
           uint32_t v0, v1, v2;
           edge3(G, hk, lk, tseed[js[k]], v0, v1, v2);
           const uint64_t fp = G.is_filter ? fingerprint(G, hk, lk) : 0ull;
           key[k] = (uint64_t)v0 | ((uint64_t)v1 << vb) | ((uint64_t)v2 << (2 * vb)) |
                    (fp << (3 * vb));
+        } else if (MODE == 2) {
+          key[k] = pack_compact(G, hk, fin64(key[k] ^ G.klo), tseed[js[k]], vb) |
+                   ((i - lo) << 48);
         }
       }
     }
@@ -441,12 +461,12 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
         const uint32_t p = lofs[js[k]] + rk[k];
         skey[p] = key[k];
         sidx[p] = (uint32_t)(c + (uint64_t)k * kRowThreads + tid);
-        if (PACK) ssh[p] = (uint16_t)js[k];
+        if (MODE) ssh[p] = (uint16_t)js[k];
       }
     __syncthreads();
     for (uint32_t e = tid; e < tot; e += kRowThreads) {
       const uint64_t x = skey[e];
-      const uint32_t j = PACK ? (uint32_t)ssh[e] : shard_of(fin64(x ^ khi), h);
+      const uint32_t j = MODE ? (uint32_t)ssh[e] : shard_of(fin64(x ^ khi), h);
       const uint32_t d = wptr[j] + (e - lofs[j]);
       bkeys[d] = x;
       if (bidx) bidx[d] = sidx[e];
@@ -472,11 +492,13 @@ __host__ __device__ inline uint32_t place_lds_bytes(uint32_t S, uint64_t seg, ui
   return b <= kPlaceLdsMax ? (uint32_t)b : 0u;
 }
 
-template <typename T>
+// WORD: positions come from bits 48..63 of the grouped words (bwords,
+// k_scatter_rows<2>) instead of bidx.
+template <typename T, bool WORD>
 __global__ void __launch_bounds__(kRowThreads) k_place_rows(
     const uint32_t *__restrict__ rows, const uint32_t *__restrict__ starts, uint32_t S,
     uint64_t n, uint64_t seg, const T *__restrict__ ans, const uint32_t *__restrict__ bidx,
-    T *__restrict__ out) {
+    const uint64_t *__restrict__ bwords, T *__restrict__ out) {
   extern __shared__ uint4 place_lds[];
   constexpr uint32_t nw = kRowThreads / 64;
   const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -531,11 +553,11 @@ __global__ void __launch_bounds__(kRowThreads) k_place_rows(
     for (int u = 0; u < U; u++)
       if (p[u] != 0xFFFFFFFFu) {
         v[u] = ans[p[u]];
-        i[u] = bidx[p[u]];
+        i[u] = WORD ? (uint32_t)(bwords[p[u]] >> 48) : (uint32_t)(bidx[p[u]] - lo);
       }
 #pragma unroll
     for (int u = 0; u < U; u++)
-      if (p[u] != 0xFFFFFFFFu) win[i[u] - lo] = v[u];
+      if (p[u] != 0xFFFFFFFFu) win[i[u]] = v[u];
   }
   __syncthreads();
   for (uint64_t i = threadIdx.x; i < hi - lo; i += kRowThreads) out[lo + i] = win[i];
@@ -2071,7 +2093,7 @@ constexpr uint32_t kGroupThreads = 1024;
 constexpr int kGroupQP = 4;
 constexpr uint64_t kGroupLdsMax = kLdsBudget - 256;
 
-template <typename T, bool PACK>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kGroupThreads) k_query_grouped(
     Geo G, const T *__restrict__ cells, const uint8_t *__restrict__ tseed,
     const uint64_t *__restrict__ off, const uint64_t *__restrict__ bkeys,
@@ -2088,8 +2110,38 @@ __global__ void __launch_bounds__(kGroupThreads) k_query_grouped(
     const uint4 *src = (const uint4 *)(cells + (uint64_t)j * G.V);
     for (uint32_t i = threadIdx.x; i < n16; i += kGroupThreads) cells_lds[i] = src[i];
     __syncthreads();
-    if (PACK) {
-      // packed edges (k_scatter_rows<true>): no hashing here
+    if (MODE == 2) {
+      // one word per query (k_scatter_rows<2>): segment, offsets, fingerprint
+      const uint32_t sg = G.sigma, ss = 1u << sg;
+      const uint64_t gm = (1ull << vb) - 1, om = ss - 1;
+      const uint32_t fsh = vb + 3 * sg;
+      const uint64_t fm = G.b >= 48 ? ~0ull : (1ull << G.b) - 1;
+      for (uint64_t q0 = p0 + threadIdx.x; q0 < p1; q0 += (uint64_t)kGroupThreads * kGroupQP) {
+        uint64_t pk[kGroupQP];
+#pragma unroll
+        for (int k = 0; k < kGroupQP; k++) {
+          const uint64_t q = q0 + (uint64_t)k * kGroupThreads;
+          pk[k] = q < p1 ? bkeys[q] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < kGroupQP; k++) {
+          const uint64_t q = q0 + (uint64_t)k * kGroupThreads;
+          if (q < p1) {
+            const uint32_t g = (uint32_t)(pk[k] & gm);
+            const uint32_t v0 = g * ss + (uint32_t)((pk[k] >> vb) & om);
+            const uint32_t v1 = (g + 1) * ss + (uint32_t)((pk[k] >> (vb + sg)) & om);
+            const uint32_t v2 = (g + 2) * ss + (uint32_t)((pk[k] >> (vb + 2 * sg)) & om);
+            const T x = w[v0] ^ w[v1] ^ w[v2];
+            if (G.is_filter) ((uint8_t *)ans)[q] = (uint64_t)x == ((pk[k] >> fsh) & fm);
+            else ((T *)ans)[q] = x;
+          }
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    if (MODE == 1) {
+      // packed edges (k_scatter_rows<1>): no hashing here
       const uint64_t vm = (1ull << vb) - 1;
       for (uint64_t q0 = p0 + threadIdx.x; q0 < p1; q0 += (uint64_t)kGroupThreads * kGroupQP) {
         uint64_t pk[kGroupQP];
@@ -2378,67 +2430,91 @@ bool pack_fits(const Geo &G, uint32_t S, uint32_t *vb) {
   return S <= kPackMaxS && (1ull << w) >= G.V && 3 * w + (G.is_filter ? G.b : 0u) <= 64;
 }
 
+bool pack_compact_fits(const Geo &G, uint32_t S, uint64_t n, uint32_t *gb) {
+  uint32_t w = 1;
+  while (w < 32 && (1ull << w) < G.l) w++;
+  *gb = w;
+  uint64_t nblk, seg;
+  group_rows_split(n, &nblk, &seg);
+  return !G.mwhc && S <= kPackMaxS && seg <= 65536 && (1ull << w) >= G.l &&
+         w + 3 * G.sigma + (G.is_filter ? G.b : 0u) <= 48;
+}
+
+template <int MODE>
+static hipError_t launch_scatter_rows_t(const uint64_t *keys, uint64_t n, uint64_t seg,
+                                        uint64_t nblk, uint64_t khi, uint32_t h, uint32_t S,
+                                        const uint32_t *rows, uint64_t *cursor, uint64_t *bkeys,
+                                        uint32_t *bidx, uint32_t *starts, const Geo &G,
+                                        const uint8_t *tseed, uint32_t vb, hipStream_t s) {
+  const size_t shm = (size_t)kRowSub * (MODE ? 14 : 12) + (size_t)S * 12;
+  hipError_t e = hipFuncSetAttribute((const void *)k_scatter_rows<MODE>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scatter_rows<MODE>, dim3((uint32_t)nblk), dim3(kRowThreads), shm, s, keys,
+                     n, seg, khi, h, S, rows, (unsigned long long *)cursor, bkeys, bidx, starts,
+                     G, tseed, vb);
+  return hipGetLastError();
+}
+
 hipError_t launch_scatter_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                                uint32_t S, const uint32_t *rows, uint64_t *cursor,
                                uint64_t *bkeys, uint32_t *bidx, uint32_t *starts, hipStream_t s,
-                               const Geo *pack, const uint8_t *tseed, uint32_t vb) {
+                               int mode, const Geo *G, const uint8_t *tseed, uint32_t vb) {
   if (!n || S > kRowMaxS || n > 0xFFFFFFFFull) return hipErrorInvalidValue;
-  if (pack && S > kPackMaxS) return hipErrorInvalidValue;
+  if (mode && (!G || !tseed || S > kPackMaxS)) return hipErrorInvalidValue;
   uint64_t nblk, seg;
   group_rows_split(n, &nblk, &seg);
-  const size_t shm = (size_t)kRowSub * (pack ? 14 : 12) + (size_t)S * 12;
-  const void *f = pack ? (const void *)k_scatter_rows<true> : (const void *)k_scatter_rows<false>;
-  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  if (e != hipSuccess) return e;
-  const Geo G = pack ? *pack : Geo{};
-  if (pack)
-    hipLaunchKernelGGL(k_scatter_rows<true>, dim3((uint32_t)nblk), dim3(kRowThreads), shm, s,
-                       keys, n, seg, khi, h, S, rows, (unsigned long long *)cursor, bkeys, bidx,
-                       starts, G, tseed, vb);
-  else
-    hipLaunchKernelGGL(k_scatter_rows<false>, dim3((uint32_t)nblk), dim3(kRowThreads), shm, s,
-                       keys, n, seg, khi, h, S, rows, (unsigned long long *)cursor, bkeys, bidx,
-                       starts, G, tseed, 0u);
-  return hipGetLastError();
+  if (mode == 2 && seg > 65536) return hipErrorInvalidValue;
+  const Geo g = G ? *G : Geo{};
+  switch (mode) {
+    case 0: return launch_scatter_rows_t<0>(keys, n, seg, nblk, khi, h, S, rows, cursor, bkeys, bidx, starts, g, tseed, 0u, s);
+    case 1: return launch_scatter_rows_t<1>(keys, n, seg, nblk, khi, h, S, rows, cursor, bkeys, bidx, starts, g, tseed, vb, s);
+    default: return launch_scatter_rows_t<2>(keys, n, seg, nblk, khi, h, S, rows, cursor, bkeys, bidx, starts, g, tseed, vb, s);
+  }
 }
 
 hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                              uint32_t S, uint32_t *rows, uint32_t *totals, uint64_t *offsets,
                              uint64_t *cursor, uint32_t *meta, uint64_t *bkeys, uint32_t *bidx,
-                             uint32_t *starts, hipStream_t s, const Geo *pack,
+                             uint32_t *starts, hipStream_t s, int mode, const Geo *G,
                              const uint8_t *tseed, uint32_t vb) {
   hipError_t e = launch_count_rows(keys, n, khi, h, S, rows, totals, s);
   if (e != hipSuccess) return e;
   e = launch_scan(totals, S, offsets, cursor, meta, s, totals);
   if (e != hipSuccess) return e;
-  return launch_scatter_rows(keys, n, khi, h, S, rows, cursor, bkeys, bidx, starts, s, pack,
+  return launch_scatter_rows(keys, n, khi, h, S, rows, cursor, bkeys, bidx, starts, s, mode, G,
                              tseed, vb);
 }
 
 template <typename T>
 static hipError_t launch_place_t(const uint32_t *rows, const uint32_t *starts, uint32_t S,
                                  uint64_t n, uint64_t nblk, uint64_t seg, uint32_t lds,
-                                 const void *ans, const uint32_t *bidx, void *out, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_place_rows<T>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                                 const void *ans, const uint32_t *bidx, const uint64_t *bwords,
+                                 void *out, hipStream_t s) {
+  const void *f = bwords ? (const void *)k_place_rows<T, true> : (const void *)k_place_rows<T, false>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_place_rows<T>, dim3((uint32_t)nblk), dim3(kRowThreads), lds, s, rows,
-                     starts, S, n, seg, (const T *)ans, bidx, (T *)out);
+  if (bwords)
+    hipLaunchKernelGGL((k_place_rows<T, true>), dim3((uint32_t)nblk), dim3(kRowThreads), lds, s,
+                       rows, starts, S, n, seg, (const T *)ans, bidx, bwords, (T *)out);
+  else
+    hipLaunchKernelGGL((k_place_rows<T, false>), dim3((uint32_t)nblk), dim3(kRowThreads), lds, s,
+                       rows, starts, S, n, seg, (const T *)ans, bidx, bwords, (T *)out);
   return hipGetLastError();
 }
 
 hipError_t launch_place_rows(const uint32_t *rows, const uint32_t *starts, uint32_t S,
                              uint64_t n, uint32_t ob, const void *ans, const uint32_t *bidx,
-                             void *out, hipStream_t s) {
+                             const uint64_t *bwords, void *out, hipStream_t s) {
   uint64_t nblk, seg;
   group_rows_split(n, &nblk, &seg);
   const uint32_t lds = place_lds_bytes(S, seg, ob);
   if (!n || S > kRowMaxS || !lds) return hipErrorInvalidValue;
   switch (ob) {
-    case 1: return launch_place_t<uint8_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, out, s);
-    case 2: return launch_place_t<uint16_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, out, s);
-    case 4: return launch_place_t<uint32_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, out, s);
-    default: return launch_place_t<uint64_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, out, s);
+    case 1: return launch_place_t<uint8_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, bwords, out, s);
+    case 2: return launch_place_t<uint16_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, bwords, out, s);
+    case 4: return launch_place_t<uint32_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, bwords, out, s);
+    default: return launch_place_t<uint64_t>(rows, starts, S, n, nblk, seg, lds, ans, bidx, bwords, out, s);
   }
 }
 
@@ -2448,15 +2524,15 @@ uint32_t query_grouped_lds_bytes(const Geo &G, const void *cells, uint32_t cell_
                                                                               : 0;
 }
 
-template <typename T, bool PACK>
+template <typename T, int MODE>
 static hipError_t launch_query_grouped_t(const Geo &G, const void *cells, const uint8_t *tseed,
                                          const uint64_t *off, const uint64_t *bkeys,
                                          const uint32_t *bidx, void *out, void *ans,
                                          uint32_t vb, uint32_t lds, dim3 g, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_query_grouped<T, PACK>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_query_grouped<T, MODE>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_query_grouped<T, PACK>), g, dim3(kGroupThreads), lds, s, G,
+  hipLaunchKernelGGL((k_query_grouped<T, MODE>), g, dim3(kGroupThreads), lds, s, G,
                      (const T *)cells, tseed, off, bkeys, bidx, out, ans, vb);
   return hipGetLastError();
 }
@@ -2465,28 +2541,30 @@ template <typename T>
 static hipError_t launch_query_grouped_p(const Geo &G, const void *cells, const uint8_t *tseed,
                                          const uint64_t *off, const uint64_t *bkeys,
                                          const uint32_t *bidx, void *out, void *ans,
-                                         uint32_t vb, uint32_t lds, dim3 g, hipStream_t s) {
-  return vb ? launch_query_grouped_t<T, true>(G, cells, tseed, off, bkeys, bidx, out, ans, vb,
-                                              lds, g, s)
-            : launch_query_grouped_t<T, false>(G, cells, tseed, off, bkeys, bidx, out, ans, 0,
-                                               lds, g, s);
+                                         uint32_t vb, int mode, uint32_t lds, dim3 g,
+                                         hipStream_t s) {
+  switch (mode) {
+    case 0: return launch_query_grouped_t<T, 0>(G, cells, tseed, off, bkeys, bidx, out, ans, 0, lds, g, s);
+    case 1: return launch_query_grouped_t<T, 1>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, lds, g, s);
+    default: return launch_query_grouped_t<T, 2>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, lds, g, s);
+  }
 }
 
 hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_bytes,
                                 const uint8_t *tseed, const uint64_t *off, const uint64_t *bkeys,
                                 const uint32_t *bidx, void *out, void *ans, uint32_t vb,
-                                int ncu, hipStream_t s) {
+                                int mode, int ncu, hipStream_t s) {
   const uint32_t lds = query_grouped_lds_bytes(G, cells, cell_bytes);
-  if (!lds) return hipErrorInvalidValue;
+  if (!lds || (mode == 2 && !ans)) return hipErrorInvalidValue;
   uint64_t blocks = G.S;
   const uint64_t cap = (uint64_t)ncu * 8;
   if (blocks > cap) blocks = cap;
   const dim3 g((uint32_t)blocks);
   switch (cell_bytes) {
-    case 1: return launch_query_grouped_p<uint8_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, lds, g, s);
-    case 2: return launch_query_grouped_p<uint16_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, lds, g, s);
-    case 4: return launch_query_grouped_p<uint32_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, lds, g, s);
-    default: return launch_query_grouped_p<uint64_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, lds, g, s);
+    case 1: return launch_query_grouped_p<uint8_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, mode, lds, g, s);
+    case 2: return launch_query_grouped_p<uint16_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, mode, lds, g, s);
+    case 4: return launch_query_grouped_p<uint32_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, mode, lds, g, s);
+    default: return launch_query_grouped_p<uint64_t>(G, cells, tseed, off, bkeys, bidx, out, ans, vb, mode, lds, g, s);
   }
 }
 

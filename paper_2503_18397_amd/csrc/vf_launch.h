@@ -137,34 +137,38 @@ hipError_t launch_count_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uin
 hipError_t launch_scatter_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                                uint32_t S, const uint32_t *rows, uint64_t *cursor,
                                uint64_t *bkeys, uint32_t *bidx, uint32_t *starts, hipStream_t s,
-                               const Geo *pack = nullptr, const uint8_t *tseed = nullptr,
-                               uint32_t vb = 0);
+                               int mode = 0, const Geo *G = nullptr,
+                               const uint8_t *tseed = nullptr, uint32_t vb = 0);
 // Whether the queries of a structure of geometry G and S shards can be
-// grouped as packed edges (three vertices of vb bits and the fingerprint in
-// a word, see k_scatter_rows); *vb gets the vertex width.
+// grouped hashed (mode 1: three vertices of vb bits and the fingerprint in a
+// word; mode 2, chunks of n keys: segment, offsets, fingerprint and the
+// position in a word, *vb bits for the segment; see k_scatter_rows).
 bool pack_fits(const Geo &G, uint32_t S, uint32_t *vb);
+bool pack_compact_fits(const Geo &G, uint32_t S, uint64_t n, uint32_t *vb);
 hipError_t launch_group_rows(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                              uint32_t S, uint32_t *rows, uint32_t *totals, uint64_t *offsets,
                              uint64_t *cursor, uint32_t *meta, uint64_t *bkeys, uint32_t *bidx,
-                             uint32_t *starts, hipStream_t s, const Geo *pack = nullptr,
-                             const uint8_t *tseed = nullptr, uint32_t vb = 0);
+                             uint32_t *starts, hipStream_t s, int mode = 0,
+                             const Geo *G = nullptr, const uint8_t *tseed = nullptr,
+                             uint32_t vb = 0);
 // Answers of a chunk of n keys in grouped order (ans, ob bytes each) moved
-// to out[bidx]: rows and starts (group_rows_words(S) words each) from
+// to out[bidx] (or, with bwords, to the positions in the grouped words of
+// mode 2): rows and starts (group_rows_words(S) words each) from
 // launch_group_rows.  place_fits tells whether a segment's window fits LDS.
 bool place_fits(uint32_t S, uint64_t n, uint32_t ob);
 hipError_t launch_place_rows(const uint32_t *rows, const uint32_t *starts, uint32_t S,
                              uint64_t n, uint32_t ob, const void *ans, const uint32_t *bidx,
-                             void *out, hipStream_t s);
+                             const uint64_t *bwords, void *out, hipStream_t s);
 // Grouped query: off (S + 1 offsets), bkeys and bidx from launch_scatter or
-// launch_group_rows (bkeys holding packed edges of vb-bit vertices when vb
-// is not 0); answers go to out[bidx], or with ans to ans in grouped order
-// (then bidx is not read).
+// launch_group_rows (bkeys holding hashed queries in mode 1 or 2, see
+// k_scatter_rows); answers go to out[bidx], or with ans to ans in grouped
+// order (then bidx is not read; mode 2 needs ans).
 // LDS bytes of one shard's cells, 0 when they do not fit (or are not
 // 16-byte aligned): then the grouped query is not launched.
 uint32_t query_grouped_lds_bytes(const Geo &G, const void *cells, uint32_t cell_bytes);
 hipError_t launch_query_grouped(const Geo &G, const void *cells, uint32_t cell_bytes,
                                 const uint8_t *tseed, const uint64_t *off, const uint64_t *bkeys,
                                 const uint32_t *bidx, void *out, void *ans, uint32_t vb,
-                                int ncu, hipStream_t s);
+                                int mode, int ncu, hipStream_t s);
 
 }  // namespace vfk

@@ -306,7 +306,8 @@ __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__r
 // carries its index.
 constexpr uint32_t kRowThreads = 1024;
 constexpr uint32_t kRowBlocksMax = 512;
-constexpr uint32_t kRowSub = 8192;  // keys per sub-chunk staged in LDS
+constexpr uint32_t kRowSub = 8192;   // keys per sub-chunk staged in LDS
+constexpr uint32_t kRowSub2 = 12288; // the same for hashed words with their positions
 constexpr uint32_t kRowMaxS = 4096;
 constexpr uint32_t kPackMaxS = 2048;  // packed edges stage their shard ids too
 
@@ -388,14 +389,16 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
     uint32_t S, const uint32_t *__restrict__ rows, unsigned long long *__restrict__ cursor,
     uint64_t *__restrict__ bkeys, uint32_t *__restrict__ bidx, uint32_t *__restrict__ starts,
     Geo G, const uint8_t *__restrict__ tseed, uint32_t vb) {
-  extern __shared__ uint64_t skey[];                      // kRowSub keys (or packed edges)
-  uint32_t *const sidx = (uint32_t *)(skey + kRowSub);    // their indices
-  uint16_t *const ssh = (uint16_t *)(sidx + kRowSub);     // MODE 1, 2: their shards
-  uint32_t *const cnt = MODE ? (uint32_t *)(ssh + kRowSub) : sidx + kRowSub;  // S: per shard
+  // keys per sub-chunk: mode 2 stages no indices, which leaves LDS for more
+  constexpr uint32_t SUB = MODE == 2 ? kRowSub2 : kRowSub;
+  extern __shared__ uint64_t skey[];                      // SUB keys (or hashed words)
+  uint32_t *const sidx = (uint32_t *)(skey + SUB);        // their indices (not in mode 2)
+  uint16_t *const ssh = (uint16_t *)(MODE == 2 ? (uint32_t *)(skey + SUB) : sidx + SUB);  // MODE 1, 2: shards
+  uint32_t *const cnt = MODE ? (uint32_t *)(ssh + SUB) : sidx + SUB;  // S: per shard
   uint32_t *const lofs = cnt + S;                         // S: first staged slot
   uint32_t *const wptr = lofs + S;                        // S: next output position
   __shared__ uint32_t wsum[kRowThreads / 64];
-  constexpr int KPT = kRowSub / kRowThreads;
+  constexpr int KPT = SUB / kRowThreads;
   const uint32_t tid = threadIdx.x;
   const uint64_t lo = blockIdx.x * seg, hi = lo < n ? min(n, lo + seg) : lo;
   for (uint32_t j = tid; j < S; j += kRowThreads) {
@@ -412,13 +415,13 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
     const uint64_t i = lo + (uint64_t)k * kRowThreads + tid;
     nkey[k] = i < hi ? keys[i] : 0ull;
   }
-  for (uint64_t c = lo; c < hi; c += kRowSub) {
+  for (uint64_t c = lo; c < hi; c += SUB) {
     for (uint32_t j = tid; j < S; j += kRowThreads) cnt[j] = 0;
     uint64_t key[KPT];
 #pragma unroll
     for (int k = 0; k < KPT; k++) {
       key[k] = nkey[k];
-      const uint64_t i = c + kRowSub + (uint64_t)k * kRowThreads + tid;
+      const uint64_t i = c + SUB + (uint64_t)k * kRowThreads + tid;
       nkey[k] = i < hi ? keys[i] : 0ull;
     }
     __syncthreads();
@@ -460,7 +463,7 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
       if (js[k] != 0xFFFFFFFFu) {
         const uint32_t p = lofs[js[k]] + rk[k];
         skey[p] = key[k];
-        sidx[p] = (uint32_t)(c + (uint64_t)k * kRowThreads + tid);
+        if (MODE != 2) sidx[p] = (uint32_t)(c + (uint64_t)k * kRowThreads + tid);
         if (MODE) ssh[p] = (uint16_t)js[k];
       }
     __syncthreads();
@@ -469,7 +472,7 @@ __global__ void __launch_bounds__(kRowThreads) k_scatter_rows(
       const uint32_t j = MODE ? (uint32_t)ssh[e] : shard_of(fin64(x ^ khi), h);
       const uint32_t d = wptr[j] + (e - lofs[j]);
       bkeys[d] = x;
-      if (bidx) bidx[d] = sidx[e];
+      if (MODE != 2 && bidx) bidx[d] = sidx[e];
     }
     __syncthreads();
     for (uint32_t j = tid; j < S; j += kRowThreads) wptr[j] += cnt[j];
@@ -2446,7 +2449,8 @@ static hipError_t launch_scatter_rows_t(const uint64_t *keys, uint64_t n, uint64
                                         const uint32_t *rows, uint64_t *cursor, uint64_t *bkeys,
                                         uint32_t *bidx, uint32_t *starts, const Geo &G,
                                         const uint8_t *tseed, uint32_t vb, hipStream_t s) {
-  const size_t shm = (size_t)kRowSub * (MODE ? 14 : 12) + (size_t)S * 12;
+  const size_t shm = MODE == 2 ? (size_t)kRowSub2 * 10 + (size_t)S * 12
+                               : (size_t)kRowSub * (MODE ? 14 : 12) + (size_t)S * 12;
   hipError_t e = hipFuncSetAttribute((const void *)k_scatter_rows<MODE>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;

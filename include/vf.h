@@ -189,7 +189,7 @@ int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n,
  * counting sort, and each shard's queries answered together while its
  * cells sit on chip.  The three probes of a query then cost no memory
  * traffic; the grouping costs streaming passes over the keys.  Queries are
- * taken in chunks of up to 2^25 keys; each chunk is counted, scattered
+ * taken in chunks of up to 2^26 keys; each chunk is counted, scattered
  * into the workspace as (key, index) pairs grouped by shard and answered,
  * and the answers are moved to the keys' own positions in out.  A
  * structure whose shards' cells do not fit in LDS (more than about 160 KB
@@ -199,7 +199,7 @@ int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n,
 
 /* Workspace that answers n keys of handle h in one chunk: per-shard
  * counters, offsets and per-segment tables, plus 12 bytes and one answer
- * (cell_bytes, 1 for a filter) per key of a chunk (up to 2^25 keys).
+ * (cell_bytes, 1 for a filter) per key of a chunk (up to 2^26 keys).
  * Errors: VF_EINVAL (null or batch handle, bytes NULL). */
 int vf_query_grouped_bytes(const vf_handle *h, uint64_t n, uint64_t *bytes);
 

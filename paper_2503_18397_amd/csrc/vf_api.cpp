@@ -689,7 +689,7 @@ int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8
 // Grouped queries: workspace = shard totals, per-segment histograms and
 // run starts, shard offsets and cursors, then for one chunk the keys grouped
 // by shard, their indices and their answers in grouped order.
-constexpr uint64_t kGroupChunkMax = 1ull << 25;
+constexpr uint64_t kGroupChunkMax = 1ull << 26;
 
 // one per-segment table (histogram rows, or run starts) of launch_group_rows
 static uint64_t group_rows_bytes(uint32_t S) {

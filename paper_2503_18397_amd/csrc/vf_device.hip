@@ -305,7 +305,7 @@ __global__ void k_scatter(const uint64_t *__restrict__ keys, const uint64_t *__r
 // within a shard depends on the order of the reservations; a query key
 // carries its index.
 constexpr uint32_t kRowThreads = 1024;
-constexpr uint32_t kRowBlocksMax = 512;
+constexpr uint32_t kRowBlocksMax = 1024;
 constexpr uint32_t kRowSub = 8192;   // keys per sub-chunk staged in LDS
 constexpr uint32_t kRowSub2 = 12288; // the same for hashed words with their positions
 constexpr uint32_t kRowMaxS = 4096;

@@ -27,9 +27,9 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy); see
 # profiles/vfilter_b8_n2p27_hbm_traffic_pmc.md.  They hold for the kernel
 # source with this SHA-256 prefix only and are reported as null otherwise.
-PMC_SOURCE_SHA = "2cbb776f48c2a5b5"
-PMC_TRAFFIC_BYTES = {"k_build": 115.47e9, "k_query": 410.87e9, "query_grouped": 61.1e9,
-                     "k_scatter": 2.95e9, "k_count+k_scan": 1.08e9}
+PMC_SOURCE_SHA = "571ed4af53708bd6"
+PMC_TRAFFIC_BYTES = {"k_build": 115.46e9, "k_query": 410.87e9, "query_grouped": 58.5e9,
+                     "k_scatter": 2.97e9, "k_count+k_scan": 1.09e9}
 
 
 def pmc_traffic(kernel: str):

@@ -104,18 +104,19 @@ def test_many_chunks_give_the_same_answers(chunk):
     _check(st, ob, q, workspace=ws)
 
 
-@pytest.mark.parametrize("b", [8, 64])
-def test_large_chunk_matches_plain(b):
-    """5.5 million queries in one chunk: the segments of the grouping are
-    22 000 keys long, so b = 8 answers are placed through LDS windows and
-    b = 64 answers (176 KB windows) are written straight to their places."""
+@pytest.mark.parametrize("b,reps,neg", [(8, 40, 3_000_000), (64, 320, 3_000_000)])
+def test_large_chunk_matches_plain(b, reps, neg):
+    """Millions of queries in one chunk: with b = 8 (5.6 million queries,
+    687 segments of 8 200) the answers are placed through LDS windows; with
+    b = 64 (24 million queries, 1024 segments of 23 400 and 183 KB windows,
+    more than LDS holds) they are written straight to their places."""
     n, h, seed = 1 << 16, 2, 41
     print(f"[grouped] large chunk b={b}", flush=True)
     keys = S.member_keys(n, 1000)
     vals = S.values(n, b, 1000)
     st = vf.Structure.build(keys.to(DEV), vals.to(DEV), b=b, h=h, seed=seed)
     assert st.rc == vf.VF_OK
-    q = torch.cat([keys.repeat(40), S.negative_keys(n, 3_000_000, 1000)]).to(DEV)
+    q = torch.cat([keys.repeat(reps), S.negative_keys(n, neg, 1000)]).to(DEV)
     dt = _NP[st.info["cell_bytes"]]
     got = st.query_grouped(q).cpu().numpy().view(dt)
     assert np.array_equal(got, st.query(q).cpu().numpy().view(dt))

@@ -190,8 +190,10 @@ int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n,
  * cells sit on chip.  The three probes of a query then cost no memory
  * traffic; the grouping costs streaming passes over the keys.  Queries are
  * taken in chunks of up to 2^26 keys; each chunk is counted, scattered
- * into the workspace as (key, index) pairs grouped by shard and answered,
- * and the answers are moved to the keys' own positions in out.  A
+ * into the workspace grouped by shard (each key hashed once, and stored as
+ * its edge, fingerprint and position where these fit a word, else as the
+ * key and its index) and answered, and the answers are moved to the keys'
+ * own positions in out.  A
  * structure whose shards' cells do not fit in LDS (more than about 160 KB
  * per shard) is answered by the plain gathers of vf_query instead.
  * Grouping pays when a chunk holds many queries per shard (thousands at

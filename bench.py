@@ -237,7 +237,7 @@ def batch_main(args) -> None:
     total = int(n.sum())
     print(f"[bench] batch: {n.size} instances, {total} keys", file=sys.stderr, flush=True)
     keys = S.member_keys(total, args.data_seed + 2, device=dev)
-    vals = S.values(total, 32, args.data_seed + 2, device=dev)
+    vals = S.batch_values(n, b, args.data_seed + 2, device=dev)
     inst = torch.repeat_interleave(torch.arange(n.size, dtype=torch.int32, device=dev),
                                    torch.as_tensor(n.astype(np.int64), device=dev))
     out = torch.empty(total, dtype=torch.int64, device=dev)

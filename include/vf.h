@@ -56,6 +56,7 @@ extern "C" {
 #define VF_ECAPACITY (-5) /* a shard exceeded a fixed on-chip capacity of
                              this implementation (elimination window or
                              pivot log); the method itself did not fail    */
+#define VF_ENOMEM (-6)    /* a host-side allocation of the library failed  */
 
 /* Options.  vf_default_opts() fills the paper's defaults. */
 typedef struct vf_opts {
@@ -132,16 +133,17 @@ int vf_plan(uint64_t n, int32_t b, double eps, int32_t is_filter,
 
 /* Build a static function (Problem 1).
  *   keys      device, n uint64 keys
- *   values    device, n uint64 words; the low b bits are stored, higher
- *             bits must be zero (VF_EINVAL is not checked on device: higher
- *             bits are masked off)
+ *   values    device, n uint64 words of b bits (Problem 1): a value with a
+ *             bit at or above b makes the call return VF_EINVAL before the
+ *             structure is written (checked on the device, read at the
+ *             call's first synchronization)
  *   b         1..64 value bits; cells are 1, 2, 4 or 8 bytes wide
  *   eps, o    sharding as in vf_plan; seed selects the hash functions
  *   workspace device scratch of at least vf_plan().workspace_bytes
  *   structure device buffer of at least vf_plan().structure_bytes
  *   handle    receives a new handle (also on VF_EFAIL, for vf_failures)
  * Errors: VF_EINVAL, VF_ENOSPC (buffers too small for the actual largest
- * shard), VF_EFAIL, VF_ECAPACITY, VF_EHIP. */
+ * shard), VF_EFAIL, VF_ECAPACITY, VF_ENOMEM, VF_EHIP. */
 int vf_build(const uint64_t *keys, const uint64_t *values, uint64_t n,
              int32_t b, double eps, uint64_t seed, const vf_opts *o,
              void *workspace, uint64_t workspace_bytes, void *structure,
@@ -266,15 +268,17 @@ int vf_batch_plan(uint64_t count, const uint64_t *n, const int32_t *b,
 /* Build a batch.
  *   keys, values device; the keys (and values) of instance i follow those
  *                of instance i - 1 (n[0] + ... + n[count-1] words each);
- *                the low b[i] bits of a value are stored
+ *                a value of instance i has b[i] bits: a higher bit makes
+ *                the call return VF_EINVAL before the structure is written
  *   count, n, b  instances and their sizes and value bits (host arrays)
  *   seed, o      hash seed shared by all instances; o->h is ignored
  *   workspace, structure  device buffers of at least vf_batch_plan() bytes
  *   handle       receives a batch handle (also on VF_EFAIL)
  * The keys are used in place (no grouping pass); every launch is enqueued
- * on stream and the call synchronizes once at the end to read the failure
- * record.  Errors: VF_EINVAL, VF_ENOSPC, VF_EFAIL (an instance failed all
- * local seeds), VF_ECAPACITY, VF_EHIP. */
+ * on stream; the call synchronizes once after checking the values and once
+ * at the end to read the failure record.  Errors: VF_EINVAL, VF_ENOSPC,
+ * VF_EFAIL (an instance failed all local seeds), VF_ECAPACITY, VF_ENOMEM,
+ * VF_EHIP. */
 int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
                    const uint64_t *n, const int32_t *b, uint64_t seed,
                    const vf_opts *o, void *workspace, uint64_t workspace_bytes,

@@ -80,6 +80,8 @@ def lib():
         L.orc_seed_words.argtypes = [C.c_uint64, u64p]
         L.orc_fingerprint.restype = C.c_uint64
         L.orc_fingerprint.argtypes = [C.c_uint64, C.c_uint64, u64p, C.c_int32]
+        L.orc_shard_of.restype = C.c_uint32
+        L.orc_shard_of.argtypes = [C.c_uint64, C.c_int32]
         L.orc_edge.argtypes = [C.c_uint64, C.c_uint64, C.c_int32, C.c_uint32,
                                C.c_int32, C.c_uint32, u32p]
         L.orc_edge_mwhc.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, u32p]
@@ -136,6 +138,11 @@ def seed_words(seed: int) -> np.ndarray:
     out = np.zeros(3, np.uint64)
     lib().orc_seed_words(seed, out)
     return out
+
+
+def shard_of(hi: int, h: int) -> int:
+    """Shard of a signature whose first word is hi (R2)."""
+    return int(lib().orc_shard_of(hi, h))
 
 
 def edge(hi: int, lo: int, h: int, l: int, sigma: int, t: int) -> tuple:

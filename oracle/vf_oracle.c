@@ -17,34 +17,49 @@
  *     SplitMix64 started at the user seed (section 4.3 hashes keys once to
  *     signatures and derives everything from them).
  *  R2 shard = the h highest bits of the first word (section 4, "higher bits").
- *  R3 segment = fixed-point inversion of the 32 bits right below the shard
- *     bits: g = (F * ell) >> 32 (section 4.5).
- *  R4 in-segment offsets = three disjoint sigma-bit fields of the second word
- *     for local seed t = 0, and of SplitMix64's finalizer of
- *     (second word + t * golden gamma) for t > 0.  Shard, segment and
- *     fingerprint never depend on t.
+ *  R3 segment = fixed-point inversion of 32 bits F: g = (F * ell) >> 32
+ *     (section 4.5), F = the 32 bits right below the shard bits for local
+ *     seed t = 0 (so the segment is monotone in the signature) and the high
+ *     32 bits of L_t (R4) for t > 0.
+ *  R4 in-segment offsets = three disjoint sigma-bit fields of L_t: the
+ *     second word for t = 0, SplitMix64's finalizer of (second word +
+ *     t * golden gamma) for t > 0.  Shard and fingerprint never depend on
+ *     t; every retry of a shard draws a new graph (segments too, as a
+ *     rehash with a local seed does in HEM, section 3.2): a fuse graph
+ *     whose segments are overloaded (more equations than vertices in a
+ *     stretch of segments) would otherwise stay unsolvable under every
+ *     local seed.
  *  R5 fingerprint = top b bits of the finalizer of (hi ^ lo ^ third seed
  *     word); it is derived from the signature (section 4.5), so keys with
  *     equal signatures have equal fingerprints.
- *  R6 geometry: c = 1.12 below 800 000 keys per shard (section 4.2, small
- *     sizes, solved with Gaussian elimination), c = 1.105 and lg s from
- *     eq. (nln) for larger shards, c = 1.125 and lg s from eq. (ln) for a
- *     single unsharded graph of at least 800 000 keys.  For small shards the
- *     paper fixes no segment size; we take the smallest s for which the
- *     expected number of duplicate edges of a shard, m / (2 c s^2)
- *     (section 4.2), is at most 1/8, but at most s = 2^9: larger segments
- *     cost locality (section 4.2), and a duplicate edge only costs a retry
- *     with the next local seed (R4), so shards beyond about 73 000 keys
- *     accept more duplicate edges (1.4 expected at 800 000 keys) instead.  Section 4 leaves shard sizing to
- *     simulation when no bound is known: simulated with this oracle, c = 1.12
- *     fails in most attempts below 2^16 keys per shard, and so does any
- *     fixed c near it at some sizes (a fuse graph with few segments is
- *     overloaded in its middle; section 4.2 notes that for small n the
- *     factor grows towards that of general random hypergraphs).  Graphs
- *     below 2^16 keys therefore use Graf and Lemire's size-dependent factor,
- *     whose estimates section 4.2 says the paper partly adopts:
- *     c = 0.875 + 0.25 ln(10^6) / ln(max(m, 10)), rounded up to thousandths.
- *     ell = max(1, ceil(c M / s) - 2), V = (ell + 2) s.
+ *  R6 geometry: c = 1.105 and lg s from eq. (nln) for shards of at least
+ *     800 000 keys, c = 1.125 and lg s from eq. (ln) for a single unsharded
+ *     graph of at least 800 000 keys (Graf and Lemire's estimate, which
+ *     section 4.2 says the paper partly adopts).  Below 800 000 keys section
+ *     4.2 keeps c = 1.12 and solves what does not peel by Gaussian
+ *     elimination, but fixes no segment size; section 4 leaves sizing to
+ *     simulation where no bound is known.  Simulated with this oracle (one
+ *     graph per size, 40 key sets, up to 64 local seeds): c = 1.12 builds
+ *     whenever the middle segments carry at most about 0.93 equations per
+ *     vertex, m / (ell s) <= 0.93, and the segments hold at least 2^8
+ *     vertices; smaller segments fail for every local seed at any size
+ *     (their local overloads do not move with the seed: the segment of a
+ *     key never depends on it), and denser middle segments fail at 2 000 to
+ *     8 000 keys.  Hence, for m keys with 64 <= m < 2^16:
+ *       sigma = min(8, floor(lg m) - 2),
+ *     and for 2^16 <= m < 800 000, sigma = 9, which keeps the expected
+ *     duplicate edges of a shard, m / (2 c s^2) (section 4.2), at 0.11 for
+ *     2^16 keys (0.45 with s = 2^8: a duplicate edge costs a retry);
+ *       c = max(1.12, 1.075 + 2 s / m), rounded up to thousandths,
+ *     which is c = 1.12 from 11 378 keys up and otherwise the smallest
+ *     factor that keeps the middle density at 1 / 1.075 = 0.93.  The cap
+ *     sigma <= 9 is a capacity parameter of the GPU elimination (the
+ *     window of rows it keeps in LDS spans three segments), not a reading
+ *     of the paper.
+ *     Graphs of fewer than 64 keys are one block of three segments
+ *     (ell = 1) with s = 2^ceil(lg((m + 1) / 2)), a random 3-partite
+ *     hypergraph with 1.5 to 3 vertices per key; c is then reported as
+ *     3 s / m.  ell = max(1, ceil(c M / s) - 2), V = (ell + 2) s.
  *  R11 MWHC (section 4.1): a 3-partite 3-hypergraph with three parts of
  *     ceil(c M / 3) vertices, c = 1.23 (the section's example); vertex i of
  *     an edge is i * part + ((f_i * part) >> 21) with f_i the i-th 21-bit
@@ -121,9 +136,10 @@ uint32_t orc_shard_of(uint64_t hi, int32_t h) {
  * (section 4.2, definition of fuse graphs). */
 void orc_edge(uint64_t hi, uint64_t lo, int32_t h, uint32_t l, int32_t sigma,
               uint32_t t, uint32_t v[3]) {
-  uint64_t F = (hi << h) >> 32; /* 32 bits right below the shard bits */
-  uint64_t g = (F * (uint64_t)l) >> 32;
   uint64_t L = t == 0 ? lo : orc_mix64(lo + (uint64_t)t * GOLDEN_GAMMA);
+  /* t = 0: the 32 bits right below the shard bits; t > 0: the top of L_t */
+  uint64_t F = t == 0 ? (hi << h) >> 32 : L >> 32;
+  uint64_t g = (F * (uint64_t)l) >> 32;
   uint64_t s = 1ULL << sigma;
   for (int i = 0; i < 3; i++)
     v[i] = (uint32_t)((g + (uint64_t)i) * s + ((L >> (i * sigma)) & (s - 1)));
@@ -221,32 +237,39 @@ double orc_dupfuse(double n, double c, double eta, double alpha, double beta) {
 void orc_geometry(uint32_t M, int32_t h, uint32_t c_num, uint32_t c_den,
                   int32_t sigma_override, orc_geom *g) {
   int large = M >= 800000u;
-  if (c_num == 0 || c_den == 0) {
-    if (large && h > 0) { c_num = 1105; c_den = 1000; }  /* 1.105 */
-    else if (large) { c_num = 1125; c_den = 1000; }      /* 1.125 */
-    else if (M >= 65536u) { c_num = 112; c_den = 100; }  /* 1.12 */
-    else {
-      /* small graphs: Graf and Lemire's factor 0.875 + 0.25 ln(10^6) / ln m
-       * (m at least 10), rounded up to thousandths */
-      double x = 875.0 + 250.0 * log(1e6) / log((double)(M < 10u ? 10u : M));
-      c_num = (uint32_t)ceil(x - 1e-9);
-      c_den = 1000;
-    }
-  }
-  int32_t sigma;
-  if (sigma_override >= 0) {
-    sigma = sigma_override;
-  } else if (large && h > 0) { /* eq. (nln) read as lg of the segment size */
+  int32_t sigma = -1;
+  if (sigma_override >= 0) sigma = sigma_override;
+  else if (large && h > 0) { /* eq. (nln) read as lg of the segment size */
     double lm = log((double)M);
     sigma = (int32_t)floor(0.41 * lm * log(lm) - 3.0);
   } else if (large) { /* eq. (ln), Graf and Lemire's segment size */
     sigma = (int32_t)floor(log((double)M) / log(3.33) + 2.25);
-  } else { /* smallest s with m / (2 c s^2) <= 1/8, at most 2^9 */
+  } else if (M < 64u) { /* one block of three segments, s >= (M + 1) / 2 */
     sigma = 0;
-    while (sigma < 9 && (uint64_t)c_num << (2 * sigma) < 4ULL * M * c_den) sigma++;
+    while ((2ULL << sigma) < (uint64_t)M + 1) sigma++;
+  } else if (M >= 65536u) { /* 2^9 from 2^16 keys */
+    sigma = 9;
+  } else { /* floor(lg M) - 2, at most 8 */
+    int32_t lg = 0;
+    while ((2ULL << lg) <= M) lg++;
+    sigma = lg - 2 < 8 ? lg - 2 : 8;
   }
   if (sigma < 0) sigma = 0;
   if (sigma > 20) sigma = 20;
+  if (c_num == 0 || c_den == 0) {
+    if (large && h > 0) { c_num = 1105; c_den = 1000; }  /* 1.105 */
+    else if (large) { c_num = 1125; c_den = 1000; }      /* 1.125 */
+    else if (M < 64u) { /* ell = 1 with the block's own segment size */
+      int32_t st = 0;
+      while ((2ULL << st) < (uint64_t)M + 1) st++;
+      c_num = 3u << st;
+      c_den = M ? M : 1u;
+    } else { /* max(1.12, 1.075 + 2 s / M) in thousandths, rounded up */
+      uint64_t x = 1075 + (2000ULL * (1ULL << sigma) + M - 1) / M;
+      c_num = x > 1120 ? (uint32_t)x : 1120u;
+      c_den = 1000;
+    }
+  }
   uint64_t num = (uint64_t)c_num * M;
   uint64_t den = (uint64_t)c_den << sigma;
   uint64_t q = (num + den - 1) / den; /* ceil(c M / s) */

@@ -10,6 +10,7 @@ no CPU fallback: importing this module fails if the library is not built.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 from dataclasses import dataclass
@@ -19,9 +20,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvf.so")
 
-VF_OK, VF_EINVAL, VF_ENOSPC, VF_EFAIL, VF_EHIP, VF_ECAPACITY = 0, -1, -2, -3, -4, -5
+VF_OK, VF_EINVAL, VF_ENOSPC, VF_EFAIL, VF_EHIP, VF_ECAPACITY, VF_ENOMEM = (
+    0, -1, -2, -3, -4, -5, -6)
 _ERR = {VF_EINVAL: "VF_EINVAL", VF_ENOSPC: "VF_ENOSPC", VF_EFAIL: "VF_EFAIL",
-        VF_EHIP: "VF_EHIP", VF_ECAPACITY: "VF_ECAPACITY"}
+        VF_EHIP: "VF_EHIP", VF_ECAPACITY: "VF_ECAPACITY", VF_ENOMEM: "VF_ENOMEM"}
 
 
 class VFError(RuntimeError):
@@ -116,6 +118,21 @@ EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build"
 def _check(rc: int, where: str) -> None:
     if rc != VF_OK:
         raise VFError(rc, where)
+
+
+def _on(stream):
+    """Context in which tensors are allocated on `stream` (a torch stream or
+    None for the current one)."""
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
+def _used_on(stream, *tensors) -> None:
+    """Marks tensors as used by work enqueued on `stream` (no-op for the
+    current stream)."""
+    if stream is not None:
+        for t in tensors:
+            if t is not None and t.is_cuda:
+                t.record_stream(stream)
 
 
 def _stream(stream) -> int:
@@ -338,33 +355,36 @@ class Structure:
         return self.structure[off: off + i["S"]]
 
     def query(self, keys: torch.Tensor, out: torch.Tensor | None = None, stream=None):
-        if self.is_filter:
+        with _on(stream):
             if out is None:
-                out = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
-            vfilter_contains(self.handle, keys, out, stream)
-        else:
-            if out is None:
-                out = torch.empty(keys.numel(), dtype=_CELL_DTYPE[self.info["cell_bytes"]],
-                                  device=keys.device)
-            vf_query(self.handle, keys, out, stream)
+                dt = torch.uint8 if self.is_filter else _CELL_DTYPE[self.info["cell_bytes"]]
+                out = torch.empty(keys.numel(), dtype=dt, device=keys.device)
+            if self.is_filter:
+                vfilter_contains(self.handle, keys, out, stream)
+            else:
+                vf_query(self.handle, keys, out, stream)
+        _used_on(stream, keys, out)
         return out
 
     def query_grouped(self, keys: torch.Tensor, out: torch.Tensor | None = None,
                       workspace: torch.Tensor | None = None, stream=None):
         """As query, with the keys grouped by shard first; workspace is a
-        uint8 device tensor (default: one chunk for all keys)."""
-        if workspace is None:
-            workspace = torch.empty(vf_query_grouped_bytes(self.handle, keys.numel()),
-                                    dtype=torch.uint8, device=keys.device)
-        if self.is_filter:
+        uint8 device tensor (default: one chunk for all keys).  Tensors made
+        here are allocated on `stream`, and every tensor the call hands to
+        the library is marked as used there, so the caching allocator does
+        not reuse it while the call's kernels may still run."""
+        with _on(stream):
+            if workspace is None:
+                workspace = torch.empty(vf_query_grouped_bytes(self.handle, keys.numel()),
+                                        dtype=torch.uint8, device=keys.device)
             if out is None:
-                out = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
-            vfilter_contains_grouped(self.handle, keys, out, workspace, stream)
-        else:
-            if out is None:
-                out = torch.empty(keys.numel(), dtype=_CELL_DTYPE[self.info["cell_bytes"]],
-                                  device=keys.device)
-            vf_query_grouped(self.handle, keys, out, workspace, stream)
+                dt = torch.uint8 if self.is_filter else _CELL_DTYPE[self.info["cell_bytes"]]
+                out = torch.empty(keys.numel(), dtype=dt, device=keys.device)
+            if self.is_filter:
+                vfilter_contains_grouped(self.handle, keys, out, workspace, stream)
+            else:
+                vf_query_grouped(self.handle, keys, out, workspace, stream)
+        _used_on(stream, keys, out, workspace)
         return out
 
     def free(self) -> None:

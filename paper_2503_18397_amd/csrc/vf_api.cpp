@@ -75,32 +75,23 @@ Geometry geometry_mwhc(uint32_t M, uint32_t cn, uint32_t cd) {
   return g;
 }
 
-// Section 4.2: c = 1.12 for shards below 800 000 keys (solved with Gaussian
-// elimination of the 2-core), c = 1.105 with lg s from eq. (nln) for larger
-// shards, c = 1.125 with lg s from eq. (ln) for a single large unsharded
-// graph.  Below 800 000 keys the segment size is the smallest power of two
-// with expected duplicate edges m / (2 c s^2) <= 1/8, at most 2^9 (larger
-// segments cost locality; a duplicate edge only costs a retry).  Graphs below 2^16
-// keys use Graf and Lemire's size-dependent factor 0.875 + 0.25 ln(10^6) /
-// ln m (section 4.2: the factor grows for small n; the paper partly adopts
-// their estimates): simulated (as section 4 suggests for sizing shards),
-// fuse systems that small are unsolvable in most attempts at c = 1.12 and,
-// at some sizes, at any fixed c near it.
+// Section 4.2: c = 1.105 with lg s from eq. (nln) for shards of at least
+// 800 000 keys, c = 1.125 with lg s from eq. (ln) for a single large
+// unsharded graph.  Below 800 000 keys the paper keeps c = 1.12 and solves
+// the unpeeled part by Gaussian elimination without fixing a segment size;
+// sized by simulation (section 4), c = 1.12 builds while the middle segments
+// carry at most about 0.93 equations per vertex and hold at least 2^8
+// vertices, so a shard of m keys takes lg s = min(8, floor(lg m) - 2) for
+// 64 <= m < 2^16 and lg s = 9 for 2^16 <= m < 800 000 (expected duplicate
+// edges m / (2 c s^2) of 0.11 at 2^16 keys instead of 0.45), and
+// c = max(1.12, 1.075 + 2 s / m) in thousandths rounded up (1.12 from
+// 11 378 keys up).  lg s <= 9 is a capacity of the elimination (its LDS
+// window spans three segments).
+// Graphs of fewer than 64 keys are one block of three segments with
+// s = 2^ceil(lg((m + 1) / 2)), c = 3 s / m.
 // ell = max(1, ceil(c M / s) - 2) start segments, V = (ell + 2) s cells.
 Geometry geometry(uint32_t M, int32_t h, uint32_t cn, uint32_t cd, int32_t sigma_ovr) {
   const bool large = M >= 800000u;
-  if (cn == 0 || cd == 0) {
-    if (large && h > 0) { cn = 1105; cd = 1000; }
-    else if (large) { cn = 1125; cd = 1000; }
-    else if (M >= 65536u) { cn = 112; cd = 100; }
-    else {
-      // small graphs: Graf and Lemire's factor 0.875 + 0.25 ln(10^6) / ln m
-      // (m at least 10), rounded up to thousandths
-      const double x = 875.0 + 250.0 * std::log(1e6) / std::log((double)(M < 10u ? 10u : M));
-      cn = (uint32_t)std::ceil(x - 1e-9);
-      cd = 1000;
-    }
-  }
   int32_t sg;
   if (sigma_ovr >= 0) {
     sg = sigma_ovr;
@@ -109,11 +100,30 @@ Geometry geometry(uint32_t M, int32_t h, uint32_t cn, uint32_t cd, int32_t sigma
     sg = (int32_t)std::floor(0.41 * lm * std::log(lm) - 3.0);
   } else if (large) {
     sg = (int32_t)std::floor(std::log((double)M) / std::log(3.33) + 2.25);
-  } else {
+  } else if (M < 64u) {
     sg = 0;
-    while (sg < 9 && ((uint64_t)cn << (2 * sg)) < 4ull * M * cd) sg++;
+    while ((2ull << sg) < (uint64_t)M + 1) sg++;
+  } else if (M >= 65536u) {
+    sg = 9;
+  } else {
+    const int32_t lg = 31 - __builtin_clz(M);
+    sg = std::min(lg - 2, 8);
   }
   sg = std::min(std::max(sg, 0), 20);
+  if (cn == 0 || cd == 0) {
+    if (large && h > 0) { cn = 1105; cd = 1000; }
+    else if (large) { cn = 1125; cd = 1000; }
+    else if (M < 64u) {
+      int32_t st = 0;
+      while ((2ull << st) < (uint64_t)M + 1) st++;
+      cn = 3u << st;
+      cd = M ? M : 1u;
+    } else {
+      const uint64_t x = 1075 + ((2000ull << sg) + M - 1) / M;
+      cn = (uint32_t)std::max<uint64_t>(x, 1120);
+      cd = 1000;
+    }
+  }
   const uint64_t den = (uint64_t)cd << sg;
   const uint64_t q = ((uint64_t)cn * M + den - 1) / den;
   Geometry g;
@@ -139,9 +149,23 @@ uint32_t shard_cap(uint64_t n, uint32_t S) {
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-// Elimination-window slots a shard needs: measured peaks of the window are
-// about 0.6 s rows for fuse graphs at c = 1.12 (s = segment size); keep a
-// margin.
+// No C++ exception crosses the C ABI: a failed host allocation becomes
+// VF_ENOMEM, anything else VF_EHIP.
+template <class F>
+int guarded(F &&f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    return VF_ENOMEM;
+  } catch (...) {
+    return VF_EHIP;
+  }
+}
+
+// Elimination-window slots a shard needs: simulated and measured peaks of
+// the window are about 0.55-0.75 s rows for fuse graphs at c = 1.12 (s =
+// segment size); shards that outgrow their share are rebuilt by a second
+// launch with a whole CU's LDS.
 uint32_t window_target(int32_t sigma) {
   const uint32_t s = 1u << sigma;
   return std::min<uint32_t>(512u, s / 2 + s / 8 + 32);
@@ -156,6 +180,33 @@ void build_occupancy(int32_t sigma, uint32_t *per_cu, uint32_t *lds_bytes) {
     if (vfk::window_slots((uint32_t)sigma, (vfk::kLdsBudget / n) & ~255u) >= want) best = n;
   *per_cu = best;
   *lds_bytes = (vfk::kLdsBudget / best) & ~255u;
+}
+
+// Launch shape of a build: workgroups per CU bounded by both LDS (each
+// keeps an elimination window of window_target slots) and registers, the
+// LDS each gets once that count is known, and its window slots.
+struct BuildShape {
+  uint32_t per_cu, lds_bytes, wmax;
+};
+BuildShape build_shape(int32_t sigma, uint32_t cell_bytes) {
+  BuildShape b{};
+  build_occupancy(sigma, &b.per_cu, &b.lds_bytes);
+  auto slots = [&] {
+    uint32_t w = vfk::window_slots((uint32_t)sigma, b.lds_bytes);
+    // fewer slot groups in registers when the target allows it
+    if (w > 384 && window_target(sigma) <= 384) w = 384;
+    if (w > 256 && window_target(sigma) <= 256) w = 256;
+    return w;
+  };
+  b.wmax = slots();
+  const int occ = vfk::build_blocks_per_cu(cell_bytes, b.wmax, b.lds_bytes);
+  if (occ > 0 && (uint32_t)occ < b.per_cu) {
+    // registers allow fewer: give each resident workgroup more LDS
+    b.per_cu = (uint32_t)occ;
+    b.lds_bytes = (vfk::kLdsBudget / b.per_cu) & ~255u;
+    b.wmax = slots();
+  }
+  return b;
 }
 
 int device_cus() {
@@ -204,14 +255,21 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
     l.gcap = geometry_mwhc(l.cap, o.c_num, o.c_den);
   } else {
     l.gcap = geometry(l.cap, h, o.c_num, o.c_den, o.sigma);
-  // the rule for c and s changes at 2^16 and 800 000 keys: size buffers for
-  // the larger side of each change, plus one spare segment
-  for (uint32_t edge : {65535u, 799999u}) {
-    if (l.cap > edge) {
-      Geometry below = geometry(edge, h, o.c_num, o.c_den, o.sigma);
-      if (below.V > l.gcap.V) l.gcap.V = below.V;
-      if (below.l > l.gcap.l) l.gcap.l = below.l;
-      if (below.sigma > l.gcap.sigma) l.gcap.sigma = below.sigma;
+  // V is not monotone in the shard size (segments double at powers of two,
+  // the factor changes at 800 000 keys): size buffers for the largest V,
+  // segment and segment count any shard up to the cap may take
+  {
+    std::vector<uint32_t> probe;
+    for (uint32_t k = 1; k <= 32 && (1ull << k) <= (uint64_t)l.cap; k++) {
+      probe.push_back((1u << k) - 1);
+      probe.push_back(1u << k);
+    }
+    if (l.cap > 799999u) probe.push_back(799999u);
+    for (uint32_t m : probe) {
+      Geometry gk = geometry(m, h, o.c_num, o.c_den, o.sigma);
+      l.gcap.V = std::max(l.gcap.V, gk.V);
+      l.gcap.l = std::max(l.gcap.l, gk.l);
+      l.gcap.sigma = std::max(l.gcap.sigma, gk.sigma);
     }
   }
   l.gcap.V += 1ull << l.gcap.sigma;
@@ -226,9 +284,9 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   l.cell_bytes = cell_bytes_for(b);
   uint32_t per_cu, lds_bytes;
   build_occupancy(l.gcap.sigma, &per_cu, &lds_bytes);
-  // the actual (smaller or equal) segment size may allow more workgroups
-  // per CU; scratch is sized for up to 4 per CU
-  per_cu = std::max<uint32_t>(per_cu, 4);
+  // registers let at most 4 build workgroups share a CU; scratch is sized
+  // for that many (the launch takes as many as are resident at once)
+  per_cu = 4;
   l.nwg = (uint32_t)std::max<uint64_t>(
       1, std::min<uint64_t>((uint64_t)per_cu * (ncu > 0 ? ncu : 256), l.S));
   // pivot log of the 2-core elimination (MWHC never eliminates)
@@ -277,6 +335,7 @@ struct BatchLayout {
   uint32_t nwg = 0, logcap = 0, fail_cap = 0;
   uint64_t scratch_stride = 0;
   uint64_t o_work = 0, o_fails = 0, o_overflow = 0, o_order = 0, o_scratch = 0, ws_bytes = 0;
+  uint64_t o_check = 0;  // instance descriptors and a flag for the value check
   uint64_t s_items = 0, s_seeds = 0, s_cells = 0, cells_bytes = 0, st_bytes = 0;
 };
 
@@ -333,6 +392,7 @@ int make_batch_layout(uint64_t count, const uint64_t *n, const int32_t *b, const
   l.o_overflow = take(8ull * count);
   l.o_order = take(8ull * count);
   l.o_scratch = take(l.scratch_stride * l.nwg);
+  l.o_check = take(sizeof(vfk::BatchItem) * count + 256);
   l.ws_bytes = o_;
   o_ = 0;
   l.s_items = take(sizeof(vfk::BatchItem) * count);
@@ -412,7 +472,7 @@ int vf_plan(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts 
   vf_opts d;
   vf_default_opts(&d);
   Layout L;
-  int rc = make_layout(n, b, eps, is_filter, o ? *o : d, device_cus(), &L);
+  int rc = guarded([&] { return make_layout(n, b, eps, is_filter, o ? *o : d, device_cus(), &L); });
   if (rc) return rc;
   out->structure_bytes = L.st_bytes;
   out->workspace_bytes = L.ws_bytes;
@@ -512,11 +572,15 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
     HIPCHK(vfk::launch_count(keys, n, sw[0], (uint32_t)L.h, L.S, counts, ncu, stream));
   }
   HIPCHK(vfk::launch_scan(counts, L.S, offsets, cursor, meta, stream));
+  // Problem 1 stores b-bit values: any higher bit makes the call fail
+  // before the structure is written (meta[1])
+  if (!is_filter) HIPCHK(vfk::launch_check_values(values, n, (uint32_t)b, meta + 1, stream));
   pe.record(1, stream);
   uint32_t hmeta[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(hmeta, meta, sizeof(hmeta), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   const uint32_t M = hmeta[0];
+  if (hmeta[1]) return VF_EINVAL;
   if (M > L.cap) return VF_ENOSPC;
   const Geometry g =
       op.mwhc ? geometry_mwhc(M, op.c_num, op.c_den) : geometry(M, L.h, op.c_num, op.c_den, op.sigma);
@@ -562,12 +626,10 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   A.fail_cap = L.fail_cap;
   A.M = M;
   A.tmax = op.tmax;
-  uint32_t per_cu = 1;
-  build_occupancy(g.sigma, &per_cu, &A.lds_bytes);
-  A.wmax = vfk::window_slots((uint32_t)g.sigma, A.lds_bytes);
-  // a window of at most 384 slots lets the kernel keep 6 instead of 8 slot
-  // groups per lane (overflowing shards go to the second launch)
-  if (A.wmax > 384 && window_target(g.sigma) <= 384) A.wmax = 384;
+  const BuildShape shape = build_shape(g.sigma, L.cell_bytes);
+  A.lds_bytes = shape.lds_bytes;
+  A.wmax = shape.wmax;
+  const uint32_t per_cu = shape.per_cu;
   const uint32_t nwg = std::min<uint32_t>(L.nwg, per_cu * (uint32_t)ncu);
   A.logcap = L.logcap;
   A.cell_bytes = L.cell_bytes;
@@ -609,7 +671,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
 #undef HIPCHK
 
   vf_handle *H = new (std::nothrow) vf_handle();
-  if (!H) return VF_EINVAL;
+  if (!H) return VF_ENOMEM;
   H->magic = kMagic;
   H->is_filter = is_filter;
   H->b = b;
@@ -644,15 +706,19 @@ int vf_build(const uint64_t *keys, const uint64_t *values, uint64_t n, int32_t b
              uint64_t seed, const vf_opts *o, void *workspace, uint64_t workspace_bytes,
              void *structure, uint64_t structure_bytes, hipStream_t stream,
              vf_handle **handle) {
-  return build_common(keys, values, n, b, eps, seed, o, workspace, workspace_bytes, structure,
-                      structure_bytes, stream, handle, 0);
+  return guarded([&] {
+    return build_common(keys, values, n, b, eps, seed, o, workspace, workspace_bytes, structure,
+                        structure_bytes, stream, handle, 0);
+  });
 }
 
 int vfilter_build(const uint64_t *keys, uint64_t n, int32_t b, double eps, uint64_t seed,
                   const vf_opts *o, void *workspace, uint64_t workspace_bytes, void *structure,
                   uint64_t structure_bytes, hipStream_t stream, vf_handle **handle) {
-  return build_common(keys, nullptr, n, b, eps, seed, o, workspace, workspace_bytes, structure,
-                      structure_bytes, stream, handle, 1);
+  return guarded([&] {
+    return build_common(keys, nullptr, n, b, eps, seed, o, workspace, workspace_bytes, structure,
+                        structure_bytes, stream, handle, 1);
+  });
 }
 
 int vfilter_build_host(const uint64_t *keys, uint64_t n, int32_t b, double eps, uint64_t seed,
@@ -662,8 +728,10 @@ int vfilter_build_host(const uint64_t *keys, uint64_t n, int32_t b, double eps, 
   HostKeys hk;
   hk.keys = keys;
   hk.chunk = chunk;
-  return build_common(nullptr, nullptr, n, b, eps, seed, o, workspace, workspace_bytes,
-                      structure, structure_bytes, stream, handle, 1, &hk);
+  return guarded([&] {
+    return build_common(nullptr, nullptr, n, b, eps, seed, o, workspace, workspace_bytes,
+                        structure, structure_bytes, stream, handle, 1, &hk);
+  });
 }
 
 static int query_common(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
@@ -714,7 +782,7 @@ int vf_query_grouped_bytes(const vf_handle *h, uint64_t n, uint64_t *bytes) {
   return VF_OK;
 }
 
-static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
+static int query_grouped_impl(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
                                 void *workspace, uint64_t workspace_bytes, hipStream_t stream,
                                 int32_t want_filter) {
   if (!h || h->magic != kMagic || h->kind != 0 || h->is_filter != want_filter) return VF_EINVAL;
@@ -787,6 +855,14 @@ static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64
   return VF_OK;
 }
 
+static int query_grouped_common(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
+                                void *workspace, uint64_t workspace_bytes, hipStream_t stream,
+                                int32_t want_filter) {
+  return guarded([&] {
+    return query_grouped_impl(h, keys, n, out, workspace, workspace_bytes, stream, want_filter);
+  });
+}
+
 int vf_query_grouped(const vf_handle *h, const uint64_t *keys, uint64_t n, void *out,
                      void *workspace, uint64_t workspace_bytes, hipStream_t stream) {
   return query_grouped_common(h, keys, n, out, workspace, workspace_bytes, stream, 0);
@@ -803,7 +879,7 @@ int vf_batch_plan(uint64_t count, const uint64_t *n, const int32_t *b, const vf_
   vf_opts d;
   vf_default_opts(&d);
   BatchLayout L;
-  const int rc = make_batch_layout(count, n, b, o ? *o : d, device_cus(), &L);
+  const int rc = guarded([&] { return make_batch_layout(count, n, b, o ? *o : d, device_cus(), &L); });
   if (rc) return rc;
   out->structure_bytes = L.st_bytes;
   out->workspace_bytes = L.ws_bytes;
@@ -812,10 +888,10 @@ int vf_batch_plan(uint64_t count, const uint64_t *n, const int32_t *b, const vf_
   return VF_OK;
 }
 
-int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
-                   const uint64_t *n, const int32_t *b, uint64_t seed, const vf_opts *o,
-                   void *ws, uint64_t ws_bytes, void *st, uint64_t st_bytes,
-                   hipStream_t stream, vf_handle **handle) {
+static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
+                       const uint64_t *n, const int32_t *b, uint64_t seed, const vf_opts *o,
+                       void *ws, uint64_t ws_bytes, void *st, uint64_t st_bytes,
+                       hipStream_t stream, vf_handle **handle) {
   if (!handle || !ws || !st) return VF_EINVAL;
   vf_opts d;
   vf_default_opts(&d);
@@ -865,6 +941,21 @@ int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
     }
     for (int c = 1; c < 5; c++) cls_begin[c] = std::max(cls_begin[c], cls_begin[c - 1]);
   }
+  // Problem 1 stores b-bit values: a value with a higher bit fails the
+  // call before the structure is written (descriptors staged in the
+  // workspace for the check)
+  if (L.keys) {
+    vfk::BatchItem *citems = (vfk::BatchItem *)(W + L.o_check);
+    uint32_t *flag = (uint32_t *)(W + L.o_check + sizeof(vfk::BatchItem) * count);
+    uint32_t hflag = 0;
+    HIPCHK(hipMemcpyAsync(citems, L.items.data(), sizeof(vfk::BatchItem) * count,
+                          hipMemcpyHostToDevice, stream));
+    HIPCHK(vfk::launch_fill_u32(flag, 1, 0, stream));
+    HIPCHK(vfk::launch_check_batch_values(citems, count, values, flag, stream));
+    HIPCHK(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (hflag) return VF_EINVAL;
+  }
   PhaseEvents pe;
   pe.record(0, stream);
   HIPCHK(hipMemcpyAsync(items, L.items.data(), sizeof(vfk::BatchItem) * count,
@@ -903,11 +994,11 @@ int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
     if (c1 == c0) continue;
     int32_t sg = 0;
     for (uint64_t i = c0; i < c1; i++) sg = std::max(sg, (int32_t)L.items[ord[2 * i]].sigma);
-    uint32_t per_cu = 1;
     A.cell_bytes = kClassBytes[c];
-    build_occupancy(sg, &per_cu, &A.lds_bytes);
-    A.wmax = vfk::window_slots((uint32_t)sg, A.lds_bytes);
-    if (A.wmax > 384 && window_target(sg) <= 384) A.wmax = 384;
+    const BuildShape shape = build_shape(sg, A.cell_bytes);
+    A.lds_bytes = shape.lds_bytes;
+    A.wmax = shape.wmax;
+    const uint32_t per_cu = shape.per_cu;
     A.list = order + 2 * c0;
     A.nlist = (uint32_t)(c1 - c0);
     A.nlist_dev = nullptr;
@@ -977,6 +1068,16 @@ int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
   if (hwork[vfk::kWorkStatus] & vfk::kStatusCapacity) return VF_ECAPACITY;
   if (H->failed_shards) return VF_EFAIL;
   return VF_OK;
+}
+
+int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
+                   const uint64_t *n, const int32_t *b, uint64_t seed, const vf_opts *o,
+                   void *ws, uint64_t ws_bytes, void *st, uint64_t st_bytes,
+                   hipStream_t stream, vf_handle **handle) {
+  return guarded([&] {
+    return batch_build(keys, values, count, n, b, seed, o, ws, ws_bytes, st, st_bytes, stream,
+                       handle);
+  });
 }
 
 int vf_batch_query(const vf_handle *h, const uint32_t *inst, const uint64_t *keys, uint64_t nq,

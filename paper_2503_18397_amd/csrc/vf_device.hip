@@ -9,10 +9,12 @@
 //  * signature = (fin(key ^ k_hi), fin(key ^ k_lo)) with fin the SplitMix64
 //    finalizer and (k_hi, k_lo, k_fp) the first three SplitMix64 outputs
 //    from the user seed;
-//  * shard = top h bits of the first word; segment g = (F * l) >> 32 with F
-//    the 32 bits right below the shard bits (fixed-point inversion);
-//  * offsets = three sigma-bit fields of the second word (local seed t = 0)
-//    or of fin(second word + t * golden gamma) (t > 0);
+//  * shard = top h bits of the first word; segment g = (F * l) >> 32
+//    (fixed-point inversion) with F the 32 bits right below the shard bits
+//    for local seed t = 0 and the top 32 bits of the offset word for t > 0
+//    (a retry draws a new graph, segments included);
+//  * offsets = three sigma-bit fields of the offset word: the second word
+//    (local seed t = 0) or fin(second word + t * golden gamma) (t > 0);
 //  * fingerprint = top b bits of fin(hi ^ lo ^ k_fp);
 //  * MWHC (section 4.1): three parts of `part` vertices, vertex i the
 //    fixed-point image of the i-th 21-bit field of the offset word; an
@@ -58,9 +60,9 @@ __device__ __forceinline__ void edge3(const Geo &G, uint64_t hi, uint64_t lo,
     v2 = (uint32_t)(2 * p + ((((L >> 42) & 0x1FFFFFull) * p) >> 21));
     return;
   }
-  uint32_t F = (uint32_t)((hi << G.h) >> 32);
+  const uint64_t L = t ? fin64(lo + (uint64_t)t * kGamma) : lo;
+  const uint32_t F = t ? (uint32_t)(L >> 32) : (uint32_t)((hi << G.h) >> 32);
   uint32_t g = __umulhi(F, G.l);
-  uint64_t L = t ? fin64(lo + (uint64_t)t * kGamma) : lo;
   uint32_t s = 1u << G.sigma, m = s - 1;
   v0 = g * s + ((uint32_t)L & m);
   v1 = (g + 1) * s + ((uint32_t)(L >> G.sigma) & m);
@@ -175,6 +177,30 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+// Problem 1 stores b-bit values: flag (bit 0 of *flag) any value with a bit
+// at or above b.  Values of one structure share b.
+__global__ void k_check_values(const uint64_t *__restrict__ vals, uint64_t n, uint32_t b,
+                               uint32_t *flag) {
+  uint64_t bad = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    bad |= vals[i] >> b;
+  if (__ballot(bad != 0) && lane_id() == 0) atomicOr(flag, 1u);
+}
+
+// The same for a batch: workgroup i checks the values of instances i,
+// i + gridDim.x, ... against their own b.
+__global__ void k_check_batch_values(const BatchItem *__restrict__ items, uint64_t count,
+                                     const uint64_t *__restrict__ vals, uint32_t *flag) {
+  uint64_t bad = 0;
+  for (uint64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const BatchItem I = items[it];
+    if (I.b >= 64) continue;
+    for (uint32_t i = threadIdx.x; i < I.n; i += blockDim.x) bad |= vals[I.key_off + i] >> I.b;
+  }
+  if (__ballot(bad != 0) && lane_id() == 0) atomicOr(flag, 1u);
 }
 
 constexpr uint32_t kLdsHistMax = 16384;
@@ -372,9 +398,9 @@ __global__ void __launch_bounds__(kRowThreads) k_count_rows(const uint64_t *__re
 //           needs no index array (vb + 3 sigma + b <= 48).
 __device__ __forceinline__ uint64_t pack_compact(const Geo &G, uint64_t hi, uint64_t lo,
                                                  uint32_t t, uint32_t gb) {
-  const uint32_t F = (uint32_t)((hi << G.h) >> 32);
-  const uint64_t g = __umulhi(F, G.l);
   const uint64_t L = t ? fin64(lo + (uint64_t)t * kGamma) : lo;
+  const uint32_t F = t ? (uint32_t)(L >> 32) : (uint32_t)((hi << G.h) >> 32);
+  const uint64_t g = __umulhi(F, G.l);
   const uint32_t sg = G.sigma;
   const uint64_t m = (1ull << sg) - 1;
   uint64_t w = g | ((L & m) << gb) | (((L >> sg) & m) << (gb + sg)) |
@@ -2300,6 +2326,24 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_check_values(const uint64_t *vals, uint64_t n, uint32_t b, uint32_t *flag,
+                              hipStream_t s) {
+  if (!n || b >= 64) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_check_values, dim3((uint32_t)blocks), dim3(256), 0, s, vals, n, b, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_batch_values(const BatchItem *items, uint64_t count, const uint64_t *vals,
+                                    uint32_t *flag, hipStream_t s) {
+  if (!count) return hipSuccess;
+  const uint64_t blocks = count < 65536 ? count : 65536;
+  hipLaunchKernelGGL(k_check_batch_values, dim3((uint32_t)blocks), dim3(256), 0, s, items, count,
+                     vals, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_count(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                         uint32_t S, uint32_t *counts, int ncu, hipStream_t s) {
   if (!n) return hipSuccess;
@@ -2355,7 +2399,37 @@ static hipError_t launch_build_q(const BuildArgs &a, int nwg, hipStream_t s) {
 // registers; fewer groups mean fewer instructions per column.
 template <typename T>
 static hipError_t launch_build_t(const BuildArgs &a, int nwg, hipStream_t s) {
-  return a.wmax <= 384 ? launch_build_q<T, 6>(a, nwg, s) : launch_build_q<T, 8>(a, nwg, s);
+  return a.wmax <= 256   ? launch_build_q<T, 4>(a, nwg, s)
+         : a.wmax <= 384 ? launch_build_q<T, 6>(a, nwg, s)
+                         : launch_build_q<T, 8>(a, nwg, s);
+}
+
+template <typename T, int QM>
+static int build_occ_q(uint32_t lds_bytes) {
+  int nb = 0;
+  if (hipFuncSetAttribute((const void *)k_build<T, QM>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_bytes) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_build<T, QM>,
+                                                  (int)kBuildThreads, lds_bytes) != hipSuccess)
+    return 0;
+  return nb;
+}
+
+template <typename T>
+static int build_occ_t(uint32_t wmax, uint32_t lds_bytes) {
+  return wmax <= 256   ? build_occ_q<T, 4>(lds_bytes)
+         : wmax <= 384 ? build_occ_q<T, 6>(lds_bytes)
+                       : build_occ_q<T, 8>(lds_bytes);
+}
+
+int build_blocks_per_cu(uint32_t cell_bytes, uint32_t wmax, uint32_t lds_bytes) {
+  switch (cell_bytes) {
+    case 1: return build_occ_t<uint8_t>(wmax, lds_bytes);
+    case 2: return build_occ_t<uint16_t>(wmax, lds_bytes);
+    case 4: return build_occ_t<uint32_t>(wmax, lds_bytes);
+    default: return build_occ_t<uint64_t>(wmax, lds_bytes);
+  }
 }
 
 hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s) {

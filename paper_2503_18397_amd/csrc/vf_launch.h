@@ -104,6 +104,12 @@ uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap
 uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes);
 
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+// Sets bit 0 of *flag if a value has a bit at or above b (per instance for a
+// batch); the flag must be cleared beforehand.
+hipError_t launch_check_values(const uint64_t *vals, uint64_t n, uint32_t b, uint32_t *flag,
+                              hipStream_t s);
+hipError_t launch_check_batch_values(const BatchItem *items, uint64_t count, const uint64_t *vals,
+                                    uint32_t *flag, hipStream_t s);
 hipError_t launch_count(const uint64_t *keys, uint64_t n, uint64_t khi, uint32_t h,
                         uint32_t S, uint32_t *counts, int ncu, hipStream_t s);
 hipError_t launch_scan(const uint32_t *counts, uint32_t S, uint64_t *offsets,
@@ -116,6 +122,9 @@ hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n
                           uint64_t *bkeys, uint64_t *bvals, uint32_t *bidx, int ncu,
                           hipStream_t s);
 hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s);
+// Build workgroups that can be resident on one CU at once (registers and
+// LDS); 0 if the runtime cannot tell.
+int build_blocks_per_cu(uint32_t cell_bytes, uint32_t wmax, uint32_t lds_bytes);
 hipError_t launch_query_batch(const Geo &G, const BatchItem *items, uint64_t count,
                               const uint8_t *cells, const uint8_t *tseed, const uint32_t *inst,
                               const uint64_t *keys, uint64_t n, uint64_t *out, int ncu,

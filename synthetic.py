@@ -80,6 +80,20 @@ def values(n: int, b: int, data_seed: int, device="cpu") -> torch.Tensor:
     return v & ((1 << b) - 1) if b < 63 else v & 0x7FFFFFFFFFFFFFFF
 
 
+def batch_values(n, b, data_seed: int, device="cpu") -> torch.Tensor:
+    """Values of a batch: instance i's n[i] values are uniform b[i]-bit
+    words (the low b[i] bits of one value stream, int64 patterns)."""
+    import numpy as np
+    total = int(np.sum(n))
+    v = values(total, 64, data_seed, device=device)
+    bits = torch.repeat_interleave(torch.as_tensor(np.asarray(b, dtype=np.int64), device=device),
+                                   torch.as_tensor(np.asarray(n, dtype=np.int64), device=device))
+    one = torch.ones_like(bits)
+    mask = torch.where(bits >= 63, torch.full_like(bits, -1), (one << bits.clamp(max=62)) - 1)
+    mask = torch.where(bits == 63, torch.full_like(bits, 0x7FFFFFFFFFFFFFFF), mask)
+    return v & mask
+
+
 def _scale(u: torch.Tensor, n: int) -> torch.Tensor:
     """floor(u * n / 2^32) for 32-bit u and n <= 2^32 without 64-bit
     overflow (u split into 16-bit halves)."""

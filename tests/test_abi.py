@@ -70,3 +70,26 @@ def test_plan_rejects_bad_arguments():
         vf.vf_plan(1000, 8, 0.01, True, vf.vf_default_opts(tmax=0))
     with pytest.raises(vf.VFError):
         vf.vf_plan(1000, 8, 0.01, True, vf.vf_default_opts(h=25))
+
+
+def test_host_allocation_failure_is_vf_enomem():
+    """A host allocation the library cannot make is reported as VF_ENOMEM
+    (never as VF_EINVAL, never as an exception crossing the C ABI).  A
+    batch of 2^32 - 1 instances needs 256 GiB of host descriptors; under an
+    8 GiB address-space limit that allocation fails before any instance
+    array is read."""
+    code = r"""
+import ctypes as C, resource, sys
+resource.setrlimit(resource.RLIMIT_AS, (8 << 30, 8 << 30))
+lib = C.CDLL(sys.argv[1])
+n = (C.c_uint64 * 1)(10)
+b = (C.c_int32 * 1)(8)
+out = (C.c_uint64 * 4)()
+rc = lib.vf_batch_plan(C.c_uint64((1 << 32) - 1), n, b, None, out)
+print(rc)
+"""
+    r = subprocess.run(["python3", "-c", code, LIB], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert int(r.stdout.strip().splitlines()[-1]) == -6  # VF_ENOMEM
+    import paper_2503_18397_amd as vf
+    assert vf.VF_ENOMEM == -6

@@ -20,7 +20,7 @@ _NP = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
 def _batch_inputs(n, b, data_seed):
     total = int(np.sum(n))
     keys = S.member_keys(total, data_seed, device=DEV)
-    vals = S.values(total, 64 if max(b) > 32 else 32, data_seed, device=DEV)
+    vals = S.batch_values(n, b, data_seed, device=DEV)
     off = np.concatenate([[0], np.cumsum(n.astype(np.int64))])
     return keys, vals, off
 

@@ -227,6 +227,24 @@ int vf_query_grouped(const vf_handle *h, const uint64_t *keys, uint64_t n, void 
 int vfilter_contains_grouped(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8_t *out,
                              void *workspace, uint64_t workspace_bytes, hipStream_t stream);
 
+/* vfilter_contains_grouped for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same answers, with the workspace taken from a static
+ * 64 MiB device array of the library instead of an argument.  No device or
+ * host memory is allocated by the call (the array's address is looked up
+ * once per device, on the first call with that device current).
+ *   keys, n, out, stream  as vfilter_contains_grouped; any n (queries are
+ *                         taken in chunks that fit the array)
+ * Every call on one GPU shares that GPU's array: calls in flight on the
+ * same GPU at the same time (other streams, other threads) race and give
+ * wrong answers; serialize them.  Nothing must start at zero in the array
+ * (each call initializes what it reads).
+ * Errors: VF_EINVAL (null handle/pointers, a function or batch handle,
+ * keys not 8-byte aligned), VF_ENOSPC (the structure's per-shard tables
+ * alone exceed the array: more than about 2^21 shards), VF_EHIP. */
+int vfilter_contains_grouped_noalloc(const vf_handle *h, const uint64_t *keys, uint64_t n,
+                                     uint8_t *out, hipStream_t stream);
+
 /* Describe a handle.  Errors: VF_EINVAL. */
 int vf_info(const vf_handle *h, vf_info_t *out);
 

@@ -94,6 +94,7 @@ _lib.vfilter_contains.argtypes = [_vp, _vp, _u64, _vp, _vp]
 _lib.vf_query_grouped_bytes.argtypes = [_vp, _u64, C.POINTER(_u64)]
 _lib.vf_query_grouped.argtypes = [_vp, _vp, _u64, _vp, _vp, _u64, _vp]
 _lib.vfilter_contains_grouped.argtypes = [_vp, _vp, _u64, _vp, _vp, _u64, _vp]
+_lib.vfilter_contains_grouped_noalloc.argtypes = [_vp, _vp, _u64, _vp, _vp]
 _lib.vf_info.argtypes = [_vp, C.POINTER(Info)]
 _lib.vf_failures.argtypes = [_vp, C.POINTER(Failure), C.c_uint32, C.POINTER(C.c_uint32)]
 _lib.vf_free.argtypes = [_vp]
@@ -106,13 +107,14 @@ _lib.vf_batch_item.argtypes = [_vp, _u64, C.POINTER(BatchItem)]
 for _f in ("vf_plan", "vf_build", "vfilter_build", "vf_query", "vfilter_contains", "vf_info",
            "vf_failures", "vf_batch_plan", "vf_batch_build", "vf_batch_query", "vf_batch_item",
            "vfilter_build_host", "vf_query_grouped_bytes", "vf_query_grouped",
-           "vfilter_contains_grouped"):
+           "vfilter_contains_grouped", "vfilter_contains_grouped_noalloc"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build",
            "vfilter_contains", "vf_info", "vf_failures", "vf_free", "vf_batch_plan",
            "vf_batch_build", "vf_batch_query", "vf_batch_item", "vfilter_build_host",
-           "vf_query_grouped_bytes", "vf_query_grouped", "vfilter_contains_grouped")
+           "vf_query_grouped_bytes", "vf_query_grouped", "vfilter_contains_grouped",
+           "vfilter_contains_grouped_noalloc")
 
 
 def _check(rc: int, where: str) -> None:
@@ -234,6 +236,12 @@ def vfilter_contains_grouped(handle, keys, out, workspace, stream=None) -> None:
                                          workspace.numel() * workspace.element_size(),
                                          _stream(stream)),
            "vfilter_contains_grouped")
+
+
+def vfilter_contains_grouped_noalloc(handle, keys, out, stream=None) -> None:
+    _check(_lib.vfilter_contains_grouped_noalloc(handle, _dev_ptr(keys, "keys"), keys.numel(),
+                                                 _dev_ptr(out, "out"), _stream(stream)),
+           "vfilter_contains_grouped_noalloc")
 
 
 def vf_info(handle) -> dict:

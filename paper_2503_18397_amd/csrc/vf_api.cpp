@@ -873,6 +873,18 @@ int vfilter_contains_grouped(const vf_handle *h, const uint64_t *keys, uint64_t 
   return query_grouped_common(h, keys, n, out, workspace, workspace_bytes, stream, 1);
 }
 
+int vfilter_contains_grouped_noalloc(const vf_handle *h, const uint64_t *keys, uint64_t n,
+                                     uint8_t *out, hipStream_t stream) {
+  if (!h || h->magic != kMagic || h->kind != 0 || !h->is_filter) return VF_EINVAL;
+  if (n && (!keys || !out)) return VF_EINVAL;
+  void *ws = nullptr;
+  uint64_t bytes = 0;
+  if (vfk::noalloc_scratch(&ws, &bytes) != hipSuccess) return VF_EHIP;
+  // the per-shard tables and one key must fit the static workspace
+  if (bytes < group_bytes(h->G.S, 1, 1)) return VF_ENOSPC;
+  return query_grouped_impl(h, keys, n, out, ws, bytes, stream, 1);
+}
+
 int vf_batch_plan(uint64_t count, const uint64_t *n, const int32_t *b, const vf_opts *o,
                   vf_sizes *out) {
   if (!out) return VF_EINVAL;

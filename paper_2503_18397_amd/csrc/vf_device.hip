@@ -30,9 +30,38 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "vf_launch.h"
 
+// Workspace of the allocation-free grouped filter query: one copy per
+// device (each GPU the library runs on holds it until the process ends).
+// Host code never passes this name to a kernel: it stands for the array
+// only on the device; the host uses the address hipGetSymbolAddress gives
+// for the current device (noalloc_scratch below).
+static __device__ __align__(256) uint8_t scratch[vfk::kNoAllocScratchBytes];
+
 namespace vfk {
+
+hipError_t noalloc_scratch(void **ptr, uint64_t *bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = kNoAllocScratchBytes;
+  return hipSuccess;
+}
 
 constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
 

@@ -122,6 +122,12 @@ hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n
                           uint64_t *bkeys, uint64_t *bvals, uint32_t *bidx, int ncu,
                           hipStream_t s);
 hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s);
+// The allocation-free grouped query's workspace: a device array of
+// kNoAllocScratchBytes per device; *ptr receives its address on the current
+// device (looked up once per device).
+constexpr uint64_t kNoAllocScratchBytes = 64ull << 20;
+hipError_t noalloc_scratch(void **ptr, uint64_t *bytes);
+
 // Build workgroups that can be resident on one CU at once (registers and
 // LDS); 0 if the runtime cannot tell.
 int build_blocks_per_cu(uint32_t cell_bytes, uint32_t wmax, uint32_t lds_bytes);

@@ -70,6 +70,13 @@ typedef struct vf_opts {
                          parts of ceil(c M / 3) cells, c = 1.23 by default,
                          peel-only (an attempt that does not peel fails, kind
                          2); keys must be distinct.  0: fuse graphs. */
+  uint32_t max_window; /* rows of the elimination window a build workgroup
+                         keeps (rounded down to a multiple of 8, at least
+                         8); a shard whose window would grow beyond it is
+                         rebuilt by the second launch, which has a whole
+                         CU's LDS.  0 (default): as many as the workgroup's
+                         share of LDS holds.  The result never depends on
+                         it. */
 } vf_opts;
 
 /* Sizes returned by vf_plan (upper bounds: the largest shard is known only

@@ -80,6 +80,7 @@ def lib():
         L.orc_seed_words.argtypes = [C.c_uint64, u64p]
         L.orc_fingerprint.restype = C.c_uint64
         L.orc_fingerprint.argtypes = [C.c_uint64, C.c_uint64, u64p, C.c_int32]
+        L.orc_shard_ids.argtypes = [u64p, C.c_uint64, C.c_int32, C.c_uint64, u32p]
         L.orc_shard_of.restype = C.c_uint32
         L.orc_shard_of.argtypes = [C.c_uint64, C.c_int32]
         L.orc_edge.argtypes = [C.c_uint64, C.c_uint64, C.c_int32, C.c_uint32,
@@ -261,13 +262,26 @@ def plan(keys, h: int, seed: int, c: tuple | None = None, sigma: int = -1,
     return g, counts
 
 
+def shard_ids(keys, h: int, seed: int) -> np.ndarray:
+    """Shard of every key (R2), as uint32."""
+    keys = _u64(keys)
+    out = np.zeros(max(keys.size, 1), np.uint32)
+    lib().orc_shard_ids(keys, keys.size, h, seed, out)
+    return out[: keys.size]
+
+
 def build(keys, values=None, *, b: int, is_filter: bool, h: int, seed: int,
           tmax: int = 255, c: tuple | None = None, sigma: int = -1,
-          shards=None, mwhc: bool = False) -> Built:
+          shards=None, mwhc: bool = False, geom: Geom | None = None) -> Built:
     """Build the listed shards (all if None) of a VFunc / VFilter (fuse
-    graphs, or MWHC 3-partite hypergraphs with mwhc=True)."""
+    graphs, or MWHC 3-partite hypergraphs with mwhc=True).  With geom (the
+    geometry plan() gives for the whole key set) the keys may be just those
+    of the listed shards."""
     keys = _u64(keys)
-    g, counts = plan(keys, h, seed, c, sigma, mwhc)
+    if geom is None:
+        g, counts = plan(keys, h, seed, c, sigma, mwhc)
+    else:
+        g, counts = geom, None
     S = 1 << h
     sh = np.arange(S, dtype=np.uint32) if shards is None else \
         np.ascontiguousarray(np.asarray(shards, np.uint32))
@@ -288,6 +302,42 @@ def build(keys, values=None, *, b: int, is_filter: bool, h: int, seed: int,
                    for r in rec[: min(nrec.value, cap)])
     return Built(g.as_dict(), g, seed, b, is_filter, counts, sh, t[: sh.size],
                  w[: sh.size], fails, status)
+
+
+def build_threaded(keys, values=None, *, b: int, is_filter: bool, h: int, seed: int,
+                   threads: int, tmax: int = 255, c: tuple | None = None, sigma: int = -1,
+                   mwhc: bool = False) -> Built:
+    """build() of every shard with the shards split over host threads (the
+    C oracle runs with the interpreter lock released): thread k builds the
+    shards j with j % threads == k from just their keys.  The result equals
+    build() of all shards."""
+    import concurrent.futures as cf
+    keys = _u64(keys)
+    vals = None if is_filter else _u64(values)
+    g, counts = plan(keys, h, seed, c, sigma, mwhc)
+    sid = shard_ids(keys, h, seed)
+    S = 1 << h
+    threads = max(1, min(threads, S))
+
+    def one(k):
+        sel = (sid % threads) == k
+        sh = np.arange(k, S, threads, dtype=np.uint32)
+        return build(keys[sel], None if vals is None else vals[sel], b=b, is_filter=is_filter,
+                     h=h, seed=seed, tmax=tmax, shards=sh, mwhc=mwhc, geom=g)
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(one, range(threads)))
+    w = np.zeros((S, g.V), np.uint64)
+    t = np.zeros(S, np.uint32)
+    fails = []
+    status = 0
+    for p in parts:
+        w[p.shards] = p.w
+        t[p.shards] = p.t
+        fails += p.failures
+        status |= p.status
+    return Built(g.as_dict(), g, seed, b, is_filter, counts, np.arange(S, dtype=np.uint32), t, w,
+                 sorted(fails), status)
 
 
 def query(built: Built, keys) -> np.ndarray:

@@ -368,16 +368,16 @@ static row_t row_xor(row_t a, row_t b) {
   return c;
 }
 
-static const uint32_t *g_rows3; /* for the sort below */
-static int by_max_desc(const void *pa, const void *pb) {
-  uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
-  uint32_t ma = g_rows3[3 * a], mb = g_rows3[3 * b];
-  for (int k = 1; k < 3; k++) {
-    if (g_rows3[3 * a + k] > ma) ma = g_rows3[3 * a + k];
-    if (g_rows3[3 * b + k] > mb) mb = g_rows3[3 * b + k];
-  }
-  if (ma != mb) return ma > mb ? -1 : 1;
-  return a < b ? -1 : (a > b);
+/* A core row keyed by its highest variable, for sorting (no shared state:
+ * the oracle may run on several threads at once). */
+typedef struct {
+  uint32_t top, row;
+} top_row;
+
+static int by_top_desc(const void *pa, const void *pb) {
+  const top_row *a = (const top_row *)pa, *b = (const top_row *)pb;
+  if (a->top != b->top) return a->top > b->top ? -1 : 1;
+  return a->row < b->row ? -1 : (a->row > b->row);
 }
 
 /* R8: lexicographically smallest solution of the k equations
@@ -393,13 +393,18 @@ int32_t orc_core_lexmin(uint64_t nv, uint32_t k, const uint32_t *rows3,
   for (uint64_t v = 0; v < nv; v++) piv[v] = -1;
   row_t *store = (row_t *)malloc((k ? k : 1) * sizeof(row_t));
   uint32_t nstore = 0;
-  uint32_t *order = (uint32_t *)malloc((k ? k : 1) * sizeof(uint32_t));
-  for (uint32_t i = 0; i < k; i++) order[i] = i;
-  g_rows3 = rows3;
-  qsort(order, k, sizeof(uint32_t), by_max_desc);
+  top_row *order = (top_row *)malloc((k ? k : 1) * sizeof(top_row));
+  for (uint32_t i = 0; i < k; i++) {
+    uint32_t t = rows3[3 * i];
+    if (rows3[3 * i + 1] > t) t = rows3[3 * i + 1];
+    if (rows3[3 * i + 2] > t) t = rows3[3 * i + 2];
+    order[i].top = t;
+    order[i].row = i;
+  }
+  qsort(order, k, sizeof(top_row), by_top_desc);
   int32_t bad = 0;
   for (uint32_t oi = 0; oi < k && !bad; oi++) {
-    uint32_t i = order[oi];
+    uint32_t i = order[oi].row;
     /* sort the three variables; a variable twice in a row cancels */
     uint32_t a[3] = {rows3[3 * i], rows3[3 * i + 1], rows3[3 * i + 2]};
     for (int p = 0; p < 3; p++)
@@ -523,6 +528,18 @@ int32_t orc_plan(const uint64_t *keys, uint64_t n, int32_t h, uint64_t seed,
     if (counts[j] > M) M = counts[j];
   orc_geometry(M, h, c_num, c_den, sigma_override, g);
   return 0;
+}
+
+/* R2 for a whole key array: out[i] = shard of keys[i]. */
+void orc_shard_ids(const uint64_t *keys, uint64_t n, int32_t h, uint64_t seed,
+                   uint32_t *out) {
+  uint64_t sw[3];
+  orc_seed_words(seed, sw);
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t hi, lo;
+    orc_signature(keys[i], sw, &hi, &lo);
+    out[i] = orc_shard_of(hi, h);
+  }
 }
 
 /* Build the listed shards (all shards if shards == NULL).  w_out holds V

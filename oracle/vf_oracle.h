@@ -77,6 +77,8 @@ int32_t orc_solve(uint64_t nv, uint32_t m, const uint32_t *e,
 int32_t orc_plan(const uint64_t *keys, uint64_t n, int32_t h, uint64_t seed,
                  uint32_t c_num, uint32_t c_den, int32_t sigma_override,
                  orc_geom *g, uint32_t *counts);
+void orc_shard_ids(const uint64_t *keys, uint64_t n, int32_t h, uint64_t seed,
+                   uint32_t *out);
 int32_t orc_build(const uint64_t *keys, const uint64_t *values, uint64_t n,
                   int32_t b, int32_t is_filter, uint64_t seed, uint32_t tmax,
                   const orc_geom *g, const uint32_t *shards, uint32_t nshards,

@@ -35,7 +35,7 @@ class VFError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("h", C.c_int32), ("sigma", C.c_int32), ("c_num", C.c_uint32),
                 ("c_den", C.c_uint32), ("tmax", C.c_uint32), ("alpha", C.c_double),
-                ("mwhc", C.c_int32)]
+                ("mwhc", C.c_int32), ("max_window", C.c_uint32)]
 
 
 class Sizes(C.Structure):
@@ -325,9 +325,10 @@ class Structure:
     def build(cls, keys: torch.Tensor, values: torch.Tensor | None = None, *, b: int,
               eps: float = 0.0, seed: int = 0, h: int | None = None, sigma: int | None = None,
               c: tuple | None = None, tmax: int | None = None, mwhc: bool = False,
-              stream=None):
+              max_window: int | None = None, stream=None):
         is_filter = values is None
-        opts = vf_default_opts(h=h, sigma=sigma, tmax=tmax, mwhc=int(mwhc))
+        opts = vf_default_opts(h=h, sigma=sigma, tmax=tmax, mwhc=int(mwhc),
+                               max_window=max_window)
         if c is not None:
             opts.c_num, opts.c_den = c
         sz = vf_plan(keys.numel(), b, eps, is_filter, opts)
@@ -419,8 +420,8 @@ class Batch:
     @classmethod
     def build(cls, keys: torch.Tensor, values: torch.Tensor, n, b, *, seed: int = 0,
               sigma: int | None = None, c: tuple | None = None, tmax: int | None = None,
-              stream=None):
-        opts = vf_default_opts(sigma=sigma, tmax=tmax)
+              max_window: int | None = None, stream=None):
+        opts = vf_default_opts(sigma=sigma, tmax=tmax, max_window=max_window)
         if c is not None:
             opts.c_num, opts.c_den = c
         sz = vf_batch_plan(n, b, opts)

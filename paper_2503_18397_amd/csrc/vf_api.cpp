@@ -464,6 +464,7 @@ void vf_default_opts(vf_opts *o) {
   o->tmax = 255;
   o->alpha = 1.0;
   o->mwhc = 0;
+  o->max_window = 0;
 }
 
 int vf_plan(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts *o,
@@ -629,6 +630,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   const BuildShape shape = build_shape(g.sigma, L.cell_bytes);
   A.lds_bytes = shape.lds_bytes;
   A.wmax = shape.wmax;
+  if (op.max_window) A.wmax = std::min(A.wmax, std::max(8u, op.max_window & ~7u));
   const uint32_t per_cu = shape.per_cu;
   const uint32_t nwg = std::min<uint32_t>(L.nwg, per_cu * (uint32_t)ncu);
   A.logcap = L.logcap;
@@ -1010,6 +1012,7 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
     const BuildShape shape = build_shape(sg, A.cell_bytes);
     A.lds_bytes = shape.lds_bytes;
     A.wmax = shape.wmax;
+    if (op.max_window) A.wmax = std::min(A.wmax, std::max(8u, op.max_window & ~7u));
     const uint32_t per_cu = shape.per_cu;
     A.list = order + 2 * c0;
     A.nlist = (uint32_t)(c1 - c0);

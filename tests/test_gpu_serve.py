@@ -1,12 +1,15 @@
 """The serving loop on the GPU: a Poisson stream of builds and query
 batches served with several slots gives, for every request, exactly the
-bytes the same request gives alone (structures are canonical)."""
+bytes the same request gives alone (structures are canonical), and a sample
+of the served builds and of the query batches against them equals the
+oracle."""
 import time
 
 import numpy as np
 import pytest
 import torch
 
+import oracle as O
 import synthetic as S
 
 pytestmark = pytest.mark.gpu
@@ -74,3 +77,26 @@ def test_each_result_is_the_same_alone_and_in_the_mix():
             assert torch.equal(a.cells(), b_.cells())
             assert torch.equal(a.local_seeds(), b_.local_seeds())
             assert a.failures == b_.failures
+    # the oracle on the three smallest served builds and every query batch
+    # against them
+    builds = sorted((r for r in reqs if r.kind != "query"), key=lambda r: r.keys.numel())[:3]
+    np_of = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
+    for r in builds:
+        res = r.result
+        info = res.info
+        k_np = r.keys.cpu().numpy().view(np.uint64)
+        is_f = r.kind == "vfilter"
+        v_np = None if is_f else r.values.cpu().numpy().view(np.uint64)
+        print(f"[serve] oracle on build {r.rid}: n={k_np.size} b={info['b']} h={info['h']}",
+              flush=True)
+        ob = O.build(k_np, v_np, b=info["b"], is_filter=is_f, h=info["h"], seed=0)
+        assert np.array_equal(res.local_seeds().cpu().numpy(), ob.t.astype(np.uint8))
+        assert res.failures == ob.failures
+        cells = res.cells().cpu().numpy().view(np_of[info["cell_bytes"]])
+        assert np.array_equal(cells, ob.w.astype(cells.dtype))
+        for q in reqs:
+            if q.kind == "query" and q.target == r.rid:
+                want = O.query(ob, q.keys.cpu().numpy().view(np.uint64))
+                got = q.result.cpu().numpy()
+                got = got.view(np_of[got.itemsize]) if not is_f else got
+                assert np.array_equal(got.astype(np.uint64), want)

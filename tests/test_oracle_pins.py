@@ -524,3 +524,16 @@ def test_mwhc_threshold_through_one_segment():
         return out
     assert sum(f == 0.0 for f in core_frac(1.30)) >= 5
     assert sum(f > 0.3 for f in core_frac(1.12)) >= 5
+
+
+def test_threaded_oracle_equals_the_serial_one():
+    """The oracle run over host threads (one call per thread, shards split
+    between them) gives exactly the serial build: the oracle keeps no state
+    shared between calls.  Shards of 2^16 keys have 2-cores of about 40 000
+    rows, so every thread eliminates large systems at once."""
+    keys = _keys(1 << 19, 55)
+    A = O.build(keys, b=8, is_filter=True, h=3, seed=2)
+    B = O.build_threaded(keys, b=8, is_filter=True, h=3, seed=2, threads=8)
+    assert A.status == B.status == 0
+    assert np.array_equal(A.w, B.w) and np.array_equal(A.t, B.t)
+    assert A.failures == B.failures

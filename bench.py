@@ -58,6 +58,10 @@ def parse():
     p.add_argument("--group-chunk-log2", type=int, default=None,
                    help="grouped queries: chunks of 2^k keys (default: the library's largest)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-serve", action="store_true",
+                   help="skip the short serving trace measured after the timed region")
+    p.add_argument("--line-serve-builds", type=int, default=24,
+                   help="builds of the serving trace reported in the default line")
     p.add_argument("--cpu-sample-shards", type=int, default=16)
     p.add_argument("--workload", choices=("vfilter", "batch", "serve", "stream", "mwhc"),
                    default="vfilter",
@@ -155,18 +159,18 @@ def stream_main(args) -> None:
     print(json.dumps(res), flush=True)
 
 
-def serve_main(args) -> None:
+def serve_measure(args, builds: int, queries: int) -> dict:
     """Serving loop: builds (10^3..10^7 keys, b in {4,8,16}, VFunc:VFilter
     1:1) and query batches (1..10^6 keys, 90% members) arriving as Poisson
     streams, served with --slots slots and again one request at a time; the
-    same trace both times, structures resident in HBM (200 GB budget)."""
+    same trace both times, structures resident in HBM (200 GB budget); then
+    the whole trace submitted at once (saturated) both ways."""
     import torch
     import synthetic as S
     from paper_2503_18397_amd.serve import Request, Server, poisson_trace
 
     dev = torch.device("cuda:0")
-    ev = poisson_trace(args.data_seed + 4, args.serve_builds, args.serve_queries,
-                       build_rate=40.0, query_rate=400.0)
+    ev = poisson_trace(args.data_seed + 4, builds, queries, build_rate=40.0, query_rate=400.0)
     data = {}
     for e in ev:
         if e["kind"] != "query":
@@ -177,7 +181,7 @@ def serve_main(args) -> None:
             e["keys"], _ = S.queries(data[e["target"]][0], e["n"], 700 + j,
                                      member_share_per_256=230)
     torch.cuda.synchronize()
-    print(f"[bench] serve: {args.serve_builds} builds, {args.serve_queries} query batches",
+    print(f"[bench] serve: {builds} builds, {queries} query batches",
           file=sys.stderr, flush=True)
 
     def serve(slots, paced=True):
@@ -205,20 +209,34 @@ def serve_main(args) -> None:
     sat = serve(args.slots, paced=False)
     sat1 = serve(1, paced=False)
     print(f"[bench] saturated: {sat} / one at a time {sat1}", file=sys.stderr, flush=True)
+
+    def kps(x):
+        return (x["build"]["keys"] + x["query"]["keys"]) / x["makespan_s"]
+
+    return {
+        "workload": f"{builds} builds (10^3..10^7 keys, b in {{4,8,16}}, VFunc:VFilter 1:1) "
+                    f"at 40/s, {queries} query batches (1..10^6 keys, 90% members) at 400/s, "
+                    "200 GB HBM budget",
+        "slots": args.slots,
+        "build_p50_ms": mixed["build"]["p50_ms"], "build_p99_ms": mixed["build"]["p99_ms"],
+        "query_p50_ms": mixed["query"]["p50_ms"], "query_p99_ms": mixed["query"]["p99_ms"],
+        "served": mixed, "one_at_a_time": one,
+        "saturated": {"served": sat, "one_at_a_time": sat1,
+                      "keys_per_s": round(kps(sat), 1),
+                      "one_at_a_time_keys_per_s": round(kps(sat1), 1),
+                      "speedup_keys_per_s": round(kps(sat) / kps(sat1), 3)},
+    }
+
+
+def serve_main(args) -> None:
+    r = serve_measure(args, args.serve_builds, args.serve_queries)
+    mixed = r["served"]
     res = {
         "metric": "serve p50/p99 ms and keys/s (Poisson builds and query batches)",
         "value": mixed.get("build", {}).get("keys_per_s"), "unit": "built keys/s",
         "higher_is_better": True, "n_gpus": 1, "vs_baseline": None, "data": "synthetic",
-        "config": {"workload": f"{args.serve_builds} builds (10^3..10^7 keys, b in {{4,8,16}}, "
-                               f"VFunc:VFilter 1:1) at 40/s, {args.serve_queries} query batches "
-                               "(1..10^6 keys, 90% members) at 400/s, 200 GB HBM budget",
-                   "slots": args.slots},
-        "served": mixed, "one_at_a_time": one,
-        "saturated": {"served": sat, "one_at_a_time": sat1,
-                      "speedup_keys_per_s": round(
-                          (sat["build"]["keys"] + sat["query"]["keys"]) / sat["makespan_s"]
-                          / ((sat1["build"]["keys"] + sat1["query"]["keys"])
-                             / sat1["makespan_s"]), 3)},
+        "config": {"workload": r["workload"], "slots": args.slots},
+        "served": mixed, "one_at_a_time": r["one_at_a_time"], "saturated": r["saturated"],
     }
     print(json.dumps(res), flush=True)
 
@@ -321,38 +339,45 @@ def batch_main(args) -> None:
     print(json.dumps(res), flush=True)
 
 
-def cpu_baseline(args) -> dict:
-    """The oracle (plain C, one thread) on a bounded sample of the same
-    workload: 16 shards of about 2^16 keys (h = 4), b = 8, same geometry
-    rule, then 2^21 queries of the same member/non-member mix."""
+def cpu_baseline(args, keys_np=None, queries_np=None) -> dict:
+    """The oracle on the GPU machine's host cores: the whole build of the same
+    workload (every shard; shards split over host threads, the C oracle
+    running with the interpreter lock released) and a sample of 2^24 of the
+    same queries in chunks over the same threads; for context, one thread on
+    16 shards of the same shape and 2^21 queries."""
+    import concurrent.futures as cf
     import numpy as np
     import oracle as O
     import synthetic as S
+    mwhc = args.workload == "mwhc"
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n = 1 << args.log2n
+    if keys_np is None:
+        keys_np = S.member_keys(n, args.data_seed).numpy().view(np.uint64)
+    h = O.shard_bits_eps(n, args.eps)
+    t0 = time.perf_counter()
+    built = O.build_threaded(keys_np, b=args.b, is_filter=True, h=h, seed=args.seed,
+                             threads=threads, mwhc=mwhc)
+    t1 = time.perf_counter()
+    qs = queries_np[: 1 << 24] if queries_np is not None else \
+        S.queries(S.member_keys(n, args.data_seed), 1 << 24, args.data_seed)[0].numpy().view(
+            np.uint64)
+    with cf.ThreadPoolExecutor(threads) as ex:
+        t2 = time.perf_counter()
+        list(ex.map(lambda c: O.query(built, c), np.array_split(qs, threads)))
+        t3 = time.perf_counter()
+    del built
+    # one thread, 16 shards of about 2^16 keys
     n_s = args.cpu_sample_shards << 16
     h_s = (args.cpu_sample_shards - 1).bit_length()
-    keys = S.member_keys(n_s, args.data_seed)
-    q, _ = S.queries(keys, 1 << 21, args.data_seed)
-    k_np = keys.numpy().view(np.uint64)
-    q_np = q.numpy().view(np.uint64)
-    mwhc = args.workload == "mwhc"
-    t0 = time.perf_counter()
-    built = O.build(k_np, b=args.b, is_filter=True, h=h_s, seed=args.seed, mwhc=mwhc)
-    t1 = time.perf_counter()
-    O.query(built, q_np)
-    t2 = time.perf_counter()
-    # the same oracle calls spread over host threads (the C oracle runs with
-    # the interpreter lock released): shards split between threads, then the
-    # queries in chunks
-    import concurrent.futures as cf
-    threads = max(1, min(16, os.cpu_count() or 1, args.cpu_sample_shards))
-    sets = [np.arange(i, 1 << h_s, threads, dtype=np.uint32) for i in range(threads)]
-    with cf.ThreadPoolExecutor(threads) as ex:
-        t3 = time.perf_counter()
-        list(ex.map(lambda sh: O.build(k_np, b=args.b, is_filter=True, h=h_s, seed=args.seed,
-                                        shards=sh, mwhc=mwhc), sets))
-        t4 = time.perf_counter()
-        list(ex.map(lambda qc: O.query(built, qc), np.array_split(q_np, threads)))
-        t5 = time.perf_counter()
+    k1 = S.member_keys(n_s, args.data_seed)
+    q1, _ = S.queries(k1, 1 << 21, args.data_seed)
+    t4 = time.perf_counter()
+    b1 = O.build(k1.numpy().view(np.uint64), b=args.b, is_filter=True, h=h_s, seed=args.seed,
+                 mwhc=mwhc)
+    t5 = time.perf_counter()
+    O.query(b1, q1.numpy().view(np.uint64))
+    t6 = time.perf_counter()
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -360,17 +385,20 @@ def cpu_baseline(args) -> dict:
     except OSError:
         pass
     return {
-        "value": round(n_s / (t1 - t0) / 1e6, 4),
+        "value": round(n / (t1 - t0) / 1e6, 4),
         "unit": "Mkeys/s",
-        "query_value": round(q_np.size / (t2 - t1) / 1e9, 6),
+        "query_value": round(qs.size / (t3 - t2) / 1e9, 6),
         "query_unit": "Gq/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"{args.cpu_sample_shards} shards x ~2^16 keys (n={n_s}, h={h_s}, b={args.b}) "
-                  f"build; 2^21 mixed queries",
-        "parallel": {"value": round(n_s / (t4 - t3) / 1e6, 4), "unit": "Mkeys/s",
-                     "query_value": round(q_np.size / (t5 - t4) / 1e9, 6), "query_unit": "Gq/s",
-                     "threads": threads, "nproc": os.cpu_count(), "cpu": model},
+        "sample": f"the whole build (n={n}, h={h}, b={args.b}, {1 << h} shards) on {threads} "
+                  f"threads; {qs.size} of the same queries",
+        "nproc": os.cpu_count(), "cpu": model,
+        "single_thread": {"value": round(n_s / (t5 - t4) / 1e6, 4), "unit": "Mkeys/s",
+                          "query_value": round(q1.numel() / (t6 - t5) / 1e9, 6),
+                          "query_unit": "Gq/s", "cores": 1,
+                          "sample": f"{args.cpu_sample_shards} shards x ~2^16 keys "
+                                    f"(n={n_s}, h={h_s}); 2^21 mixed queries"},
     }
 
 
@@ -487,8 +515,13 @@ def main():
             "query_grouped" if name == "k_query" and args.query == "grouped" else name)
         k["GB/s"] = round(k["bytes"] / (k["ms"] * 1e-3) / 1e9, 2) if k["ms"] > 0 else None
         k["frac"] = round(k["GB/s"] / HBM_PEAK_GBS, 5) if k["GB/s"] else None
-    dom = "k_build" if k_build_ms >= query_ms else "k_query"
-    achieved = kern[dom]["GB/s"]
+    # The build's algorithmic bytes per key: read the key, write it grouped
+    # by shard, read it back, write the structure (cells and local seeds).
+    # k_build is the build's dominant kernel (its launch is almost all of
+    # the build's time), so the build's bytes are priced on its duration.
+    build_bpk = 8 + 8 + 8 + (S_ * V * cb + S_) / n
+    build_gbs = build_bpk * n / (k_build_ms * 1e-3) / 1e9
+    query_gbs = kern["k_query"]["GB/s"]
     res = {
         "metric": METRIC,
         "value": round(n / (build_ms * 1e-3) / 1e6, 3),
@@ -519,17 +552,32 @@ def main():
                   "failed_attempts": info["n_failures"],
                   "relaunched_shards": info["relaunched_shards"],
                   "space_bits_per_key": round(info["space_bits"] / n, 4)},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_build", "achieved": round(build_gbs, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5) if achieved else None,
-                     "traffic": kern[dom]["traffic"],
+                     "frac": round(build_gbs / HBM_PEAK_GBS, 5),
+                     "traffic": kern["k_build"]["traffic"],
+                     "bytes_per_key": round(build_bpk, 3),
+                     "basis": "the build's algorithmic bytes (read key, write and read it "
+                              "grouped by shard, write cells and seeds) per k_build launch",
+                     "k_build_own": {"bytes_per_key": round(kern["k_build"]["bytes"] / n, 3),
+                                     "achieved": kern["k_build"]["GB/s"],
+                                     "frac": kern["k_build"]["frac"]},
+                     "query": {"bytes_per_query": 8 + 3 * cb + 1, "achieved": query_gbs,
+                               "frac": kern["k_query"]["frac"], "path": args.query},
                      "copy_GBps": round(copy_gbs, 1),
-                     "frac_of_copy": round(achieved / copy_gbs, 5) if achieved else None},
+                     "frac_of_copy": round(build_gbs / copy_gbs, 5)},
         "kernels": kern,
     }
+    del ws, st
+    if not args.no_serve and not mwhc:
+        # the serving loop, measured after the timed region
+        res["serve"] = serve_measure(args, args.line_serve_builds, 10 * args.line_serve_builds)
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(args)
+        print("[bench] cpu baseline (oracle on host cores)", file=sys.stderr, flush=True)
+        import numpy as np
+        k_np = keys.cpu().numpy().view(np.uint64)
+        q_np = queries[: 1 << 24].cpu().numpy().view(np.uint64)
+        res["cpu_baseline"] = cpu_baseline(args, k_np, q_np)
     print(json.dumps(res), flush=True)
 
 

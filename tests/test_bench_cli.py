@@ -17,12 +17,12 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in msg["error"]
 
 
-def test_cpu_baseline_reports_single_and_threaded_oracle():
+def test_cpu_baseline_reports_threaded_and_single_thread_oracle():
     import bench
     args = types.SimpleNamespace(cpu_sample_shards=2, data_seed=7, b=8, seed=0,
-                                 workload="vfilter")
+                                 workload="vfilter", log2n=17, eps=0.08)
     cb = bench.cpu_baseline(args)
-    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["unit"] == "Mkeys/s"
-    assert cb["value"] > 0 and cb["query_value"] > 0
-    par = cb["parallel"]
-    assert 1 <= par["threads"] <= 16 and par["value"] > 0 and par["query_value"] > 0
+    assert cb["kind"] == "oracle" and cb["unit"] == "Mkeys/s"
+    assert 1 <= cb["cores"] <= 16 and cb["value"] > 0 and cb["query_value"] > 0
+    one = cb["single_thread"]
+    assert one["cores"] == 1 and one["value"] > 0 and one["query_value"] > 0

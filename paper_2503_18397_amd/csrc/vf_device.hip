@@ -645,14 +645,19 @@ struct ShardBufs {
   uint32_t *plog;   // pivot records
 };
 
-// Vertex state of the peeling wavefront (one copy per workgroup).
+// Vertex state of the peeling wavefront (one copy per workgroup).  A
+// vertex's degree and the sum of the indices of its incident edges share
+// one 64-bit word (degree in the high half), updated by one atomic add:
+// when one incident edge is left, the sum is its index (section 4.3 keeps
+// the xor of the edges for the same purpose; a sum serves as well and
+// takes one atomic instead of two).
 struct FrontBufs {
-  uint32_t *deg;     // vertex degrees
-  uint32_t *xr;      // xor of incident edge indices (Djamal's trick, section 4.3)
+  uint64_t *st;      // (degree << 32) + sum of incident edge indices
   uint8_t *pe;       // 1 = edge peeled
   uint32_t *F0, *F1; // frontiers of degree-one vertices
   uint32_t *cc;      // group cursors
 };
+constexpr uint64_t kDegOne = 1ull << 32;
 
 // Shard records per workgroup: one being peeled, one being eliminated and
 // one being assigned.
@@ -701,8 +706,7 @@ __host__ __device__ inline uint64_t front_layout(uint8_t *base, uint32_t M, uint
   };
   const uint64_t m = (uint64_t)M + 1;
   FrontBufs f;
-  f.deg = (uint32_t *)take(4 * V);
-  f.xr = (uint32_t *)take(4 * V);
+  f.st = (uint64_t *)take(8 * V);
   f.pe = (uint8_t *)take(m);
   f.F0 = (uint32_t *)take(4 * V);
   f.F1 = (uint32_t *)take(4 * V);
@@ -1475,54 +1479,126 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
 // Back-substitution in increasing pivot column, 64 pivots per step: each
 // lane gathers the values of vertices below its batch, then the in-batch
 // dependencies are resolved lane by lane.  Values of free vertices are 0.
+// Xor of a 64-bit value over the wavefront, in every lane.
+__device__ __forceinline__ uint64_t wave_xor64(uint64_t x) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, d);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), d);
+    x ^= (uint64_t)lo | ((uint64_t)hi << 32);
+  }
+  return x;
+}
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, d);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), d);
+    x |= (uint64_t)lo | ((uint64_t)hi << 32);
+  }
+  return x;
+}
+
+// Back-substitution of the pivot log (records [column, count, rhs lo, rhs
+// hi, vertices below the column], poff[i] the i-th in decreasing column
+// order): from the lowest pivot up, 64 pivots at a time, the value of a
+// pivot column is its right side xor the values of its record's vertices.
+// Vertices below the batch have their final values; a vertex inside the
+// batch's range is a pivot column of the batch (a dependency, resolved in
+// lane order) or free (value 0).  The next batch's record headers and first
+// kPre entries, and the offsets of the batch after it, are loaded while
+// the current batch gathers its values, so a batch costs about one round
+// trip to memory and its stores; the few long records are gathered by the
+// whole wavefront, 64 entries per round trip.
 template <typename T>
 __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np, T *wl,
                                                 uint32_t *bcol, bool cells_global) {
+  constexpr uint32_t kPre = 4;
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t lane = lane_id();
   const uint32_t *const plog = sc.plog;
   const uint32_t *const poff = sc.poff;
-  for (uint32_t bs = 0; bs < np; bs += 64) {
+  auto load_off = [&](uint32_t bs) -> uint32_t {
     const uint32_t i = bs + lane;
-    const bool valid = i < np;
-    const uint32_t *rec = valid ? plog + poff[np - 1 - i] : nullptr;
-    const uint32_t col = valid ? rec[0] : 0xFFFFFFFFu;
-    bcol[lane] = col;
+    return i < np ? poff[np - 1 - i] : kNone;
+  };
+  struct Head {
+    uint32_t col, cnt, off;
+    uint64_t rhs;
+    uint32_t ent[kPre];
+  };
+  auto load_head = [&](uint32_t off) {
+    Head hd;
+    hd.off = off;
+    hd.col = kNone;
+    hd.cnt = 0;
+    hd.rhs = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPre; k++) hd.ent[k] = 0;
+    if (off != kNone) {
+      const uint32_t *const rec = plog + off;
+      hd.col = rec[0];
+      hd.cnt = rec[1];
+      hd.rhs = (uint64_t)rec[2] | ((uint64_t)rec[3] << 32);
+#pragma unroll
+      for (uint32_t k = 0; k < kPre; k++)
+        if (k < hd.cnt) hd.ent[k] = rec[4 + k];
+    }
+    return hd;
+  };
+  Head cur = load_head(load_off(0));
+  uint32_t off_next = load_off(64);
+  for (uint32_t bs = 0; bs < np; bs += 64) {
+    const bool valid = bs + lane < np;
+    bcol[lane] = cur.col;
     wave_sync();
     const uint32_t bmin = bcol[0];
-    uint64_t acc = 0, dep = 0;
-    // vertex v of the record, w its current value: vertices below the batch
-    // have their final values; a vertex in the batch's range is either a
-    // pivot column of the batch (a dependency, resolved below) or free (0)
-    auto take = [&](uint32_t v, uint64_t w) {
-      if (v < bmin) {
-        acc ^= w;
-      } else {
-        uint32_t lo = 0, hi = lane;  // bcol is increasing; v < col
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (bcol[mid] < v) lo = mid + 1;
-          else hi = mid;
-        }
-        if (lo < lane && bcol[lo] == v) dep |= 1ull << lo;
+    // the next batch's headers and the offsets of the one after it
+    const Head nxt = load_head(off_next);
+    const uint32_t off_after = load_off(bs + 128);
+    uint64_t acc = cur.rhs, dep = 0;
+    // dependency bit of vertex v of this batch's range (bcol increases
+    // with the lane; a pivot only depends on lower lanes)
+    auto depbit = [&](uint32_t v, uint32_t below) -> uint64_t {
+      uint32_t lo = 0, hi = below;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (bcol[mid] < v) lo = mid + 1;
+        else hi = mid;
       }
+      return lo < below && bcol[lo] == v ? 1ull << lo : 0ull;
     };
-    if (valid) {
-      acc = (uint64_t)rec[2] | ((uint64_t)rec[3] << 32);
-      const uint32_t cnt = rec[1];
-      const uint32_t *const ent = rec + 4;
-      uint32_t e = 0;
-      for (; e + 4 <= cnt; e += 4) {  // four entries and their values in flight
-        const uint32_t v0 = ent[e], v1 = ent[e + 1], v2 = ent[e + 2], v3 = ent[e + 3];
-        const uint64_t w0 = (uint64_t)wl[v0], w1 = (uint64_t)wl[v1];
-        const uint64_t w2 = (uint64_t)wl[v2], w3 = (uint64_t)wl[v3];
-        take(v0, w0);
-        take(v1, w1);
-        take(v2, w2);
-        take(v3, w3);
+    {
+      uint64_t w[kPre];
+#pragma unroll
+      for (uint32_t k = 0; k < kPre; k++)
+        w[k] = k < cur.cnt && cur.ent[k] < bmin ? (uint64_t)wl[cur.ent[k]] : 0ull;
+#pragma unroll
+      for (uint32_t k = 0; k < kPre; k++) {
+        if (k < cur.cnt) {
+          if (cur.ent[k] < bmin) acc ^= w[k];
+          else dep |= depbit(cur.ent[k], lane);
+        }
       }
-      for (; e < cnt; e++) {
-        const uint32_t v = ent[e];
-        take(v, (uint64_t)wl[v]);
+    }
+    // records longer than kPre: the whole wavefront gathers one at a time
+    for (uint64_t lm = __ballot(valid && cur.cnt > kPre); lm; lm &= lm - 1) {
+      const uint32_t L = (uint32_t)__ffsll((long long)lm) - 1;
+      const uint32_t off = readlane(cur.off, (int)L), cnt = readlane(cur.cnt, (int)L);
+      uint64_t pacc = 0, pdep = 0;
+      for (uint32_t e0 = kPre; e0 < cnt; e0 += 64) {
+        const uint32_t e = e0 + lane;
+        if (e < cnt) {
+          const uint32_t v = plog[off + 4 + e];
+          if (v < bmin) pacc ^= (uint64_t)wl[v];
+          else pdep |= depbit(v, L);
+        }
+      }
+      pacc = wave_xor64(pacc);
+      pdep = wave_or64(pdep);
+      if (lane == L) {
+        acc ^= pacc;
+        dep |= pdep;
       }
     }
     uint64_t x = acc;
@@ -1530,9 +1606,11 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
       const uint64_t xk = readlane64(x, (int)k);
       if ((dep >> k) & 1ull) x ^= xk;
     }
-    if (valid) wl[col] = (T)x;
+    if (valid) wl[cur.col] = (T)x;
     if (cells_global) wave_sync_global();
     else wave_sync();
+    cur = nxt;
+    off_next = off_after;
   }
 }
 
@@ -1615,13 +1693,13 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   // run before it).  The helpers below take the calling threads' index tid
   // in [0, nthr) and sync(), which orders their memory operations (the
   // workgroup barrier, or a wavefront fence when one wavefront calls).
-  uint32_t *f_deg, *f_xr, *f_F0, *f_F1, *f_cc;
+  uint64_t *f_st;
+  uint32_t *f_F0, *f_F1, *f_cc;
   uint8_t *f_pe;
   {
     FrontBufs fb;
     front_layout(wbase + (uint64_t)kSlots * slot_bytes, A.M, A.scr_V, A.scr_l, &fb);
-    f_deg = fb.deg;
-    f_xr = fb.xr;
+    f_st = fb.st;
     f_F0 = fb.F0;
     f_F1 = fb.F1;
     f_cc = fb.cc;
@@ -1643,7 +1721,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
     const uint64_t *const R = sb.R;
     uint32_t *const stk = sb.stack, *const rst = sb.rst;
     const uint32_t w0t = tid - lane;  // this wavefront's first thread
-    const FrontBufs fb{f_deg, f_xr, f_pe, f_F0, f_F1, f_cc};
+    const FrontBufs fb{f_st, f_pe, f_F0, f_F1, f_cc};
     uint32_t nrounds = 0;
     if (tid == 0)
       for (int i = 0; i < 7; i++) fcnt[i] = 0;
@@ -1656,8 +1734,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       fb.pe[i] = 0;
     }
     for (uint64_t v = tid; v < V; v += nthr) {
-      fb.deg[v] = 0;
-      fb.xr[v] = 0;
+      fb.st[v] = 0;
     }
     sync();
     // incidence: degree and xor of incident edges
@@ -1665,15 +1742,14 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       uint32_t v[3];
       unpack3(E[i], v);
       for (int k = 0; k < 3; k++) {
-        atomicAdd(&fb.deg[v[k]], 1u);
-        atomicXor(&fb.xr[v[k]], i);
+        atomicAdd((unsigned long long *)&fb.st[v[k]], kDegOne + i);
       }
     }
     sync();
     // round-synchronous peeling
     for (uint64_t v0 = w0t; v0 < V; v0 += nthr) {
       const uint64_t v = v0 + lane;
-      const bool one = v < V && fb.deg[v] == 1;
+      const bool one = v < V && (fb.st[v] >> 32) == 1;
       const uint32_t at = wave_append(one, &fcnt[0]);
       if (one) fb.F0[at] = (uint32_t)v;
     }
@@ -1692,14 +1768,15 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         uint32_t e = 0, side = 0;
         if (i < nf) {
           const uint32_t v = cur[i];
-          if (fb.deg[v] == 1) {
-            e = fb.xr[v];
+          const uint64_t sv = fb.st[v];
+          if ((sv >> 32) == 1) {
+            e = (uint32_t)sv;
             uint32_t a[3];
             unpack3(E[e], a);
             side = a[0] == v ? 0u : (a[1] == v ? 1u : 2u);
             take = true;
             for (uint32_t k = 0; k < side; k++)
-              if (fb.deg[a[k]] == 1) take = false;
+              if ((fb.st[a[k]] >> 32) == 1) take = false;
           }
         }
         const uint32_t at = wave_append(take, &fcnt[1]);
@@ -1719,9 +1796,9 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
           const uint32_t e = stk[i] & 0x3FFFFFFFu;
           unpack3(E[e], a);
           for (int k = 0; k < 3; k++) {
-            const uint32_t old = atomicSub(&fb.deg[a[k]], 1u);
-            atomicXor(&fb.xr[a[k]], e);
-            push[k] = old == 2;
+            const uint64_t old =
+                atomicAdd((unsigned long long *)&fb.st[a[k]], (unsigned long long)(-(kDegOne + e)));
+            push[k] = (old >> 32) == 2;
           }
         }
         for (int k = 0; k < 3; k++) {
@@ -1777,7 +1854,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
     // before the elimination: rows are listed by top vertex in the degree
     // array, which peeling no longer needs
     const uint32_t kl = G.mwhc ? 0u : k;
-    uint32_t *const head = fb.deg, *const next = fb.F0;
+    uint32_t *const head = (uint32_t *)fb.st, *const next = fb.F0;
     if (kl)
       for (uint64_t v = tid; v < V; v += nthr) head[v] = 0xFFFFFFFFu;
     sync();

@@ -1476,9 +1476,6 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   return fl ? kSolveCapacity : kSolveOk;
 }
 
-// Back-substitution in increasing pivot column, 64 pivots per step: each
-// lane gathers the values of vertices below its batch, then the in-batch
-// dependencies are resolved lane by lane.  Values of free vertices are 0.
 // Xor of a 64-bit value over the wavefront, in every lane.
 __device__ __forceinline__ uint64_t wave_xor64(uint64_t x) {
 #pragma unroll

@@ -58,6 +58,8 @@ def parse():
     p.add_argument("--group-chunk-log2", type=int, default=None,
                    help="grouped queries: chunks of 2^k keys (default: the library's largest)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-packed", action="store_true",
+                   help="batch workload: cells of 1/2/4/8 bytes instead of b-bit fields")
     p.add_argument("--no-serve", action="store_true",
                    help="skip the short serving trace measured after the timed region")
     p.add_argument("--line-serve-builds", type=int, default=24,
@@ -259,7 +261,8 @@ def batch_main(args) -> None:
     inst = torch.repeat_interleave(torch.arange(n.size, dtype=torch.int32, device=dev),
                                    torch.as_tensor(n.astype(np.int64), device=dev))
     out = torch.empty(total, dtype=torch.int64, device=dev)
-    opts = vf.vf_default_opts()
+    # cells packed to b bits each (bit-array storage), unless --no-packed
+    opts = vf.vf_default_opts(packed=0 if args.no_packed else 1)
     sz = vf.vf_batch_plan(n, b, opts)
     ws = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=dev)
     st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
@@ -330,7 +333,10 @@ def batch_main(args) -> None:
                   "failed_instances": info["failed_shards"],
                   "failed_attempts": info["n_failures"],
                   "relaunched_instances": info["relaunched_shards"],
-                  "space_bits_per_key": round(info["space_bits"] / total, 4)},
+                  "space_bits_per_key": round(info["space_bits"] / total, 4),
+                  "stored_bits_per_key": round(8 * sz.structure_bytes / total, 4),
+                  "mean_b": round(float((n.astype(np.float64) * b).sum() / total), 4),
+                  "packed": not args.no_packed},
         "per_instance_launches": {"value": round(single, 3), "unit": "Mkeys/s",
                                   "instances_timed": int(sample.size), "keys": keys_done,
                                   "seconds": round(per_s, 3)},

@@ -77,6 +77,15 @@ typedef struct vf_opts {
                          CU's LDS.  0 (default): as many as the workgroup's
                          share of LDS holds.  The result never depends on
                          it. */
+  uint32_t packed;    /* 1: store the cells as one bit string of b-bit fields
+                         (cell i of the structure, or of an instance of a
+                         batch, at bits [i b, i b + b) of little-endian
+                         64-bit words), the bit-array storage of values of
+                         any width (section 5); the build assembles byte
+                         cells in the workspace and packs them at the end.
+                         Queries read the packed fields; grouped queries
+                         use the plain gathers.  0 (default): cells of 1, 2,
+                         4 or 8 bytes. */
 } vf_opts;
 
 /* Sizes returned by vf_plan (upper bounds: the largest shard is known only
@@ -114,6 +123,7 @@ typedef struct vf_info_t {
    * (same result, slower). */
   uint32_t relaunched_shards;
   int32_t mwhc;           /* 1: MWHC hypergraphs (sigma 0, l 1, V = 3 parts) */
+  uint32_t packed;        /* 1: cells is a bit string of b-bit fields      */
 } vf_info_t;
 
 /* One failed construction attempt of one shard. */
@@ -280,7 +290,9 @@ typedef struct vf_batch_item_t {
   uint64_t V;             /* cells = (l + 2) 2^sigma                     */
   uint32_t cell_bytes;    /* 1, 2, 4 or 8                                */
   uint32_t local_seed;    /* successful local seed, 255 = failed         */
-  const void *cells;      /* device: V cells of cell_bytes               */
+  const void *cells;      /* device: V cells of cell_bytes, or with packed
+                             a bit string of V b-bit fields              */
+  uint32_t packed;        /* 1: packed cells                             */
 } vf_batch_item_t;
 
 /* Buffer sizes for a batch of count instances with n[i] keys of b[i] bits

@@ -81,6 +81,9 @@ def lib():
         L.orc_fingerprint.restype = C.c_uint64
         L.orc_fingerprint.argtypes = [C.c_uint64, C.c_uint64, u64p, C.c_int32]
         L.orc_shard_ids.argtypes = [u64p, C.c_uint64, C.c_int32, C.c_uint64, u32p]
+        L.orc_pack.argtypes = [u64p, C.c_uint64, C.c_int32, u64p]
+        L.orc_unpack.restype = C.c_uint64
+        L.orc_unpack.argtypes = [u64p, C.c_uint64, C.c_int32]
         L.orc_shard_of.restype = C.c_uint32
         L.orc_shard_of.argtypes = [C.c_uint64, C.c_int32]
         L.orc_edge.argtypes = [C.c_uint64, C.c_uint64, C.c_int32, C.c_uint32,
@@ -338,6 +341,19 @@ def build_threaded(keys, values=None, *, b: int, is_filter: bool, h: int, seed: 
         status |= p.status
     return Built(g.as_dict(), g, seed, b, is_filter, counts, np.arange(S, dtype=np.uint32), t, w,
                  sorted(fails), status)
+
+
+def pack(w, b: int) -> np.ndarray:
+    """Cells w (uint64, b bits used) as a packed bit string of 64-bit words."""
+    w = np.ascontiguousarray(np.asarray(w, np.uint64).reshape(-1))
+    out = np.zeros(max((w.size * b + 63) // 64, 1), np.uint64)
+    lib().orc_pack(w, w.size, b, out)
+    return out[: (w.size * b + 63) // 64]
+
+
+def unpack(words, i: int, b: int) -> int:
+    words = np.ascontiguousarray(np.asarray(words, np.uint64))
+    return int(lib().orc_unpack(words, i, b))
 
 
 def query(built: Built, keys) -> np.ndarray:

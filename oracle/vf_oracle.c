@@ -636,6 +636,28 @@ int32_t orc_build(const uint64_t *keys, const uint64_t *values, uint64_t n,
   return status;
 }
 
+/* Bit-array storage of b-bit values (section 5): cell i occupies bits
+ * [i b, i b + b) of a string of little-endian 64-bit words, bit k of the
+ * cell at bit i b + k.  out (ceil(count b / 64) words) must be zero. */
+void orc_pack(const uint64_t *w, uint64_t count, int32_t b, uint64_t *out) {
+  for (uint64_t i = 0; i < count; i++)
+    for (int32_t k = 0; k < b; k++)
+      if ((w[i] >> k) & 1u) {
+        uint64_t bit = i * (uint64_t)b + (uint64_t)k;
+        out[bit / 64] |= 1ULL << (bit % 64);
+      }
+}
+
+/* The b-bit cell i of a packed string. */
+uint64_t orc_unpack(const uint64_t *words, uint64_t i, int32_t b) {
+  uint64_t v = 0;
+  for (int32_t k = 0; k < b; k++) {
+    uint64_t bit = i * (uint64_t)b + (uint64_t)k;
+    v |= ((words[bit / 64] >> (bit % 64)) & 1u) << k;
+  }
+  return v;
+}
+
 /* Query (eq. (MWHC) with k = 3): the xor of the three cells of the key's
  * edge in its shard; a filter compares it with the key's fingerprint.
  * slot_of_shard maps a shard to its block of V words in w (NULL: identity;

@@ -84,6 +84,8 @@ int32_t orc_build(const uint64_t *keys, const uint64_t *values, uint64_t n,
                   const orc_geom *g, const uint32_t *shards, uint32_t nshards,
                   uint32_t *t_out, uint64_t *w_out, orc_fail *rec,
                   uint32_t rec_cap, uint32_t *nrec);
+void orc_pack(const uint64_t *w, uint64_t count, int32_t b, uint64_t *out);
+uint64_t orc_unpack(const uint64_t *words, uint64_t i, int32_t b);
 void orc_query(const uint64_t *keys, uint64_t n, uint64_t seed, int32_t b,
                int32_t is_filter, const orc_geom *g, const uint32_t *t_of_shard,
                const int32_t *slot_of_shard, const uint64_t *w, uint64_t *out);

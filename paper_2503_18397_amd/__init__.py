@@ -35,7 +35,7 @@ class VFError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("h", C.c_int32), ("sigma", C.c_int32), ("c_num", C.c_uint32),
                 ("c_den", C.c_uint32), ("tmax", C.c_uint32), ("alpha", C.c_double),
-                ("mwhc", C.c_int32), ("max_window", C.c_uint32)]
+                ("mwhc", C.c_int32), ("max_window", C.c_uint32), ("packed", C.c_uint32)]
 
 
 class Sizes(C.Structure):
@@ -52,7 +52,7 @@ class Info(C.Structure):
                 ("n_failures", C.c_uint32), ("space_bits", C.c_uint64),
                 ("cells", C.c_void_p), ("local_seeds", C.c_void_p),
                 ("ms_count", C.c_float), ("ms_scatter", C.c_float), ("ms_build", C.c_float),
-                ("relaunched_shards", C.c_uint32), ("mwhc", C.c_int32)]
+                ("relaunched_shards", C.c_uint32), ("mwhc", C.c_int32), ("packed", C.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -62,7 +62,7 @@ class BatchItem(C.Structure):
     _fields_ = [("n", C.c_uint64), ("b", C.c_int32), ("c_num", C.c_uint32),
                 ("c_den", C.c_uint32), ("sigma", C.c_int32), ("l", C.c_uint32),
                 ("V", C.c_uint64), ("cell_bytes", C.c_uint32), ("local_seed", C.c_uint32),
-                ("cells", C.c_void_p)]
+                ("cells", C.c_void_p), ("packed", C.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -325,10 +325,10 @@ class Structure:
     def build(cls, keys: torch.Tensor, values: torch.Tensor | None = None, *, b: int,
               eps: float = 0.0, seed: int = 0, h: int | None = None, sigma: int | None = None,
               c: tuple | None = None, tmax: int | None = None, mwhc: bool = False,
-              max_window: int | None = None, stream=None):
+              max_window: int | None = None, packed: bool = False, stream=None):
         is_filter = values is None
         opts = vf_default_opts(h=h, sigma=sigma, tmax=tmax, mwhc=int(mwhc),
-                               max_window=max_window)
+                               max_window=max_window, packed=int(packed))
         if c is not None:
             opts.c_num, opts.c_den = c
         sz = vf_plan(keys.numel(), b, eps, is_filter, opts)
@@ -353,8 +353,12 @@ class Structure:
         return vf_failures(self.handle)
 
     def cells(self) -> torch.Tensor:
-        """Device view of the S * V cells (cell_bytes each)."""
+        """Device view of the S * V cells (cell_bytes each); for a packed
+        structure the bit string of S * V b-bit fields as 64-bit words."""
         i = self.info
+        if i["packed"]:
+            nw = (i["S"] * i["V"] * i["b"] + 63) // 64
+            return self.structure[: 8 * nw].view(torch.int64)
         nbytes = i["S"] * i["V"] * i["cell_bytes"]
         return self.structure[:nbytes].view(_CELL_DTYPE[i["cell_bytes"]]).view(i["S"], i["V"])
 
@@ -420,8 +424,9 @@ class Batch:
     @classmethod
     def build(cls, keys: torch.Tensor, values: torch.Tensor, n, b, *, seed: int = 0,
               sigma: int | None = None, c: tuple | None = None, tmax: int | None = None,
-              max_window: int | None = None, stream=None):
-        opts = vf_default_opts(sigma=sigma, tmax=tmax, max_window=max_window)
+              max_window: int | None = None, packed: bool = False, stream=None):
+        opts = vf_default_opts(sigma=sigma, tmax=tmax, max_window=max_window,
+                               packed=int(packed))
         if c is not None:
             opts.c_num, opts.c_den = c
         sz = vf_batch_plan(n, b, opts)
@@ -443,9 +448,13 @@ class Batch:
         return vf_batch_item(self.handle, i)
 
     def cells(self, i: int) -> torch.Tensor:
-        """Device view of instance i's V cells."""
+        """Device view of instance i's V cells (packed: its bit string as
+        64-bit words)."""
         it = self.item(i)
         off = it["cells"] - self.structure.data_ptr()
+        if it["packed"]:
+            nw = (it["V"] * it["b"] + 63) // 64
+            return self.structure[off: off + 8 * nw].view(torch.int64)
         nbytes = it["V"] * it["cell_bytes"]
         return self.structure[off: off + nbytes].view(_CELL_DTYPE[it["cell_bytes"]])
 

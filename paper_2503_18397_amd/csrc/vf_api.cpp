@@ -232,6 +232,9 @@ struct Layout {
       o_bvals, o_scratch, o_rows;
   bool rows;  // keys grouped by per-segment histograms (filters, S <= 4096)
   uint32_t fail_cap;
+  bool packed;         // cells packed to b bits in the structure
+  uint64_t o_tcells;   // packed: byte-aligned cells of the build (workspace)
+  uint64_t tcells_bytes;
 };
 
 int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts &o,
@@ -315,8 +318,12 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   l.o_scratch = take(l.scratch_stride * l.nwg);
   l.rows = is_filter && vfk::group_rows_fit(l.S) && n >= 1 && n <= 0xFFFFFFFFull;
   l.o_rows = l.rows ? take(4 * vfk::group_rows_words(l.S)) : 0;
+  l.packed = o.packed != 0;
+  l.tcells_bytes = l.packed ? align256((uint64_t)l.S * l.gcap.V * l.cell_bytes) : 0;
+  l.o_tcells = l.packed ? take(l.tcells_bytes) : 0;
   l.ws_bytes = o_;
-  l.cells_bytes = align256((uint64_t)l.S * l.gcap.V * l.cell_bytes);
+  l.cells_bytes = l.packed ? align256(8 * (((uint64_t)l.S * l.gcap.V * b + 63) / 64))
+                           : align256((uint64_t)l.S * l.gcap.V * l.cell_bytes);
   l.st_bytes = l.cells_bytes + align256(l.S);
   *L = l;
   return VF_OK;
@@ -336,6 +343,9 @@ struct BatchLayout {
   uint64_t scratch_stride = 0;
   uint64_t o_work = 0, o_fails = 0, o_overflow = 0, o_order = 0, o_scratch = 0, ws_bytes = 0;
   uint64_t o_check = 0;  // instance descriptors and a flag for the value check
+  bool packed = false;   // instance cells packed to b bits in the structure
+  std::vector<vfk::BatchItem> pitems;  // packed: descriptors with structure offsets
+  uint64_t o_tcells = 0, tcells_bytes = 0;  // packed: byte cells of the build
   uint64_t s_items = 0, s_seeds = 0, s_cells = 0, cells_bytes = 0, st_bytes = 0;
 };
 
@@ -349,7 +359,9 @@ int make_batch_layout(uint64_t count, const uint64_t *n, const int32_t *b, const
   BatchLayout l;
   l.count = count;
   l.items.resize(count);
-  uint64_t cell_off = 0;
+  l.packed = o.packed != 0;
+  if (l.packed) l.pitems.reserve(count);
+  uint64_t cell_off = 0, packed_off = 0;
   for (uint64_t i = 0; i < count; i++) {
     if (b[i] < 1 || b[i] > 64 || n[i] > 0xFFFFFFFFull) return VF_EINVAL;
     const Geometry g = geometry((uint32_t)n[i], 0, o.c_num, o.c_den, o.sigma);
@@ -369,6 +381,12 @@ int make_batch_layout(uint64_t count, const uint64_t *n, const int32_t *b, const
     it.pad = 0;
     l.keys += n[i];
     cell_off += (g.V * it.cell_bytes + 7) & ~7ull;
+    if (o.packed) {
+      vfk::BatchItem pit = it;
+      pit.cell_off = packed_off;
+      l.pitems.push_back(pit);
+      packed_off += 8 * ((g.V * (uint64_t)b[i] + 63) / 64);
+    }
     l.maxM = std::max(l.maxM, it.n);
     l.maxV = std::max(l.maxV, g.V);
     l.maxl = std::max(l.maxl, g.l);
@@ -393,11 +411,13 @@ int make_batch_layout(uint64_t count, const uint64_t *n, const int32_t *b, const
   l.o_order = take(8ull * count);
   l.o_scratch = take(l.scratch_stride * l.nwg);
   l.o_check = take(sizeof(vfk::BatchItem) * count + 256);
+  l.tcells_bytes = l.packed ? align256(cell_off) : 0;
+  l.o_tcells = l.packed ? take(l.tcells_bytes) : 0;
   l.ws_bytes = o_;
   o_ = 0;
   l.s_items = take(sizeof(vfk::BatchItem) * count);
   l.s_seeds = take(count);
-  l.cells_bytes = align256(cell_off);
+  l.cells_bytes = align256(l.packed ? packed_off : cell_off);
   l.s_cells = take(l.cells_bytes);
   l.st_bytes = o_;
   *L = std::move(l);
@@ -422,6 +442,7 @@ struct vf_handle {
   int ncu;
   float ms[3];
   uint32_t relaunched;
+  uint32_t packed;  // cells are a bit string of b-bit fields
   // batches (kind 1): one descriptor and local seed per instance
   int32_t kind;
   uint64_t count;
@@ -465,6 +486,7 @@ void vf_default_opts(vf_opts *o) {
   o->alpha = 1.0;
   o->mwhc = 0;
   o->max_window = 0;
+  o->packed = 0;
 }
 
 int vf_plan(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts *o,
@@ -586,9 +608,14 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   const Geometry g =
       op.mwhc ? geometry_mwhc(M, op.c_num, op.c_den) : geometry(M, L.h, op.c_num, op.c_den, op.sigma);
   if (g.V > kMaxCells) return VF_ECAPACITY;
-  if ((uint64_t)L.S * g.V * L.cell_bytes > L.cells_bytes ||
+  const uint64_t need_cells = L.packed ? 8 * (((uint64_t)L.S * g.V * b + 63) / 64)
+                                      : (uint64_t)L.S * g.V * L.cell_bytes;
+  if (need_cells > L.cells_bytes ||
+      (L.packed && (uint64_t)L.S * g.V * L.cell_bytes > L.tcells_bytes) ||
       vfk::build_scratch_bytes(M, g.V, g.l, L.logcap) > L.scratch_stride)
     return VF_ENOSPC;
+  // packed structures are built on byte cells in the workspace
+  uint8_t *const bcells = L.packed ? W + L.o_tcells : cells;
 
   // 2. group keys by shard; build order (largest shards first)
   HIPCHK(vfk::launch_order(counts, L.S, M, order, stream));
@@ -618,7 +645,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   A.bkeys = bkeys;
   A.bvals = bvals;
   A.offsets = offsets;
-  A.cells = cells;
+  A.cells = bcells;
   A.tseed = tseed;
   A.scratch = scratch;
   A.scratch_stride = L.scratch_stride;
@@ -659,6 +686,9 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
     HIPCHK(hipMemcpyAsync(hwork, work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
   }
+  if (L.packed)
+    HIPCHK(vfk::launch_pack(bcells, L.cell_bytes, (uint64_t)L.S * g.V, (uint32_t)b,
+                            (uint64_t *)cells, stream));
   pe.record(3, stream);
 
   // 4. failure record
@@ -685,6 +715,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   H->cell_bytes = L.cell_bytes;
   H->G = A.G;
   H->cells = cells;
+  H->packed = L.packed ? 1u : 0u;
   H->tseed = tseed;
   H->ncu = ncu;
   H->n_fail_total = hwork[vfk::kWorkFails];
@@ -740,8 +771,8 @@ static int query_common(const vf_handle *h, const uint64_t *keys, uint64_t n, vo
                         hipStream_t stream, int32_t want_filter) {
   if (!h || h->magic != kMagic || h->kind != 0 || h->is_filter != want_filter) return VF_EINVAL;
   if (n && (!keys || !out)) return VF_EINVAL;
-  if (vfk::launch_query(h->G, h->cells, h->cell_bytes, h->tseed, keys, n, out, h->ncu, stream) !=
-      hipSuccess)
+  if (vfk::launch_query(h->G, h->cells, h->cell_bytes, h->tseed, keys, n, out, h->ncu, stream,
+                        h->packed != 0) != hipSuccess)
     return VF_EHIP;
   return VF_OK;
 }
@@ -797,9 +828,9 @@ static int query_grouped_impl(const vf_handle *h, const uint64_t *keys, uint64_t
   if (workspace_bytes < group_bytes(S, 1, ob)) return VF_ENOSPC;
   // a shard whose cells do not fit in LDS gains nothing from grouping: its
   // probes would miss the L2 as the plain gathers do
-  if (!vfk::query_grouped_lds_bytes(h->G, h->cells, h->cell_bytes))
+  if (h->packed || !vfk::query_grouped_lds_bytes(h->G, h->cells, h->cell_bytes))
     return vfk::launch_query(h->G, h->cells, h->cell_bytes, h->tseed, keys, n, out, h->ncu,
-                             stream) == hipSuccess
+                             stream, h->packed != 0) == hipSuccess
                ? VF_OK
                : VF_EHIP;
   // the largest chunk the workspace holds (the alignment costs < 64 keys)
@@ -958,12 +989,15 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
   // Problem 1 stores b-bit values: a value with a higher bit fails the
   // call before the structure is written (descriptors staged in the
   // workspace for the check)
-  if (L.keys) {
-    vfk::BatchItem *citems = (vfk::BatchItem *)(W + L.o_check);
-    uint32_t *flag = (uint32_t *)(W + L.o_check + sizeof(vfk::BatchItem) * count);
-    uint32_t hflag = 0;
+  // descriptors with workspace offsets: the value check, and the build of
+  // packed batches (byte cells in the workspace)
+  vfk::BatchItem *const citems = (vfk::BatchItem *)(W + L.o_check);
+  if (L.keys || L.packed)
     HIPCHK(hipMemcpyAsync(citems, L.items.data(), sizeof(vfk::BatchItem) * count,
                           hipMemcpyHostToDevice, stream));
+  if (L.keys) {
+    uint32_t *flag = (uint32_t *)(W + L.o_check + sizeof(vfk::BatchItem) * count);
+    uint32_t hflag = 0;
     HIPCHK(vfk::launch_fill_u32(flag, 1, 0, stream));
     HIPCHK(vfk::launch_check_batch_values(citems, count, values, flag, stream));
     HIPCHK(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, stream));
@@ -972,8 +1006,8 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
   }
   PhaseEvents pe;
   pe.record(0, stream);
-  HIPCHK(hipMemcpyAsync(items, L.items.data(), sizeof(vfk::BatchItem) * count,
-                        hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(items, (L.packed ? L.pitems : L.items).data(),
+                        sizeof(vfk::BatchItem) * count, hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(order, ord.data(), 8ull * count, hipMemcpyHostToDevice, stream));
   HIPCHK(vfk::launch_fill_u32(work, vfk::kWorkWords, 0, stream));
   pe.record(1, stream);
@@ -989,7 +1023,7 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
   A.bkeys = keys;
   A.bvals = values;
   A.offsets = nullptr;
-  A.cells = cells;
+  A.cells = L.packed ? W + L.o_tcells : cells;
   A.tseed = tseed;
   A.scratch = W + L.o_scratch;
   A.scratch_stride = L.scratch_stride;
@@ -999,7 +1033,7 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
   A.M = L.maxM;
   A.tmax = op.tmax;
   A.logcap = L.logcap;
-  A.items = items;
+  A.items = L.packed ? citems : items;
   A.scr_V = L.maxV;
   A.scr_l = L.maxl;
   static const uint32_t kClassBytes[4] = {1, 2, 4, 8};
@@ -1034,6 +1068,8 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
     HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkNext, 1, 0, stream));
     HIPCHK(vfk::launch_build(A, (int)std::min<uint32_t>(nwg, (uint32_t)ncu), stream));
   }
+  if (L.packed)
+    HIPCHK(vfk::launch_pack_batch(citems, items, count, W + L.o_tcells, cells, stream));
   pe.record(3, stream);
   uint32_t hwork[vfk::kWorkWords];
   HIPCHK(hipMemcpyAsync(hwork, work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
@@ -1049,9 +1085,10 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
 #undef HIPCHK
 
   vf_handle *H = new (std::nothrow) vf_handle();
-  if (!H) return VF_EHIP;
+  if (!H) return VF_ENOMEM;
   H->magic = kMagic;
   H->kind = 1;
+  H->packed = L.packed ? 1u : 0u;
   H->is_filter = 0;
   H->b = 0;
   H->h = 0;
@@ -1075,7 +1112,7 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
   });
   H->failed_shards = (uint32_t)std::count(ts.begin(), ts.end(), (uint8_t)255);
   H->count = count;
-  H->items = std::move(L.items);
+  H->items = std::move(L.packed ? L.pitems : L.items);
   H->seeds = std::move(ts);
   H->items_dev = items;
   *handle = H;
@@ -1100,7 +1137,7 @@ int vf_batch_query(const vf_handle *h, const uint32_t *inst, const uint64_t *key
   if (!h || h->magic != kMagic || h->kind != 1) return VF_EINVAL;
   if (nq && (!inst || !keys || !out)) return VF_EINVAL;
   if (vfk::launch_query_batch(h->G, h->items_dev, h->count, (const uint8_t *)h->cells, h->tseed,
-                              inst, keys, nq, out, h->ncu, stream) != hipSuccess)
+                              inst, keys, nq, out, h->ncu, stream, h->packed != 0) != hipSuccess)
     return VF_EHIP;
   return VF_OK;
 }
@@ -1118,6 +1155,7 @@ int vf_batch_item(const vf_handle *h, uint64_t i, vf_batch_item_t *out) {
   out->cell_bytes = it.cell_bytes;
   out->local_seed = h->seeds[i];
   out->cells = (const uint8_t *)h->cells + it.cell_off;
+  out->packed = h->packed;
   return VF_OK;
 }
 
@@ -1150,6 +1188,7 @@ int vf_info(const vf_handle *h, vf_info_t *out) {
   out->ms_build = h->ms[2];
   out->relaunched_shards = h->relaunched;
   out->mwhc = (int32_t)h->g.mwhc;
+  out->packed = h->packed;
   return VF_OK;
 }
 

@@ -2214,6 +2214,116 @@ __global__ void __launch_bounds__(256) k_query(Geo G, const T *__restrict__ cell
   }
 }
 
+// ------------------------------------------------------------ packed cells
+//
+// A structure may keep its cells as one little-endian bit string of b-bit
+// fields: cell i at bits [i b, i b + b) of consecutive 64-bit words (the
+// paper's bit-array storage of values of any width, section 5).  The build
+// works on byte-aligned cells in the workspace and packs them at the end.
+
+__device__ __forceinline__ uint64_t packed_get(const uint64_t *__restrict__ w, uint64_t i,
+                                               uint32_t b) {
+  const uint64_t bit = i * b;
+  const uint64_t q = bit >> 6;
+  const uint32_t sh = (uint32_t)bit & 63u;
+  uint64_t x = w[q] >> sh;
+  if (sh + b > 64) x |= w[q + 1] << (64 - sh);
+  return b >= 64 ? x : x & ((1ull << b) - 1);
+}
+
+// Word j of the packed string of count cells (each in[i] holds b bits).
+template <typename T>
+__device__ __forceinline__ uint64_t pack_word(const T *__restrict__ in, uint64_t count,
+                                              uint32_t b, uint64_t j) {
+  const uint64_t lo = j * 64, hi = lo + 64;
+  const uint64_t mask = b >= 64 ? ~0ull : (1ull << b) - 1;
+  uint64_t acc = 0;
+  for (uint64_t i = lo / b; i < count && i * b < hi; i++) {
+    const uint64_t v = (uint64_t)in[i] & mask;
+    const uint64_t at = i * b;
+    acc |= at >= lo ? v << (at - lo) : v >> (lo - at);
+  }
+  return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_pack(const T *__restrict__ in, uint64_t count, uint32_t b,
+                                              uint64_t *__restrict__ out, uint64_t nwords) {
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < nwords;
+       j += (uint64_t)gridDim.x * blockDim.x)
+    out[j] = pack_word(in, count, b, j);
+}
+
+// Packing of a batch: instance i's cells at src[i].cell_off bytes of `in`
+// (byte-aligned cells of src[i].cell_bytes) go to dst[i].cell_off bytes of
+// `out` as a packed string of b bits each.
+__global__ void __launch_bounds__(256) k_pack_batch(const BatchItem *__restrict__ src,
+                                                    const BatchItem *__restrict__ dst,
+                                                    uint64_t count, const uint8_t *__restrict__ in,
+                                                    uint8_t *__restrict__ out) {
+  for (uint64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const BatchItem I = src[it];
+    uint64_t *const o = (uint64_t *)(out + dst[it].cell_off);
+    const uint64_t nw = (I.V * I.b + 63) / 64;
+    const uint8_t *const c = in + I.cell_off;
+    for (uint64_t j = threadIdx.x; j < nw; j += blockDim.x) {
+      uint64_t w;
+      switch (I.cell_bytes) {
+        case 1: w = pack_word((const uint8_t *)c, I.V, I.b, j); break;
+        case 2: w = pack_word((const uint16_t *)c, I.V, I.b, j); break;
+        case 4: w = pack_word((const uint32_t *)c, I.V, I.b, j); break;
+        default: w = pack_word((const uint64_t *)c, I.V, I.b, j); break;
+      }
+      o[j] = w;
+    }
+  }
+}
+
+// k_query on packed cells (T: the answer type of a function).
+template <typename T, int QP>
+__global__ void __launch_bounds__(256) k_query_packed(Geo G, const uint64_t *__restrict__ words,
+                                                      const uint8_t *__restrict__ tseed,
+                                                      const uint64_t *__restrict__ keys,
+                                                      uint64_t n, void *__restrict__ out) {
+  extern __shared__ uint8_t seeds_lds[];
+  const bool lds_seeds = G.S <= kSeedLds;
+  if (lds_seeds) {
+    for (uint32_t i = threadIdx.x; i < G.S; i += blockDim.x) seeds_lds[i] = tseed[i];
+    __syncthreads();
+  }
+  const uint8_t *const ts = lds_seeds ? seeds_lds : tseed;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i0 < n;
+       i0 += stride * QP) {
+    uint64_t hi[QP], lo[QP];
+#pragma unroll
+    for (int k = 0; k < QP; k++) {
+      const uint64_t i = i0 + (uint64_t)k * stride;
+      const uint64_t key = i < n ? keys[i] : 0ull;
+      hi[k] = fin64(key ^ G.khi);
+      lo[k] = fin64(key ^ G.klo);
+    }
+    uint64_t x[QP];
+#pragma unroll
+    for (int k = 0; k < QP; k++) {
+      const uint32_t j = shard_of(hi[k], G.h);
+      uint32_t v0, v1, v2;
+      edge3(G, hi[k], lo[k], ts[j], v0, v1, v2);
+      const uint64_t base = (uint64_t)j * G.V;
+      x[k] = packed_get(words, base + v0, G.b) ^ packed_get(words, base + v1, G.b) ^
+             packed_get(words, base + v2, G.b);
+    }
+#pragma unroll
+    for (int k = 0; k < QP; k++) {
+      const uint64_t i = i0 + (uint64_t)k * stride;
+      if (i < n) {
+        if (G.is_filter) ((uint8_t *)out)[i] = x[k] == fingerprint(G, hi[k], lo[k]);
+        else ((T *)out)[i] = (T)x[k];
+      }
+    }
+  }
+}
+
 // Query of keys grouped by shard (section 4: a key's shard is fixed by its
 // signature, so the queries of one shard need only that shard's cells).  A
 // workgroup takes whole shards: it copies the shard's cells to LDS (the
@@ -2344,7 +2454,7 @@ __global__ void __launch_bounds__(256) k_query_batch(Geo G, const BatchItem *__r
                                                      const uint8_t *__restrict__ tseed,
                                                      const uint32_t *__restrict__ inst,
                                                      const uint64_t *__restrict__ keys, uint64_t n,
-                                                     uint64_t *__restrict__ out) {
+                                                     uint64_t *__restrict__ out, uint32_t packed) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t q = inst[i];
@@ -2364,6 +2474,11 @@ __global__ void __launch_bounds__(256) k_query_batch(Geo G, const BatchItem *__r
     edge3(g, hi, lo, tseed[q], v0, v1, v2);
     const uint8_t *w = cells + it.cell_off;
     uint64_t x;
+    if (packed) {
+      const uint64_t *pw = (const uint64_t *)w;
+      out[i] = packed_get(pw, v0, it.b) ^ packed_get(pw, v1, it.b) ^ packed_get(pw, v2, it.b);
+      continue;
+    }
     switch (it.cell_bytes) {
       case 1: x = (uint64_t)(w[v0] ^ w[v1] ^ w[v2]); break;
       case 2: {
@@ -2426,6 +2541,30 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
   uint64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const void *in, uint32_t cell_bytes, uint64_t count, uint32_t b,
+                       uint64_t *out, hipStream_t s) {
+  const uint64_t nw = (count * b + 63) / 64;
+  if (!nw) return hipSuccess;
+  uint64_t blocks = (nw + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  switch (cell_bytes) {
+    case 1: hipLaunchKernelGGL(k_pack<uint8_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint8_t *)in, count, b, out, nw); break;
+    case 2: hipLaunchKernelGGL(k_pack<uint16_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint16_t *)in, count, b, out, nw); break;
+    case 4: hipLaunchKernelGGL(k_pack<uint32_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint32_t *)in, count, b, out, nw); break;
+    default: hipLaunchKernelGGL(k_pack<uint64_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint64_t *)in, count, b, out, nw); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_batch(const BatchItem *src, const BatchItem *dst, uint64_t count,
+                             const uint8_t *in, uint8_t *out, hipStream_t s) {
+  if (!count) return hipSuccess;
+  const uint64_t blocks = count < 65536 ? count : 65536;
+  hipLaunchKernelGGL(k_pack_batch, dim3((uint32_t)blocks), dim3(256), 0, s, src, dst, count, in,
+                     out);
   return hipGetLastError();
 }
 
@@ -2547,19 +2686,19 @@ hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s) {
 hipError_t launch_query_batch(const Geo &G, const BatchItem *items, uint64_t count,
                               const uint8_t *cells, const uint8_t *tseed, const uint32_t *inst,
                               const uint64_t *keys, uint64_t n, uint64_t *out, int ncu,
-                              hipStream_t s) {
+                              hipStream_t s, bool packed) {
   if (!n) return hipSuccess;
   uint64_t blocks = (n + 255) / 256;
   const uint64_t cap = (uint64_t)ncu * 16;
   if (blocks > cap) blocks = cap;
   hipLaunchKernelGGL(k_query_batch, dim3((uint32_t)blocks), dim3(256), 0, s, G, items, count,
-                     cells, tseed, inst, keys, n, out);
+                     cells, tseed, inst, keys, n, out, packed ? 1u : 0u);
   return hipGetLastError();
 }
 
 hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
                         const uint8_t *tseed, const uint64_t *keys, uint64_t n,
-                        void *out, int ncu, hipStream_t s) {
+                        void *out, int ncu, hipStream_t s, bool packed) {
   if (!n) return hipSuccess;
   constexpr int QP = 4;
   // 8 workgroups of 4 wavefronts per CU, each thread QP queries per step
@@ -2568,6 +2707,16 @@ hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
   if (blocks > cap) blocks = cap;
   dim3 g((uint32_t)blocks), b(256);
   const size_t shm = G.S <= kSeedLds ? G.S : 0;
+  if (packed) {
+    const uint64_t *w = (const uint64_t *)cells;
+    switch (cell_bytes) {
+      case 1: hipLaunchKernelGGL((k_query_packed<uint8_t, QP>), g, b, shm, s, G, w, tseed, keys, n, out); break;
+      case 2: hipLaunchKernelGGL((k_query_packed<uint16_t, QP>), g, b, shm, s, G, w, tseed, keys, n, out); break;
+      case 4: hipLaunchKernelGGL((k_query_packed<uint32_t, QP>), g, b, shm, s, G, w, tseed, keys, n, out); break;
+      default: hipLaunchKernelGGL((k_query_packed<uint64_t, QP>), g, b, shm, s, G, w, tseed, keys, n, out); break;
+    }
+    return hipGetLastError();
+  }
   switch (cell_bytes) {
     case 1: hipLaunchKernelGGL((k_query<uint8_t, QP>), g, b, shm, s, G, (const uint8_t *)cells, tseed, keys, n, out); break;
     case 2: hipLaunchKernelGGL((k_query<uint16_t, QP>), g, b, shm, s, G, (const uint16_t *)cells, tseed, keys, n, out); break;

@@ -104,6 +104,13 @@ uint64_t build_scratch_bytes(uint32_t M, uint64_t V, uint32_t l, uint32_t logcap
 uint32_t window_slots(uint32_t sigma, uint32_t lds_bytes);
 
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+// Packs count cells of cell_bytes each (b bits used) into a little-endian
+// bit string of 64-bit words (cell i at bits [i b, i b + b)).
+hipError_t launch_pack(const void *in, uint32_t cell_bytes, uint64_t count, uint32_t b,
+                       uint64_t *out, hipStream_t s);
+// The same per instance of a batch: src offsets into in, dst into out.
+hipError_t launch_pack_batch(const BatchItem *src, const BatchItem *dst, uint64_t count,
+                             const uint8_t *in, uint8_t *out, hipStream_t s);
 // Sets bit 0 of *flag if a value has a bit at or above b (per instance for a
 // batch); the flag must be cleared beforehand.
 hipError_t launch_check_values(const uint64_t *vals, uint64_t n, uint32_t b, uint32_t *flag,
@@ -134,10 +141,11 @@ int build_blocks_per_cu(uint32_t cell_bytes, uint32_t wmax, uint32_t lds_bytes);
 hipError_t launch_query_batch(const Geo &G, const BatchItem *items, uint64_t count,
                               const uint8_t *cells, const uint8_t *tseed, const uint32_t *inst,
                               const uint64_t *keys, uint64_t n, uint64_t *out, int ncu,
-                              hipStream_t s);
+                              hipStream_t s,
+                              bool packed);
 hipError_t launch_query(const Geo &G, const void *cells, uint32_t cell_bytes,
                         const uint8_t *tseed, const uint64_t *keys, uint64_t n,
-                        void *out, int ncu, hipStream_t s);
+                        void *out, int ncu, hipStream_t s, bool packed = false);
 // Keys of a query chunk (n < 2^32) grouped by shard, one reservation per
 // shard and segment (S <= 4096): rows is scratch of group_rows_words(S)
 // words, totals (zero on entry, zero again on return) and cursor of S

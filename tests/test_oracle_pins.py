@@ -537,3 +537,23 @@ def test_threaded_oracle_equals_the_serial_one():
     assert A.status == B.status == 0
     assert np.array_equal(A.w, B.w) and np.array_equal(A.t, B.t)
     assert A.failures == B.failures
+
+
+def test_bit_array_storage_hand_worked_and_round_trip():
+    """Bit-array storage of b-bit values (section 5): cell i at bits
+    [i b, i b + b) of little-endian 64-bit words.  Hand-worked: three 4-bit
+    cells 1, 2, 3 are the word 0x321; eight 9-bit cells put cell 7 across
+    the first word boundary (bits 63..71)."""
+    assert [int(x) for x in O.pack(np.array([1, 2, 3], np.uint64), 4)] == [0x321]
+    w = np.zeros(8, np.uint64)
+    w[7] = 0b101010101  # bits 63 .. 71
+    p = O.pack(w, 9)
+    assert len(p) == 2 and int(p[0]) == 1 << 63 and int(p[1]) == 0b10101010
+    rng = np.random.default_rng(8)
+    for b in (1, 3, 4, 9, 17, 31, 33, 63, 64):
+        vals = rng.integers(0, 2**63, 300, dtype=np.int64).astype(np.uint64)
+        if b < 64:
+            vals &= np.uint64((1 << b) - 1)
+        p = O.pack(vals, b)
+        assert len(p) == (300 * b + 63) // 64
+        assert [O.unpack(p, i, b) for i in range(300)] == [int(v) for v in vals]

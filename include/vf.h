@@ -86,6 +86,10 @@ typedef struct vf_opts {
                          Queries read the packed fields; grouped queries
                          use the plain gathers.  0 (default): cells of 1, 2,
                          4 or 8 bytes. */
+  int32_t small;      /* batches: 0 (default) the kernel vf_batch_tuning
+                         chose for each size class, 1 the one-wavefront
+                         kernel for every instance it fits, 2 never it;
+                         the cells are the same either way. */
 } vf_opts;
 
 /* Sizes returned by vf_plan (upper bounds: the largest shard is known only
@@ -136,6 +140,11 @@ typedef struct vf_failure {
 } vf_failure;
 
 typedef struct vf_handle vf_handle;
+
+/* A description of the calling thread's last VF_EHIP (the failing HIP
+ * call and its error), or an empty string.  The text stays valid until the
+ * thread's next failing call. */
+const char *vf_last_error(void);
 
 /* Paper defaults: h from eps with alpha = 1 (section 4), c and the segment
  * size by the size rule (section 4.2), tmax = 255. */
@@ -328,6 +337,27 @@ int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
  * Errors: VF_EINVAL (null pointers, or a handle that is not a batch). */
 int vf_batch_query(const vf_handle *h, const uint32_t *inst, const uint64_t *keys,
                    uint64_t nq, uint64_t *out, hipStream_t stream);
+
+/* How batches are built on the current device.  Instances of at most 128
+ * keys and 256 cells can be built by a one-wavefront kernel that keeps the
+ * whole instance on chip (edges in registers, peeling and values in LDS, a
+ * dense elimination of the 2-core in registers; section 4.2 solves small
+ * sizes by Gaussian elimination) instead of the peel + band kernel; both
+ * give the same cells.  The first vf_batch_build on a device that has at
+ * least 256 such instances (one-byte cells) in a size class times both
+ * kernels on up to 2048 of them per class and keeps the faster, and tunes
+ * the grid of the one-wavefront kernel; until then the one-wavefront
+ * kernel builds every instance that fits it.  Errors: VF_EINVAL. */
+typedef struct vf_batch_tuning_t {
+  int32_t tuned;            /* 1 once the classes have been measured       */
+  uint32_t max_keys[4];     /* size classes: up to 16, 32, 64, 128 keys    */
+  int32_t use_small[4];     /* 1: the one-wavefront kernel builds the class */
+  float ms_small[4];        /* time of the sampled instances, each kernel  */
+  float ms_band[4];
+  uint32_t sampled[4];      /* instances timed per class                   */
+  uint32_t small_groups_per_cu; /* workgroups per CU of the small kernel   */
+} vf_batch_tuning_t;
+int vf_batch_tuning(vf_batch_tuning_t *out);
 
 /* Describe instance i of a batch.  Errors: VF_EINVAL (not a batch handle,
  * i out of range, out NULL). */

@@ -28,14 +28,18 @@ _ERR = {VF_EINVAL: "VF_EINVAL", VF_ENOSPC: "VF_ENOSPC", VF_EFAIL: "VF_EFAIL",
 
 class VFError(RuntimeError):
     def __init__(self, code: int, where: str):
-        super().__init__(f"{where}: {_ERR.get(code, code)}")
+        detail = ""
+        if code == VF_EHIP:
+            detail = " (" + (_lib.vf_last_error() or b"").decode(errors="replace") + ")"
+        super().__init__(f"{where}: {_ERR.get(code, code)}{detail}")
         self.code = code
 
 
 class Opts(C.Structure):
     _fields_ = [("h", C.c_int32), ("sigma", C.c_int32), ("c_num", C.c_uint32),
                 ("c_den", C.c_uint32), ("tmax", C.c_uint32), ("alpha", C.c_double),
-                ("mwhc", C.c_int32), ("max_window", C.c_uint32), ("packed", C.c_uint32)]
+                ("mwhc", C.c_int32), ("max_window", C.c_uint32), ("packed", C.c_uint32),
+                ("small", C.c_int32)]
 
 
 class Sizes(C.Structure):
@@ -66,6 +70,16 @@ class BatchItem(C.Structure):
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Tuning(C.Structure):
+    _fields_ = [("tuned", C.c_int32), ("max_keys", C.c_uint32 * 4), ("use_small", C.c_int32 * 4),
+                ("ms_small", C.c_float * 4), ("ms_band", C.c_float * 4),
+                ("sampled", C.c_uint32 * 4), ("small_groups_per_cu", C.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: (list(getattr(self, f)) if hasattr(getattr(self, f), "__len__")
+                    else getattr(self, f)) for f, _ in self._fields_}
 
 
 class Failure(C.Structure):
@@ -104,17 +118,20 @@ _lib.vf_batch_build.argtypes = [_vp, _vp, _u64, _vp, _vp, _u64, C.POINTER(Opts),
                                 _vp, _u64, _vp, C.POINTER(_vp)]
 _lib.vf_batch_query.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp]
 _lib.vf_batch_item.argtypes = [_vp, _u64, C.POINTER(BatchItem)]
+_lib.vf_batch_tuning.argtypes = [C.POINTER(Tuning)]
+_lib.vf_last_error.argtypes = []
+_lib.vf_last_error.restype = C.c_char_p
 for _f in ("vf_plan", "vf_build", "vfilter_build", "vf_query", "vfilter_contains", "vf_info",
            "vf_failures", "vf_batch_plan", "vf_batch_build", "vf_batch_query", "vf_batch_item",
            "vfilter_build_host", "vf_query_grouped_bytes", "vf_query_grouped",
-           "vfilter_contains_grouped", "vfilter_contains_grouped_noalloc"):
+           "vfilter_contains_grouped", "vfilter_contains_grouped_noalloc", "vf_batch_tuning"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build",
            "vfilter_contains", "vf_info", "vf_failures", "vf_free", "vf_batch_plan",
            "vf_batch_build", "vf_batch_query", "vf_batch_item", "vfilter_build_host",
            "vf_query_grouped_bytes", "vf_query_grouped", "vfilter_contains_grouped",
-           "vfilter_contains_grouped_noalloc")
+           "vfilter_contains_grouped_noalloc", "vf_batch_tuning", "vf_last_error")
 
 
 def _check(rc: int, where: str) -> None:
@@ -305,6 +322,17 @@ def vf_batch_item(handle, i: int) -> dict:
     return it.as_dict()
 
 
+def vf_last_error() -> str:
+    """The calling thread's last VF_EHIP: the failing HIP call and its error."""
+    return (_lib.vf_last_error() or b"").decode(errors="replace")
+
+
+def vf_batch_tuning() -> dict:
+    t = Tuning()
+    _check(_lib.vf_batch_tuning(C.byref(t)), "vf_batch_tuning")
+    return t.as_dict()
+
+
 _CELL_DTYPE = {1: torch.uint8, 2: torch.int16, 4: torch.int32, 8: torch.int64}
 
 
@@ -424,9 +452,10 @@ class Batch:
     @classmethod
     def build(cls, keys: torch.Tensor, values: torch.Tensor, n, b, *, seed: int = 0,
               sigma: int | None = None, c: tuple | None = None, tmax: int | None = None,
-              max_window: int | None = None, packed: bool = False, stream=None):
+              max_window: int | None = None, packed: bool = False, small: int = 0,
+              stream=None):
         opts = vf_default_opts(sigma=sigma, tmax=tmax, max_window=max_window,
-                               packed=int(packed))
+                               packed=int(packed), small=small)
         if c is not None:
             opts.c_num, opts.c_den = c
         sz = vf_batch_plan(n, b, opts)

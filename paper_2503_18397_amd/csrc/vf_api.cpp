@@ -6,7 +6,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -148,6 +150,15 @@ uint32_t shard_cap(uint64_t n, uint32_t S) {
 }
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// The last failure of this thread, for vf_last_error.
+thread_local char g_last_error[160];
+
+int hip_failed(hipError_t e, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "vf_api.cpp:%d: %s (%d)", line, hipGetErrorString(e),
+           (int)e);
+  return VF_EHIP;
+}
 
 // No C++ exception crosses the C ABI: a failed host allocation becomes
 // VF_ENOMEM, anything else VF_EHIP.
@@ -329,6 +340,42 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   return VF_OK;
 }
 
+// Size classes of small batch instances (up to 16, 32, 64, 128 keys) and
+// the choice of kernel for each, measured once per device by the first
+// batch build that has enough instances of a class (batch_build below).
+constexpr uint32_t kClassKeys[4] = {16, 32, 64, 128};
+int size_class(uint64_t n) {
+  for (int c = 0; c < 4; c++)
+    if (n && n <= kClassKeys[c]) return c;
+  return -1;
+}
+struct BatchTuning {
+  bool done = false;
+  bool use_small[4] = {true, true, true, true};
+  float ms_small[4] = {0, 0, 0, 0}, ms_band[4] = {0, 0, 0, 0};
+  uint32_t sampled[4] = {0, 0, 0, 0};
+  uint32_t small_groups_per_cu = 8;
+};
+constexpr int kTuneDevices = 64;
+std::mutex g_tune_mu;
+BatchTuning g_tune[kTuneDevices];
+int current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kTuneDevices) return -1;
+  return dev;
+}
+BatchTuning batch_tuning() {
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  return dev < 0 ? BatchTuning{} : g_tune[dev];
+}
+void set_batch_tuning(const BatchTuning &t) {
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  if (dev >= 0) g_tune[dev] = t;
+}
+constexpr uint32_t kTuneSample = 2048;  // instances timed per class
+
 // Buffers of a batch of unsharded functions.  Workspace: work counters,
 // failure records, overflow list, per-class build orders, scratch; the
 // structure: instance descriptors, local seeds, cells (8-byte aligned per
@@ -343,6 +390,7 @@ struct BatchLayout {
   uint64_t scratch_stride = 0;
   uint64_t o_work = 0, o_fails = 0, o_overflow = 0, o_order = 0, o_scratch = 0, ws_bytes = 0;
   uint64_t o_check = 0;  // instance descriptors and a flag for the value check
+  uint64_t o_tune = 0;   // lists of the instances timed by the tuning
   bool packed = false;   // instance cells packed to b bits in the structure
   std::vector<vfk::BatchItem> pitems;  // packed: descriptors with structure offsets
   uint64_t o_tcells = 0, tcells_bytes = 0;  // packed: byte cells of the build
@@ -411,6 +459,7 @@ int make_batch_layout(uint64_t count, const uint64_t *n, const int32_t *b, const
   l.o_order = take(8ull * count);
   l.o_scratch = take(l.scratch_stride * l.nwg);
   l.o_check = take(sizeof(vfk::BatchItem) * count + 256);
+  l.o_tune = take(8ull * kTuneSample);
   l.tcells_bytes = l.packed ? align256(cell_off) : 0;
   l.o_tcells = l.packed ? take(l.tcells_bytes) : 0;
   l.ws_bytes = o_;
@@ -476,6 +525,8 @@ struct PhaseEvents {
 
 extern "C" {
 
+const char *vf_last_error(void) { return g_last_error; }
+
 void vf_default_opts(vf_opts *o) {
   if (!o) return;
   o->h = -1;
@@ -487,6 +538,7 @@ void vf_default_opts(vf_opts *o) {
   o->mwhc = 0;
   o->max_window = 0;
   o->packed = 0;
+  o->small = 0;
 }
 
 int vf_plan(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts *o,
@@ -554,9 +606,10 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   uint64_t sw[3];
   seed_words(seed, sw);
 
-#define HIPCHK(x)                         \
-  do {                                    \
-    if ((x) != hipSuccess) return VF_EHIP; \
+#define HIPCHK(x)                                      \
+  do {                                                 \
+    const hipError_t e_ = (x);                         \
+    if (e_ != hipSuccess) return hip_failed(e_, __LINE__); \
   } while (0)
 
   PhaseEvents pe;
@@ -729,7 +782,10 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   });
   H->failed_shards = (uint32_t)std::count(ts.begin(), ts.end(), (uint8_t)255);
   *handle = H;
-  if (hwork[vfk::kWorkStatus] & vfk::kStatusStalled) return VF_EHIP;
+  if (hwork[vfk::kWorkStatus] & vfk::kStatusStalled) {
+    snprintf(g_last_error, sizeof(g_last_error), "a build workgroup gave up on a wait");
+    return VF_EHIP;
+  }
   if (hwork[vfk::kWorkStatus] & vfk::kStatusCapacity) return VF_ECAPACITY;
   if (H->failed_shards) return VF_EFAIL;
   return VF_OK;
@@ -961,31 +1017,46 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
   uint64_t sw[3];
   seed_words(seed, sw);
 
-#define HIPCHK(x)                         \
-  do {                                    \
-    if ((x) != hipSuccess) return VF_EHIP; \
+#define HIPCHK(x)                                      \
+  do {                                                 \
+    const hipError_t e_ = (x);                         \
+    if (e_ != hipSuccess) return hip_failed(e_, __LINE__); \
   } while (0)
 
-  // build orders: instances of each cell width, largest first
+  // build orders: the instances the one-wavefront kernel takes (chosen per
+  // size class by the tuning below, or by default), then those of each
+  // cell width for the peel + band kernel, largest first in each list
+  BatchTuning tune = batch_tuning();
   std::vector<uint32_t> ord(2 * count);
-  uint64_t cls_begin[5] = {0, 0, 0, 0, 0};
-  {
+  uint64_t cls_begin[6] = {0, 0, 0, 0, 0, 0};
+  auto small = [&](uint32_t i) {
+    const vfk::BatchItem &it = L.items[i];
+    if (op.small == 2 || !vfk::small_instance(it.n, it.V)) return false;
+    const int sc = size_class(it.n);
+    return op.small == 1 || sc < 0 || !tune.done || tune.use_small[sc];
+  };
+  auto cls = [&](uint32_t i) {
+    if (small(i)) return 0;
+    const uint32_t cb = L.items[i].cell_bytes;
+    return cb == 1 ? 1 : cb == 2 ? 2 : cb == 4 ? 3 : 4;
+  };
+  auto order_lists = [&] {
     std::vector<uint32_t> idx(count);
     for (uint64_t i = 0; i < count; i++) idx[i] = (uint32_t)i;
-    auto cls = [&](uint32_t i) {
-      const uint32_t cb = L.items[i].cell_bytes;
-      return cb == 1 ? 0 : cb == 2 ? 1 : cb == 4 ? 2 : 3;
-    };
+    std::vector<int> c_of(count);
+    for (uint64_t i = 0; i < count; i++) c_of[i] = cls((uint32_t)i);
     std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t c) {
-      return cls(a) != cls(c) ? cls(a) < cls(c) : L.items[a].n > L.items[c].n;
+      return c_of[a] != c_of[c] ? c_of[a] < c_of[c] : L.items[a].n > L.items[c].n;
     });
+    for (int c = 0; c < 6; c++) cls_begin[c] = 0;
     for (uint64_t i = 0; i < count; i++) {
       ord[2 * i] = idx[i];
       ord[2 * i + 1] = 0;
-      cls_begin[cls(idx[i]) + 1] = i + 1;
+      cls_begin[c_of[idx[i]] + 1] = i + 1;
     }
-    for (int c = 1; c < 5; c++) cls_begin[c] = std::max(cls_begin[c], cls_begin[c - 1]);
-  }
+    for (int c = 1; c < 6; c++) cls_begin[c] = std::max(cls_begin[c], cls_begin[c - 1]);
+  };
+  order_lists();
   // Problem 1 stores b-bit values: a value with a higher bit fails the
   // call before the structure is written (descriptors staged in the
   // workspace for the check)
@@ -1037,8 +1108,111 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
   A.scr_V = L.maxV;
   A.scr_l = L.maxl;
   static const uint32_t kClassBytes[4] = {1, 2, 4, 8};
+  if (!tune.done && op.small == 0) {
+    // Tuning: for each size class with enough small instances of one-byte
+    // cells, the sampled instances are built by both kernels (the same
+    // cells either way) and timed; the faster builds the class from now
+    // on, on this device; the grid of the one-wavefront kernel is tuned on
+    // the largest sample.  The whole batch is then built as usual.
+    BatchTuning nt;
+    uint32_t *const tl = (uint32_t *)(W + L.o_tune);
+    PhaseEvents te;
+    int biggest = -1;
+    uint32_t biggest_n = 0;
+    std::vector<uint32_t> lists[4];
+    for (uint64_t i = 0; i < count; i++) {
+      const vfk::BatchItem &it = L.items[i];
+      const int sc = size_class(it.n);
+      if (sc >= 0 && it.cell_bytes == 1 && vfk::small_instance(it.n, it.V) &&
+          lists[sc].size() < 2 * kTuneSample) {
+        lists[sc].push_back((uint32_t)i);
+        lists[sc].push_back(0);
+      }
+    }
+    bool any = false;
+    for (int sc = 0; sc < 4; sc++) {
+      const uint32_t ns = (uint32_t)(lists[sc].size() / 2);
+      nt.sampled[sc] = ns;
+      if (ns < 256) continue;
+      any = true;
+      HIPCHK(hipMemcpyAsync(tl, lists[sc].data(), 8ull * ns, hipMemcpyHostToDevice, stream));
+      vfk::BuildArgs T = A;
+      T.list = tl;
+      T.nlist = ns;
+      T.nlist_dev = nullptr;
+      T.overflow = overflow;
+      T.cell_bytes = 1;
+      auto time_small = [&](uint32_t per_cu) -> float {
+        const uint64_t nwg = std::max<uint64_t>(1, std::min<uint64_t>(
+            (ns + vfk::kSmallWavesPerGroup - 1) / vfk::kSmallWavesPerGroup, (uint64_t)ncu * per_cu));
+        te.record(0, stream);
+        if (vfk::launch_small(T, (int)nwg, stream) != hipSuccess) return -1.f;
+        te.record(1, stream);
+        return hipStreamSynchronize(stream) == hipSuccess ? te.between(0, 1) : -1.f;
+      };
+      nt.ms_small[sc] = time_small(nt.small_groups_per_cu);
+      int32_t sg = 0;
+      for (uint32_t k = 0; k < ns; k++) sg = std::max(sg, (int32_t)L.items[lists[sc][2 * k]].sigma);
+      const BuildShape shape = build_shape(sg, 1);
+      T.lds_bytes = shape.lds_bytes;
+      T.wmax = shape.wmax;
+      HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkNext, 1, 0, stream));
+      te.record(2, stream);
+      HIPCHK(vfk::launch_build(T, (int)std::min<uint64_t>(ns, (uint64_t)shape.per_cu * ncu), stream));
+      te.record(3, stream);
+      HIPCHK(hipStreamSynchronize(stream));
+      nt.ms_band[sc] = te.between(2, 3);
+      nt.use_small[sc] = nt.ms_small[sc] >= 0 && nt.ms_small[sc] <= nt.ms_band[sc];
+      if (ns > biggest_n) {
+        biggest_n = ns;
+        biggest = sc;
+      }
+    }
+    if (any) {
+      // the grid of the one-wavefront kernel, on the largest sample
+      HIPCHK(hipMemcpyAsync(tl, lists[biggest].data(), 8ull * biggest_n, hipMemcpyHostToDevice,
+                            stream));
+      vfk::BuildArgs T = A;
+      T.list = tl;
+      T.nlist = biggest_n;
+      T.nlist_dev = nullptr;
+      float best = -1.f;
+      for (uint32_t per_cu : {2u, 4u, 8u, 16u}) {
+        const uint64_t nwg = std::max<uint64_t>(1, std::min<uint64_t>(
+            (biggest_n + vfk::kSmallWavesPerGroup - 1) / vfk::kSmallWavesPerGroup,
+            (uint64_t)ncu * per_cu));
+        te.record(0, stream);
+        HIPCHK(vfk::launch_small(T, (int)nwg, stream));
+        te.record(1, stream);
+        HIPCHK(hipStreamSynchronize(stream));
+        const float ms = te.between(0, 1);
+        if (best < 0 || ms < best) {
+          best = ms;
+          nt.small_groups_per_cu = per_cu;
+        }
+      }
+      nt.done = true;
+      set_batch_tuning(nt);
+      tune = nt;
+      // the timed builds left counters, failure records and an order: start
+      // over with the tuned choice
+      HIPCHK(vfk::launch_fill_u32(work, vfk::kWorkWords, 0, stream));
+      order_lists();
+      HIPCHK(hipMemcpyAsync(order, ord.data(), 8ull * count, hipMemcpyHostToDevice, stream));
+    }
+  }
+  if (cls_begin[1] > 0) {
+    A.list = order;
+    A.nlist = (uint32_t)cls_begin[1];
+    A.nlist_dev = nullptr;
+    A.overflow = nullptr;
+    const uint64_t want = (cls_begin[1] + vfk::kSmallWavesPerGroup - 1) / vfk::kSmallWavesPerGroup;
+    const uint64_t nwg = std::max<uint64_t>(
+        1, std::min<uint64_t>(want, (uint64_t)ncu * (tune.done ? tune.small_groups_per_cu : 8)));
+    HIPCHK(vfk::launch_small(A, (int)nwg, stream));
+  }
   for (int c = 0; c < 4; c++) {
-    const uint64_t c0 = cls_begin[c], c1 = cls_begin[c + 1];
+    const uint64_t c0 = cls_begin[c + 1], c1 = cls_begin[c + 2];
     if (c1 == c0) continue;
     int32_t sg = 0;
     for (uint64_t i = c0; i < c1; i++) sg = std::max(sg, (int32_t)L.items[ord[2 * i]].sigma);
@@ -1116,7 +1290,10 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
   H->seeds = std::move(ts);
   H->items_dev = items;
   *handle = H;
-  if (hwork[vfk::kWorkStatus] & vfk::kStatusStalled) return VF_EHIP;
+  if (hwork[vfk::kWorkStatus] & vfk::kStatusStalled) {
+    snprintf(g_last_error, sizeof(g_last_error), "a build workgroup gave up on a wait");
+    return VF_EHIP;
+  }
   if (hwork[vfk::kWorkStatus] & vfk::kStatusCapacity) return VF_ECAPACITY;
   if (H->failed_shards) return VF_EFAIL;
   return VF_OK;
@@ -1130,6 +1307,21 @@ int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
     return batch_build(keys, values, count, n, b, seed, o, ws, ws_bytes, st, st_bytes, stream,
                        handle);
   });
+}
+
+int vf_batch_tuning(vf_batch_tuning_t *out) {
+  if (!out) return VF_EINVAL;
+  const BatchTuning t = batch_tuning();
+  out->tuned = t.done ? 1 : 0;
+  for (int c = 0; c < 4; c++) {
+    out->max_keys[c] = kClassKeys[c];
+    out->use_small[c] = t.use_small[c] ? 1 : 0;
+    out->ms_small[c] = t.ms_small[c];
+    out->ms_band[c] = t.ms_band[c];
+    out->sampled[c] = t.sampled[c];
+  }
+  out->small_groups_per_cu = t.small_groups_per_cu;
+  return VF_OK;
 }
 
 int vf_batch_query(const vf_handle *h, const uint32_t *inst, const uint64_t *keys, uint64_t nq,

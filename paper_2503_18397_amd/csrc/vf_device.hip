@@ -2161,6 +2161,244 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   }
 }
 
+// ------------------------------------------------- small instances (batches)
+//
+// An instance of at most kSmallKeys keys and kSmallCells cells is built by
+// one wavefront, everything on chip: its edges sit in registers (two keys
+// per lane), peeling keeps each vertex's degree and edge-index sum in LDS,
+// the 2-core is eliminated densely in registers (each row an 8-word mask
+// over the cells, one row per lane and register set), swept from the top
+// column down with the first candidate row as pivot (the same canonical
+// solution as any other choice: pivots are the highest columns, free
+// variables zero), then back-substituted and the peeled edges assigned in
+// reverse round order in LDS.  Failed attempts retry with the next local
+// seed, exactly as the large-instance kernel does.
+constexpr uint32_t kSmallKeys = 128;
+constexpr uint32_t kSmallCells = 256;
+constexpr uint32_t kSmallWaves = kSmallWavesPerGroup;
+
+bool small_instance(uint64_t n, uint64_t V) { return n <= kSmallKeys && V <= kSmallCells; }
+
+template <typename T>
+__device__ __forceinline__ void small_store(uint8_t *cells, const uint64_t *x, uint64_t V,
+                                            uint64_t vmask, uint32_t lane) {
+  T *const c = (T *)cells;
+  for (uint32_t v = lane; v < V; v += 64) c[v] = (T)(x[v] & vmask);
+}
+
+__global__ void __launch_bounds__(64 * kSmallWaves) k_small(BuildArgs A) {
+  __shared__ uint64_t xs_all[kSmallWaves][kSmallCells];        // vertex state, then values
+  __shared__ uint32_t prow_all[kSmallWaves][kSmallKeys][8];    // pivot rows
+  __shared__ uint64_t prhs_all[kSmallWaves][kSmallKeys];       // their right sides
+  __shared__ uint16_t pcol_all[kSmallWaves][kSmallKeys];       // their columns
+  const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
+  uint64_t *const xs = xs_all[wv];
+  uint32_t (*const prow)[8] = prow_all[wv];
+  uint64_t *const prhs = prhs_all[wv];
+  uint16_t *const pcol = pcol_all[wv];
+  const uint32_t nlist = A.nlist_dev ? *A.nlist_dev : A.nlist;
+  for (uint32_t w = blockIdx.x * kSmallWaves + wv; w < nlist; w += gridDim.x * kSmallWaves) {
+    const uint32_t q = A.list[2 * w], t0 = A.list[2 * w + 1];
+    const BatchItem I = A.items[q];
+    Geo g = A.G;
+    g.V = I.V;
+    g.vmask = I.vmask;
+    g.l = I.l;
+    g.sigma = I.sigma;
+    g.b = I.b;
+    g.h = 0;
+    const uint32_t m = I.n, V = (uint32_t)I.V;
+    uint8_t *const cells = (uint8_t *)A.cells + I.cell_off;
+    uint64_t hi[2], lo[2], rhs[2];
+    bool valid[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const uint32_t i = lane + 64 * r;
+      valid[r] = i < m;
+      const uint64_t key = valid[r] ? A.bkeys[I.key_off + i] : 0ull;
+      hi[r] = fin64(key ^ g.khi);
+      lo[r] = fin64(key ^ g.klo);
+      rhs[r] = !valid[r] ? 0ull
+               : g.is_filter ? fingerprint(g, hi[r], lo[r])
+                             : A.bvals[I.key_off + i] & g.vmask;
+    }
+    uint32_t t = t0;
+    bool ok = false;
+    for (; t < A.tmax && !ok; t++) {
+      uint32_t ev[2][3];
+#pragma unroll
+      for (int r = 0; r < 2; r++) {
+        ev[r][0] = ev[r][1] = ev[r][2] = 0;
+        if (valid[r]) edge3(g, hi[r], lo[r], t, ev[r][0], ev[r][1], ev[r][2]);
+      }
+      for (uint32_t v = lane; v < V; v += 64) xs[v] = 0;
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < 2; r++)
+        if (valid[r])
+#pragma unroll
+          for (int k = 0; k < 3; k++)
+            atomicAdd((unsigned long long *)&xs[ev[r][k]], kDegOne + lane + 64 * r);
+      wave_sync();
+      // round-synchronous peeling: degrees as they stand when the round
+      // starts, hinge = the edge's first degree-one vertex
+      int32_t rnd[2] = {-1, -1};
+      uint32_t side[2] = {0, 0};
+      int32_t nrounds = 0;
+      for (;;) {
+        bool take[2] = {false, false};
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+          if (valid[r] && rnd[r] < 0) {
+#pragma unroll
+            for (int k = 2; k >= 0; k--)
+              if ((xs[ev[r][k]] >> 32) == 1) {
+                take[r] = true;
+                side[r] = (uint32_t)k;
+              }
+          }
+        }
+        wave_sync();
+        if (!(__ballot(take[0]) | __ballot(take[1]))) break;
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+          if (take[r]) {
+            rnd[r] = nrounds;
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+              atomicAdd((unsigned long long *)&xs[ev[r][k]],
+                        (unsigned long long)(-(kDegOne + lane + 64 * r)));
+          }
+        wave_sync();
+        nrounds++;
+      }
+      // the 2-core as rows over the cells
+      uint32_t row[2][8];
+      uint64_t rr[2];
+      bool live[2];
+#pragma unroll
+      for (int r = 0; r < 2; r++) {
+        live[r] = valid[r] && rnd[r] < 0;
+        rr[r] = live[r] ? rhs[r] : 0ull;
+#pragma unroll
+        for (int d = 0; d < 8; d++) {
+          uint32_t x = 0;
+          if (live[r])
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+              if ((ev[r][k] >> 5) == (uint32_t)d) x ^= 1u << (ev[r][k] & 31);
+          row[r][d] = x;
+        }
+      }
+      const uint32_t ncore = (uint32_t)(__popcll(__ballot(live[0])) + __popcll(__ballot(live[1])));
+      uint32_t np = 0;
+      const int nwords = (int)((V + 31) >> 5);
+#pragma unroll
+      for (int d = 7; d >= 0; d--) {
+        if (d >= nwords) continue;
+        uint32_t colmask = wave_or((live[0] ? row[0][d] : 0u) | (live[1] ? row[1][d] : 0u));
+        while (colmask) {
+          const uint32_t b = 31 - __clz(colmask), bit = 1u << b;
+          const uint64_t m0 = __ballot(live[0] && (row[0][d] & bit));
+          const uint64_t m1 = __ballot(live[1] && (row[1][d] & bit));
+          if (!(m0 | m1)) {
+            colmask &= bit - 1u;
+            continue;
+          }
+          const int pr = m0 ? 0 : 1;
+          const int pl = (int)__ffsll((long long)(m0 ? m0 : m1)) - 1;
+          uint32_t pw[8];
+#pragma unroll
+          for (int dd = 0; dd < 8; dd++) pw[dd] = readlane(pr == 0 ? row[0][dd] : row[1][dd], pl);
+          const uint64_t prh = readlane64(pr == 0 ? rr[0] : rr[1], pl);
+          if (lane == 0) {
+#pragma unroll
+            for (int dd = 0; dd < 8; dd++) prow[np][dd] = pw[dd];
+            prhs[np] = prh;
+            pcol[np] = (uint16_t)(d * 32 + b);
+          }
+#pragma unroll
+          for (int r = 0; r < 2; r++) {
+            const bool cand = live[r] && (row[r][d] & bit);
+            if (r == pr && (int)lane == pl) {
+              live[r] = false;  // the pivot row leaves
+            } else if (cand) {
+#pragma unroll
+              for (int dd = 0; dd < 8; dd++) row[r][dd] ^= pw[dd];
+              rr[r] ^= prh;
+            }
+          }
+          np++;
+          colmask = (colmask | pw[d]) & (bit - 1u);
+        }
+      }
+      // rows left over are zero: a right side that is not zero is a
+      // contradiction
+      if (__ballot((live[0] && rr[0] != 0) || (live[1] && rr[1] != 0))) {
+        if (lane == 0) {
+          const uint32_t idx = atomicAdd(&A.work[kWorkFails], 1u);
+          if (idx < A.fail_cap) A.fails[idx] = FailRec{q, t, 1u, ncore};
+        }
+        continue;
+      }
+      // values: pivots by increasing column (the last found is the lowest)
+      for (uint32_t v = lane; v < V; v += 64) xs[v] = 0;
+      wave_sync();
+      for (int i = (int)np - 1; i >= 0; i--) {
+        const uint32_t c = pcol[i];
+        const uint32_t word = prow[i][lane >> 3];
+        const uint32_t nib = (word >> ((lane & 7u) * 4)) & 0xFu;
+        uint64_t acc = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; j++) {
+          const uint32_t v = lane * 4 + j;
+          if (((nib >> j) & 1u) && v != c) acc ^= xs[v];
+        }
+        acc = wave_xor64(acc);
+        if (lane == 0) xs[c] = acc ^ prhs[i];
+        wave_sync();
+      }
+      for (int rd = nrounds - 1; rd >= 0; rd--) {
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+          if (rnd[r] == rd) {
+            uint64_t val = rhs[r];
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+              if ((uint32_t)k != side[r]) val ^= xs[ev[r][k]];
+            xs[ev[r][side[r]]] = val;
+          }
+        wave_sync();
+      }
+      switch (I.cell_bytes) {
+        case 1: small_store<uint8_t>(cells, xs, V, g.vmask, lane); break;
+        case 2: small_store<uint16_t>(cells, xs, V, g.vmask, lane); break;
+        case 4: small_store<uint32_t>(cells, xs, V, g.vmask, lane); break;
+        default: small_store<uint64_t>(cells, xs, V, g.vmask, lane); break;
+      }
+      if (lane == 0) A.tseed[q] = (uint8_t)t;
+      ok = true;
+    }
+    if (!ok) {
+      for (uint32_t v = lane; v < V; v += 64) xs[v] = 0;
+      wave_sync();
+      switch (I.cell_bytes) {
+        case 1: small_store<uint8_t>(cells, xs, V, 0, lane); break;
+        case 2: small_store<uint16_t>(cells, xs, V, 0, lane); break;
+        case 4: small_store<uint32_t>(cells, xs, V, 0, lane); break;
+        default: small_store<uint64_t>(cells, xs, V, 0, lane); break;
+      }
+      if (lane == 0) A.tseed[q] = 255;
+    }
+    wave_sync();
+  }
+}
+
+hipError_t launch_small(const BuildArgs &a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_small, dim3((uint32_t)nwg), dim3(64 * kSmallWaves), 0, s, a);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ query
 
 // Each thread answers QP queries that are a grid apart (coalesced per

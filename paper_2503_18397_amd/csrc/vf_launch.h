@@ -129,6 +129,13 @@ hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n
                           uint64_t *bkeys, uint64_t *bvals, uint32_t *bidx, int ncu,
                           hipStream_t s);
 hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s);
+// Wavefronts (instances in flight) per workgroup of the one-wavefront kernel.
+constexpr uint32_t kSmallWavesPerGroup = 4;
+// Instances small enough for the one-wavefront kernel (batches only).
+bool small_instance(uint64_t n, uint64_t V);
+// The one-wavefront build of the (instance, first local seed) pairs of
+// a.list (a.items, a.cells, a.tseed, a.fails, a.work as for launch_build).
+hipError_t launch_small(const BuildArgs &a, int nwg, hipStream_t s);
 // The allocation-free grouped query's workspace: a device array of
 // kNoAllocScratchBytes per device; *ptr receives its address on the current
 // device (looked up once per device).

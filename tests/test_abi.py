@@ -19,7 +19,7 @@ LIB = os.path.join(ROOT, "paper_2503_18397_amd", "libvf.so")
 def _declared():
     src = open(HDR).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void)\s+\**\s*(vf\w*|vfilter\w*)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|const\s+char)\s+\**\s*(vf\w*|vfilter\w*)\s*\(", src, re.M)))
 
 
 def test_header_declares_the_boundary():

@@ -331,6 +331,42 @@ int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
                    void *structure, uint64_t structure_bytes,
                    hipStream_t stream, vf_handle **handle);
 
+/* The same build in three calls, so that its device work can be captured
+ * into a HIP graph and replayed (for instance on new keys written into the
+ * same buffers).  The cells, seeds and failure record are those
+ * vf_batch_build gives for the same input.
+ *   vf_batch_prepare  plans the batch on the host and copies its instance
+ *                     descriptors and launch lists into workspace and
+ *                     structure (synchronizes stream once).  *handle
+ *                     receives a batch handle that answers no query until
+ *                     a vf_batch_finish has reported a built structure.
+ *                     Uses the device's kernel choice as vf_batch_tuning
+ *                     describes it at that moment (it does not tune).
+ *   vf_batch_launch   enqueues the build on stream and nothing else: no
+ *                     allocation, no copy from the host, no wait, so it may
+ *                     run under stream capture.  The values are checked
+ *                     on the device first; a value with a bit at or above
+ *                     its b makes every build kernel return at once, and
+ *                     the structure keeps what it held.
+ *   vf_batch_finish   once stream has run the launch (or a graph holding
+ *                     it): reads the check, the failure record and the
+ *                     local seeds into the handle (synchronizes stream).
+ *                     VF_EINVAL: a value was too wide (handle unchanged);
+ *                     otherwise what vf_batch_build returns.
+ * The handle refers to workspace and structure (caller-owned, kept for the
+ * handle's life); keys and values are read when the launched work runs.
+ * Launches of one handle that overlap on the device race on its buffers.
+ * Errors of prepare as vf_batch_build's before any device work; of launch:
+ * VF_EINVAL (not a prepared handle, null keys or values), VF_EHIP. */
+int vf_batch_prepare(uint64_t count, const uint64_t *n, const int32_t *b,
+                     uint64_t seed, const vf_opts *o, void *workspace,
+                     uint64_t workspace_bytes, void *structure,
+                     uint64_t structure_bytes, hipStream_t stream,
+                     vf_handle **handle);
+int vf_batch_launch(vf_handle *h, const uint64_t *keys, const uint64_t *values,
+                    hipStream_t stream);
+int vf_batch_finish(vf_handle *h, hipStream_t stream);
+
 /* Query a batch: out[i] = value of keys[i] in instance inst[i] (eq. (MWHC)
  * in that instance), as a uint64 word.  inst, keys and out are device
  * arrays of nq entries; an instance index >= count gives all ones.

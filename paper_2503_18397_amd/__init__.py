@@ -116,6 +116,10 @@ _lib.vf_free.restype = None
 _lib.vf_batch_plan.argtypes = [_u64, _vp, _vp, C.POINTER(Opts), C.POINTER(Sizes)]
 _lib.vf_batch_build.argtypes = [_vp, _vp, _u64, _vp, _vp, _u64, C.POINTER(Opts), _vp, _u64,
                                 _vp, _u64, _vp, C.POINTER(_vp)]
+_lib.vf_batch_prepare.argtypes = [_u64, _vp, _vp, _u64, C.POINTER(Opts), _vp, _u64, _vp, _u64,
+                                  _vp, C.POINTER(_vp)]
+_lib.vf_batch_launch.argtypes = [_vp, _vp, _vp, _vp]
+_lib.vf_batch_finish.argtypes = [_vp, _vp]
 _lib.vf_batch_query.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp]
 _lib.vf_batch_item.argtypes = [_vp, _u64, C.POINTER(BatchItem)]
 _lib.vf_batch_tuning.argtypes = [C.POINTER(Tuning)]
@@ -124,14 +128,16 @@ _lib.vf_last_error.restype = C.c_char_p
 for _f in ("vf_plan", "vf_build", "vfilter_build", "vf_query", "vfilter_contains", "vf_info",
            "vf_failures", "vf_batch_plan", "vf_batch_build", "vf_batch_query", "vf_batch_item",
            "vfilter_build_host", "vf_query_grouped_bytes", "vf_query_grouped",
-           "vfilter_contains_grouped", "vfilter_contains_grouped_noalloc", "vf_batch_tuning"):
+           "vfilter_contains_grouped", "vfilter_contains_grouped_noalloc", "vf_batch_tuning",
+           "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build",
            "vfilter_contains", "vf_info", "vf_failures", "vf_free", "vf_batch_plan",
            "vf_batch_build", "vf_batch_query", "vf_batch_item", "vfilter_build_host",
            "vf_query_grouped_bytes", "vf_query_grouped", "vfilter_contains_grouped",
-           "vfilter_contains_grouped_noalloc", "vf_batch_tuning", "vf_last_error")
+           "vfilter_contains_grouped_noalloc", "vf_batch_tuning", "vf_last_error",
+           "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish")
 
 
 def _check(rc: int, where: str) -> None:
@@ -310,6 +316,31 @@ def vf_batch_build(keys, values, n, b, seed, opts, workspace, structure, stream=
     return rc, h
 
 
+def vf_batch_prepare(n, b, seed, opts, workspace, structure, stream=None):
+    """Returns the handle of a prepared batch (host arrays n and b)."""
+    n, b = _host_arrays(n, b)
+    h = C.c_void_p()
+    _check(_lib.vf_batch_prepare(n.size, n.ctypes.data, b.ctypes.data, seed,
+                                 C.byref(opts) if opts else None,
+                                 _dev_ptr(workspace, "workspace"), workspace.numel(),
+                                 _dev_ptr(structure, "structure"), structure.numel(),
+                                 _stream(stream), C.byref(h)), "vf_batch_prepare")
+    return h
+
+
+def vf_batch_launch(handle, keys, values, stream=None) -> None:
+    _check(_lib.vf_batch_launch(handle, _dev_ptr(keys, "keys"), _dev_ptr(values, "values"),
+                                _stream(stream)), "vf_batch_launch")
+
+
+def vf_batch_finish(handle, stream=None) -> int:
+    """Returns VF_OK or VF_EFAIL; raises on the other codes."""
+    rc = _lib.vf_batch_finish(handle, _stream(stream))
+    if rc not in (VF_OK, VF_EFAIL):
+        raise VFError(rc, "vf_batch_finish")
+    return rc
+
+
 def vf_batch_query(handle, inst, keys, out, stream=None) -> None:
     _check(_lib.vf_batch_query(handle, _dev_ptr(inst, "inst"), _dev_ptr(keys, "keys"),
                                keys.numel(), _dev_ptr(out, "out"), _stream(stream)),
@@ -464,6 +495,31 @@ class Batch:
         st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
         rc, hd = vf_batch_build(keys, values, n, b, seed, opts, ws, st, stream)
         return cls(hd, rc, st, ws)
+
+    @classmethod
+    def prepare(cls, n, b, *, seed: int = 0, device=None, sigma: int | None = None,
+                c: tuple | None = None, tmax: int | None = None,
+                max_window: int | None = None, packed: bool = False, small: int = 0,
+                stream=None):
+        """A batch whose build is enqueued by launch() (capturable into a
+        graph) and read back by finish()."""
+        opts = vf_default_opts(sigma=sigma, tmax=tmax, max_window=max_window,
+                               packed=int(packed), small=small)
+        if c is not None:
+            opts.c_num, opts.c_den = c
+        sz = vf_batch_plan(n, b, opts)
+        dev = torch.device(device if device is not None else "cuda")
+        ws = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=dev)
+        st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
+        hd = vf_batch_prepare(n, b, seed, opts, ws, st, stream)
+        return cls(hd, VF_OK, st, ws)
+
+    def launch(self, keys: torch.Tensor, values: torch.Tensor, stream=None) -> None:
+        vf_batch_launch(self.handle, keys, values, stream)
+
+    def finish(self, stream=None) -> int:
+        self.rc = vf_batch_finish(self.handle, stream)
+        return self.rc
 
     @property
     def info(self) -> dict:

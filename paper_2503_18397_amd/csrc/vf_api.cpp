@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -475,6 +476,8 @@ int make_batch_layout(uint64_t count, const uint64_t *n, const int32_t *b, const
 
 }  // namespace
 
+struct BatchRun;
+
 struct vf_handle {
   uint32_t magic;
   int32_t is_filter, b, h;
@@ -498,6 +501,9 @@ struct vf_handle {
   std::vector<vfk::BatchItem> items;
   std::vector<uint8_t> seeds;
   const vfk::BatchItem *items_dev;
+  // a batch prepared by vf_batch_prepare (kind 2 until its first
+  // vf_batch_finish reports a built structure, kind 1 after)
+  std::shared_ptr<BatchRun> run;
 };
 
 namespace {
@@ -989,307 +995,282 @@ int vf_batch_plan(uint64_t count, const uint64_t *n, const int32_t *b, const vf_
   return VF_OK;
 }
 
-static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
-                       const uint64_t *n, const int32_t *b, uint64_t seed, const vf_opts *o,
-                       void *ws, uint64_t ws_bytes, void *st, uint64_t st_bytes,
-                       hipStream_t stream, vf_handle **handle) {
-  if (!handle || !ws || !st) return VF_EINVAL;
-  vf_opts d;
-  vf_default_opts(&d);
-  const vf_opts &op = o ? *o : d;
-  const int ncu = device_cus();
-  if (ncu <= 0) return VF_EHIP;
+// Everything the host decides for one batch build: buffers, launch lists
+// and launch shapes.  A prepared batch keeps it in its handle, so that the
+// device work can be enqueued again and again (for instance as a captured
+// graph) without host synchronization or allocation.
+struct BatchRun {
   BatchLayout L;
-  int rc = make_batch_layout(count, n, b, op, ncu, &L);
-  if (rc) return rc;
-  if (L.keys && (!keys || !values)) return VF_EINVAL;
-  if (ws_bytes < L.ws_bytes || st_bytes < L.st_bytes) return VF_ENOSPC;
-
-  uint8_t *W = (uint8_t *)ws;
-  uint32_t *work = (uint32_t *)(W + L.o_work);
-  vfk::FailRec *fails = (vfk::FailRec *)(W + L.o_fails);
-  uint32_t *overflow = (uint32_t *)(W + L.o_overflow);
-  uint32_t *order = (uint32_t *)(W + L.o_order);
-  uint8_t *S8 = (uint8_t *)st;
-  vfk::BatchItem *items = (vfk::BatchItem *)(S8 + L.s_items);
-  uint8_t *tseed = S8 + L.s_seeds;
-  uint8_t *cells = S8 + L.s_cells;
-  uint64_t sw[3];
-  seed_words(seed, sw);
-
-#define HIPCHK(x)                                      \
-  do {                                                 \
-    const hipError_t e_ = (x);                         \
-    if (e_ != hipSuccess) return hip_failed(e_, __LINE__); \
-  } while (0)
-
-  // build orders: the instances the one-wavefront kernel takes (chosen per
-  // size class by the tuning below, or by default), then those of each
-  // cell width for the peel + band kernel, largest first in each list
-  BatchTuning tune = batch_tuning();
-  std::vector<uint32_t> ord(2 * count);
+  uint64_t count = 0;
+  int ncu = 0;
+  vf_opts op{};
+  BatchTuning tune;
+  std::vector<uint32_t> ord;
   uint64_t cls_begin[6] = {0, 0, 0, 0, 0, 0};
+  struct Launch {
+    uint32_t lds = 0, wmax = 0, nwg = 0;
+    int32_t sigma = 0;
+  } cls[4];
+  uint32_t small_nwg = 0;
+  vfk::BuildArgs A{};  // common arguments; keys and values are set per launch
+  uint8_t *W = nullptr;
+  uint32_t *work = nullptr, *overflow = nullptr, *order = nullptr, *flag = nullptr;
+  vfk::FailRec *fails = nullptr;
+  vfk::BatchItem *items = nullptr, *citems = nullptr;
+  uint8_t *tseed = nullptr, *cells = nullptr;
+};
+
+static const uint32_t kClassBytes[4] = {1, 2, 4, 8};
+
+// Launch lists: the instances the one-wavefront kernel takes (by the
+// tuning, or by default), then those of each cell width for the peel + band
+// kernel, largest first in each list; and the launch shape of each list.
+static void batch_lists(BatchRun &R) {
+  const uint64_t count = R.count;
+  const BatchLayout &L = R.L;
   auto small = [&](uint32_t i) {
     const vfk::BatchItem &it = L.items[i];
-    if (op.small == 2 || !vfk::small_instance(it.n, it.V)) return false;
+    if (R.op.small == 2 || !vfk::small_instance(it.n, it.V)) return false;
     const int sc = size_class(it.n);
-    return op.small == 1 || sc < 0 || !tune.done || tune.use_small[sc];
+    return R.op.small == 1 || sc < 0 || !R.tune.done || R.tune.use_small[sc];
   };
-  auto cls = [&](uint32_t i) {
-    if (small(i)) return 0;
-    const uint32_t cb = L.items[i].cell_bytes;
-    return cb == 1 ? 1 : cb == 2 ? 2 : cb == 4 ? 3 : 4;
-  };
-  auto order_lists = [&] {
-    std::vector<uint32_t> idx(count);
-    for (uint64_t i = 0; i < count; i++) idx[i] = (uint32_t)i;
-    std::vector<int> c_of(count);
-    for (uint64_t i = 0; i < count; i++) c_of[i] = cls((uint32_t)i);
-    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t c) {
-      return c_of[a] != c_of[c] ? c_of[a] < c_of[c] : L.items[a].n > L.items[c].n;
-    });
-    for (int c = 0; c < 6; c++) cls_begin[c] = 0;
-    for (uint64_t i = 0; i < count; i++) {
-      ord[2 * i] = idx[i];
-      ord[2 * i + 1] = 0;
-      cls_begin[c_of[idx[i]] + 1] = i + 1;
+  std::vector<uint32_t> idx(count);
+  std::vector<int> c_of(count);
+  for (uint64_t i = 0; i < count; i++) {
+    idx[i] = (uint32_t)i;
+    if (small((uint32_t)i)) {
+      c_of[i] = 0;
+    } else {
+      const uint32_t cb = L.items[i].cell_bytes;
+      c_of[i] = cb == 1 ? 1 : cb == 2 ? 2 : cb == 4 ? 3 : 4;
     }
-    for (int c = 1; c < 6; c++) cls_begin[c] = std::max(cls_begin[c], cls_begin[c - 1]);
-  };
-  order_lists();
-  // Problem 1 stores b-bit values: a value with a higher bit fails the
-  // call before the structure is written (descriptors staged in the
-  // workspace for the check)
-  // descriptors with workspace offsets: the value check, and the build of
-  // packed batches (byte cells in the workspace)
-  vfk::BatchItem *const citems = (vfk::BatchItem *)(W + L.o_check);
-  if (L.keys || L.packed)
-    HIPCHK(hipMemcpyAsync(citems, L.items.data(), sizeof(vfk::BatchItem) * count,
-                          hipMemcpyHostToDevice, stream));
-  if (L.keys) {
-    uint32_t *flag = (uint32_t *)(W + L.o_check + sizeof(vfk::BatchItem) * count);
-    uint32_t hflag = 0;
-    HIPCHK(vfk::launch_fill_u32(flag, 1, 0, stream));
-    HIPCHK(vfk::launch_check_batch_values(citems, count, values, flag, stream));
-    HIPCHK(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    if (hflag) return VF_EINVAL;
   }
-  PhaseEvents pe;
-  pe.record(0, stream);
-  HIPCHK(hipMemcpyAsync(items, (L.packed ? L.pitems : L.items).data(),
-                        sizeof(vfk::BatchItem) * count, hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(order, ord.data(), 8ull * count, hipMemcpyHostToDevice, stream));
-  HIPCHK(vfk::launch_fill_u32(work, vfk::kWorkWords, 0, stream));
-  pe.record(1, stream);
-  pe.record(2, stream);
+  std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t c) {
+    return c_of[a] != c_of[c] ? c_of[a] < c_of[c] : L.items[a].n > L.items[c].n;
+  });
+  R.ord.assign(2 * count, 0);
+  for (int c = 0; c < 6; c++) R.cls_begin[c] = 0;
+  for (uint64_t i = 0; i < count; i++) {
+    R.ord[2 * i] = idx[i];
+    R.cls_begin[c_of[idx[i]] + 1] = i + 1;
+  }
+  for (int c = 1; c < 6; c++) R.cls_begin[c] = std::max(R.cls_begin[c], R.cls_begin[c - 1]);
+  const uint64_t ns = R.cls_begin[1];
+  R.small_nwg = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>((ns + vfk::kSmallWavesPerGroup - 1) / vfk::kSmallWavesPerGroup,
+                            (uint64_t)R.ncu * (R.tune.done ? R.tune.small_groups_per_cu : 8)));
+  for (int c = 0; c < 4; c++) {
+    const uint64_t c0 = R.cls_begin[c + 1], c1 = R.cls_begin[c + 2];
+    BatchRun::Launch &la = R.cls[c];
+    la = BatchRun::Launch{};
+    if (c1 == c0) continue;
+    int32_t sg = 0;
+    for (uint64_t i = c0; i < c1; i++) sg = std::max(sg, (int32_t)L.items[R.ord[2 * i]].sigma);
+    const BuildShape shape = build_shape(sg, kClassBytes[c]);
+    la.sigma = sg;
+    la.lds = shape.lds_bytes;
+    la.wmax = shape.wmax;
+    if (R.op.max_window) la.wmax = std::min(la.wmax, std::max(8u, R.op.max_window & ~7u));
+    la.nwg = (uint32_t)std::min<uint64_t>(
+        std::min<uint64_t>(L.nwg, (uint64_t)shape.per_cu * R.ncu), c1 - c0);
+  }
+}
 
-  vfk::BuildArgs A{};
+// Host-side plan of a batch (no device work).
+static int batch_setup(BatchRun &R, uint64_t count, const uint64_t *n, const int32_t *b,
+                       uint64_t seed, const vf_opts *o, void *ws, uint64_t ws_bytes, void *st,
+                       uint64_t st_bytes) {
+  if (!ws || !st) return VF_EINVAL;
+  vf_default_opts(&R.op);
+  if (o) R.op = *o;
+  R.ncu = device_cus();
+  if (R.ncu <= 0) return VF_EHIP;
+  int rc = make_batch_layout(count, n, b, R.op, R.ncu, &R.L);
+  if (rc) return rc;
+  if (ws_bytes < R.L.ws_bytes || st_bytes < R.L.st_bytes) return VF_ENOSPC;
+  R.count = count;
+  R.tune = batch_tuning();
+  const BatchLayout &L = R.L;
+  R.W = (uint8_t *)ws;
+  R.work = (uint32_t *)(R.W + L.o_work);
+  R.fails = (vfk::FailRec *)(R.W + L.o_fails);
+  R.overflow = (uint32_t *)(R.W + L.o_overflow);
+  R.order = (uint32_t *)(R.W + L.o_order);
+  R.citems = (vfk::BatchItem *)(R.W + L.o_check);
+  R.flag = (uint32_t *)(R.W + L.o_check + sizeof(vfk::BatchItem) * count);
+  uint8_t *S8 = (uint8_t *)st;
+  R.items = (vfk::BatchItem *)(S8 + L.s_items);
+  R.tseed = S8 + L.s_seeds;
+  R.cells = S8 + L.s_cells;
+  uint64_t sw[3];
+  seed_words(seed, sw);
+  vfk::BuildArgs &A = R.A;
+  A = vfk::BuildArgs{};
   A.G.khi = sw[0];
   A.G.klo = sw[1];
   A.G.kfp = sw[2];
   A.G.h = 0;
   A.G.S = 1;
   A.G.is_filter = 0;
-  A.bkeys = keys;
-  A.bvals = values;
   A.offsets = nullptr;
-  A.cells = L.packed ? W + L.o_tcells : cells;
-  A.tseed = tseed;
-  A.scratch = W + L.o_scratch;
+  A.cells = L.packed ? R.W + L.o_tcells : R.cells;
+  A.tseed = R.tseed;
+  A.scratch = R.W + L.o_scratch;
   A.scratch_stride = L.scratch_stride;
-  A.work = work;
-  A.fails = fails;
+  A.work = R.work;
+  A.fails = R.fails;
   A.fail_cap = L.fail_cap;
   A.M = L.maxM;
-  A.tmax = op.tmax;
+  A.tmax = R.op.tmax;
   A.logcap = L.logcap;
-  A.items = L.packed ? citems : items;
+  // the build reads the workspace descriptors (byte cells); queries read
+  // the structure's (packed offsets when packed)
+  A.items = R.citems;
   A.scr_V = L.maxV;
   A.scr_l = L.maxl;
-  static const uint32_t kClassBytes[4] = {1, 2, 4, 8};
-  if (!tune.done && op.small == 0) {
-    // Tuning: for each size class with enough small instances of one-byte
-    // cells, the sampled instances are built by both kernels (the same
-    // cells either way) and timed; the faster builds the class from now
-    // on, on this device; the grid of the one-wavefront kernel is tuned on
-    // the largest sample.  The whole batch is then built as usual.
-    BatchTuning nt;
-    uint32_t *const tl = (uint32_t *)(W + L.o_tune);
-    PhaseEvents te;
-    int biggest = -1;
-    uint32_t biggest_n = 0;
-    std::vector<uint32_t> lists[4];
-    for (uint64_t i = 0; i < count; i++) {
-      const vfk::BatchItem &it = L.items[i];
-      const int sc = size_class(it.n);
-      if (sc >= 0 && it.cell_bytes == 1 && vfk::small_instance(it.n, it.V) &&
-          lists[sc].size() < 2 * kTuneSample) {
-        lists[sc].push_back((uint32_t)i);
-        lists[sc].push_back(0);
-      }
-    }
-    bool any = false;
-    for (int sc = 0; sc < 4; sc++) {
-      const uint32_t ns = (uint32_t)(lists[sc].size() / 2);
-      nt.sampled[sc] = ns;
-      if (ns < 256) continue;
-      any = true;
-      HIPCHK(hipMemcpyAsync(tl, lists[sc].data(), 8ull * ns, hipMemcpyHostToDevice, stream));
-      vfk::BuildArgs T = A;
-      T.list = tl;
-      T.nlist = ns;
-      T.nlist_dev = nullptr;
-      T.overflow = overflow;
-      T.cell_bytes = 1;
-      auto time_small = [&](uint32_t per_cu) -> float {
-        const uint64_t nwg = std::max<uint64_t>(1, std::min<uint64_t>(
-            (ns + vfk::kSmallWavesPerGroup - 1) / vfk::kSmallWavesPerGroup, (uint64_t)ncu * per_cu));
-        te.record(0, stream);
-        if (vfk::launch_small(T, (int)nwg, stream) != hipSuccess) return -1.f;
-        te.record(1, stream);
-        return hipStreamSynchronize(stream) == hipSuccess ? te.between(0, 1) : -1.f;
-      };
-      nt.ms_small[sc] = time_small(nt.small_groups_per_cu);
-      int32_t sg = 0;
-      for (uint32_t k = 0; k < ns; k++) sg = std::max(sg, (int32_t)L.items[lists[sc][2 * k]].sigma);
-      const BuildShape shape = build_shape(sg, 1);
-      T.lds_bytes = shape.lds_bytes;
-      T.wmax = shape.wmax;
-      HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkNext, 1, 0, stream));
-      te.record(2, stream);
-      HIPCHK(vfk::launch_build(T, (int)std::min<uint64_t>(ns, (uint64_t)shape.per_cu * ncu), stream));
-      te.record(3, stream);
-      HIPCHK(hipStreamSynchronize(stream));
-      nt.ms_band[sc] = te.between(2, 3);
-      nt.use_small[sc] = nt.ms_small[sc] >= 0 && nt.ms_small[sc] <= nt.ms_band[sc];
-      if (ns > biggest_n) {
-        biggest_n = ns;
-        biggest = sc;
-      }
-    }
-    if (any) {
-      // the grid of the one-wavefront kernel, on the largest sample
-      HIPCHK(hipMemcpyAsync(tl, lists[biggest].data(), 8ull * biggest_n, hipMemcpyHostToDevice,
-                            stream));
-      vfk::BuildArgs T = A;
-      T.list = tl;
-      T.nlist = biggest_n;
-      T.nlist_dev = nullptr;
-      float best = -1.f;
-      for (uint32_t per_cu : {2u, 4u, 8u, 16u}) {
-        const uint64_t nwg = std::max<uint64_t>(1, std::min<uint64_t>(
-            (biggest_n + vfk::kSmallWavesPerGroup - 1) / vfk::kSmallWavesPerGroup,
-            (uint64_t)ncu * per_cu));
-        te.record(0, stream);
-        HIPCHK(vfk::launch_small(T, (int)nwg, stream));
-        te.record(1, stream);
-        HIPCHK(hipStreamSynchronize(stream));
-        const float ms = te.between(0, 1);
-        if (best < 0 || ms < best) {
-          best = ms;
-          nt.small_groups_per_cu = per_cu;
-        }
-      }
-      nt.done = true;
-      set_batch_tuning(nt);
-      tune = nt;
-      // the timed builds left counters, failure records and an order: start
-      // over with the tuned choice
-      HIPCHK(vfk::launch_fill_u32(work, vfk::kWorkWords, 0, stream));
-      order_lists();
-      HIPCHK(hipMemcpyAsync(order, ord.data(), 8ull * count, hipMemcpyHostToDevice, stream));
-    }
+  batch_lists(R);
+  return VF_OK;
+}
+
+#define HIPCHK(x)                                          \
+  do {                                                     \
+    const hipError_t e_ = (x);                             \
+    if (e_ != hipSuccess) return hip_failed(e_, __LINE__); \
+  } while (0)
+
+// Descriptors into the structure and the workspace, launch lists.
+static int batch_upload(const BatchRun &R, hipStream_t stream) {
+  const uint64_t count = R.count;
+  HIPCHK(hipMemcpyAsync(R.citems, R.L.items.data(), sizeof(vfk::BatchItem) * count,
+                        hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(R.items, (R.L.packed ? R.L.pitems : R.L.items).data(),
+                        sizeof(vfk::BatchItem) * count, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(R.order, R.ord.data(), 8ull * count, hipMemcpyHostToDevice, stream));
+  return VF_OK;
+}
+
+// Kernel attributes a launch needs (dynamic LDS above the default), set
+// ahead so that batch_enqueue makes no such call.
+static int batch_prepare_kernels(const BatchRun &R) {
+  for (int c = 0; c < 4; c++) {
+    const BatchRun::Launch &la = R.cls[c];
+    if (!la.nwg) continue;
+    vfk::BuildArgs a = R.A;
+    a.cell_bytes = kClassBytes[c];
+    a.lds_bytes = la.lds;
+    a.wmax = la.wmax;
+    HIPCHK(vfk::prepare_build(a));
+    a.lds_bytes = (vfk::kLdsBudget - 256) & ~255u;
+    a.wmax = vfk::window_slots((uint32_t)la.sigma, a.lds_bytes);
+    HIPCHK(vfk::prepare_build(a));
   }
-  if (cls_begin[1] > 0) {
-    A.list = order;
-    A.nlist = (uint32_t)cls_begin[1];
+  return VF_OK;
+}
+
+// The device work of a build: kernels only (no host wait, no allocation,
+// no memset), so it can be captured into a graph.  With check, the values
+// are checked first and a value wider than its b makes every build kernel
+// end at once (the structure is not written; batch_collect reports it).
+static int batch_enqueue(const BatchRun &R, const uint64_t *keys, const uint64_t *values,
+                         hipStream_t stream, bool check) {
+  vfk::BuildArgs A = R.A;
+  A.bkeys = keys;
+  A.bvals = values;
+  A.abort = check ? R.flag : nullptr;
+  HIPCHK(vfk::launch_fill_u32(R.flag, 1, 0, stream));
+  if (check && R.L.keys)
+    HIPCHK(vfk::launch_check_batch_values(R.citems, R.count, values, R.flag, stream));
+  HIPCHK(vfk::launch_fill_u32(R.work, vfk::kWorkWords, 0, stream));
+  if (R.cls_begin[1] > 0) {
+    A.list = R.order;
+    A.nlist = (uint32_t)R.cls_begin[1];
     A.nlist_dev = nullptr;
     A.overflow = nullptr;
-    const uint64_t want = (cls_begin[1] + vfk::kSmallWavesPerGroup - 1) / vfk::kSmallWavesPerGroup;
-    const uint64_t nwg = std::max<uint64_t>(
-        1, std::min<uint64_t>(want, (uint64_t)ncu * (tune.done ? tune.small_groups_per_cu : 8)));
-    HIPCHK(vfk::launch_small(A, (int)nwg, stream));
+    HIPCHK(vfk::launch_small(A, (int)R.small_nwg, stream));
   }
   for (int c = 0; c < 4; c++) {
-    const uint64_t c0 = cls_begin[c + 1], c1 = cls_begin[c + 2];
-    if (c1 == c0) continue;
-    int32_t sg = 0;
-    for (uint64_t i = c0; i < c1; i++) sg = std::max(sg, (int32_t)L.items[ord[2 * i]].sigma);
+    const BatchRun::Launch &la = R.cls[c];
+    if (!la.nwg) continue;
+    const uint64_t c0 = R.cls_begin[c + 1], c1 = R.cls_begin[c + 2];
     A.cell_bytes = kClassBytes[c];
-    const BuildShape shape = build_shape(sg, A.cell_bytes);
-    A.lds_bytes = shape.lds_bytes;
-    A.wmax = shape.wmax;
-    if (op.max_window) A.wmax = std::min(A.wmax, std::max(8u, op.max_window & ~7u));
-    const uint32_t per_cu = shape.per_cu;
-    A.list = order + 2 * c0;
+    A.lds_bytes = la.lds;
+    A.wmax = la.wmax;
+    A.list = R.order + 2 * c0;
     A.nlist = (uint32_t)(c1 - c0);
     A.nlist_dev = nullptr;
-    A.overflow = overflow;
-    const uint32_t nwg =
-        (uint32_t)std::min<uint64_t>(std::min<uint64_t>(L.nwg, (uint64_t)per_cu * ncu), c1 - c0);
-    HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkNext, 1, 0, stream));
-    HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkCap, 1, 0, stream));
-    HIPCHK(vfk::launch_build(A, (int)nwg, stream));
+    A.overflow = R.overflow;
+    HIPCHK(vfk::launch_fill_u32(R.work + vfk::kWorkNext, 1, 0, stream));
+    HIPCHK(vfk::launch_fill_u32(R.work + vfk::kWorkCap, 1, 0, stream));
+    HIPCHK(vfk::launch_build(A, (int)la.nwg, stream));
     // instances whose window outgrew their share of LDS, again with a
     // whole CU's LDS; the list length is read on the device (no host wait)
-    A.list = overflow;
-    A.nlist = 0;
-    A.nlist_dev = work + vfk::kWorkCap;
-    A.overflow = nullptr;
-    A.lds_bytes = (vfk::kLdsBudget - 256) & ~255u;
-    A.wmax = vfk::window_slots((uint32_t)sg, A.lds_bytes);
-    HIPCHK(vfk::launch_fill_u32(work + vfk::kWorkNext, 1, 0, stream));
-    HIPCHK(vfk::launch_build(A, (int)std::min<uint32_t>(nwg, (uint32_t)ncu), stream));
+    vfk::BuildArgs B = A;
+    B.list = R.overflow;
+    B.nlist = 0;
+    B.nlist_dev = R.work + vfk::kWorkCap;
+    B.overflow = nullptr;
+    B.lds_bytes = (vfk::kLdsBudget - 256) & ~255u;
+    B.wmax = vfk::window_slots((uint32_t)la.sigma, B.lds_bytes);
+    HIPCHK(vfk::launch_fill_u32(R.work + vfk::kWorkNext, 1, 0, stream));
+    HIPCHK(vfk::launch_build(B, (int)std::min<uint32_t>(la.nwg, (uint32_t)R.ncu), stream));
   }
-  if (L.packed)
-    HIPCHK(vfk::launch_pack_batch(citems, items, count, W + L.o_tcells, cells, stream));
-  pe.record(3, stream);
+  if (R.L.packed)
+    HIPCHK(vfk::launch_pack_batch(R.citems, R.items, R.count, R.W + R.L.o_tcells, R.cells,
+                                  A.abort, stream));
+  return VF_OK;
+}
+
+// After the stream has passed batch_enqueue's work: the value check, the
+// counters, failure record and local seeds.  Returns VF_EINVAL (failed value
+// check) or a HIP error without touching *H; otherwise fills *H and returns
+// the build's status.  take: move the descriptors into *H (the plan is not
+// used again).
+static int batch_collect(BatchRun &R, hipStream_t stream, vf_handle *H, bool take) {
   uint32_t hwork[vfk::kWorkWords];
-  HIPCHK(hipMemcpyAsync(hwork, work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
+  uint32_t hflag = 0;
+  HIPCHK(hipMemcpyAsync(hwork, R.work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(&hflag, R.flag, 4, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
-  const uint32_t nf = std::min(hwork[vfk::kWorkFails], L.fail_cap);
+  if (hflag) return VF_EINVAL;
+  const uint32_t nf = std::min(hwork[vfk::kWorkFails], R.L.fail_cap);
   std::vector<vfk::FailRec> fr(nf);
   if (nf)
-    HIPCHK(hipMemcpyAsync(fr.data(), fails, nf * sizeof(vfk::FailRec), hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(fr.data(), R.fails, nf * sizeof(vfk::FailRec), hipMemcpyDeviceToHost,
                           stream));
-  std::vector<uint8_t> ts(count);
-  HIPCHK(hipMemcpyAsync(ts.data(), tseed, count, hipMemcpyDeviceToHost, stream));
+  std::vector<uint8_t> ts(R.count);
+  HIPCHK(hipMemcpyAsync(ts.data(), R.tseed, R.count, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
-#undef HIPCHK
-
-  vf_handle *H = new (std::nothrow) vf_handle();
-  if (!H) return VF_ENOMEM;
+  BatchLayout &L = R.L;
   H->magic = kMagic;
   H->kind = 1;
   H->packed = L.packed ? 1u : 0u;
   H->is_filter = 0;
   H->b = 0;
   H->h = 0;
-  H->S = (uint32_t)count;
+  H->S = (uint32_t)R.count;
   H->g = Geometry{L.maxM, 0, 0, L.maxl, L.maxsigma, L.maxV};
   H->n = L.keys;
-  H->seed = seed;
   H->cell_bytes = 0;
-  H->G = A.G;
-  H->cells = cells;
-  H->tseed = tseed;
-  H->ncu = ncu;
+  H->G = R.A.G;
+  H->cells = R.cells;
+  H->tseed = R.tseed;
+  H->ncu = R.ncu;
   H->n_fail_total = hwork[vfk::kWorkFails];
   H->relaunched = hwork[vfk::kWorkRelaunch];
-  H->ms[0] = pe.between(0, 1);
-  H->ms[1] = 0.f;
-  H->ms[2] = pe.between(2, 3);
+  H->fails.clear();
   for (const auto &f : fr) H->fails.push_back(vf_failure{f.shard, f.attempt, f.kind, f.core_edges});
   std::sort(H->fails.begin(), H->fails.end(), [](const vf_failure &a, const vf_failure &c) {
     return a.shard != c.shard ? a.shard < c.shard : a.attempt < c.attempt;
   });
   H->failed_shards = (uint32_t)std::count(ts.begin(), ts.end(), (uint8_t)255);
-  H->count = count;
-  H->items = std::move(L.packed ? L.pitems : L.items);
+  H->count = R.count;
+  std::vector<vfk::BatchItem> &src = L.packed ? L.pitems : L.items;
+  if (take)
+    H->items = std::move(src);
+  else
+    H->items = src;
   H->seeds = std::move(ts);
-  H->items_dev = items;
-  *handle = H;
+  H->items_dev = R.items;
   if (hwork[vfk::kWorkStatus] & vfk::kStatusStalled) {
     snprintf(g_last_error, sizeof(g_last_error), "a build workgroup gave up on a wait");
     return VF_EHIP;
@@ -1299,6 +1280,149 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
   return VF_OK;
 }
 
+// Tuning (see vf_batch_tuning): for each size class with enough small
+// instances of one-byte cells, the sampled instances are built by both
+// kernels (the same cells either way) and timed; the faster builds the
+// class from now on, on this device; the grid of the one-wavefront kernel
+// is tuned on the largest sample.  Leaves counters and cells to be
+// rebuilt.
+static int batch_tune(BatchRun &R, const uint64_t *keys, const uint64_t *values,
+                      hipStream_t stream) {
+  const BatchLayout &L = R.L;
+  BatchTuning nt;
+  uint32_t *const tl = (uint32_t *)(R.W + L.o_tune);
+  PhaseEvents te;
+  int biggest = -1;
+  uint32_t biggest_n = 0;
+  std::vector<uint32_t> lists[4];
+  for (uint64_t i = 0; i < R.count; i++) {
+    const vfk::BatchItem &it = L.items[i];
+    const int sc = size_class(it.n);
+    if (sc >= 0 && it.cell_bytes == 1 && vfk::small_instance(it.n, it.V) &&
+        lists[sc].size() < 2 * kTuneSample) {
+      lists[sc].push_back((uint32_t)i);
+      lists[sc].push_back(0);
+    }
+  }
+  vfk::BuildArgs T = R.A;
+  T.bkeys = keys;
+  T.bvals = values;
+  T.abort = nullptr;
+  T.nlist_dev = nullptr;
+  T.overflow = R.overflow;
+  T.cell_bytes = 1;
+  T.list = tl;
+  HIPCHK(vfk::launch_fill_u32(R.work, vfk::kWorkWords, 0, stream));
+  bool any = false;
+  for (int sc = 0; sc < 4; sc++) {
+    const uint32_t ns = (uint32_t)(lists[sc].size() / 2);
+    nt.sampled[sc] = ns;
+    if (ns < 256) continue;
+    any = true;
+    HIPCHK(hipMemcpyAsync(tl, lists[sc].data(), 8ull * ns, hipMemcpyHostToDevice, stream));
+    T.nlist = ns;
+    const uint64_t snwg = std::max<uint64_t>(1, std::min<uint64_t>(
+        (ns + vfk::kSmallWavesPerGroup - 1) / vfk::kSmallWavesPerGroup,
+        (uint64_t)R.ncu * nt.small_groups_per_cu));
+    te.record(0, stream);
+    HIPCHK(vfk::launch_small(T, (int)snwg, stream));
+    te.record(1, stream);
+    HIPCHK(hipStreamSynchronize(stream));
+    nt.ms_small[sc] = te.between(0, 1);
+    int32_t sg = 0;
+    for (uint32_t k = 0; k < ns; k++) sg = std::max(sg, (int32_t)L.items[lists[sc][2 * k]].sigma);
+    const BuildShape shape = build_shape(sg, 1);
+    T.lds_bytes = shape.lds_bytes;
+    T.wmax = shape.wmax;
+    HIPCHK(vfk::launch_fill_u32(R.work + vfk::kWorkNext, 1, 0, stream));
+    te.record(2, stream);
+    HIPCHK(vfk::launch_build(T, (int)std::min<uint64_t>(ns, (uint64_t)shape.per_cu * R.ncu),
+                             stream));
+    te.record(3, stream);
+    HIPCHK(hipStreamSynchronize(stream));
+    nt.ms_band[sc] = te.between(2, 3);
+    nt.use_small[sc] = nt.ms_small[sc] >= 0 && nt.ms_small[sc] <= nt.ms_band[sc];
+    if (ns > biggest_n) {
+      biggest_n = ns;
+      biggest = sc;
+    }
+  }
+  if (!any) return VF_OK;
+  // the grid of the one-wavefront kernel, on the largest sample
+  HIPCHK(hipMemcpyAsync(tl, lists[biggest].data(), 8ull * biggest_n, hipMemcpyHostToDevice,
+                        stream));
+  T.nlist = biggest_n;
+  float best = -1.f;
+  for (uint32_t per_cu : {2u, 4u, 8u, 16u}) {
+    const uint64_t nwg = std::max<uint64_t>(1, std::min<uint64_t>(
+        (biggest_n + vfk::kSmallWavesPerGroup - 1) / vfk::kSmallWavesPerGroup,
+        (uint64_t)R.ncu * per_cu));
+    te.record(0, stream);
+    HIPCHK(vfk::launch_small(T, (int)nwg, stream));
+    te.record(1, stream);
+    HIPCHK(hipStreamSynchronize(stream));
+    const float ms = te.between(0, 1);
+    if (best < 0 || ms < best) {
+      best = ms;
+      nt.small_groups_per_cu = per_cu;
+    }
+  }
+  nt.done = true;
+  set_batch_tuning(nt);
+  R.tune = nt;
+  batch_lists(R);
+  HIPCHK(hipMemcpyAsync(R.order, R.ord.data(), 8ull * R.count, hipMemcpyHostToDevice, stream));
+  return VF_OK;
+}
+
+static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
+                       const uint64_t *n, const int32_t *b, uint64_t seed, const vf_opts *o,
+                       void *ws, uint64_t ws_bytes, void *st, uint64_t st_bytes,
+                       hipStream_t stream, vf_handle **handle) {
+  if (!handle) return VF_EINVAL;
+  BatchRun R;
+  int rc = batch_setup(R, count, n, b, seed, o, ws, ws_bytes, st, st_bytes);
+  if (rc) return rc;
+  if (R.L.keys && (!keys || !values)) return VF_EINVAL;
+  PhaseEvents pe;
+  pe.record(0, stream);
+  rc = batch_upload(R, stream);
+  if (rc) return rc;
+  pe.record(1, stream);
+  // Problem 1 stores b-bit values: a value with a higher bit fails the
+  // call before the structure is written
+  if (R.L.keys) {
+    uint32_t hflag = 0;
+    HIPCHK(vfk::launch_fill_u32(R.flag, 1, 0, stream));
+    HIPCHK(vfk::launch_check_batch_values(R.citems, count, values, R.flag, stream));
+    HIPCHK(hipMemcpyAsync(&hflag, R.flag, 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (hflag) return VF_EINVAL;
+  }
+  if (!R.tune.done && R.op.small == 0) {
+    rc = batch_tune(R, keys, values, stream);
+    if (rc) return rc;
+  }
+  pe.record(2, stream);
+  rc = batch_enqueue(R, keys, values, stream, false);
+  if (rc) return rc;
+  pe.record(3, stream);
+  vf_handle *H = new (std::nothrow) vf_handle();
+  if (!H) return VF_ENOMEM;
+  H->seed = seed;
+  rc = batch_collect(R, stream, H, true);
+  if (H->magic != kMagic) {  // nothing was built
+    delete H;
+    return rc;
+  }
+  H->ms[0] = pe.between(0, 1);
+  H->ms[1] = 0.f;
+  H->ms[2] = pe.between(2, 3);
+  *handle = H;
+  return rc;
+}
+#undef HIPCHK
+
 int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
                    const uint64_t *n, const int32_t *b, uint64_t seed, const vf_opts *o,
                    void *ws, uint64_t ws_bytes, void *st, uint64_t st_bytes,
@@ -1306,6 +1430,48 @@ int vf_batch_build(const uint64_t *keys, const uint64_t *values, uint64_t count,
   return guarded([&] {
     return batch_build(keys, values, count, n, b, seed, o, ws, ws_bytes, st, st_bytes, stream,
                        handle);
+  });
+}
+
+int vf_batch_prepare(uint64_t count, const uint64_t *n, const int32_t *b, uint64_t seed,
+                     const vf_opts *o, void *ws, uint64_t ws_bytes, void *st, uint64_t st_bytes,
+                     hipStream_t stream, vf_handle **handle) {
+  return guarded([&]() -> int {
+    if (!handle) return VF_EINVAL;
+    auto R = std::make_shared<BatchRun>();
+    int rc = batch_setup(*R, count, n, b, seed, o, ws, ws_bytes, st, st_bytes);
+    if (rc) return rc;
+    rc = batch_prepare_kernels(*R);
+    if (rc) return rc;
+    rc = batch_upload(*R, stream);
+    if (rc) return rc;
+    if (hipStreamSynchronize(stream) != hipSuccess) return VF_EHIP;
+    vf_handle *H = new (std::nothrow) vf_handle();
+    if (!H) return VF_ENOMEM;
+    H->magic = kMagic;
+    H->kind = 2;
+    H->seed = seed;
+    H->count = count;
+    H->run = std::move(R);
+    *handle = H;
+    return VF_OK;
+  });
+}
+
+int vf_batch_launch(vf_handle *h, const uint64_t *keys, const uint64_t *values,
+                    hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!h || h->magic != kMagic || !h->run) return VF_EINVAL;
+    const BatchRun &R = *h->run;
+    if (R.L.keys && (!keys || !values)) return VF_EINVAL;
+    return batch_enqueue(R, keys, values, stream, true);
+  });
+}
+
+int vf_batch_finish(vf_handle *h, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!h || h->magic != kMagic || !h->run) return VF_EINVAL;
+    return batch_collect(*h->run, stream, h, false);
   });
 }
 

@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "vf_launch.h"
@@ -1650,6 +1651,7 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
 template <typename T, int QM>
 __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   extern __shared__ __align__(16) uint8_t lds[];
+  if (A.abort && *A.abort) return;  // same value for every thread
   const uint32_t lane = lane_id();
   const uint32_t wid = uniform(threadIdx.x >> 6);  // one value per wavefront
   uint8_t *const wbase = A.scratch + (uint64_t)blockIdx.x * A.scratch_stride;
@@ -2196,6 +2198,7 @@ __global__ void __launch_bounds__(64 * kSmallWaves) k_small(BuildArgs A) {
   uint32_t (*const prow)[8] = prow_all[wv];
   uint64_t *const prhs = prhs_all[wv];
   uint16_t *const pcol = pcol_all[wv];
+  if (A.abort && *A.abort) return;
   const uint32_t nlist = A.nlist_dev ? *A.nlist_dev : A.nlist;
   for (uint32_t w = blockIdx.x * kSmallWaves + wv; w < nlist; w += gridDim.x * kSmallWaves) {
     const uint32_t q = A.list[2 * w], t0 = A.list[2 * w + 1];
@@ -2498,7 +2501,9 @@ __global__ void __launch_bounds__(256) k_pack(const T *__restrict__ in, uint64_t
 __global__ void __launch_bounds__(256) k_pack_batch(const BatchItem *__restrict__ src,
                                                     const BatchItem *__restrict__ dst,
                                                     uint64_t count, const uint8_t *__restrict__ in,
-                                                    uint8_t *__restrict__ out) {
+                                                    uint8_t *__restrict__ out,
+                                                    const uint32_t *__restrict__ abort) {
+  if (abort && *abort) return;
   for (uint64_t it = blockIdx.x; it < count; it += gridDim.x) {
     const BatchItem I = src[it];
     uint64_t *const o = (uint64_t *)(out + dst[it].cell_off);
@@ -2798,11 +2803,12 @@ hipError_t launch_pack(const void *in, uint32_t cell_bytes, uint64_t count, uint
 }
 
 hipError_t launch_pack_batch(const BatchItem *src, const BatchItem *dst, uint64_t count,
-                             const uint8_t *in, uint8_t *out, hipStream_t s) {
+                             const uint8_t *in, uint8_t *out, const uint32_t *abort,
+                             hipStream_t s) {
   if (!count) return hipSuccess;
   const uint64_t blocks = count < 65536 ? count : 65536;
   hipLaunchKernelGGL(k_pack_batch, dim3((uint32_t)blocks), dim3(256), 0, s, src, dst, count, in,
-                     out);
+                     out, abort);
   return hipGetLastError();
 }
 
@@ -2866,10 +2872,29 @@ hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n
 }
 
 template <typename T, int QM>
+static hipError_t set_build_lds(uint32_t lds_bytes) {
+  // largest dynamic LDS set so far, per device: a launch within it makes no
+  // attribute call (none is made while a stream is being captured then)
+  constexpr int kDevs = 64;
+  static std::atomic<uint32_t> done[kDevs];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  const bool cached = dev >= 0 && dev < kDevs;
+  if (cached && done[dev].load(std::memory_order_relaxed) >= lds_bytes) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute((const void *)k_build<T, QM>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_bytes);
+  if (e == hipSuccess && cached) {
+    uint32_t cur = done[dev].load(std::memory_order_relaxed);
+    while (cur < lds_bytes && !done[dev].compare_exchange_weak(cur, lds_bytes)) {
+    }
+  }
+  return e;
+}
+
+template <typename T, int QM>
 static hipError_t launch_build_q(const BuildArgs &a, int nwg, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_build<T, QM>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)a.lds_bytes);
+  const hipError_t e = set_build_lds<T, QM>(a.lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_build<T, QM>), dim3(nwg), dim3(kBuildThreads), a.lds_bytes, s, a);
   return hipGetLastError();
@@ -2887,9 +2912,7 @@ static hipError_t launch_build_t(const BuildArgs &a, int nwg, hipStream_t s) {
 template <typename T, int QM>
 static int build_occ_q(uint32_t lds_bytes) {
   int nb = 0;
-  if (hipFuncSetAttribute((const void *)k_build<T, QM>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds_bytes) != hipSuccess ||
+  if (set_build_lds<T, QM>(lds_bytes) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_build<T, QM>,
                                                   (int)kBuildThreads, lds_bytes) != hipSuccess)
     return 0;
@@ -2909,6 +2932,22 @@ int build_blocks_per_cu(uint32_t cell_bytes, uint32_t wmax, uint32_t lds_bytes) 
     case 2: return build_occ_t<uint16_t>(wmax, lds_bytes);
     case 4: return build_occ_t<uint32_t>(wmax, lds_bytes);
     default: return build_occ_t<uint64_t>(wmax, lds_bytes);
+  }
+}
+
+template <typename T>
+static hipError_t prepare_build_t(const BuildArgs &a) {
+  return a.wmax <= 256   ? set_build_lds<T, 4>(a.lds_bytes)
+         : a.wmax <= 384 ? set_build_lds<T, 6>(a.lds_bytes)
+                         : set_build_lds<T, 8>(a.lds_bytes);
+}
+
+hipError_t prepare_build(const BuildArgs &a) {
+  switch (a.cell_bytes) {
+    case 1: return prepare_build_t<uint8_t>(a);
+    case 2: return prepare_build_t<uint16_t>(a);
+    case 4: return prepare_build_t<uint32_t>(a);
+    default: return prepare_build_t<uint64_t>(a);
   }
 }
 

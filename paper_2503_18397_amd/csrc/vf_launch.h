@@ -89,6 +89,9 @@ struct BuildArgs {
   // Largest cells and segment count over all items (scratch layout).
   uint64_t scr_V;
   uint32_t scr_l;
+  // If set and nonzero when the kernel starts (a failed value check earlier
+  // on the stream), the kernel returns without writing anything.
+  const uint32_t *abort;
 };
 
 constexpr uint32_t kLdsBudget = 160 * 1024;  // LDS of one CU
@@ -110,7 +113,8 @@ hipError_t launch_pack(const void *in, uint32_t cell_bytes, uint64_t count, uint
                        uint64_t *out, hipStream_t s);
 // The same per instance of a batch: src offsets into in, dst into out.
 hipError_t launch_pack_batch(const BatchItem *src, const BatchItem *dst, uint64_t count,
-                             const uint8_t *in, uint8_t *out, hipStream_t s);
+                             const uint8_t *in, uint8_t *out, const uint32_t *abort,
+                             hipStream_t s);
 // Sets bit 0 of *flag if a value has a bit at or above b (per instance for a
 // batch); the flag must be cleared beforehand.
 hipError_t launch_check_values(const uint64_t *vals, uint64_t n, uint32_t b, uint32_t *flag,
@@ -136,6 +140,9 @@ bool small_instance(uint64_t n, uint64_t V);
 // The one-wavefront build of the (instance, first local seed) pairs of
 // a.list (a.items, a.cells, a.tseed, a.fails, a.work as for launch_build).
 hipError_t launch_small(const BuildArgs &a, int nwg, hipStream_t s);
+// Sets the kernel attributes launch_build needs for a's shape on the
+// current device (launch_build sets them too when they are missing).
+hipError_t prepare_build(const BuildArgs &a);
 // The allocation-free grouped query's workspace: a device array of
 // kNoAllocScratchBytes per device; *ptr receives its address on the current
 // device (looked up once per device).

@@ -1138,14 +1138,16 @@ static int batch_setup(BatchRun &R, uint64_t count, const uint64_t *n, const int
     if (e_ != hipSuccess) return hip_failed(e_, __LINE__); \
   } while (0)
 
-// Descriptors into the structure and the workspace, launch lists.
-static int batch_upload(const BatchRun &R, hipStream_t stream) {
+// Descriptors and launch lists into the workspace; with structure, the
+// descriptors queries read into the structure as well.
+static int batch_upload(const BatchRun &R, hipStream_t stream, bool structure) {
   const uint64_t count = R.count;
   HIPCHK(hipMemcpyAsync(R.citems, R.L.items.data(), sizeof(vfk::BatchItem) * count,
                         hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(R.items, (R.L.packed ? R.L.pitems : R.L.items).data(),
-                        sizeof(vfk::BatchItem) * count, hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(R.order, R.ord.data(), 8ull * count, hipMemcpyHostToDevice, stream));
+  if (structure)
+    HIPCHK(hipMemcpyAsync(R.items, (R.L.packed ? R.L.pitems : R.L.items).data(),
+                          sizeof(vfk::BatchItem) * count, hipMemcpyHostToDevice, stream));
   return VF_OK;
 }
 
@@ -1386,9 +1388,8 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
   if (R.L.keys && (!keys || !values)) return VF_EINVAL;
   PhaseEvents pe;
   pe.record(0, stream);
-  rc = batch_upload(R, stream);
+  rc = batch_upload(R, stream, false);
   if (rc) return rc;
-  pe.record(1, stream);
   // Problem 1 stores b-bit values: a value with a higher bit fails the
   // call before the structure is written
   if (R.L.keys) {
@@ -1399,6 +1400,9 @@ static int batch_build(const uint64_t *keys, const uint64_t *values, uint64_t co
     HIPCHK(hipStreamSynchronize(stream));
     if (hflag) return VF_EINVAL;
   }
+  HIPCHK(hipMemcpyAsync(R.items, (R.L.packed ? R.L.pitems : R.L.items).data(),
+                        sizeof(vfk::BatchItem) * count, hipMemcpyHostToDevice, stream));
+  pe.record(1, stream);
   if (!R.tune.done && R.op.small == 0) {
     rc = batch_tune(R, keys, values, stream);
     if (rc) return rc;
@@ -1443,7 +1447,7 @@ int vf_batch_prepare(uint64_t count, const uint64_t *n, const int32_t *b, uint64
     if (rc) return rc;
     rc = batch_prepare_kernels(*R);
     if (rc) return rc;
-    rc = batch_upload(*R, stream);
+    rc = batch_upload(*R, stream, true);
     if (rc) return rc;
     if (hipStreamSynchronize(stream) != hipSuccess) return VF_EHIP;
     vf_handle *H = new (std::nothrow) vf_handle();

@@ -166,7 +166,9 @@ def serve_measure(args, builds: int, queries: int) -> dict:
     1:1) and query batches (1..10^6 keys, 90% members) arriving as Poisson
     streams, served with --slots slots and again one request at a time; the
     same trace both times, structures resident in HBM (200 GB budget); then
-    the whole trace submitted at once (saturated) both ways."""
+    the whole trace submitted at once (saturated) both ways.  The served runs
+    merge waiting query batches into combined launches (vf_query_multi); one
+    request at a time does not."""
     import torch
     import synthetic as S
     from paper_2503_18397_amd.serve import Request, Server, poisson_trace
@@ -186,8 +188,8 @@ def serve_measure(args, builds: int, queries: int) -> dict:
     print(f"[bench] serve: {builds} builds, {queries} query batches",
           file=sys.stderr, flush=True)
 
-    def serve(slots, paced=True):
-        srv = Server(slots=slots)
+    def serve(slots, paced=True, coalesce=16):
+        srv = Server(slots=slots, coalesce=coalesce)
         t0 = time.perf_counter()
         for j, e in enumerate(ev):
             while paced and time.perf_counter() - t0 < e["t"]:
@@ -199,17 +201,19 @@ def serve_measure(args, builds: int, queries: int) -> dict:
                 srv.submit(Request(e["id"], e["kind"], k, v, b=e["b"], eps=args.eps))
         st = srv.drain(timeout=600)
         srv.close()
-        return st.summary()
+        out = st.summary()
+        out["merged_query_launches"] = srv.merged_launches
+        return out
 
     serve(args.slots)  # warm-up (allocator, kernels)
     mixed = serve(args.slots)
     print(f"[bench] served: {mixed}", file=sys.stderr, flush=True)
-    one = serve(1)
+    one = serve(1, coalesce=1)
     print(f"[bench] one at a time: {one}", file=sys.stderr, flush=True)
     # saturated: the whole trace at once, so the device and not the
     # arrivals bounds the throughput
     sat = serve(args.slots, paced=False)
-    sat1 = serve(1, paced=False)
+    sat1 = serve(1, paced=False, coalesce=1)
     print(f"[bench] saturated: {sat} / one at a time {sat1}", file=sys.stderr, flush=True)
 
     def kps(x):

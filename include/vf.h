@@ -204,6 +204,28 @@ int vfilter_build_host(const uint64_t *keys, uint64_t n, int32_t b, double eps,
                        void *structure, uint64_t structure_bytes,
                        hipStream_t stream, vf_handle **handle);
 
+/* One request of vf_query_multi: n keys (device) asked of structure h, the
+ * answers written to out (device) exactly as vf_query (a function) or
+ * vfilter_contains (a filter) would write them. */
+typedef struct vf_query_req {
+  const vf_handle *h;
+  const uint64_t *keys;
+  uint64_t n;
+  void *out;
+} vf_query_req;
+
+/* Answers count query requests, each against its own structure (functions
+ * and filters of any geometry, byte or packed cells, not batches), with one
+ * kernel launch per VF_QUERY_MULTI_MAX requests: the per-key work of
+ * vf_query and vfilter_contains (eq. (MWHC) per shard, sections 3 and 4.5)
+ * over the concatenation of the requests' keys, without copying them.
+ * Serving loops merge concurrent small query batches this way.  reqs is a
+ * host array; no allocation, no wait, no copy from the host (the requests
+ * travel as kernel arguments).  Errors: VF_EINVAL (reqs NULL with count >
+ * 0, a NULL or batch handle, NULL keys or out with n > 0), VF_EHIP. */
+#define VF_QUERY_MULTI_MAX 16
+int vf_query_multi(const vf_query_req *reqs, uint32_t count, hipStream_t stream);
+
 /* Filter query: out[i] = 1 if keys[i] may be in the set, 0 if it is not
  * (sections 3.1 and 4.5).  out is n bytes of device memory.
  * Errors: VF_EINVAL (null handle/pointers, or a function handle). */

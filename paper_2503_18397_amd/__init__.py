@@ -120,6 +120,7 @@ _lib.vf_batch_prepare.argtypes = [_u64, _vp, _vp, _u64, C.POINTER(Opts), _vp, _u
                                   _vp, C.POINTER(_vp)]
 _lib.vf_batch_launch.argtypes = [_vp, _vp, _vp, _vp]
 _lib.vf_batch_finish.argtypes = [_vp, _vp]
+_lib.vf_query_multi.argtypes = [_vp, C.c_uint32, _vp]
 _lib.vf_batch_query.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp]
 _lib.vf_batch_item.argtypes = [_vp, _u64, C.POINTER(BatchItem)]
 _lib.vf_batch_tuning.argtypes = [C.POINTER(Tuning)]
@@ -129,7 +130,7 @@ for _f in ("vf_plan", "vf_build", "vfilter_build", "vf_query", "vfilter_contains
            "vf_failures", "vf_batch_plan", "vf_batch_build", "vf_batch_query", "vf_batch_item",
            "vfilter_build_host", "vf_query_grouped_bytes", "vf_query_grouped",
            "vfilter_contains_grouped", "vfilter_contains_grouped_noalloc", "vf_batch_tuning",
-           "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish"):
+           "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish", "vf_query_multi"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build",
@@ -137,7 +138,7 @@ EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build"
            "vf_batch_build", "vf_batch_query", "vf_batch_item", "vfilter_build_host",
            "vf_query_grouped_bytes", "vf_query_grouped", "vfilter_contains_grouped",
            "vfilter_contains_grouped_noalloc", "vf_batch_tuning", "vf_last_error",
-           "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish")
+           "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish", "vf_query_multi")
 
 
 def _check(rc: int, where: str) -> None:
@@ -238,6 +239,40 @@ def vf_query(handle, keys, out, stream=None) -> None:
 def vfilter_contains(handle, keys, out, stream=None) -> None:
     _check(_lib.vfilter_contains(handle, _dev_ptr(keys, "keys"), keys.numel(),
                                  _dev_ptr(out, "out"), _stream(stream)), "vfilter_contains")
+
+
+class QueryReq(C.Structure):
+    _fields_ = [("h", C.c_void_p), ("keys", C.c_void_p), ("n", C.c_uint64), ("out", C.c_void_p)]
+
+
+VF_QUERY_MULTI_MAX = 16
+
+
+def vf_query_multi(reqs, stream=None) -> None:
+    """reqs: (handle, keys, out) triples; one launch per 16 requests."""
+    arr = (QueryReq * max(1, len(reqs)))()
+    for i, (h, keys, out) in enumerate(reqs):
+        arr[i].h = h.value if isinstance(h, C.c_void_p) else h
+        arr[i].keys = _dev_ptr(keys, "keys")
+        arr[i].n = keys.numel()
+        arr[i].out = _dev_ptr(out, "out")
+    _check(_lib.vf_query_multi(arr, len(reqs), _stream(stream)), "vf_query_multi")
+
+
+def query_many(pairs, stream=None) -> list:
+    """Answers [(structure, keys), ...] with combined launches (vf_query_multi);
+    returns the answer tensors, typed as Structure.query returns them."""
+    outs, reqs = [], []
+    with _on(stream):
+        for st, keys in pairs:
+            dt = torch.uint8 if st.is_filter else _CELL_DTYPE[st.info["cell_bytes"]]
+            out = torch.empty(keys.numel(), dtype=dt, device=keys.device)
+            outs.append(out)
+            reqs.append((st.handle, keys, out))
+        vf_query_multi(reqs, stream)
+    for (st, keys), out in zip(pairs, outs):
+        _used_on(stream, keys, out)
+    return outs
 
 
 def vf_query_grouped_bytes(handle, n: int) -> int:

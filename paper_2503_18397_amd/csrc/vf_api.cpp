@@ -849,6 +849,43 @@ int vfilter_contains(const vf_handle *h, const uint64_t *keys, uint64_t n, uint8
   return query_common(h, keys, n, out, stream, 1);
 }
 
+static_assert(VF_QUERY_MULTI_MAX == vfk::kMultiMax, "combined query width");
+
+int vf_query_multi(const vf_query_req *reqs, uint32_t count, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (count && !reqs) return VF_EINVAL;
+    int ncu = 0;
+    for (uint32_t r = 0; r < count; r++) {
+      const vf_handle *h = reqs[r].h;
+      if (!h || h->magic != kMagic || h->kind != 0) return VF_EINVAL;
+      if (reqs[r].n && (!reqs[r].keys || !reqs[r].out)) return VF_EINVAL;
+      ncu = std::max(ncu, h->ncu);
+    }
+    for (uint32_t r0 = 0; r0 < count; r0 += vfk::kMultiMax) {
+      vfk::MultiArgs a{};
+      a.count = std::min<uint32_t>(vfk::kMultiMax, count - r0);
+      a.start[0] = 0;
+      for (uint32_t i = 0; i < a.count; i++) {
+        const vf_query_req &q = reqs[r0 + i];
+        const vf_handle *h = q.h;
+        vfk::MultiReq &m = a.req[i];
+        m.G = h->G;
+        m.cells = h->cells;
+        m.tseed = h->tseed;
+        m.keys = q.keys;
+        m.out = q.out;
+        m.cell_bytes = h->cell_bytes;
+        m.packed = h->packed;
+        a.start[i + 1] = a.start[i] + q.n;
+      }
+      for (uint32_t i = a.count; i < vfk::kMultiMax; i++) a.start[i + 1] = a.start[a.count];
+      const hipError_t e = vfk::launch_query_multi(a, ncu, stream);
+      if (e != hipSuccess) return hip_failed(e, __LINE__);
+    }
+    return VF_OK;
+  });
+}
+
 // Grouped queries: workspace = shard totals, per-segment histograms and
 // run starts, shard offsets and cursors, then for one chunk the keys grouped
 // by shard, their indices and their answers in grouped order.

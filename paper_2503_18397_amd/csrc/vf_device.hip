@@ -2960,6 +2960,73 @@ hipError_t launch_build(const BuildArgs &a, int nwg, hipStream_t s) {
   }
 }
 
+// Query requests against several structures (functions and filters of any
+// geometry, byte or packed cells) in one launch: a thread finds the request
+// of its combined index by binary search over the request starts.
+__global__ void __launch_bounds__(256) k_query_multi(MultiArgs A) {
+  const uint64_t total = A.start[A.count];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total; i += stride) {
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t step = kMultiMax / 2; step; step >>= 1)
+      if (r + step < A.count && A.start[r + step] <= i) r += step;
+    const MultiReq &q = A.req[r];
+    const uint64_t o = i - A.start[r];
+    const uint64_t key = q.keys[o];
+    const uint64_t hi = fin64(key ^ q.G.khi), lo = fin64(key ^ q.G.klo);
+    const uint32_t j = shard_of(hi, q.G.h);
+    uint32_t v0, v1, v2;
+    edge3(q.G, hi, lo, q.tseed[j], v0, v1, v2);
+    const uint64_t base = (uint64_t)j * q.G.V;
+    uint64_t x;
+    if (q.packed) {
+      const uint64_t *w = (const uint64_t *)q.cells;
+      x = packed_get(w, base + v0, q.G.b) ^ packed_get(w, base + v1, q.G.b) ^
+          packed_get(w, base + v2, q.G.b);
+    } else {
+      switch (q.cell_bytes) {
+        case 1: {
+          const uint8_t *w = (const uint8_t *)q.cells + base;
+          x = w[v0] ^ w[v1] ^ w[v2];
+        } break;
+        case 2: {
+          const uint16_t *w = (const uint16_t *)q.cells + base;
+          x = w[v0] ^ w[v1] ^ w[v2];
+        } break;
+        case 4: {
+          const uint32_t *w = (const uint32_t *)q.cells + base;
+          x = w[v0] ^ w[v1] ^ w[v2];
+        } break;
+        default: {
+          const uint64_t *w = (const uint64_t *)q.cells + base;
+          x = w[v0] ^ w[v1] ^ w[v2];
+        } break;
+      }
+    }
+    if (q.G.is_filter) {
+      ((uint8_t *)q.out)[o] = x == fingerprint(q.G, hi, lo);
+    } else {
+      switch (q.cell_bytes) {
+        case 1: ((uint8_t *)q.out)[o] = (uint8_t)x; break;
+        case 2: ((uint16_t *)q.out)[o] = (uint16_t)x; break;
+        case 4: ((uint32_t *)q.out)[o] = (uint32_t)x; break;
+        default: ((uint64_t *)q.out)[o] = x; break;
+      }
+    }
+  }
+}
+
+hipError_t launch_query_multi(const MultiArgs &a, int ncu, hipStream_t s) {
+  const uint64_t total = a.start[a.count];
+  if (!total) return hipSuccess;
+  uint64_t blocks = (total + 255) / 256;
+  const uint64_t cap = (uint64_t)ncu * 8;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL(k_query_multi, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_query_batch(const Geo &G, const BatchItem *items, uint64_t count,
                               const uint8_t *cells, const uint8_t *tseed, const uint32_t *inst,
                               const uint64_t *keys, uint64_t n, uint64_t *out, int ncu,

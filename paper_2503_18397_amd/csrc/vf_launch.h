@@ -152,6 +152,24 @@ hipError_t noalloc_scratch(void **ptr, uint64_t *bytes);
 // Build workgroups that can be resident on one CU at once (registers and
 // LDS); 0 if the runtime cannot tell.
 int build_blocks_per_cu(uint32_t cell_bytes, uint32_t wmax, uint32_t lds_bytes);
+// Requests of one combined query launch: request r answers the keys of
+// combined indices [start[r], start[r + 1]) against its own structure.
+struct MultiReq {
+  Geo G;
+  const void *cells;
+  const uint8_t *tseed;
+  const uint64_t *keys;
+  void *out;
+  uint32_t cell_bytes;  // answer width of a function (1, 2, 4, 8)
+  uint32_t packed;      // cells are a bit string of b-bit fields
+};
+constexpr uint32_t kMultiMax = 16;  // a power of two
+struct MultiArgs {
+  uint64_t start[kMultiMax + 1];
+  MultiReq req[kMultiMax];
+  uint32_t count;
+};
+hipError_t launch_query_multi(const MultiArgs &a, int ncu, hipStream_t s);
 hipError_t launch_query_batch(const Geo &G, const BatchItem *items, uint64_t count,
                               const uint8_t *cells, const uint8_t *tseed, const uint32_t *inst,
                               const uint64_t *keys, uint64_t n, uint64_t *out, int ncu,

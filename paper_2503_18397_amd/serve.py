@@ -8,10 +8,13 @@ slots and memory free up: a build needs its workspace and structure bytes
 resident structures stays within the HBM budget.  Admission is first-fit in
 arrival order, so a large build that does not fit yet does not hold back
 smaller requests behind it; a query waits until its structure is built.
-Work admitted to different slots overlaps on the device.  Builds and
-queries are the library's (``vf_build``, ``vfilter_build``, ``vf_query``,
-``vfilter_contains``); their results are canonical, so a request gives the
-same bytes alone and in any mix.
+Work admitted to different slots overlaps on the device.  Query requests
+that wait together are merged: when a query is admitted, up to
+``coalesce`` - 1 other ready queries (any structures) join it, and the slot
+answers all of them with one combined launch (``vf_query_multi``).  Builds
+and queries are the library's (``vf_build``, ``vfilter_build``,
+``vf_query_multi``); their results are canonical, so a request gives the
+same bytes alone, merged and in any mix.
 
 The scheduling core (``Scheduler``) knows nothing about the GPU: it takes
 the footprint of a request and an executor callable, which the tests replace
@@ -79,16 +82,23 @@ class Stats:
 
 
 class Scheduler:
-    """Slots, memory admission and dependencies; ``execute(slot, request)``
-    runs a request on a slot and returns its result (called on the slot's
-    worker thread).  ``footprint(request)`` returns (bytes while running,
-    bytes that stay resident afterwards)."""
+    """Slots, memory admission and dependencies; ``execute(slot, request,
+    target)`` runs a request on a slot and returns its result (called on the
+    slot's worker thread).  ``footprint(request)`` returns (bytes while
+    running, bytes that stay resident afterwards).  With ``execute_many``
+    and ``coalesce`` > 1, queries admitted together run as one group:
+    ``execute_many(slot, requests, targets)`` returns their results in
+    order."""
 
-    def __init__(self, slots: int, budget: int, execute: Callable, footprint: Callable):
+    def __init__(self, slots: int, budget: int, execute: Callable, footprint: Callable,
+                 execute_many: Callable | None = None, coalesce: int = 1):
         if slots < 1:
             raise ValueError("at least one slot")
         self.budget = budget
         self.execute = execute
+        self.execute_many = execute_many
+        self.coalesce = max(1, int(coalesce)) if execute_many is not None else 1
+        self.groups = 0  # launches of merged query groups (two or more requests)
         self.footprint = footprint
         self.cv = threading.Condition()
         self.queue: deque = deque()
@@ -166,16 +176,37 @@ class Scheduler:
             if ok is None:
                 req.error = "cannot run (too large for the budget, or its build failed)"
                 req.done = time.perf_counter()
+                if req.kind != "query":
+                    self.failed.add(req.rid)  # its queries fail too, not wait
                 self._finish(req)
                 continue
             if not ok:
                 keep.append(req)
                 continue
             slot = self.free_slots.pop()
-            self.used += req.footprint
+            group = [req]
+            if req.kind == "query" and self.coalesce > 1:
+                # ready queries behind it (any structure) join its launch
+                rest = deque()
+                while self.queue:
+                    other = self.queue.popleft()
+                    if (len(group) < self.coalesce and other.kind == "query"
+                            and self._ready(other)
+                            and self.used + req.footprint
+                            + sum(g.footprint for g in group[1:]) + other.footprint
+                            <= self.budget):
+                        group.append(other)
+                    else:
+                        rest.append(other)
+                self.queue = rest
+            now = time.perf_counter()
+            for g in group:
+                self.used += g.footprint
+                g.admitted = now
             self.stats.peak_bytes = max(self.stats.peak_bytes, self.used)
-            req.admitted = time.perf_counter()
-            self.inbox[slot].append(req)
+            if len(group) > 1:
+                self.groups += 1
+            self.inbox[slot].append(group)
             self.cv.notify_all()
         self.queue = keep
 
@@ -193,33 +224,43 @@ class Scheduler:
                     self.cv.wait()
                 if not self.inbox[slot]:
                     return
-                req = self.inbox[slot].popleft()
-                target = self.built.get(req.target) if req.kind == "query" else None
+                group = self.inbox[slot].popleft()
+                targets = [self.built.get(r.target) if r.kind == "query" else None
+                           for r in group]
             try:
-                req.result = self.execute(slot, req, target)
+                if len(group) == 1:
+                    group[0].result = self.execute(slot, group[0], targets[0])
+                else:
+                    for r, res in zip(group, self.execute_many(slot, group, targets)):
+                        r.result = res
             except Exception as e:  # reported per request, the server goes on
-                req.error = f"{type(e).__name__}: {e}"
-            req.done = time.perf_counter()
+                for r in group:
+                    r.error = f"{type(e).__name__}: {e}"
+            done = time.perf_counter()
             with self.cv:
-                # the running footprint is released; a built structure stays
-                self.used -= req.footprint
-                if req.kind != "query":
-                    if req.error is None:
-                        self.used += req.resident
-                        self.stats.peak_bytes = max(self.stats.peak_bytes, self.used)
-                        self.built[req.rid] = req
-                    else:
-                        self.failed.add(req.rid)
+                for req in group:
+                    req.done = done
+                    # the running footprint is released; a built structure stays
+                    self.used -= req.footprint
+                    if req.kind != "query":
+                        if req.error is None:
+                            self.used += req.resident
+                            self.stats.peak_bytes = max(self.stats.peak_bytes, self.used)
+                            self.built[req.rid] = req
+                        else:
+                            self.failed.add(req.rid)
+                    self._finish(req)
                 self.free_slots.append(slot)
-                self._finish(req)
                 self._dispatch()
 
 
 class Server:
     """GPU serving loop: ``slots`` worker streams on one device, admission by
-    HBM footprint within ``budget`` bytes (structures stay resident)."""
+    HBM footprint within ``budget`` bytes (structures stay resident); up to
+    ``coalesce`` waiting queries share one combined launch."""
 
-    def __init__(self, slots: int = 4, budget: int = 200 << 30, device: str = "cuda:0"):
+    def __init__(self, slots: int = 4, budget: int = 200 << 30, device: str = "cuda:0",
+                 coalesce: int = 16):
         import torch
 
         import paper_2503_18397_amd as vf
@@ -227,7 +268,9 @@ class Server:
         self.torch = torch
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
-        self.sched = Scheduler(slots, budget, self._execute, self._footprint)
+        self.sched = Scheduler(slots, budget, self._execute, self._footprint,
+                               execute_many=self._execute_many,
+                               coalesce=min(coalesce, vf.VF_QUERY_MULTI_MAX))
 
     def _footprint(self, req: Request):
         vf = self.vf
@@ -252,6 +295,20 @@ class Server:
             if st.rc != vf.VF_OK:
                 raise vf.VFError(st.rc, "build")
             return st
+
+    def _execute_many(self, slot: int, reqs: list, targets: list) -> list:
+        torch, vf = self.torch, self.vf
+        stream = self.streams[slot]
+        with torch.cuda.stream(stream):
+            outs = vf.query_many([(t.result, r.keys) for r, t in zip(reqs, targets)],
+                                 stream=stream)
+            stream.synchronize()
+        return outs
+
+    @property
+    def merged_launches(self) -> int:
+        """Combined launches that answered two or more queries."""
+        return self.sched.groups
 
     def submit(self, req: Request) -> None:
         self.sched.submit(req)

@@ -94,3 +94,77 @@ def test_resident_structures_count_until_released():
     s.drain(timeout=5)
     s.close()
     assert sorted(done) == [0, 1, 2]
+
+
+def _coalescing_run(nq, slots, budget, coalesce):
+    calls = []
+    lock = threading.Lock()
+    live = {"mem": 0, "peak": 0}
+
+    def footprint(r):
+        return (100, 100) if r.kind != "query" else (10, 0)
+
+    def execute(slot, r, target):
+        if r.kind != "query":
+            time.sleep(0.2)  # the queries arrive meanwhile and wait for it
+            return r.rid
+        with lock:
+            calls.append([r.rid])
+        return 2 * r.rid
+
+    def execute_many(slot, rs, targets):
+        assert all(t is not None and t.rid == r.target for r, t in zip(rs, targets))
+        with lock:
+            calls.append([r.rid for r in rs])
+        return [2 * r.rid for r in rs]
+
+    s = Scheduler(slots, budget, execute, footprint, execute_many=execute_many,
+                  coalesce=coalesce)
+    s.submit(Request(0, "vfilter", _Keys(100)))
+    for i in range(1, nq + 1):
+        s.submit(Request(i, "query", _Keys(5), target=0))
+    st = s.drain(timeout=30)
+    s.close()
+    return st, calls, s.groups
+
+
+def test_waiting_queries_share_one_launch():
+    st, calls, groups = _coalescing_run(12, slots=2, budget=10 ** 6, coalesce=8)
+    assert st.summary()["errors"] == 0
+    res = {r.rid: r.result for r in st.completed}
+    assert all(res[i] == 2 * i for i in range(1, 13))
+    assert sorted(i for c in calls for i in c) == list(range(1, 13))
+    assert max(len(c) for c in calls) == 8 and groups >= 1
+    # arrival order is kept inside a group
+    assert all(c == sorted(c) for c in calls)
+
+
+def test_merged_queries_stay_within_the_budget():
+    # the build's 100 resident bytes plus at most two 10-byte queries fit
+    st, calls, _ = _coalescing_run(9, slots=3, budget=125, coalesce=8)
+    assert st.summary()["errors"] == 0
+    assert st.peak_bytes <= 125
+    assert max(len(c) for c in calls) <= 2
+    assert sorted(i for c in calls for i in c) == list(range(1, 10))
+
+
+def test_without_execute_many_queries_run_one_by_one():
+    done = []
+    s = Scheduler(1, 10 ** 6, lambda slot, r, t: done.append(r.rid), lambda r: (1, 0),
+                  coalesce=8)
+    s.submit(Request(0, "vfunc", _Keys(1)))
+    for i in range(1, 5):
+        s.submit(Request(i, "query", _Keys(1), target=0))
+    s.drain(timeout=5)
+    s.close()
+    assert sorted(done) == [0, 1, 2, 3, 4] and s.groups == 0
+
+
+def test_queries_of_a_build_too_large_for_the_budget_fail_not_wait():
+    s = Scheduler(2, 50, lambda slot, r, t: r.rid,
+                  lambda r: (100, 100) if r.kind != "query" else (1, 0))
+    s.submit(Request(0, "vfilter", _Keys(1)))
+    s.submit(Request(1, "query", _Keys(1), target=0))
+    st = s.drain(timeout=5)
+    s.close()
+    assert all(r.error is not None for r in st.completed) and len(st.completed) == 2

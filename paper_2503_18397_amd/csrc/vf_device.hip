@@ -1240,23 +1240,25 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
               ccm[g] = 0;
               orv |= ccw[g];
             }
+            // key of a row: popcount estimate (high half, below 2^16) and
+            // compact index (the low half of kcap)
+            uint32_t key[NC], kcap[NC];
+#pragma unroll
+            for (int g = 0; g < NC; g++) {
+              kcap[g] = 0xFFFF0000u | ((uint32_t)g * 64 + lane);
+              key[g] = (cpop[g] << 16) | ((uint32_t)g * 64 + lane);
+            }
             uint32_t colmask = wave_or(orv);
+            // One path through the loop body (a column whose rows all lost it
+            // finds no pivot and changes nothing), so that the loop carries
+            // its registers without copies.
             while (colmask) {
               const uint32_t b = 31 - __clz(colmask), bit = 1u << b;
-              bool has[NC];
               uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
-              for (int g = 0; g < NC; g++) {
-                has[g] = (ccw[g] & bit) != 0;
-                // popcount estimates stay below 2^16
-                const uint32_t key = (cpop[g] << 16) | ((uint32_t)g * 64 + lane);
-                best = min(best, has[g] ? key : 0xFFFFFFFFu);
-              }
+              for (int g = 0; g < NC; g++) best = min(best, (ccw[g] & bit) ? key[g] : 0xFFFFFFFFu);
               best = wave_min(best);
-              if (best == 0xFFFFFFFFu) {  // every row that held this column lost it
-                colmask &= bit - 1u;
-                continue;
-              }
+              const bool found = best != 0xFFFFFFFFu;
               const uint32_t p = best & 0xFFFFu, pg = p >> 6, pl = p & 63u;
               const uint32_t dpop = (best >> 16) - 2u;
               uint32_t pw = 0, pcm = 0, ps = 0;
@@ -1268,27 +1270,28 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
                   ps = readlane(csl[g], (int)pl);
                 }
               }
-              if (lane == k) {
-                pivtab = ps;
-                pivcol = wbase + b;
-                pivcm = pcm;
-              }
-              if (lane == pl) cpiv |= 1u << pg;
-              const uint32_t kbit = pcm | (1u << k);
+              const bool me = found && lane == k;
+              pivtab = me ? ps : pivtab;
+              pivcol = me ? wbase + b : pivcol;
+              pivcm = me ? pcm : pivcm;
+              cpiv |= found && lane == pl ? 1u << (pg & 31u) : 0u;
+              const uint32_t kbit = pcm | (1u << (k & 31u));
 #pragma unroll
               for (int g = 0; g < NC; g++) {
-                if (has[g]) {
-                  ccw[g] ^= pw;
-                  ccm[g] ^= kbit;
-                  cpop[g] = min(cpop[g] + dpop, 0xFFFFu);
-                }
+                const bool has = (ccw[g] & bit) != 0;
+                ccw[g] = has ? ccw[g] ^ pw : ccw[g];
+                ccm[g] = has ? ccm[g] ^ kbit : ccm[g];
+                const uint32_t np_ = min((key[g] >> 16) + dpop, 0xFFFFu);
+                key[g] = has ? (np_ << 16) | (kcap[g] & 0xFFFFu) : key[g];
               }
-              k++;
+              k += found ? 1u : 0u;
               // columns below b that may still have rows: the earlier ones
               // and those of the pivot word (a column whose rows all lost
               // it is skipped when visited)
               colmask = (colmask | pw) & (bit - 1u);
             }
+#pragma unroll
+            for (int g = 0; g < NC; g++) cpop[g] = key[g] >> 16;
             if (k) {
               // popcount estimates back to LDS (zero marks a pivot row, no
               // longer live in the window); padding words: zero for every

@@ -1116,7 +1116,19 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   // slot.  apply() xors the masked pivot rows (slots in lanes of ptab) into
   // row x, right side included; true if the row became zero, rset: its
   // right side is not zero.
+  const uint32_t mu_l = umul(lane), au_l = uadd(lane);  // the lane's word (NW == 1)
   auto apply = [&](uint32_t x, uint32_t cmx, uint32_t ptab, bool &rset) -> bool {
+    if (NW == 1) {
+      const bool in = lane < RW + 2;
+      uint32_t acc = 0;
+      if (in) {
+        const uint32_t xa = __umul24(x, mu_l) + au_l;
+        acc = rows[xa] ^ xor_rows(rows, ptab, cmx, mu_l, au_l);
+        rows[xa] = acc;
+      }
+      rset = __ballot(in && lane >= RW && acc != 0) != 0;
+      return __ballot(lane < RW && acc != 0) == 0;
+    }
     uint32_t any = 0, rany = 0;
     for (uint32_t w = 0; w < NW; w++) {
       const uint32_t u = w * 64 + lane;

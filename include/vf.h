@@ -421,6 +421,19 @@ int vf_batch_tuning(vf_batch_tuning_t *out);
  * i out of range, out NULL). */
 int vf_batch_item(const vf_handle *h, uint64_t i, vf_batch_item_t *out);
 
+/* Stage clocks of the shard build kernel, for profiling.  With reset != 0
+ * the counters are cleared; otherwise VF_STAGE_CLOCK_WORDS counters are
+ * copied to out (host, at least that many words): for each of the first
+ * 4096 build workgroups 32 counters of 100 MHz wall-clock ticks and counts
+ * (the peeling wavefront per item, the elimination of a 2-core, the
+ * assignment, the workgroup's first item and whole run, and per 32-column
+ * word the phases of the searching and of an emitting wavefront).  Only a
+ * library built with stage clocks keeps them (build.py --stage-clocks
+ * writes libvf_stages.so); the plain library returns VF_EINVAL.
+ * Errors: VF_EINVAL (no stage clocks, out NULL or too small), VF_EHIP. */
+#define VF_STAGE_CLOCK_WORDS (4096 * 32)
+int vf_stage_clocks(uint64_t *out, uint64_t words, int32_t reset);
+
 /* Free the host-side handle only; the caller still owns every buffer. */
 void vf_free(vf_handle *h);
 

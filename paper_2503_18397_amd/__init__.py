@@ -18,7 +18,9 @@ from dataclasses import dataclass
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvf.so")
+# VF_LIBRARY selects another build of the library (the stage-clock build
+# for profiling); the default is the in-tree libvf.so.
+LIB_PATH = os.environ.get("VF_LIBRARY") or os.path.join(_HERE, "libvf.so")
 
 VF_OK, VF_EINVAL, VF_ENOSPC, VF_EFAIL, VF_EHIP, VF_ECAPACITY, VF_ENOMEM = (
     0, -1, -2, -3, -4, -5, -6)
@@ -124,13 +126,16 @@ _lib.vf_query_multi.argtypes = [_vp, C.c_uint32, _vp]
 _lib.vf_batch_query.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp]
 _lib.vf_batch_item.argtypes = [_vp, _u64, C.POINTER(BatchItem)]
 _lib.vf_batch_tuning.argtypes = [C.POINTER(Tuning)]
+_lib.vf_stage_clocks.argtypes = [_vp, _u64, _i32]
+_lib.vf_stage_clocks.restype = C.c_int
 _lib.vf_last_error.argtypes = []
 _lib.vf_last_error.restype = C.c_char_p
 for _f in ("vf_plan", "vf_build", "vfilter_build", "vf_query", "vfilter_contains", "vf_info",
            "vf_failures", "vf_batch_plan", "vf_batch_build", "vf_batch_query", "vf_batch_item",
            "vfilter_build_host", "vf_query_grouped_bytes", "vf_query_grouped",
            "vfilter_contains_grouped", "vfilter_contains_grouped_noalloc", "vf_batch_tuning",
-           "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish", "vf_query_multi"):
+           "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish", "vf_query_multi",
+           "vf_stage_clocks"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build",
@@ -386,6 +391,21 @@ def vf_batch_item(handle, i: int) -> dict:
     it = BatchItem()
     _check(_lib.vf_batch_item(handle, i, C.byref(it)), "vf_batch_item")
     return it.as_dict()
+
+
+VF_STAGE_CLOCK_WORDS = 4096 * 32
+
+
+def vf_stage_clocks(reset: bool = False):
+    """Stage clocks of the build kernel (profiling build only): clears them
+    (reset) or returns a (4096, 32) uint64 array of counters."""
+    import numpy as np
+    if reset:
+        _check(_lib.vf_stage_clocks(None, 0, 1), "vf_stage_clocks")
+        return None
+    out = np.zeros(VF_STAGE_CLOCK_WORDS, np.uint64)
+    _check(_lib.vf_stage_clocks(out.ctypes.data, out.size, 0), "vf_stage_clocks")
+    return out.reshape(4096, 32)
 
 
 def vf_last_error() -> str:

@@ -19,15 +19,22 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-x", "hip", SRC[0], "-x", "hip", SRC[1], "-o", tmp]
+# The same library with the build kernel's stage clocks (vf_stage_clocks),
+# for profiling only.
+LIB_STAGES = os.path.join(HERE, "libvf_stages.so")
+
+
+def build(verbose: bool = False, stage_clocks: bool = False) -> str:
+    out = LIB_STAGES if stage_clocks else LIB
+    tmp = out + ".tmp%d" % os.getpid()
+    extra = ["-DVF_STAGE_CLOCKS"] if stage_clocks else []
+    cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", SRC[0], "-x", "hip", SRC[1], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, stage_clocks="--stage-clocks" in sys.argv)

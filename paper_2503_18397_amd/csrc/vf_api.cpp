@@ -1516,6 +1516,15 @@ int vf_batch_finish(vf_handle *h, hipStream_t stream) {
   });
 }
 
+static_assert(VF_STAGE_CLOCK_WORDS == vfk::kClkWGs * vfk::kClkSlots, "stage clock layout");
+
+int vf_stage_clocks(uint64_t *out, uint64_t words, int32_t reset) {
+  if (!reset && (!out || words < VF_STAGE_CLOCK_WORDS)) return VF_EINVAL;
+  const hipError_t e = vfk::stage_clocks(out, reset);
+  if (e == hipErrorNotSupported) return VF_EINVAL;
+  return e == hipSuccess ? VF_OK : hip_failed(e, __LINE__);
+}
+
 int vf_batch_tuning(vf_batch_tuning_t *out) {
   if (!out) return VF_EINVAL;
   const BatchTuning t = batch_tuning();

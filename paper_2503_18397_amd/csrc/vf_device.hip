@@ -42,7 +42,40 @@
 // for the current device (noalloc_scratch below).
 static __device__ __align__(256) uint8_t scratch[vfk::kNoAllocScratchBytes];
 
+// Stage clocks (a build with -DVF_STAGE_CLOCKS only): per build workgroup,
+// 100 MHz wall-clock ticks spent in each stage of k_build, read back by
+// vf_stage_clocks.  Slots: see kClk* in vf_launch.h.
+#ifdef VF_STAGE_CLOCKS
+static __device__ unsigned long long stage_clk[vfk::kClkWGs * vfk::kClkSlots];
+#define VF_CLK(v) const uint64_t v = wall_clock64()
+#define VF_CLKV(v) uint64_t v = wall_clock64()
+#define VF_CLK_SET(v) v = wall_clock64()
+#define VF_CLK_ADD(slot, ticks)                                                        \
+  do {                                                                                 \
+    if (lane_id() == 0 && blockIdx.x < vfk::kClkWGs)                                   \
+      atomicAdd(&stage_clk[blockIdx.x * vfk::kClkSlots + (slot)],                      \
+                (unsigned long long)(ticks));                                          \
+  } while (0)
+#else
+#define VF_CLK(v)
+#define VF_CLKV(v)
+#define VF_CLK_SET(v)
+#define VF_CLK_ADD(slot, ticks)
+#endif
+
 namespace vfk {
+
+hipError_t stage_clocks(uint64_t *out, int reset) {
+#ifdef VF_STAGE_CLOCKS
+  static const unsigned long long zero[kClkWGs * kClkSlots] = {};
+  if (reset) return hipMemcpyToSymbol(HIP_SYMBOL(stage_clk), zero, sizeof(zero));
+  return hipMemcpyFromSymbol(out, HIP_SYMBOL(stage_clk), sizeof(zero));
+#else
+  (void)out;
+  (void)reset;
+  return hipErrorNotSupported;
+#endif
+}
 
 hipError_t noalloc_scratch(void **ptr, uint64_t *bytes) {
   constexpr int kMaxDevices = 64;
@@ -1169,6 +1202,11 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
       const uint32_t wbase = c - (cpos & 31);  // column of bit 0 of this word
       const uint32_t wlo_col = max(segbot, wbase);
       const uint32_t cur = it & 1u, prev = cur ^ 1u;
+      VF_CLK(tw0);
+      VF_CLKV(tw1);
+      VF_CLKV(tw2);
+      VF_CLKV(tw3);
+      VF_CLKV(tw4);
       bool incons = false;
       if (wid == 0) {
         // slots emitted during the previous word come back (those marked
@@ -1215,6 +1253,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           else if (lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveCapacity);
         } else {
           enter(rb, re);
+          VF_CLK_SET(tw1);
           // rows of the next word of the segment, loaded ahead
           if (gsh == 5 && wlo_col != segbot) {
             const uint32_t wi2 = ((wlo_col - 1) >> 5) - g0;
@@ -1329,6 +1368,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
               }
             }
             publish();
+            VF_CLK_SET(tw3);
             // 2. whole rows, wavefront 0's share (see apply)
             if (k) {
 #pragma unroll
@@ -1406,6 +1446,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
             case 8: if constexpr (QM >= 8) nc = compact(Groups<8>{}); break;
             default: break;
           }
+          VF_CLK_SET(tw2);
           switch (uniform(nc)) {
             case 1: search(Groups<1>{}); break;
             case 2: search(Groups<2>{}); break;
@@ -1419,7 +1460,9 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           }
         }
         if (!published) publish();
+        VF_CLK_SET(tw4);
       } else {
+        VF_CLK_SET(tw1);
         if (it == 0) {
           if (lane == 0) ctl->nret[cur][em] = 0;
         } else if (!emit(prev, cur)) {
@@ -1429,6 +1472,7 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           }
         }
         // this word's batch from wavefront 0
+        VF_CLK_SET(tw2);
         const uint32_t want = it + 1;
         wait_for(pc, A.work, [&] { return lds_load(&ctl->bseq) >= want; });
         acquire_wg();
@@ -1459,9 +1503,24 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           }
           if (lane == 0) ctl->nret[cur][em] = nr;
         }
+        VF_CLK_SET(tw3);
+        VF_CLK_SET(tw4);
       }
       if (incons && lane == 0) atomicOr(&ctl->flag[cur], (uint32_t)kSolveInconsistent);
+      VF_CLK(tw5);
       psync();
+#ifdef VF_STAGE_CLOCKS
+      if (wid != 2) {
+        const uint32_t o = wid == 0 ? kClkSearch : kClkEmit;
+        VF_CLK_ADD(o + 0, tw1 - tw0);
+        VF_CLK_ADD(o + 1, tw2 - tw1);
+        VF_CLK_ADD(o + 2, tw3 - tw2);
+        VF_CLK_ADD(o + 3, tw4 - tw3);
+        VF_CLK_ADD(o + 4, tw5 - tw4);
+        VF_CLK_ADD(o + 5, wall_clock64() - tw5);
+        VF_CLK_ADD(o + 6, 1);
+      }
+#endif
       it++;
       if (uniform(ctl->flag[cur])) {
         stop = true;
@@ -1993,6 +2052,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
 
   // the workgroup's first item, peeled by all five wavefronts into record 0
   bool exhausted;
+  VF_CLK(ck0);
   {
     auto bar = [] { __syncthreads(); };
     if (threadIdx.x == 0) {
@@ -2011,6 +2071,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       attempts(0, t0, threadIdx.x, kBuildThreads, bar);
     }
     __syncthreads();
+    if (threadIdx.x == 0) VF_CLK_ADD(kClkFirst, wall_clock64() - ck0);
   }
 
   if (wid == 2) {
@@ -2058,7 +2119,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       }
       if (what == kRecRetry) {
         if (lane == 0) rec[s].state = kRecFront;
+        VF_CLK(c0);
         attempts(s, uniform(rec[s].t) + 1u, lane, 64, wsync);
+        VF_CLK_ADD(kClkPeel, wall_clock64() - c0);
+        VF_CLK_ADD(kClkPeel + 1, 1);
         continue;
       }
       // the next work item
@@ -2073,7 +2137,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       if (lane == 0) fill(s, j, t0);
       wave_sync();
       rights(s, lane, 64);
+      VF_CLK(c0);
       attempts(s, t0, lane, 64, wsync);
+      VF_CLK_ADD(kClkPeel, wall_clock64() - c0);
+      VF_CLK_ADD(kClkPeel + 1, 1);
     }
   } else if (wid != 3) {
     // -------------------------------------- elimination (wavefronts 0, 1, 4)
@@ -2108,7 +2175,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       const Geo G = geo(s);
       const uint32_t W = min(A.wmax, window_slots_for(G.sigma, A.lds_bytes));
       uint32_t np = 0;
+      VF_CLK(c0b);
       const int st = band_solve<QM>(A, G, W, sb, lds, ctl, bw, &np, pc, gen);
+      if (bw == 0) {
+        VF_CLK_ADD(kClkBand, wall_clock64() - c0b);
+        VF_CLK_ADD(kClkBand + 1, 1);
+      }
       if (bw == 0) {
         const uint32_t j = uniform(rec[s].shard), t = uniform(rec[s].t);
         uint32_t next = kRecSolved;
@@ -2157,6 +2229,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       const uint32_t np = uniform(rec[s].np), nrounds = uniform(rec[s].rounds);
       for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
       wave_sync_global();
+      VF_CLK(c0a);
       if (np) back_substitute<T>(sb, np, wg, bcol, true);
       for (int r = (int)nrounds - 1; r >= 0; r--) {
         const uint32_t e0 = sb.rst[r], e1 = sb.rst[r + 1];
@@ -2173,9 +2246,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         wave_sync_global();
       }
       if (lane == 0) A.tseed[uniform(rec[s].shard)] = (uint8_t)uniform(rec[s].t);
+      VF_CLK_ADD(kClkAssign, wall_clock64() - c0a);
+      VF_CLK_ADD(kClkAssign + 1, 1);
       lds_publish(&rec[s].state, kRecFree);
     }
   }
+  if (wid == 3) VF_CLK_ADD(kClkTotal, wall_clock64() - ck0);
 }
 
 // ------------------------------------------------- small instances (batches)

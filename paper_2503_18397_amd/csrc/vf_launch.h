@@ -140,6 +140,25 @@ bool small_instance(uint64_t n, uint64_t V);
 // The one-wavefront build of the (instance, first local seed) pairs of
 // a.list (a.items, a.cells, a.tseed, a.fails, a.work as for launch_build).
 hipError_t launch_small(const BuildArgs &a, int nwg, hipStream_t s);
+
+// Stage clocks of k_build (a build with -DVF_STAGE_CLOCKS): kClkSlots
+// counters per workgroup for the first kClkWGs workgroups.
+constexpr uint32_t kClkWGs = 4096, kClkSlots = 32;
+enum : uint32_t {
+  kClkPeel = 0,     // ticks, calls: peeling wavefront, per item's attempts
+  kClkBand = 2,     // ticks, calls: elimination of a 2-core
+  kClkAssign = 4,   // ticks, calls: back-substitution and assignment
+  kClkFirst = 6,    // ticks: the workgroup's first item (all wavefronts)
+  kClkTotal = 7,    // ticks: the whole workgroup
+  kClkSearch = 8,   // 7 slots, per 32-column word of the searching wavefront:
+                    // returned slots + entering rows, compaction, pivot
+                    // search, row updates, flags, barrier; words
+  kClkEmit = 16     // the same 7 slots for emitting wavefront 1 (emission,
+                    // wait for the batch + row updates in slots 1 and 2)
+};
+// Copies kClkWGs * kClkSlots counters to out (host), or clears them;
+// hipErrorNotSupported without -DVF_STAGE_CLOCKS.
+hipError_t stage_clocks(uint64_t *out, int reset);
 // Sets the kernel attributes launch_build needs for a's shape on the
 // current device (launch_build sets them too when they are missing).
 hipError_t prepare_build(const BuildArgs &a);

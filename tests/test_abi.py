@@ -93,3 +93,11 @@ print(rc)
     assert int(r.stdout.strip().splitlines()[-1]) == -6  # VF_ENOMEM
     import paper_2503_18397_amd as vf
     assert vf.VF_ENOMEM == -6
+
+
+def test_plain_library_keeps_no_stage_clocks():
+    """The stage clocks exist only in the profiling build; the plain library
+    says so (no device call is made)."""
+    import paper_2503_18397_amd as vf
+    assert vf._lib.vf_stage_clocks(None, 0, 1) == vf.VF_EINVAL
+    assert vf._lib.vf_stage_clocks(None, 0, 0) == vf.VF_EINVAL

@@ -205,9 +205,11 @@ BuildShape build_shape(int32_t sigma, uint32_t cell_bytes) {
   build_occupancy(sigma, &b.per_cu, &b.lds_bytes);
   auto slots = [&] {
     uint32_t w = vfk::window_slots((uint32_t)sigma, b.lds_bytes);
-    // fewer slot groups in registers when the target allows it
+    // at most six slot groups in registers when the target allows it (the
+    // peaks of a window run well above the target for the larger graphs
+    // of a segment size, and a window that outgrows its slots costs a
+    // second launch)
     if (w > 384 && window_target(sigma) <= 384) w = 384;
-    if (w > 256 && window_target(sigma) <= 256) w = 256;
     return w;
   };
   b.wmax = slots();

@@ -60,6 +60,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-packed", action="store_true",
                    help="batch workload: cells of 1/2/4/8 bytes instead of b-bit fields")
+    p.add_argument("--no-batch", action="store_true",
+                   help="leave the batched workload out of the default line")
     p.add_argument("--no-serve", action="store_true",
                    help="skip the short serving trace measured after the timed region")
     p.add_argument("--line-serve-builds", type=int, default=24,
@@ -259,6 +261,10 @@ def serve_main(args) -> None:
 
 
 def batch_main(args) -> None:
+    print(json.dumps(batch_measure(args)), flush=True)
+
+
+def batch_measure(args) -> dict:
     """Batched uneven instances: one build launch per cell width for all
     instances (vf_batch_build) against one vf_build per instance, timed on
     a random sample of the same instances."""
@@ -357,7 +363,9 @@ def batch_main(args) -> None:
                                   "seconds": round(per_s, 3)},
         "speedup_vs_per_instance": round(batched / single, 2),
     }
-    print(json.dumps(res), flush=True)
+    del keys, vals, inst, out, ws, st, ws1, st1
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(args, keys_np=None, queries_np=None) -> dict:
@@ -593,6 +601,13 @@ def main():
     if not args.no_serve and not mwhc:
         # the serving loop, measured after the timed region
         res["serve"] = serve_measure(args, args.line_serve_builds, 10 * args.line_serve_builds)
+    if not args.no_batch and not mwhc:
+        # the batched workload (--workload batch), one timed step, after the
+        # timed region
+        import copy
+        bargs = copy.copy(args)
+        bargs.steps, bargs.warmup = 1, 1
+        res["batch"] = batch_measure(bargs)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle on host cores)", file=sys.stderr, flush=True)
         import numpy as np

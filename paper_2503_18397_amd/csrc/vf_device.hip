@@ -692,6 +692,8 @@ struct FrontBufs {
   uint32_t *cc;      // group cursors
 };
 constexpr uint64_t kDegOne = 1ull << 32;
+// Elements per lane in flight in the peel's passes over edges and vertices.
+constexpr uint32_t kPU = 4;
 
 // Shard records per workgroup: one being peeled, one being eliminated and
 // one being assigned.
@@ -1796,87 +1798,149 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
     const uint32_t w0t = tid - lane;  // this wavefront's first thread
     const FrontBufs fb{f_st, f_pe, f_F0, f_F1, f_cc};
     uint32_t nrounds = 0;
+    VF_CLK(pf0);
     if (tid == 0)
       for (int i = 0; i < 7; i++) fcnt[i] = 0;
-    // edges of this attempt, cleared vertex state
-    for (uint32_t i = tid; i < m; i += nthr) {
-      const uint64_t key = A.bkeys[base + i];
-      uint32_t v0, v1, v2;
-      edge3(G, fin64(key ^ G.khi), fin64(key ^ G.klo), t, v0, v1, v2);
-      E[i] = pack3(v0, v1, v2);
-      fb.pe[i] = 0;
+    // edges of this attempt, cleared vertex state.  The passes over edges
+    // and vertices keep kPU loads per lane in flight: a wavefront alone
+    // would otherwise wait a memory round trip per 64 elements.
+    for (uint32_t i0 = tid; i0 < m; i0 += nthr * kPU) {
+      uint64_t key[kPU];
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++) {
+        const uint32_t i = i0 + u * nthr;
+        key[u] = i < m ? A.bkeys[base + i] : 0ull;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++) {
+        const uint32_t i = i0 + u * nthr;
+        if (i < m) {
+          uint32_t v0, v1, v2;
+          edge3(G, fin64(key[u] ^ G.khi), fin64(key[u] ^ G.klo), t, v0, v1, v2);
+          E[i] = pack3(v0, v1, v2);
+          fb.pe[i] = 0;
+        }
+      }
     }
     for (uint64_t v = tid; v < V; v += nthr) {
       fb.st[v] = 0;
     }
     sync();
+    VF_CLK(pf1);
     // incidence: degree and xor of incident edges
-    for (uint32_t i = tid; i < m; i += nthr) {
-      uint32_t v[3];
-      unpack3(E[i], v);
-      for (int k = 0; k < 3; k++) {
-        atomicAdd((unsigned long long *)&fb.st[v[k]], kDegOne + i);
+    for (uint32_t i0 = tid; i0 < m; i0 += nthr * kPU) {
+      uint64_t e[kPU];
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++) {
+        const uint32_t i = i0 + u * nthr;
+        e[u] = i < m ? E[i] : 0ull;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++) {
+        const uint32_t i = i0 + u * nthr;
+        if (i < m) {
+          uint32_t v[3];
+          unpack3(e[u], v);
+          for (int k = 0; k < 3; k++)
+            atomicAdd((unsigned long long *)&fb.st[v[k]], kDegOne + i);
+        }
       }
     }
     sync();
+    VF_CLK(pf2);
     // round-synchronous peeling
-    for (uint64_t v0 = w0t; v0 < V; v0 += nthr) {
-      const uint64_t v = v0 + lane;
-      const bool one = v < V && (fb.st[v] >> 32) == 1;
-      const uint32_t at = wave_append(one, &fcnt[0]);
-      if (one) fb.F0[at] = (uint32_t)v;
+    for (uint64_t v0 = w0t; v0 < V; v0 += (uint64_t)nthr * kPU) {
+      uint64_t sv[kPU];
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++) {
+        const uint64_t v = v0 + (uint64_t)u * nthr + lane;
+        sv[u] = v < V ? fb.st[v] : 0ull;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++) {
+        const uint64_t v = v0 + (uint64_t)u * nthr + lane;
+        const bool one = v < V && (sv[u] >> 32) == 1;
+        const uint32_t at = wave_append(one, &fcnt[0]);
+        if (one) fb.F0[at] = (uint32_t)v;
+      }
     }
     sync();
     uint32_t nf = lds_load(&fcnt[0]), nst = 0;
+    VF_CLK(pf3);
     uint32_t *cur = fb.F0, *nxt = fb.F1;
     if (tid == 0) rst[0] = 0;
     while (nf) {
       const uint32_t r0 = nst;
       uint32_t *const ncnt = &fcnt[2 + nrounds % 3];
       if (tid == 0) fcnt[2 + (nrounds + 1) % 3] = 0;
-      // select with the degrees of the start of the round
-      for (uint32_t i0 = w0t; i0 < nf; i0 += nthr) {
-        const uint32_t i = i0 + lane;
-        bool take = false;
-        uint32_t e = 0, side = 0;
-        if (i < nf) {
-          const uint32_t v = cur[i];
-          const uint64_t sv = fb.st[v];
-          if ((sv >> 32) == 1) {
-            e = (uint32_t)sv;
+      // select with the degrees of the start of the round (kPU frontier
+      // vertices per lane at a time, each step's loads in flight together)
+      for (uint32_t i0 = w0t; i0 < nf; i0 += nthr * kPU) {
+        uint32_t v[kPU], e[kPU], side[kPU];
+        uint64_t sv[kPU], ev[kPU];
+        bool take[kPU];
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) {
+          const uint32_t i = i0 + u * nthr + lane;
+          v[u] = i < nf ? cur[i] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) sv[u] = v[u] != 0xFFFFFFFFu ? fb.st[v[u]] : 0ull;
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) {
+          take[u] = (sv[u] >> 32) == 1;
+          e[u] = (uint32_t)sv[u];
+          ev[u] = take[u] ? E[e[u]] : 0ull;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) {
+          side[u] = 0;
+          if (take[u]) {
             uint32_t a[3];
-            unpack3(E[e], a);
-            side = a[0] == v ? 0u : (a[1] == v ? 1u : 2u);
-            take = true;
-            for (uint32_t k = 0; k < side; k++)
-              if ((fb.st[a[k]] >> 32) == 1) take = false;
+            unpack3(ev[u], a);
+            side[u] = a[0] == v[u] ? 0u : (a[1] == v[u] ? 1u : 2u);
+            for (uint32_t k = 0; k < side[u]; k++)
+              if ((fb.st[a[k]] >> 32) == 1) take[u] = false;
           }
         }
-        const uint32_t at = wave_append(take, &fcnt[1]);
-        if (take) {
-          stk[at] = e | (side << 30);
-          fb.pe[e] = 1;
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) {
+          const uint32_t at = wave_append(take[u], &fcnt[1]);
+          if (take[u]) {
+            stk[at] = e[u] | (side[u] << 30);
+            fb.pe[e[u]] = 1;
+          }
         }
       }
       sync();
       nst = lds_load(&fcnt[1]);
       // remove the selected edges
-      for (uint32_t i0 = r0 + w0t; i0 < nst; i0 += nthr) {
-        const uint32_t i = i0 + lane;
-        bool push[3] = {false, false, false};
-        uint32_t a[3] = {0, 0, 0};
-        if (i < nst) {
-          const uint32_t e = stk[i] & 0x3FFFFFFFu;
-          unpack3(E[e], a);
-          for (int k = 0; k < 3; k++) {
-            const uint64_t old =
-                atomicAdd((unsigned long long *)&fb.st[a[k]], (unsigned long long)(-(kDegOne + e)));
-            push[k] = (old >> 32) == 2;
-          }
+      for (uint32_t i0 = r0 + w0t; i0 < nst; i0 += nthr * kPU) {
+        uint32_t e[kPU];
+        uint64_t ev[kPU];
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) {
+          const uint32_t i = i0 + u * nthr + lane;
+          e[u] = i < nst ? stk[i] & 0x3FFFFFFFu : 0xFFFFFFFFu;
         }
-        for (int k = 0; k < 3; k++) {
-          const uint32_t at = wave_append(push[k], ncnt);
-          if (push[k]) nxt[at] = a[k];
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) ev[u] = e[u] != 0xFFFFFFFFu ? E[e[u]] : 0ull;
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) {
+          bool push[3] = {false, false, false};
+          uint32_t a[3] = {0, 0, 0};
+          if (e[u] != 0xFFFFFFFFu) {
+            unpack3(ev[u], a);
+            for (int k = 0; k < 3; k++) {
+              const uint64_t old = atomicAdd((unsigned long long *)&fb.st[a[k]],
+                                             (unsigned long long)(-(kDegOne + e[u])));
+              push[k] = (old >> 32) == 2;
+            }
+          }
+          for (int k = 0; k < 3; k++) {
+            const uint32_t at = wave_append(push[k], ncnt);
+            if (push[k]) nxt[at] = a[k];
+          }
         }
       }
       nrounds++;
@@ -1888,6 +1952,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       nxt = tmp;
     }
 
+    VF_CLK(pf4);
     // 2-core edges, grouped by the entry group of their top vertex (an
     // MWHC hypergraph is peel-only: only its unpeeled edges are counted)
     uint32_t k;
@@ -1903,8 +1968,19 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       const uint32_t ngroups = (uint32_t)((V - 1) >> gsh) + 2;
       for (uint32_t g = tid; g < ngroups; g += nthr) fb.cc[g] = 0;
       sync();
-      for (uint32_t i = tid; i < m; i += nthr)
-        if (!fb.pe[i]) atomicAdd(&fb.cc[(uint32_t)(E[i] >> 42) >> gsh], 1u);
+      for (uint32_t i0 = tid; i0 < m; i0 += nthr * kPU) {
+        uint64_t e[kPU];
+        uint8_t pe[kPU];
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) {
+          const uint32_t i = i0 + u * nthr;
+          pe[u] = i < m ? fb.pe[i] : (uint8_t)1;
+          e[u] = i < m ? E[i] : 0ull;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++)
+          if (!pe[u]) atomicAdd(&fb.cc[(uint32_t)(e[u] >> 42) >> gsh], 1u);
+      }
       sync();
       if (tid < 64) {  // one wavefront scans the group counts
         const uint32_t kk = wave_scan_array(fb.cc, sb.cb, ngroups);
@@ -1912,13 +1988,27 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       }
       sync();
       k = lds_load(&fcnt[5]);
-      for (uint32_t i = tid; i < m; i += nthr)
-        if (!fb.pe[i]) {
-          const uint64_t e = E[i];
-          const uint32_t pos = atomicAdd(&fb.cc[(uint32_t)(e >> 42) >> gsh], 1u);
-          sb.cE[pos] = e;
-          sb.cR[pos] = R[i];
+      for (uint32_t i0 = tid; i0 < m; i0 += nthr * kPU) {
+        uint64_t e[kPU], r[kPU];
+        uint8_t pe[kPU];
+        uint32_t pos[kPU];
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) {
+          const uint32_t i = i0 + u * nthr;
+          pe[u] = i < m ? fb.pe[i] : (uint8_t)1;
+          e[u] = i < m ? E[i] : 0ull;
+          r[u] = i < m ? R[i] : 0ull;
         }
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++)
+          pos[u] = pe[u] ? 0u : atomicAdd(&fb.cc[(uint32_t)(e[u] >> 42) >> gsh], 1u);
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++)
+          if (!pe[u]) {
+            sb.cE[pos[u]] = e[u];
+            sb.cR[pos[u]] = r[u];
+          }
+      }
       sync();
     }
     // MWHC is peel-only: any unpeeled edge ends the attempt (kind 2).
@@ -1926,23 +2016,61 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
     // sides (the usual reason for an inconsistent system) end the attempt
     // before the elimination: rows are listed by top vertex in the degree
     // array, which peeling no longer needs
+    VF_CLK(pf5);
     const uint32_t kl = G.mwhc ? 0u : k;
     uint32_t *const head = (uint32_t *)fb.st, *const next = fb.F0;
     if (kl)
       for (uint64_t v = tid; v < V; v += nthr) head[v] = 0xFFFFFFFFu;
     sync();
-    for (uint32_t i = tid; i < kl; i += nthr)
-      next[i] = atomicExch(&head[(uint32_t)(sb.cE[i] >> 42)], i);
+    for (uint32_t i0 = tid; i0 < kl; i0 += nthr * kPU) {
+      uint64_t e[kPU];
+      uint32_t nx[kPU];
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++) {
+        const uint32_t i = i0 + u * nthr;
+        e[u] = i < kl ? sb.cE[i] : 0ull;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++) {
+        const uint32_t i = i0 + u * nthr;
+        nx[u] = i < kl ? atomicExch(&head[(uint32_t)(e[u] >> 42)], i) : 0u;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++)
+        if (i0 + u * nthr < kl) next[i0 + u * nthr] = nx[u];
+    }
     sync();
     bool clash = false;
-    for (uint32_t i = tid; i < kl; i += nthr) {
-      const uint64_t e = sb.cE[i], r = sb.cR[i];
-      for (uint32_t x = next[i]; x != 0xFFFFFFFFu; x = next[x])
-        clash |= sb.cE[x] == e && sb.cR[x] != r;
+    for (uint32_t i0 = tid; i0 < kl; i0 += nthr * kPU) {
+      uint64_t e[kPU], r[kPU];
+      uint32_t x[kPU];
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++) {
+        const uint32_t i = i0 + u * nthr;
+        e[u] = i < kl ? sb.cE[i] : 0ull;
+        r[u] = i < kl ? sb.cR[i] : 0ull;
+        x[u] = i < kl ? next[i] : 0xFFFFFFFFu;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kPU; u++)
+        for (; x[u] != 0xFFFFFFFFu; x[u] = next[x[u]])
+          clash |= sb.cE[x[u]] == e[u] && sb.cR[x[u]] != r[u];
     }
     if (__ballot(clash) != 0 && lane == 0) atomicOr(&fcnt[6], 1u);
     sync();
     const bool dup = lds_load(&fcnt[6]) != 0;
+#ifdef VF_STAGE_CLOCKS
+    if (tid == w0t && w0t == 0) {
+      VF_CLK_ADD(kClkPeelPhases + 0, pf1 - pf0);
+      VF_CLK_ADD(kClkPeelPhases + 1, pf2 - pf1);
+      VF_CLK_ADD(kClkPeelPhases + 2, pf3 - pf2);
+      VF_CLK_ADD(kClkPeelPhases + 3, pf4 - pf3);
+      VF_CLK_ADD(kClkPeelPhases + 4, pf5 - pf4);
+      VF_CLK_ADD(kClkPeelPhases + 5, wall_clock64() - pf5);
+      VF_CLK_ADD(kClkPeelPhases + 6, 1);
+      VF_CLK_ADD(kClkPeelPhases + 7, nrounds);
+    }
+#endif
     k_out = k;
     rounds_out = nrounds;
     early_out = G.mwhc && k ? 2u : (dup ? 1u : 0u);

@@ -153,8 +153,11 @@ enum : uint32_t {
   kClkSearch = 8,   // 7 slots, per 32-column word of the searching wavefront:
                     // returned slots + entering rows, compaction, pivot
                     // search, row updates, flags, barrier; words
-  kClkEmit = 16     // the same 7 slots for emitting wavefront 1 (emission,
+  kClkEmit = 16,    // the same 7 slots for emitting wavefront 1 (emission,
                     // wait for the batch + row updates in slots 1 and 2)
+  kClkPeelPhases = 24  // 8 slots, per attempt's peel: edges + cleared state,
+                       // incidence, first frontier, rounds, 2-core grouping,
+                       // duplicate-row check; attempts; rounds
 };
 // Copies kClkWGs * kClkSlots counters to out (host), or clears them;
 // hipErrorNotSupported without -DVF_STAGE_CLOCKS.

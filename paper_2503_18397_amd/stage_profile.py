@@ -63,6 +63,12 @@ def main() -> None:
                                     "wait_for_batch_and_row_updates": e["pivot_search"],
                                     "barrier": e["barrier"],
                                     "words_per_workgroup": e["words_per_workgroup"]}
+        att = max(raw[:, 30].sum(), 1)
+        pnames = ("edges_and_cleared_state", "incidence", "first_frontier", "rounds",
+                  "core_grouping", "duplicate_row_check")
+        peel = {k: round(float(us[:, 24 + i].sum() / att), 1) for i, k in enumerate(pnames)}
+        peel["attempts"] = int(att)
+        peel["rounds_per_attempt"] = round(float(raw[:, 31].sum() / att), 1)
         out = {
             "workload": f"VFilter b={args.b}, n=2^{args.log2n}, eps={args.eps}",
             "S": info["S"], "M": info["M"], "sigma": info["sigma"],
@@ -78,6 +84,7 @@ def main() -> None:
             "per_item_ms": {"peel": per(0, 1), "elimination": per(2, 3),
                             "assignment": per(4, 5)},
             "per_word_us": ph,
+            "peel_per_attempt_us": peel,
         }
     print(json.dumps(out))
 

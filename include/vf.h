@@ -204,6 +204,47 @@ int vfilter_build_host(const uint64_t *keys, uint64_t n, int32_t b, double eps,
                        void *structure, uint64_t structure_bytes,
                        hipStream_t stream, vf_handle **handle);
 
+/* The sharded build in three calls, so that its device work can be
+ * captured into a HIP graph and replayed (for instance on new keys written
+ * into the same buffers).  Every shard is sized for a bound on the largest
+ * shard fixed in advance (max_shard; 0: the bound vf_plan sizes buffers
+ * for, which a larger max_shard may not exceed) instead of the measured
+ * largest shard (section 4 sizes every shard
+ * by the largest one; a bound at least as large gives every shard room, at
+ * the cost of the gap), so no step waits for the host.  The cells, seeds
+ * and failure record are those vf_build / vfilter_build give for the same
+ * keys when their largest shard is max_shard.
+ *   vf_build_prepare  host only: plans layout and geometry, sets kernel
+ *                     attributes; *handle answers no query until a
+ *                     vf_build_finish reports a built structure.  Errors:
+ *                     VF_EINVAL (as vf_build, or n = 0), VF_ENOSPC,
+ *                     VF_ECAPACITY, VF_ENOMEM, VF_EHIP.
+ *   vf_build_launch   enqueues counting, grouping, checks and the build on
+ *                     stream: kernels only (no allocation, copy from the
+ *                     host or wait), so it may run under stream capture.
+ *                     keys (and values for a function, is_filter = 0) are
+ *                     n device words read when the work runs.  A value with
+ *                     a bit at or above b, or a shard above the bound, makes
+ *                     every build kernel return at once (the structure
+ *                     keeps what it held).  Errors: VF_EINVAL, VF_EHIP.
+ *   vf_build_finish   once stream has run the launch (or a graph holding
+ *                     it): reads the checks, the failure record and the
+ *                     local seeds into the handle (synchronizes stream).
+ *                     VF_EINVAL: a value was too wide; VF_ENOSPC: a shard
+ *                     exceeded the bound (vf_last_error gives both sizes);
+ *                     the handle is unchanged in both cases.  Otherwise as
+ *                     vf_build (VF_OK, VF_EFAIL, VF_ECAPACITY, VF_EHIP).
+ * workspace and structure (vf_plan sizes, caller-owned) stay with the
+ * handle; launches of one handle that overlap on the device race. */
+int vf_build_prepare(uint64_t n, uint32_t max_shard, int32_t b, double eps,
+                     int32_t is_filter, uint64_t seed, const vf_opts *o,
+                     void *workspace, uint64_t workspace_bytes,
+                     void *structure, uint64_t structure_bytes,
+                     vf_handle **handle);
+int vf_build_launch(vf_handle *h, const uint64_t *keys, const uint64_t *values,
+                    hipStream_t stream);
+int vf_build_finish(vf_handle *h, hipStream_t stream);
+
 /* One request of vf_query_multi: n keys (device) asked of structure h, the
  * answers written to out (device) exactly as vf_query (a function) or
  * vfilter_contains (a filter) would write them. */

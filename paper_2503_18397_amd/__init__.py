@@ -123,6 +123,10 @@ _lib.vf_batch_prepare.argtypes = [_u64, _vp, _vp, _u64, C.POINTER(Opts), _vp, _u
 _lib.vf_batch_launch.argtypes = [_vp, _vp, _vp, _vp]
 _lib.vf_batch_finish.argtypes = [_vp, _vp]
 _lib.vf_query_multi.argtypes = [_vp, C.c_uint32, _vp]
+_lib.vf_build_prepare.argtypes = [_u64, C.c_uint32, _i32, _dbl, _i32, _u64, C.POINTER(Opts), _vp,
+                                  _u64, _vp, _u64, C.POINTER(_vp)]
+_lib.vf_build_launch.argtypes = [_vp, _vp, _vp, _vp]
+_lib.vf_build_finish.argtypes = [_vp, _vp]
 _lib.vf_batch_query.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp]
 _lib.vf_batch_item.argtypes = [_vp, _u64, C.POINTER(BatchItem)]
 _lib.vf_batch_tuning.argtypes = [C.POINTER(Tuning)]
@@ -135,7 +139,7 @@ for _f in ("vf_plan", "vf_build", "vfilter_build", "vf_query", "vfilter_contains
            "vfilter_build_host", "vf_query_grouped_bytes", "vf_query_grouped",
            "vfilter_contains_grouped", "vfilter_contains_grouped_noalloc", "vf_batch_tuning",
            "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish", "vf_query_multi",
-           "vf_stage_clocks"):
+           "vf_stage_clocks", "vf_build_prepare", "vf_build_launch", "vf_build_finish"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build",
@@ -143,7 +147,8 @@ EXPORTS = ("vf_default_opts", "vf_plan", "vf_build", "vf_query", "vfilter_build"
            "vf_batch_build", "vf_batch_query", "vf_batch_item", "vfilter_build_host",
            "vf_query_grouped_bytes", "vf_query_grouped", "vfilter_contains_grouped",
            "vfilter_contains_grouped_noalloc", "vf_batch_tuning", "vf_last_error",
-           "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish", "vf_query_multi")
+           "vf_batch_prepare", "vf_batch_launch", "vf_batch_finish", "vf_query_multi",
+           "vf_stage_clocks", "vf_build_prepare", "vf_build_launch", "vf_build_finish")
 
 
 def _check(rc: int, where: str) -> None:
@@ -356,6 +361,32 @@ def vf_batch_build(keys, values, n, b, seed, opts, workspace, structure, stream=
     return rc, h
 
 
+def vf_build_prepare(n: int, b: int, eps: float, is_filter: bool, seed: int, opts, workspace,
+                     structure, max_shard: int = 0):
+    """Handle of a prepared sharded build (vf_build_prepare)."""
+    h = C.c_void_p()
+    _check(_lib.vf_build_prepare(n, max_shard, b, eps, int(is_filter), seed,
+                                 C.byref(opts) if opts else None,
+                                 _dev_ptr(workspace, "workspace"), workspace.numel(),
+                                 _dev_ptr(structure, "structure"), structure.numel(),
+                                 C.byref(h)), "vf_build_prepare")
+    return h
+
+
+def vf_build_launch(handle, keys, values=None, stream=None) -> None:
+    _check(_lib.vf_build_launch(handle, _dev_ptr(keys, "keys"),
+                                None if values is None else _dev_ptr(values, "values"),
+                                _stream(stream)), "vf_build_launch")
+
+
+def vf_build_finish(handle, stream=None) -> int:
+    """Returns VF_OK or VF_EFAIL; raises on the other codes."""
+    rc = _lib.vf_build_finish(handle, _stream(stream))
+    if rc not in (VF_OK, VF_EFAIL):
+        raise VFError(rc, "vf_build_finish")
+    return rc
+
+
 def vf_batch_prepare(n, b, seed, opts, workspace, structure, stream=None):
     """Returns the handle of a prepared batch (host arrays n and b)."""
     n, b = _host_arrays(n, b)
@@ -454,6 +485,30 @@ class Structure:
         else:
             rc, hd = vf_build(keys, values, b, eps, seed, opts, ws, st, stream)
         return cls(hd, rc, is_filter, b, st, ws)
+
+    @classmethod
+    def prepare(cls, n: int, *, b: int, filter: bool, eps: float = 0.0, seed: int = 0,
+                h: int | None = None, max_shard: int = 0, sigma: int | None = None,
+                tmax: int | None = None, mwhc: bool = False, packed: bool = False,
+                device=None):
+        """A structure whose build is enqueued by launch() (capturable into a
+        graph) and read back by finish(); shards sized for max_shard keys
+        (0: the plan's bound)."""
+        opts = vf_default_opts(h=h, sigma=sigma, tmax=tmax, mwhc=int(mwhc), packed=int(packed))
+        sz = vf_plan(n, b, eps, filter, opts)
+        dev = torch.device(device if device is not None else "cuda")
+        ws = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=dev)
+        st = torch.empty(sz.structure_bytes, dtype=torch.uint8, device=dev)
+        hd = vf_build_prepare(n, b, eps, filter, seed, opts, ws, st, max_shard)
+        return cls(hd, VF_OK, filter, b, st, ws)
+
+    def launch(self, keys: torch.Tensor, values: torch.Tensor | None = None,
+               stream=None) -> None:
+        vf_build_launch(self.handle, keys, values, stream)
+
+    def finish(self, stream=None) -> int:
+        self.rc = vf_build_finish(self.handle, stream)
+        return self.rc
 
     def release_workspace(self) -> None:
         self.workspace = None

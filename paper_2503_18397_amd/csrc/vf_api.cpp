@@ -252,7 +252,7 @@ struct Layout {
 };
 
 int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts &o,
-                int ncu, Layout *L) {
+                int ncu, Layout *L, uint32_t cap_override = 0) {
   if (b < 1 || b > 64) return VF_EINVAL;
   int32_t h = o.h;
   if (h < 0) {
@@ -268,6 +268,7 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   l.h = h;
   l.S = 1u << h;
   l.cap = shard_cap(n, l.S);
+  if (cap_override) l.cap = std::min(l.cap, cap_override);
   if (o.mwhc) {
     l.gcap = geometry_mwhc(l.cap, o.c_num, o.c_den);
   } else {
@@ -479,6 +480,7 @@ int make_batch_layout(uint64_t count, const uint64_t *n, const int32_t *b, const
 }  // namespace
 
 struct BatchRun;
+struct BuildRun;
 
 struct vf_handle {
   uint32_t magic;
@@ -506,6 +508,9 @@ struct vf_handle {
   // a batch prepared by vf_batch_prepare (kind 2 until its first
   // vf_batch_finish reports a built structure, kind 1 after)
   std::shared_ptr<BatchRun> run;
+  // a structure prepared by vf_build_prepare (kind 3 until its first
+  // vf_build_finish reports a built structure, kind 0 after)
+  std::shared_ptr<BuildRun> brun;
 };
 
 namespace {
@@ -797,6 +802,273 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   if (hwork[vfk::kWorkStatus] & vfk::kStatusCapacity) return VF_ECAPACITY;
   if (H->failed_shards) return VF_EFAIL;
   return VF_OK;
+}
+
+// A sharded build whose geometry is fixed before the keys are seen (the
+// largest shard is bounded by max_shard instead of measured), so that its
+// device work needs no host read: vf_build_prepare / launch / finish.
+struct BuildRun {
+  Layout L;
+  vf_opts op{};
+  int ncu = 0;
+  Geometry g{};
+  int32_t b = 0, is_filter = 0;
+  uint64_t n = 0, seed = 0;
+  bool rows = false;
+  uint32_t nwg = 0, relaunch_lds = 0, relaunch_wmax = 0;
+  vfk::BuildArgs A{};  // keys, values and the abort flag are set per launch
+  uint32_t *counts = nullptr, *meta = nullptr, *work = nullptr, *order = nullptr,
+           *overflow = nullptr, *row_counts = nullptr;
+  uint64_t *offsets = nullptr, *cursor = nullptr, *bkeys = nullptr, *bvals = nullptr;
+  vfk::FailRec *fails = nullptr;
+  uint8_t *cells = nullptr, *bcells = nullptr, *tseed = nullptr;
+};
+
+#define HIPCHK(x)                                          \
+  do {                                                     \
+    const hipError_t e_ = (x);                             \
+    if (e_ != hipSuccess) return hip_failed(e_, __LINE__); \
+  } while (0)
+
+static int build_prepare(uint64_t n, uint32_t max_shard, int32_t b, double eps, int32_t is_filter,
+                         uint64_t seed, const vf_opts *o, void *ws, uint64_t ws_bytes, void *st,
+                         uint64_t st_bytes, vf_handle **handle) {
+  if (!handle || !ws || !st || !n) return VF_EINVAL;
+  auto R = std::make_shared<BuildRun>();
+  vf_default_opts(&R->op);
+  if (o) R->op = *o;
+  const vf_opts &op = R->op;
+  R->ncu = device_cus();
+  if (R->ncu <= 0) return VF_EHIP;
+  Layout &L = R->L;
+  int rc = make_layout(n, b, eps, is_filter, op, R->ncu, &L);
+  if (rc) return rc;
+  // buffers are sized for the plan's bound: a tighter bound only
+  if (max_shard > L.cap) return VF_EINVAL;
+  if (max_shard) {
+    rc = make_layout(n, b, eps, is_filter, op, R->ncu, &L, max_shard);
+    if (rc) return rc;
+  }
+  if (ws_bytes < L.ws_bytes || st_bytes < L.st_bytes) return VF_ENOSPC;
+  const uint32_t M = L.cap;  // every shard is sized for the bound
+  R->g = op.mwhc ? geometry_mwhc(M, op.c_num, op.c_den)
+                 : geometry(M, L.h, op.c_num, op.c_den, op.sigma);
+  const Geometry &g = R->g;
+  if (g.V > kMaxCells) return VF_ECAPACITY;
+  const uint64_t need_cells = L.packed ? 8 * (((uint64_t)L.S * g.V * b + 63) / 64)
+                                      : (uint64_t)L.S * g.V * L.cell_bytes;
+  if (need_cells > L.cells_bytes ||
+      (L.packed && (uint64_t)L.S * g.V * L.cell_bytes > L.tcells_bytes) ||
+      vfk::build_scratch_bytes(M, g.V, g.l, L.logcap) > L.scratch_stride)
+    return VF_ENOSPC;
+  R->b = b;
+  R->is_filter = is_filter;
+  R->n = n;
+  R->seed = seed;
+  R->rows = L.rows;
+  uint8_t *W = (uint8_t *)ws;
+  R->counts = (uint32_t *)(W + L.o_counts);
+  R->offsets = (uint64_t *)(W + L.o_offsets);
+  R->cursor = (uint64_t *)(W + L.o_cursor);
+  R->meta = (uint32_t *)(W + L.o_meta);
+  R->work = (uint32_t *)(W + L.o_work);
+  R->fails = (vfk::FailRec *)(W + L.o_fails);
+  R->overflow = (uint32_t *)(W + L.o_overflow);
+  R->order = (uint32_t *)(W + L.o_order);
+  R->bkeys = (uint64_t *)(W + L.o_bkeys);
+  R->bvals = is_filter ? nullptr : (uint64_t *)(W + L.o_bvals);
+  R->row_counts = R->rows ? (uint32_t *)(W + L.o_rows) : nullptr;
+  R->cells = (uint8_t *)st;
+  R->tseed = R->cells + L.cells_bytes;
+  R->bcells = L.packed ? W + L.o_tcells : R->cells;
+  uint64_t sw[3];
+  seed_words(seed, sw);
+  vfk::BuildArgs &A = R->A;
+  A.G.khi = sw[0];
+  A.G.klo = sw[1];
+  A.G.kfp = sw[2];
+  A.G.V = g.V;
+  A.G.vmask = b >= 64 ? ~0ull : ((1ull << b) - 1);
+  A.G.h = (uint32_t)L.h;
+  A.G.S = L.S;
+  A.G.l = g.l;
+  A.G.sigma = (uint32_t)g.sigma;
+  A.G.b = (uint32_t)b;
+  A.G.is_filter = (uint32_t)is_filter;
+  A.G.mwhc = g.mwhc;
+  A.G.part = g.part;
+  A.bkeys = R->bkeys;
+  A.bvals = R->bvals;
+  A.offsets = R->offsets;
+  A.cells = R->bcells;
+  A.tseed = R->tseed;
+  A.scratch = W + L.o_scratch;
+  A.scratch_stride = L.scratch_stride;
+  A.work = R->work;
+  A.fails = R->fails;
+  A.fail_cap = L.fail_cap;
+  A.M = M;
+  A.tmax = op.tmax;
+  const BuildShape shape = build_shape(g.sigma, L.cell_bytes);
+  A.lds_bytes = shape.lds_bytes;
+  A.wmax = shape.wmax;
+  if (op.max_window) A.wmax = std::min(A.wmax, std::max(8u, op.max_window & ~7u));
+  R->nwg = std::min<uint32_t>(L.nwg, shape.per_cu * (uint32_t)R->ncu);
+  A.logcap = L.logcap;
+  A.cell_bytes = L.cell_bytes;
+  A.list = R->order;
+  A.nlist = L.S;
+  A.overflow = R->overflow;
+  A.items = nullptr;
+  A.scr_V = g.V;
+  A.scr_l = g.l;
+  R->relaunch_lds = (vfk::kLdsBudget - 256) & ~255u;
+  R->relaunch_wmax = vfk::window_slots((uint32_t)g.sigma, R->relaunch_lds);
+  // dynamic-LDS attributes now, so that a launch makes no such call
+  HIPCHK(vfk::prepare_build(A));
+  vfk::BuildArgs B = A;
+  B.lds_bytes = R->relaunch_lds;
+  B.wmax = R->relaunch_wmax;
+  HIPCHK(vfk::prepare_build(B));
+  vf_handle *H = new (std::nothrow) vf_handle();
+  if (!H) return VF_ENOMEM;
+  H->magic = kMagic;
+  H->kind = 3;
+  H->is_filter = is_filter;
+  H->b = b;
+  H->seed = seed;
+  H->h = L.h;
+  H->S = L.S;
+  H->g = g;
+  H->n = n;
+  H->cell_bytes = L.cell_bytes;
+  H->packed = L.packed ? 1u : 0u;
+  H->brun = std::move(R);
+  *handle = H;
+  return VF_OK;
+}
+
+// Kernels only: count, scan, value and bound checks (either sets meta[1]
+// and every later kernel of the build returns at once), order, scatter,
+// build, rebuild of overflowing windows (list length read on the device),
+// packing.
+static int build_enqueue(const BuildRun &R, const uint64_t *keys, const uint64_t *values,
+                         hipStream_t stream) {
+  const Layout &L = R.L;
+  const uint64_t n = R.n;
+  const uint64_t khi = R.A.G.khi;
+  HIPCHK(vfk::launch_fill_u32(R.counts, L.S, 0, stream));
+  HIPCHK(vfk::launch_fill_u32(R.meta, 4, 0, stream));
+  HIPCHK(vfk::launch_fill_u32(R.work, vfk::kWorkWords, 0, stream));
+  if (R.rows)
+    HIPCHK(vfk::launch_count_rows(keys, n, khi, (uint32_t)L.h, L.S, R.row_counts, R.counts,
+                                  stream));
+  else
+    HIPCHK(vfk::launch_count(keys, n, khi, (uint32_t)L.h, L.S, R.counts, R.ncu, stream));
+  HIPCHK(vfk::launch_scan(R.counts, L.S, R.offsets, R.cursor, R.meta, stream));
+  if (!R.is_filter)
+    HIPCHK(vfk::launch_check_values(values, n, (uint32_t)R.b, R.meta + 1, stream));
+  HIPCHK(vfk::launch_check_bound(R.meta, L.cap, stream));
+  HIPCHK(vfk::launch_order(R.counts, L.S, L.cap, R.order, stream));
+  if (R.rows)
+    HIPCHK(vfk::launch_scatter_rows(keys, n, khi, (uint32_t)L.h, L.S, R.row_counts, R.cursor,
+                                    R.bkeys, nullptr, nullptr, stream));
+  else
+    HIPCHK(vfk::launch_scatter(keys, values, n, khi, (uint32_t)L.h, L.S, R.cursor, R.bkeys,
+                               R.bvals, nullptr, R.ncu, stream));
+  vfk::BuildArgs A = R.A;
+  A.abort = R.meta + 1;
+  HIPCHK(vfk::launch_build(A, (int)R.nwg, stream));
+  vfk::BuildArgs B = A;
+  B.list = R.overflow;
+  B.nlist = 0;
+  B.nlist_dev = R.work + vfk::kWorkCap;
+  B.overflow = nullptr;
+  B.lds_bytes = R.relaunch_lds;
+  B.wmax = R.relaunch_wmax;
+  HIPCHK(vfk::launch_fill_u32(R.work + vfk::kWorkNext, 1, 0, stream));
+  HIPCHK(vfk::launch_build(B, (int)std::min<uint32_t>(R.nwg, (uint32_t)R.ncu), stream));
+  if (L.packed)
+    HIPCHK(vfk::launch_pack_checked(R.bcells, L.cell_bytes, (uint64_t)L.S * R.g.V,
+                                    (uint32_t)R.b, (uint64_t *)R.cells, A.abort, stream));
+  return VF_OK;
+}
+
+// After the launched work: the checks, counters, failure record and seeds
+// into the handle (untouched when a check failed).
+static int build_collect(const BuildRun &R, hipStream_t stream, vf_handle *H) {
+  const Layout &L = R.L;
+  uint32_t hmeta[4], hwork[vfk::kWorkWords];
+  HIPCHK(hipMemcpyAsync(hmeta, R.meta, sizeof(hmeta), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(hwork, R.work, sizeof(hwork), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (hmeta[1] & 1u) return VF_EINVAL;
+  if (hmeta[1] & 2u) {
+    snprintf(g_last_error, sizeof(g_last_error), "largest shard %u above the bound %u", hmeta[0],
+             L.cap);
+    return VF_ENOSPC;
+  }
+  const uint32_t nf = std::min(hwork[vfk::kWorkFails], L.fail_cap);
+  std::vector<vfk::FailRec> fr(nf);
+  if (nf)
+    HIPCHK(hipMemcpyAsync(fr.data(), R.fails, nf * sizeof(vfk::FailRec), hipMemcpyDeviceToHost,
+                          stream));
+  std::vector<uint8_t> ts(L.S);
+  HIPCHK(hipMemcpyAsync(ts.data(), R.tseed, L.S, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  H->kind = 0;
+  H->h = L.h;
+  H->S = L.S;
+  H->g = R.g;
+  H->n = R.n;
+  H->cell_bytes = L.cell_bytes;
+  H->G = R.A.G;
+  H->cells = R.cells;
+  H->packed = L.packed ? 1u : 0u;
+  H->tseed = R.tseed;
+  H->ncu = R.ncu;
+  H->n_fail_total = hwork[vfk::kWorkFails];
+  H->relaunched = hwork[vfk::kWorkCap];
+  H->ms[0] = H->ms[1] = H->ms[2] = 0.f;
+  H->fails.clear();
+  for (const auto &f : fr) H->fails.push_back(vf_failure{f.shard, f.attempt, f.kind, f.core_edges});
+  std::sort(H->fails.begin(), H->fails.end(), [](const vf_failure &a, const vf_failure &c) {
+    return a.shard != c.shard ? a.shard < c.shard : a.attempt < c.attempt;
+  });
+  H->failed_shards = (uint32_t)std::count(ts.begin(), ts.end(), (uint8_t)255);
+  if (hwork[vfk::kWorkStatus] & vfk::kStatusStalled) {
+    snprintf(g_last_error, sizeof(g_last_error), "a build workgroup gave up on a wait");
+    return VF_EHIP;
+  }
+  if (hwork[vfk::kWorkStatus] & vfk::kStatusCapacity) return VF_ECAPACITY;
+  if (H->failed_shards) return VF_EFAIL;
+  return VF_OK;
+}
+#undef HIPCHK
+
+int vf_build_prepare(uint64_t n, uint32_t max_shard, int32_t b, double eps, int32_t is_filter,
+                     uint64_t seed, const vf_opts *o, void *workspace, uint64_t workspace_bytes,
+                     void *structure, uint64_t structure_bytes, vf_handle **handle) {
+  return guarded([&] {
+    return build_prepare(n, max_shard, b, eps, is_filter ? 1 : 0, seed, o, workspace,
+                         workspace_bytes, structure, structure_bytes, handle);
+  });
+}
+
+int vf_build_launch(vf_handle *h, const uint64_t *keys, const uint64_t *values,
+                    hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!h || h->magic != kMagic || !h->brun || !keys) return VF_EINVAL;
+    if (!h->brun->is_filter && !values) return VF_EINVAL;
+    return build_enqueue(*h->brun, keys, values, stream);
+  });
+}
+
+int vf_build_finish(vf_handle *h, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!h || h->magic != kMagic || !h->brun) return VF_EINVAL;
+    return build_collect(*h->brun, stream, h);
+  });
 }
 
 int vf_build(const uint64_t *keys, const uint64_t *values, uint64_t n, int32_t b, double eps,

@@ -2708,7 +2708,9 @@ __device__ __forceinline__ uint64_t pack_word(const T *__restrict__ in, uint64_t
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_pack(const T *__restrict__ in, uint64_t count, uint32_t b,
-                                              uint64_t *__restrict__ out, uint64_t nwords) {
+                                              uint64_t *__restrict__ out, uint64_t nwords,
+                                              const uint32_t *__restrict__ abort) {
+  if (abort && *abort) return;
   for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < nwords;
        j += (uint64_t)gridDim.x * blockDim.x)
     out[j] = pack_word(in, count, b, j);
@@ -3006,19 +3008,24 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pack(const void *in, uint32_t cell_bytes, uint64_t count, uint32_t b,
-                       uint64_t *out, hipStream_t s) {
+hipError_t launch_pack_checked(const void *in, uint32_t cell_bytes, uint64_t count, uint32_t b,
+                               uint64_t *out, const uint32_t *abort, hipStream_t s) {
   const uint64_t nw = (count * b + 63) / 64;
   if (!nw) return hipSuccess;
   uint64_t blocks = (nw + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   switch (cell_bytes) {
-    case 1: hipLaunchKernelGGL(k_pack<uint8_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint8_t *)in, count, b, out, nw); break;
-    case 2: hipLaunchKernelGGL(k_pack<uint16_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint16_t *)in, count, b, out, nw); break;
-    case 4: hipLaunchKernelGGL(k_pack<uint32_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint32_t *)in, count, b, out, nw); break;
-    default: hipLaunchKernelGGL(k_pack<uint64_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint64_t *)in, count, b, out, nw); break;
+    case 1: hipLaunchKernelGGL(k_pack<uint8_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint8_t *)in, count, b, out, nw, abort); break;
+    case 2: hipLaunchKernelGGL(k_pack<uint16_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint16_t *)in, count, b, out, nw, abort); break;
+    case 4: hipLaunchKernelGGL(k_pack<uint32_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint32_t *)in, count, b, out, nw, abort); break;
+    default: hipLaunchKernelGGL(k_pack<uint64_t>, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint64_t *)in, count, b, out, nw, abort); break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_pack(const void *in, uint32_t cell_bytes, uint64_t count, uint32_t b,
+                       uint64_t *out, hipStream_t s) {
+  return launch_pack_checked(in, cell_bytes, count, b, out, nullptr, s);
 }
 
 hipError_t launch_pack_batch(const BatchItem *src, const BatchItem *dst, uint64_t count,
@@ -3028,6 +3035,17 @@ hipError_t launch_pack_batch(const BatchItem *src, const BatchItem *dst, uint64_
   const uint64_t blocks = count < 65536 ? count : 65536;
   hipLaunchKernelGGL(k_pack_batch, dim3((uint32_t)blocks), dim3(256), 0, s, src, dst, count, in,
                      out, abort);
+  return hipGetLastError();
+}
+
+// Bit 1 of meta[1] when the largest shard (meta[0], from k_scan) exceeds
+// the bound the structure was sized for.
+__global__ void k_check_bound(uint32_t *meta, uint32_t cap) {
+  if (threadIdx.x == 0 && meta[0] > cap) atomicOr(&meta[1], 2u);
+}
+
+hipError_t launch_check_bound(uint32_t *meta, uint32_t cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_bound, dim3(1), dim3(64), 0, s, meta, cap);
   return hipGetLastError();
 }
 

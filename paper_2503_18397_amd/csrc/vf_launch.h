@@ -111,6 +111,11 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 // bit string of 64-bit words (cell i at bits [i b, i b + b)).
 hipError_t launch_pack(const void *in, uint32_t cell_bytes, uint64_t count, uint32_t b,
                        uint64_t *out, hipStream_t s);
+// The same, returning at once if abort is set and nonzero.
+hipError_t launch_pack_checked(const void *in, uint32_t cell_bytes, uint64_t count, uint32_t b,
+                               uint64_t *out, const uint32_t *abort, hipStream_t s);
+// Sets bit 1 of meta[1] if meta[0] (the largest shard) exceeds cap.
+hipError_t launch_check_bound(uint32_t *meta, uint32_t cap, hipStream_t s);
 // The same per instance of a batch: src offsets into in, dst into out.
 hipError_t launch_pack_batch(const BatchItem *src, const BatchItem *dst, uint64_t count,
                              const uint8_t *in, uint8_t *out, const uint32_t *abort,

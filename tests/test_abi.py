@@ -101,3 +101,22 @@ def test_plain_library_keeps_no_stage_clocks():
     import paper_2503_18397_amd as vf
     assert vf._lib.vf_stage_clocks(None, 0, 1) == vf.VF_EINVAL
     assert vf._lib.vf_stage_clocks(None, 0, 0) == vf.VF_EINVAL
+
+
+def test_split_calls_reject_null_arguments_before_any_device_call():
+    """The three-call builds and the combined query check their arguments
+    on the host (VF_EINVAL) before they touch a device."""
+    import paper_2503_18397_amd as vf
+    L = vf._lib
+    h = C.c_void_p()
+    assert L.vf_build_prepare(0, 0, 8, 0.0, 1, 0, None, None, 0, None, 0, C.byref(h)) == \
+        vf.VF_EINVAL
+    assert L.vf_build_prepare(1000, 0, 8, 0.0, 1, 0, None, None, 0, None, 0, None) == vf.VF_EINVAL
+    assert L.vf_build_launch(None, None, None, None) == vf.VF_EINVAL
+    assert L.vf_build_finish(None, None) == vf.VF_EINVAL
+    assert L.vf_batch_launch(None, None, None, None) == vf.VF_EINVAL
+    assert L.vf_batch_finish(None, None) == vf.VF_EINVAL
+    assert L.vf_query_multi(None, 1, None) == vf.VF_EINVAL
+    assert L.vf_query_multi(None, 0, None) == vf.VF_OK  # nothing to answer
+    bad = (vf.QueryReq * 1)()
+    assert L.vf_query_multi(bad, 1, None) == vf.VF_EINVAL  # null handle

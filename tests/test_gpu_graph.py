@@ -155,3 +155,114 @@ def test_graph_replays_match_eager_and_oracle():
     assert bt.finish() == vf.VF_OK
     _same(_state(bt, count), built2)
     bt.free()
+
+
+# ----------------------------------------------- sharded builds in three calls
+
+def _oracle_fixed(keys, vals, b, is_filter, h, seed, cap):
+    """The oracle's structure with every shard sized for cap keys."""
+    import ctypes as C
+    g = O.Geom()
+    O.lib().orc_geometry(cap, h, 0, 0, -1, C.byref(g))
+    return O.build(keys.cpu().numpy().view(np.uint64),
+                   None if vals is None else vals.cpu().numpy().view(np.uint64),
+                   b=b, is_filter=is_filter, h=h, seed=seed, geom=g)
+
+
+def _same_as_oracle(st, ob, b):
+    info = st.info
+    assert (info["M"], info["V"], info["l"], info["sigma"]) == \
+        (ob.geom["M"], ob.geom["V"], ob.geom["l"], ob.geom["sigma"])
+    assert np.array_equal(st.local_seeds().cpu().numpy(), ob.t.astype(np.uint8))
+    assert st.failures == ob.failures
+    if info["packed"]:
+        got = st.cells().cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, O.pack(ob.w.reshape(-1), b))
+    else:
+        cells = st.cells().cpu().numpy().view(_NP[info["cell_bytes"]])
+        assert np.array_equal(cells, ob.w.astype(cells.dtype))
+
+
+@pytest.mark.parametrize("is_filter,b,h,packed", [(True, 8, 4, False), (False, 12, 2, True)])
+def test_prepared_sharded_build_equals_the_oracle(is_filter, b, h, packed):
+    n = 1 << 18
+    keys = S.member_keys(n, 61, device=DEV)
+    vals = None if is_filter else S.values(n, b, 61, device=DEV)
+    print(f"[graph] prepared sharded build filter={is_filter} b={b} h={h} packed={packed}",
+          flush=True)
+    st = vf.Structure.prepare(n, b=b, filter=is_filter, h=h, seed=4, packed=packed,
+                              device=DEV)
+    with pytest.raises(vf.VFError):
+        st.query(keys[:1])
+    st.launch(keys, vals)
+    assert st.finish() == vf.VF_OK
+    ob = _oracle_fixed(keys, vals, b, is_filter, h, 4, st.info["M"])
+    _same_as_oracle(st, ob, b)
+    q, _ = S.queries(keys, 20000, 62)
+    got = st.query(q).cpu().numpy()
+    if not is_filter:
+        got = got.view(_NP[got.itemsize])
+    assert np.array_equal(got.astype(np.uint64), O.query(ob, q.cpu().numpy().view(np.uint64)))
+    st.free()
+
+
+def test_captured_sharded_build_replays_and_reports_bad_input():
+    n, b, h = 1 << 17, 12, 3
+    keys = S.member_keys(n, 71, device=DEV)
+    vals = S.values(n, b, 71, device=DEV)
+    print("[graph] sharded build capture", flush=True)
+    st = vf.Structure.prepare(n, b=b, filter=False, h=h, seed=2, device=DEV)
+    st.launch(keys, vals)  # eager run first (loads the kernels)
+    assert st.finish() == vf.VF_OK
+    eager = (st.cells().cpu().clone(), st.local_seeds().cpu().clone(), st.failures)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        st.launch(keys, vals)
+    torch.cuda.synchronize()
+    x = torch.arange(1 << 20, device=DEV, dtype=torch.float32)
+    for r in range(3):
+        print(f"[graph] sharded replay {r}", flush=True)
+        st.structure.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        assert st.finish() == vf.VF_OK
+        assert torch.equal(st.cells().cpu(), eager[0])
+        assert torch.equal(st.local_seeds().cpu(), eager[1]) and st.failures == eager[2]
+        x = torch.sqrt(x + 1.0)
+        torch.cuda.synchronize()
+    # new keys in the captured buffers: the oracle's structure for them
+    # (keys of data seed 72 put 16 857 keys in one shard, above the bound of
+    # 16 840: that build is refused, see the test below)
+    keys2, vals2 = S.member_keys(n, 73, device=DEV), S.values(n, b, 73, device=DEV)
+    keys.copy_(keys2)
+    vals.copy_(vals2)
+    torch.cuda.synchronize()
+    g.replay()
+    assert st.finish() == vf.VF_OK
+    _same_as_oracle(st, _oracle_fixed(keys2, vals2, b, False, h, 2, st.info["M"]), b)
+    # a value too wide: nothing is written, finish reports it
+    before = st.structure.clone()
+    vals[5] = vals[5] | (1 << b)
+    torch.cuda.synchronize()
+    g.replay()
+    with pytest.raises(vf.VFError) as e:
+        st.finish()
+    assert e.value.code == vf.VF_EINVAL
+    assert torch.equal(st.structure, before)
+    st.free()
+
+
+def test_prepared_build_with_a_bound_below_the_largest_shard_is_refused():
+    n, h = 1 << 16, 4
+    keys = S.member_keys(n, 81, device=DEV)
+    st = vf.Structure.prepare(n, b=8, filter=True, h=h, max_shard=n >> h, device=DEV)
+    before = st.structure.clone()
+    st.launch(keys)
+    with pytest.raises(vf.VFError) as e:
+        st.finish()
+    assert e.value.code == vf.VF_ENOSPC
+    assert "above the bound" in vf.vf_last_error()
+    assert torch.equal(st.structure, before)
+    st.free()

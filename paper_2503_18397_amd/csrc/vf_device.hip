@@ -1395,44 +1395,30 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
               }
             }
           };
-          // the slot of the c-th active row: the r-th set bit of the mask of
-          // the group that holds it (binary search on the count below)
+          // the slot of the c-th active row: each active slot writes itself
+          // to position c (its group's offset plus the active lanes below
+          // it) in the rows' padding words, which hold nothing between the
+          // end of the previous word and this word's masks (the search
+          // zeroes them for every slot in use before writing masks, and the
+          // emitters read them only for a word with pivots)
           auto compact = [&](auto groups) -> uint32_t {
             constexpr int NG = decltype(groups)::value;
-            uint64_t act[NG];
-            uint32_t off[NG + 1];
-            off[0] = 0;
+            uint32_t off = 0;
 #pragma unroll
             for (int q = 0; q < NG; q++) {
               const uint32_t slot = (uint32_t)q * 64 + lane;
               const uint32_t sl = slot < W ? slot : 0u;
               const bool a = slot < W && rpop[sl] != 0 && (rows[(uint64_t)sl * RS + word] & range) != 0;
-              act[q] = __ballot(a);
-              off[q + 1] = off[q] + (uint32_t)__popcll(act[q]);
+              const uint64_t act = __ballot(a);
+              if (a) rows[(uint64_t)(off + lanes_below(act)) * RS + RW] = slot;
+              off += (uint32_t)__popcll(act);
             }
-            const uint32_t na = off[NG], nc = (na + 63) >> 6;
+            const uint32_t na = off, nc = (na + 63) >> 6;
+            wave_sync();
 #pragma unroll
             for (int g = 0; g < QM; g++) {
               const uint32_t ci = (uint32_t)g * 64 + lane;
-              uint32_t sl = kNoSlot;
-              if ((uint32_t)g < nc && ci < na) {
-                uint64_t msk = 0;
-                uint32_t base = 0, qs = 0;
-#pragma unroll
-                for (int q = 0; q < NG; q++)
-                  if (act[q] && ci >= off[q]) {
-                    msk = act[q];
-                    base = off[q];
-                    qs = (uint32_t)q;
-                  }
-                const uint32_t r = ci - base;
-                uint32_t lo = 0;
-#pragma unroll
-                for (uint32_t step = 32; step; step >>= 1)
-                  if ((uint32_t)__popcll(msk & ((1ull << (lo + step)) - 1ull)) <= r) lo += step;
-                sl = qs * 64 + lo;
-              }
-              csl[g] = sl;
+              csl[g] = (uint32_t)g < nc && ci < na ? rows[(uint64_t)ci * RS + RW] : kNoSlot;
             }
             return nc;
           };

@@ -1570,10 +1570,27 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
 // the current batch gathers its values, so a batch costs about one round
 // trip to memory and its stores; the few long records are gathered by the
 // whole wavefront, 64 entries per round trip.
+//
+// With ring (LDS, kRing cells), the values of the kRing columns below the
+// batch are kept there too: most of a record's vertices lie within three
+// segments below its column, so with 3 s + 64 <= kRing nearly every gather
+// is an LDS read and a batch waits for no global store of the batch before
+// it.  A vertex farther down (records grown by elimination) is read from
+// the cells after the wavefront's stores have completed.  The columns
+// between consecutive pivots (free or outside the 2-core) are cleared in
+// the ring as the sweep passes them.
+constexpr uint32_t kRing = 2048;
+// LDS of the ring for cells of T (none for 8-byte cells, whose ring would
+// cost the window too many slots).
+template <typename T>
+__host__ __device__ constexpr uint32_t ring_bytes() {
+  return sizeof(T) <= 4 ? kRing * (uint32_t)sizeof(T) : 0u;
+}
 template <typename T>
 __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np, T *wl,
-                                                uint32_t *bcol, bool cells_global) {
-  constexpr uint32_t kPre = 4;
+                                                uint32_t *bcol, bool cells_global,
+                                                T *ring = nullptr) {
+  constexpr uint32_t kPre = 8;
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t lane = lane_id();
   const uint32_t *const plog = sc.plog;
@@ -1608,11 +1625,28 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
   };
   Head cur = load_head(load_off(0));
   uint32_t off_next = load_off(64);
+  if (ring) {
+    for (uint32_t i = lane; i < kRing; i += 64) ring[i] = (T)0;
+    wave_sync();
+  }
+  // a vertex v below the batch's lowest column bmin held by the ring
+  auto in_ring = [&](uint32_t v, uint32_t bmin) { return ring && bmin - v <= kRing; };
+  auto cell = [&](uint32_t v, uint32_t bmin) -> uint64_t {
+    return in_ring(v, bmin) ? (uint64_t)ring[v & (kRing - 1)] : (uint64_t)wl[v];
+  };
+  uint32_t prev_last = 0xFFFFFFFFu;  // the previous batch's highest pivot column
   for (uint32_t bs = 0; bs < np; bs += 64) {
     const bool valid = bs + lane < np;
     bcol[lane] = cur.col;
     wave_sync();
     const uint32_t bmin = bcol[0];
+    if (ring && bs) {
+      // the columns between the previous batch and this one, which this
+      // batch's records may reference, are cleared before they are read
+      const uint32_t gap = min(bmin - prev_last - 1u, kRing);
+      for (uint32_t g = lane; g < gap; g += 64) ring[(bmin - 1u - g) & (kRing - 1)] = (T)0;
+      wave_sync();
+    }
     // the next batch's headers and the offsets of the one after it
     const Head nxt = load_head(off_next);
     const uint32_t off_after = load_off(bs + 128);
@@ -1629,10 +1663,17 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
       return lo < below && bcol[lo] == v ? 1ull << lo : 0ull;
     };
     {
+      if (ring) {
+        bool far = false;
+#pragma unroll
+        for (uint32_t k = 0; k < kPre; k++)
+          far |= k < cur.cnt && cur.ent[k] < bmin && !in_ring(cur.ent[k], bmin);
+        if (__ballot(far)) wave_sync_global();
+      }
       uint64_t w[kPre];
 #pragma unroll
       for (uint32_t k = 0; k < kPre; k++)
-        w[k] = k < cur.cnt && cur.ent[k] < bmin ? (uint64_t)wl[cur.ent[k]] : 0ull;
+        w[k] = k < cur.cnt && cur.ent[k] < bmin ? cell(cur.ent[k], bmin) : 0ull;
 #pragma unroll
       for (uint32_t k = 0; k < kPre; k++) {
         if (k < cur.cnt) {
@@ -1648,9 +1689,10 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
       uint64_t pacc = 0, pdep = 0;
       for (uint32_t e0 = kPre; e0 < cnt; e0 += 64) {
         const uint32_t e = e0 + lane;
+        const uint32_t v = e < cnt ? plog[off + 4 + e] : kNone;
+        if (ring && __ballot(v < bmin && !in_ring(v, bmin))) wave_sync_global();
         if (e < cnt) {
-          const uint32_t v = plog[off + 4 + e];
-          if (v < bmin) pacc ^= (uint64_t)wl[v];
+          if (v < bmin) pacc ^= cell(v, bmin);
           else pdep |= depbit(v, L);
         }
       }
@@ -1667,11 +1709,30 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
       if ((dep >> k) & 1ull) x ^= xk;
     }
     if (valid) wl[cur.col] = (T)x;
-    if (cells_global) wave_sync_global();
-    else wave_sync();
+    if (ring) {
+      // this batch's pivots into the ring, the columns between them
+      // cleared (below the first, at the start of the next batch).  Only
+      // the kRing columns up to the batch's highest pivot are written, so
+      // no two lanes write one slot (the batch may span more columns).
+      const uint32_t last = readlane(cur.col, (int)min(63u, np - 1 - bs));
+      const uint32_t below = __shfl_up(cur.col, 1);
+      const uint32_t pc = lane == 0 ? cur.col - 1u : below;
+      if (valid && last - cur.col < kRing) {
+        const uint32_t gap = min(cur.col - pc - 1u, kRing - 1u - (last - cur.col));
+        for (uint32_t g = 0; g < gap; g++) ring[(cur.col - 1u - g) & (kRing - 1)] = (T)0;
+        ring[cur.col & (kRing - 1)] = (T)x;
+      }
+      prev_last = last;
+      wave_sync();
+    } else if (cells_global) {
+      wave_sync_global();
+    } else {
+      wave_sync();
+    }
     cur = nxt;
     off_next = off_after;
   }
+  if (ring && cells_global) wave_sync_global();
 }
 
 // Exclusive prefix sum of a[0..n) in place (one wavefront), returns the total.
@@ -2287,7 +2348,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       if (s >= kSlots) break;
       const ShardBufs sb = bufs(s);
       const Geo G = geo(s);
-      const uint32_t W = min(A.wmax, window_slots_for(G.sigma, A.lds_bytes));
+      const uint32_t W = min(A.wmax, window_slots_for(G.sigma, A.lds_bytes - ring_bytes<T>()));
       uint32_t np = 0;
       VF_CLK(c0b);
       const int st = band_solve<QM>(A, G, W, sb, lds, ctl, bw, &np, pc, gen);
@@ -2325,6 +2386,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   } else {
     // ----------------------------------------------- assignment (wavefront 3)
     uint32_t *const bcol = (uint32_t *)(lds + A.lds_bytes - kBcolBytes);
+    // the ring of the back-substitution sits between the window and the
+    // control blocks at the end of the LDS
+    T *const ring = ring_bytes<T>() ? (T *)(lds + A.lds_bytes - kLdsTail - ring_bytes<T>())
+                                    : nullptr;
     for (;;) {
       uint32_t s = kSlots;
       wait_for(pc, A.work, [&] {
@@ -2344,7 +2409,8 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
       wave_sync_global();
       VF_CLK(c0a);
-      if (np) back_substitute<T>(sb, np, wg, bcol, true);
+      const bool use_ring = ring && 3u * (1u << uniform(rec[s].sigma)) + 64u <= kRing;
+      if (np) back_substitute<T>(sb, np, wg, bcol, true, use_ring ? ring : nullptr);
       for (int r = (int)nrounds - 1; r >= 0; r--) {
         const uint32_t e0 = sb.rst[r], e1 = sb.rst[r + 1];
         for (uint32_t i = e0 + lane; i < e1; i += 64) {

@@ -56,11 +56,18 @@ static __device__ unsigned long long stage_clk[vfk::kClkWGs * vfk::kClkSlots];
       atomicAdd(&stage_clk[blockIdx.x * vfk::kClkSlots + (slot)],                      \
                 (unsigned long long)(ticks));                                          \
   } while (0)
+#define VF_CLK_MAX(slot, ticks)                                                        \
+  do {                                                                                 \
+    if (lane_id() == 0 && blockIdx.x < vfk::kClkWGs)                                   \
+      atomicMax(&stage_clk[blockIdx.x * vfk::kClkSlots + (slot)],                      \
+                (unsigned long long)(ticks));                                          \
+  } while (0)
 #else
 #define VF_CLK(v)
 #define VF_CLKV(v)
 #define VF_CLK_SET(v)
 #define VF_CLK_ADD(slot, ticks)
+#define VF_CLK_MAX(slot, ticks)
 #endif
 
 namespace vfk {
@@ -701,6 +708,11 @@ constexpr uint32_t kSlots = 3;
 
 __host__ __device__ inline uint64_t align8(uint64_t x) { return (x + 7) & ~7ull; }
 
+// Entries the back-substitution loads with each pivot record's header, all
+// of them whatever the record's length: the pivot log has as many words of
+// slack after its capacity.
+constexpr uint32_t kBackPre = 8;
+
 // Core rows enter the elimination window in groups: the 32 columns of one
 // ring word (segments of at least 32 vertices) or one segment (smaller
 // segments), keyed by the row's top vertex.
@@ -726,7 +738,7 @@ __host__ __device__ inline uint64_t slot_layout(uint8_t *base, uint32_t M, uint6
   t.cR = (uint64_t *)take(8 * m);
   t.cb = (uint32_t *)take(4 * max_groups(V, l));
   t.poff = (uint32_t *)take(4 * m);
-  t.plog = (uint32_t *)take(4 * (uint64_t)logcap);
+  t.plog = (uint32_t *)take(4 * ((uint64_t)logcap + kBackPre));
   if (sb) *sb = t;
   return o;
 }
@@ -1549,14 +1561,36 @@ __device__ __forceinline__ uint64_t wave_xor64(uint64_t x) {
   }
   return x;
 }
-__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, d);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), d);
-    x |= (uint64_t)lo | ((uint64_t)hi << 32);
-  }
-  return x;
+
+// Xor and or of a 64-bit value over the wavefront, in every lane (the DPP
+// row steps, then the four rows' totals); every lane must take part.
+__device__ __forceinline__ uint64_t wave_xor64_total(uint64_t x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  lo ^= VF_DPP(lo, kQuadSwap1, 0u);
+  hi ^= VF_DPP(hi, kQuadSwap1, 0u);
+  lo ^= VF_DPP(lo, kQuadSwap2, 0u);
+  hi ^= VF_DPP(hi, kQuadSwap2, 0u);
+  lo ^= VF_DPP(lo, kRowHalfMirror, 0u);
+  hi ^= VF_DPP(hi, kRowHalfMirror, 0u);
+  lo ^= VF_DPP(lo, kRowMirror, 0u);
+  hi ^= VF_DPP(hi, kRowMirror, 0u);
+  lo = readlane(lo, 0) ^ readlane(lo, 16) ^ readlane(lo, 32) ^ readlane(lo, 48);
+  hi = readlane(hi, 0) ^ readlane(hi, 16) ^ readlane(hi, 32) ^ readlane(hi, 48);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+__device__ __forceinline__ uint64_t wave_or64_total(uint64_t x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  lo |= VF_DPP(lo, kQuadSwap1, 0u);
+  hi |= VF_DPP(hi, kQuadSwap1, 0u);
+  lo |= VF_DPP(lo, kQuadSwap2, 0u);
+  hi |= VF_DPP(hi, kQuadSwap2, 0u);
+  lo |= VF_DPP(lo, kRowHalfMirror, 0u);
+  hi |= VF_DPP(hi, kRowHalfMirror, 0u);
+  lo |= VF_DPP(lo, kRowMirror, 0u);
+  hi |= VF_DPP(hi, kRowMirror, 0u);
+  lo = readlane(lo, 0) | readlane(lo, 16) | readlane(lo, 32) | readlane(lo, 48);
+  hi = readlane(hi, 0) | readlane(hi, 16) | readlane(hi, 32) | readlane(hi, 48);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 // Back-substitution of the pivot log (records [column, count, rhs lo, rhs
@@ -1565,20 +1599,26 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
 // pivot column is its right side xor the values of its record's vertices.
 // Vertices below the batch have their final values; a vertex inside the
 // batch's range is a pivot column of the batch (a dependency, resolved in
-// lane order) or free (value 0).  The next batch's record headers and first
-// kPre entries, and the offsets of the batch after it, are loaded while
-// the current batch gathers its values, so a batch costs about one round
-// trip to memory and its stores; the few long records are gathered by the
-// whole wavefront, 64 entries per round trip.
+// lane order) or free (value 0).
 //
-// With ring (LDS, kRing cells), the values of the kRing columns below the
-// batch are kept there too: most of a record's vertices lie within three
-// segments below its column, so with 3 s + 64 <= kRing nearly every gather
-// is an LDS read and a batch waits for no global store of the batch before
-// it.  A vertex farther down (records grown by elimination) is read from
-// the cells after the wavefront's stores have completed.  The columns
+// Loads run ahead of their use: the next batch's record headers with their
+// first kBackPre entries (read whole: the pivot log has kBackPre words of
+// slack) and the offsets of the batch after it load while the current
+// batch gathers.  The longer records are gathered by the whole wavefront,
+// 64 entries per step, each step's entries loading while the step before
+// is combined (the first step's from before the end of the previous batch).
+//
+// With ring (LDS, kRing cells), the values of the columns up to kRing below
+// the batch are kept there too: most of a record's vertices lie within
+// three segments below its column, so with 3 s + 64 <= kRing nearly every
+// gather is an LDS read and a batch waits for no global store of the batch
+// before it.  A vertex farther down (records grown by elimination) is read
+// from the cells after the wavefront's stores have completed.  The columns
 // between consecutive pivots (free or outside the 2-core) are cleared in
-// the ring as the sweep passes them.
+// the ring as the sweep passes them.  While a batch that spans fewer than
+// kRing / 2 columns gathers, the slots of its own columns hold the lane of
+// each of its pivots, so a dependency takes two LDS reads (the lane, then
+// its column to confirm) instead of a binary search over the batch.
 constexpr uint32_t kRing = 2048;
 // LDS of the ring for cells of T (none for 8-byte cells, whose ring would
 // cost the window too many slots).
@@ -1588,9 +1628,8 @@ __host__ __device__ constexpr uint32_t ring_bytes() {
 }
 template <typename T>
 __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np, T *wl,
-                                                uint32_t *bcol, bool cells_global,
-                                                T *ring = nullptr) {
-  constexpr uint32_t kPre = 8;
+                                                uint32_t *bcol, T *ring) {
+  constexpr uint32_t kPre = kBackPre;
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t lane = lane_id();
   const uint32_t *const plog = sc.plog;
@@ -1602,7 +1641,7 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
   struct Head {
     uint32_t col, cnt, off;
     uint64_t rhs;
-    uint32_t ent[kPre];
+    uint32_t ent[kPre];  // entries k < cnt are the record's
   };
   auto load_head = [&](uint32_t off) {
     Head hd;
@@ -1611,17 +1650,39 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
     hd.cnt = 0;
     hd.rhs = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < kPre; k++) hd.ent[k] = 0;
+    for (uint32_t k = 0; k < kPre; k++) hd.ent[k] = kNone;
     if (off != kNone) {
       const uint32_t *const rec = plog + off;
       hd.col = rec[0];
       hd.cnt = rec[1];
       hd.rhs = (uint64_t)rec[2] | ((uint64_t)rec[3] << 32);
+      // independent of cnt, so that all of them load at once
 #pragma unroll
-      for (uint32_t k = 0; k < kPre; k++)
-        if (k < hd.cnt) hd.ent[k] = rec[4 + k];
+      for (uint32_t k = 0; k < kPre; k++) hd.ent[k] = rec[4 + k];
     }
     return hd;
+  };
+  // one step over a record longer than kPre: lanes lm of such records still
+  // to gather (the lowest, L, in this step), L's offset and count, the
+  // step's first entry e and this lane's entry v (kNone: none)
+  struct Step {
+    uint64_t lm;
+    uint32_t L, off, cnt, e, v;
+  };
+  auto first_step = [&](const Head &h) {
+    Step st;
+    st.lm = __ballot(h.cnt > kPre);
+    st.L = 64;
+    st.off = st.cnt = 0;
+    st.e = kPre;
+    st.v = kNone;
+    if (st.lm) {
+      st.L = (uint32_t)__ffsll((long long)st.lm) - 1;
+      st.off = readlane(h.off, (int)st.L);
+      st.cnt = readlane(h.cnt, (int)st.L);
+      if (kPre + lane < st.cnt) st.v = plog[st.off + 4 + kPre + lane];
+    }
+    return st;
   };
   Head cur = load_head(load_off(0));
   uint32_t off_next = load_off(64);
@@ -1629,51 +1690,64 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
     for (uint32_t i = lane; i < kRing; i += 64) ring[i] = (T)0;
     wave_sync();
   }
-  // a vertex v below the batch's lowest column bmin held by the ring
-  auto in_ring = [&](uint32_t v, uint32_t bmin) { return ring && bmin - v <= kRing; };
-  auto cell = [&](uint32_t v, uint32_t bmin) -> uint64_t {
-    return in_ring(v, bmin) ? (uint64_t)ring[v & (kRing - 1)] : (uint64_t)wl[v];
-  };
-  uint32_t prev_last = 0xFFFFFFFFu;  // the previous batch's highest pivot column
+  Step st = first_step(cur);
+  uint32_t prev_last = kNone;  // the previous batch's highest pivot column
   for (uint32_t bs = 0; bs < np; bs += 64) {
     const bool valid = bs + lane < np;
+    const uint32_t bmin = readlane(cur.col, 0);
+    const uint32_t last = readlane(cur.col, (int)min(63u, np - 1 - bs));
     bcol[lane] = cur.col;
-    wave_sync();
-    const uint32_t bmin = bcol[0];
-    if (ring && bs) {
+    const bool tags = ring && last - bmin < kRing / 2;
+    if (ring) {
       // the columns between the previous batch and this one, which this
       // batch's records may reference, are cleared before they are read
-      const uint32_t gap = min(bmin - prev_last - 1u, kRing);
-      for (uint32_t g = lane; g < gap; g += 64) ring[(bmin - 1u - g) & (kRing - 1)] = (T)0;
+      if (bs) {
+        const uint32_t gap = min(bmin - prev_last - 1u, kRing);
+        for (uint32_t g = lane; g < gap; g += 64) ring[(bmin - 1u - g) & (kRing - 1)] = (T)0;
+      }
       wave_sync();
+      if (tags && valid) ring[cur.col & (kRing - 1)] = (T)lane;
     }
+    wave_sync();
+    // the ring holds the values of columns [rtop - kRing, bmin)
+    const uint32_t rtop = tags ? last + 1u : bmin;
+    auto in_ring = [&](uint32_t v) { return ring && rtop - v <= kRing; };
+    auto cell = [&](uint32_t v) -> uint64_t {
+      return in_ring(v) ? (uint64_t)ring[v & (kRing - 1)] : (uint64_t)wl[v];
+    };
+    // dependency bit of vertex v of this batch's range (bcol increases
+    // with the lane; a pivot only depends on lower lanes)
+    auto depbit = [&](uint32_t v, uint32_t below) -> uint64_t {
+      uint32_t i;
+      if (tags) {
+        i = (uint32_t)ring[v & (kRing - 1)] & 63u;
+      } else {
+        uint32_t lo = 0, hi = below;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (bcol[mid] < v) lo = mid + 1;
+          else hi = mid;
+        }
+        i = lo;
+      }
+      return i < below && bcol[i] == v ? 1ull << i : 0ull;
+    };
     // the next batch's headers and the offsets of the one after it
     const Head nxt = load_head(off_next);
     const uint32_t off_after = load_off(bs + 128);
     uint64_t acc = cur.rhs, dep = 0;
-    // dependency bit of vertex v of this batch's range (bcol increases
-    // with the lane; a pivot only depends on lower lanes)
-    auto depbit = [&](uint32_t v, uint32_t below) -> uint64_t {
-      uint32_t lo = 0, hi = below;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (bcol[mid] < v) lo = mid + 1;
-        else hi = mid;
-      }
-      return lo < below && bcol[lo] == v ? 1ull << lo : 0ull;
-    };
     {
       if (ring) {
         bool far = false;
 #pragma unroll
         for (uint32_t k = 0; k < kPre; k++)
-          far |= k < cur.cnt && cur.ent[k] < bmin && !in_ring(cur.ent[k], bmin);
+          far |= k < cur.cnt && cur.ent[k] < bmin && !in_ring(cur.ent[k]);
         if (__ballot(far)) wave_sync_global();
       }
       uint64_t w[kPre];
 #pragma unroll
       for (uint32_t k = 0; k < kPre; k++)
-        w[k] = k < cur.cnt && cur.ent[k] < bmin ? cell(cur.ent[k], bmin) : 0ull;
+        w[k] = k < cur.cnt && cur.ent[k] < bmin ? cell(cur.ent[k]) : 0ull;
 #pragma unroll
       for (uint32_t k = 0; k < kPre; k++) {
         if (k < cur.cnt) {
@@ -1682,29 +1756,48 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
         }
       }
     }
-    // records longer than kPre: the whole wavefront gathers one at a time
-    for (uint64_t lm = __ballot(valid && cur.cnt > kPre); lm; lm &= lm - 1) {
-      const uint32_t L = (uint32_t)__ffsll((long long)lm) - 1;
-      const uint32_t off = readlane(cur.off, (int)L), cnt = readlane(cur.cnt, (int)L);
+    // records longer than kPre, one step of 64 entries at a time
+    if (st.lm) {
       uint64_t pacc = 0, pdep = 0;
-      for (uint32_t e0 = kPre; e0 < cnt; e0 += 64) {
-        const uint32_t e = e0 + lane;
-        const uint32_t v = e < cnt ? plog[off + 4 + e] : kNone;
-        if (ring && __ballot(v < bmin && !in_ring(v, bmin))) wave_sync_global();
-        if (e < cnt) {
-          if (v < bmin) pacc ^= cell(v, bmin);
-          else pdep |= depbit(v, L);
+      for (;;) {
+        // the step after this one: record L's next entries, or the next
+        // long record's first
+        Step nx = st;
+        nx.e = st.e + 64;
+        const bool rec_done = nx.e >= st.cnt;
+        if (rec_done) {
+          nx.lm &= nx.lm - 1;
+          nx.e = kPre;
+          if (nx.lm) {
+            nx.L = (uint32_t)__ffsll((long long)nx.lm) - 1;
+            nx.off = readlane(cur.off, (int)nx.L);
+            nx.cnt = readlane(cur.cnt, (int)nx.L);
+          }
         }
-      }
-      pacc = wave_xor64(pacc);
-      pdep = wave_or64(pdep);
-      if (lane == L) {
-        acc ^= pacc;
-        dep |= pdep;
+        nx.v = kNone;
+        if (nx.lm && nx.e + lane < nx.cnt) nx.v = plog[nx.off + 4 + nx.e + lane];
+        const uint32_t v = st.v;
+        if (ring && __ballot(v < bmin && !in_ring(v))) wave_sync_global();
+        if (v < bmin) pacc ^= cell(v);
+        else if (v != kNone) pdep |= depbit(v, st.L);
+        if (rec_done) {
+          const uint64_t ta = wave_xor64_total(pacc), td = wave_or64_total(pdep);
+          if (lane == st.L) {
+            acc ^= ta;
+            dep |= td;
+          }
+          pacc = pdep = 0;
+        }
+        st = nx;
+        if (!st.lm) break;
       }
     }
+    // the next batch's first long step loads while this one finishes
+    st = first_step(nxt);
+    // dependencies in lane order (only lanes some pivot depends on)
     uint64_t x = acc;
-    for (uint32_t k = 0; k < 64 && bs + k < np; k++) {
+    for (uint64_t dm = wave_or64_total(dep); dm; dm &= dm - 1) {
+      const uint32_t k = (uint32_t)__ffsll((long long)dm) - 1;
       const uint64_t xk = readlane64(x, (int)k);
       if ((dep >> k) & 1ull) x ^= xk;
     }
@@ -1714,7 +1807,6 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
       // cleared (below the first, at the start of the next batch).  Only
       // the kRing columns up to the batch's highest pivot are written, so
       // no two lanes write one slot (the batch may span more columns).
-      const uint32_t last = readlane(cur.col, (int)min(63u, np - 1 - bs));
       const uint32_t below = __shfl_up(cur.col, 1);
       const uint32_t pc = lane == 0 ? cur.col - 1u : below;
       if (valid && last - cur.col < kRing) {
@@ -1724,15 +1816,13 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
       }
       prev_last = last;
       wave_sync();
-    } else if (cells_global) {
-      wave_sync_global();
     } else {
-      wave_sync();
+      wave_sync_global();
     }
     cur = nxt;
     off_next = off_after;
   }
-  if (ring && cells_global) wave_sync_global();
+  if (ring) wave_sync_global();
 }
 
 // Exclusive prefix sum of a[0..n) in place (one wavefront), returns the total.
@@ -2355,6 +2445,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       if (bw == 0) {
         VF_CLK_ADD(kClkBand, wall_clock64() - c0b);
         VF_CLK_ADD(kClkBand + 1, 1);
+        VF_CLK_MAX(kClkElimEnd, wall_clock64() - ck0);
       }
       if (bw == 0) {
         const uint32_t j = uniform(rec[s].shard), t = uniform(rec[s].t);
@@ -2410,7 +2501,8 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       wave_sync_global();
       VF_CLK(c0a);
       const bool use_ring = ring && 3u * (1u << uniform(rec[s].sigma)) + 64u <= kRing;
-      if (np) back_substitute<T>(sb, np, wg, bcol, true, use_ring ? ring : nullptr);
+      if (np) back_substitute<T>(sb, np, wg, bcol, use_ring ? ring : nullptr);
+      VF_CLK_ADD(kClkBackSub, wall_clock64() - c0a);
       for (int r = (int)nrounds - 1; r >= 0; r--) {
         const uint32_t e0 = sb.rst[r], e1 = sb.rst[r + 1];
         for (uint32_t i = e0 + lane; i < e1; i += 64) {

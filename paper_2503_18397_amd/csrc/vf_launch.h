@@ -158,8 +158,10 @@ enum : uint32_t {
   kClkSearch = 8,   // 7 slots, per 32-column word of the searching wavefront:
                     // returned slots + entering rows, compaction, pivot
                     // search, row updates, flags, barrier; words
+  kClkBackSub = 15, // ticks: back-substitutions (within kClkAssign)
   kClkEmit = 16,    // the same 7 slots for emitting wavefront 1 (emission,
                     // wait for the batch + row updates in slots 1 and 2)
+  kClkElimEnd = 23, // ticks from the start to the end of the last elimination
   kClkPeelPhases = 24  // 8 slots, per attempt's peel: edges + cleared state,
                        // incidence, first frontier, rounds, 2-core grouping,
                        // duplicate-row check; attempts; rounds

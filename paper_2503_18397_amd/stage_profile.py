@@ -81,8 +81,12 @@ def main() -> None:
                 "peeling_wavefront": round(float(us[:, 0].mean()) / 1e3, 3),
                 "elimination": round(float(us[:, 2].mean()) / 1e3, 3),
                 "assignment": round(float(us[:, 4].mean()) / 1e3, 3)},
+            "after_last_elimination_ms": {
+                "mean": round(float((us[:, 7] - us[:, 23]).mean()) / 1e3, 3),
+                "of_the_slowest_workgroup": round(float(
+                    (us[:, 7] - us[:, 23])[int(us[:, 7].argmax())]) / 1e3, 3)},
             "per_item_ms": {"peel": per(0, 1), "elimination": per(2, 3),
-                            "assignment": per(4, 5)},
+                            "assignment": per(4, 5), "of_which_back_substitution": per(15, 5)},
             "per_word_us": ph,
             "peel_per_attempt_us": peel,
         }

@@ -172,6 +172,9 @@ __device__ __forceinline__ void wave_sync_global() {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Two 16-bit lanes of one register (packed saturating arithmetic).
+typedef int16_t ss2 __attribute__((ext_vector_type(2)));
+
 // Cross-lane reductions with DPP (VALU only, no LDS round trip): within each
 // row of 16 lanes quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror
 // and row_mirror leave the row's total in every lane.  For the idempotent
@@ -185,6 +188,12 @@ constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
 
 __device__ __forceinline__ uint32_t readlane(uint32_t x, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
+}
+// Lane `lane` of old set to a value the wavefront holds alike (the LLVM
+// intrinsic behind v_writelane_b32, which has no clang builtin).
+extern "C" __device__ int vf_writelane_i32(int, int, int) __asm("llvm.amdgcn.writelane.i32");
+__device__ __forceinline__ uint32_t writelane(uint32_t old, uint32_t val, uint32_t lane) {
+  return (uint32_t)vf_writelane_i32((int)val, (int)lane, (int)old);
 }
 // A value the whole wavefront holds alike, kept in a scalar register.
 __device__ __forceinline__ uint32_t uniform(uint32_t x) {
@@ -1305,27 +1314,31 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
               ccm[g] = 0;
               orv |= ccw[g];
             }
-            // key of a row: popcount estimate (high half, below 2^16) and
-            // compact index (the low half of kcap)
-            uint32_t key[NC], kcap[NC];
+            // key of a row: popcount estimate (high half, below 2^15) and
+            // compact index (low half)
+            uint32_t key[NC];
 #pragma unroll
-            for (int g = 0; g < NC; g++) {
-              kcap[g] = 0xFFFF0000u | ((uint32_t)g * 64 + lane);
-              key[g] = (cpop[g] << 16) | ((uint32_t)g * 64 + lane);
-            }
+            for (int g = 0; g < NC; g++) key[g] = (cpop[g] << 16) | ((uint32_t)g * 64 + lane);
             uint32_t colmask = wave_or(orv);
             // One path through the loop body (a column whose rows all lost it
             // finds no pivot and changes nothing), so that the loop carries
             // its registers without copies.
             while (colmask) {
               const uint32_t b = 31 - __clz(colmask), bit = 1u << b;
+              // all ones where the row has column b
+              uint32_t hm[NC];
+#pragma unroll
+              for (int g = 0; g < NC; g++) hm[g] = (uint32_t)__builtin_amdgcn_sbfe((int)ccw[g], (int)b, 1);
               uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
-              for (int g = 0; g < NC; g++) best = min(best, (ccw[g] & bit) ? key[g] : 0xFFFFFFFFu);
+              for (int g = 0; g < NC; g++) best = min(best, key[g] | ~hm[g]);
               best = wave_min(best);
               const bool found = best != 0xFFFFFFFFu;
               const uint32_t p = best & 0xFFFFu, pg = p >> 6, pl = p & 63u;
-              const uint32_t dpop = (best >> 16) - 2u;
+              // a row that takes the pivot row: its estimate grows by the
+              // pivot's less the two copies of column b (the high half of
+              // the key, saturating at 2^15 - 1; the low half is unchanged)
+              const ss2 grow = {0, (int16_t)((int32_t)(best >> 16) - 2)};
               uint32_t pw = 0, pcm = 0, ps = 0;
 #pragma unroll
               for (int g = 0; g < NC; g++) {
@@ -1335,19 +1348,19 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
                   ps = readlane(csl[g], (int)pl);
                 }
               }
-              const bool me = found && lane == k;
-              pivtab = me ? ps : pivtab;
-              pivcol = me ? wbase + b : pivcol;
-              pivcm = me ? pcm : pivcm;
+              // lane k describes pivot k (written whether or not a pivot was
+              // found: lanes from k on are read only once they hold one)
+              pivtab = writelane(pivtab, ps, k);
+              pivcol = writelane(pivcol, wbase + b, k);
+              pivcm = writelane(pivcm, pcm, k);
               cpiv |= found && lane == pl ? 1u << (pg & 31u) : 0u;
               const uint32_t kbit = pcm | (1u << (k & 31u));
 #pragma unroll
               for (int g = 0; g < NC; g++) {
-                const bool has = (ccw[g] & bit) != 0;
-                ccw[g] = has ? ccw[g] ^ pw : ccw[g];
-                ccm[g] = has ? ccm[g] ^ kbit : ccm[g];
-                const uint32_t np_ = min((key[g] >> 16) + dpop, 0xFFFFu);
-                key[g] = has ? (np_ << 16) | (kcap[g] & 0xFFFFu) : key[g];
+                ccw[g] ^= pw & hm[g];
+                ccm[g] ^= kbit & hm[g];
+                const ss2 nk = __builtin_elementwise_add_sat(__builtin_bit_cast(ss2, key[g]), grow);
+                key[g] ^= (key[g] ^ __builtin_bit_cast(uint32_t, nk)) & hm[g];
               }
               k += found ? 1u : 0u;
               // columns below b that may still have rows: the earlier ones

@@ -1428,14 +1428,21 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
           // emitters read them only for a word with pivots)
           auto compact = [&](auto groups) -> uint32_t {
             constexpr int NG = decltype(groups)::value;
-            uint32_t off = 0;
+            // every group's state loads before the first position is written
+            // (the writes go to the same rows array)
+            bool a[NG];
 #pragma unroll
             for (int q = 0; q < NG; q++) {
               const uint32_t slot = (uint32_t)q * 64 + lane;
               const uint32_t sl = slot < W ? slot : 0u;
-              const bool a = slot < W && rpop[sl] != 0 && (rows[(uint64_t)sl * RS + word] & range) != 0;
-              const uint64_t act = __ballot(a);
-              if (a) rows[(uint64_t)(off + lanes_below(act)) * RS + RW] = slot;
+              const uint32_t pop = rpop[sl], wd = rows[(uint64_t)sl * RS + word];
+              a[q] = slot < W && pop != 0 && (wd & range) != 0;
+            }
+            uint32_t off = 0;
+#pragma unroll
+            for (int q = 0; q < NG; q++) {
+              const uint64_t act = __ballot(a[q]);
+              if (a[q]) rows[(uint64_t)(off + lanes_below(act)) * RS + RW] = (uint32_t)q * 64 + lane;
               off += (uint32_t)__popcll(act);
             }
             const uint32_t na = off, nc = (na + 63) >> 6;

@@ -2438,6 +2438,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   } else if (wid != 4) {
     // -------------------------------------- elimination (wavefronts 0, 1, 2)
     const uint32_t bw = wid;  // 0: search, 1 and 2: emit
+    // the SIMDs issue the elimination's instructions ahead of the peeling
+    // and assigning wavefronts', the search's ahead of all
+    if (bw == 0) __builtin_amdgcn_s_setprio(3);
+    else __builtin_amdgcn_s_setprio(2);
     uint32_t gen = 0;
     for (;;) {
       if (bw == 0) {

@@ -1204,10 +1204,10 @@ __device__ __forceinline__ int band_solve(const BuildArgs &A, const Geo &G, uint
   // into up to QM register groups in slot order ("compact" index c =
   // group * 64 + lane); csl holds their slots (kNoSlot past the last).
   // The searching wavefront takes the rows whose compact index is below
-  // kW0Share mod 16 from its registers; the emitters take the others through
+  // kW0Share mod 8 from its registers; the emitters take the others through
   // the rows' padding words, split by slot parity.
-  constexpr uint32_t kNoSlot = 0xFFFFu, kW0Share = 7;
-  auto w1share = [](uint32_t c) { return (c & 15u) >= kW0Share; };
+  constexpr uint32_t kNoSlot = 0xFFFFu, kW0Share = 3;
+  auto w1share = [](uint32_t c) { return (c & 7u) >= kW0Share; };
   uint32_t csl[QM], ccw[QM], cpop[QM], ccm[QM];
   uint32_t it = 0;
   bool stop = false;

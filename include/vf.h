@@ -90,6 +90,14 @@ typedef struct vf_opts {
                          chose for each size class, 1 the one-wavefront
                          kernel for every instance it fits, 2 never it;
                          the cells are the same either way. */
+  uint32_t ring_cols; /* test option: columns the back-substitution keeps in
+                         its LDS ring, a power of two from 64 to 2048, for
+                         every shard with cells of at most 4 bytes whatever
+                         its segment size (so that vertices beyond the ring
+                         and batches wider than half of it occur); 0
+                         (default): 2048, for segment sizes s with
+                         3 s + 64 <= 2048.  The result never depends on it;
+                         other values are VF_EINVAL. */
 } vf_opts;
 
 /* Sizes returned by vf_plan (upper bounds: the largest shard is known only

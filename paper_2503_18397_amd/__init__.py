@@ -41,7 +41,7 @@ class Opts(C.Structure):
     _fields_ = [("h", C.c_int32), ("sigma", C.c_int32), ("c_num", C.c_uint32),
                 ("c_den", C.c_uint32), ("tmax", C.c_uint32), ("alpha", C.c_double),
                 ("mwhc", C.c_int32), ("max_window", C.c_uint32), ("packed", C.c_uint32),
-                ("small", C.c_int32)]
+                ("small", C.c_int32), ("ring_cols", C.c_uint32)]
 
 
 class Sizes(C.Structure):
@@ -470,10 +470,12 @@ class Structure:
     def build(cls, keys: torch.Tensor, values: torch.Tensor | None = None, *, b: int,
               eps: float = 0.0, seed: int = 0, h: int | None = None, sigma: int | None = None,
               c: tuple | None = None, tmax: int | None = None, mwhc: bool = False,
-              max_window: int | None = None, packed: bool = False, stream=None):
+              max_window: int | None = None, packed: bool = False,
+              ring_cols: int | None = None, stream=None):
         is_filter = values is None
         opts = vf_default_opts(h=h, sigma=sigma, tmax=tmax, mwhc=int(mwhc),
-                               max_window=max_window, packed=int(packed))
+                               max_window=max_window, packed=int(packed),
+                               ring_cols=ring_cols)
         if c is not None:
             opts.c_num, opts.c_den = c
         sz = vf_plan(keys.numel(), b, eps, is_filter, opts)
@@ -594,9 +596,9 @@ class Batch:
     def build(cls, keys: torch.Tensor, values: torch.Tensor, n, b, *, seed: int = 0,
               sigma: int | None = None, c: tuple | None = None, tmax: int | None = None,
               max_window: int | None = None, packed: bool = False, small: int = 0,
-              stream=None):
+              ring_cols: int | None = None, stream=None):
         opts = vf_default_opts(sigma=sigma, tmax=tmax, max_window=max_window,
-                               packed=int(packed), small=small)
+                               packed=int(packed), small=small, ring_cols=ring_cols)
         if c is not None:
             opts.c_num, opts.c_den = c
         sz = vf_batch_plan(n, b, opts)

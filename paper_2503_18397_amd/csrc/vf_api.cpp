@@ -251,6 +251,12 @@ struct Layout {
   uint64_t tcells_bytes;
 };
 
+// The back-substitution ring's column count of a test build: 0, or a
+// power of two the kernel's ring holds.
+bool ring_cols_ok(uint32_t c) {
+  return c == 0 || (c >= 64 && c <= vfk::kRingCols && (c & (c - 1)) == 0);
+}
+
 int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts &o,
                 int ncu, Layout *L, uint32_t cap_override = 0) {
   if (b < 1 || b > 64) return VF_EINVAL;
@@ -261,6 +267,7 @@ int make_layout(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_o
   }
   if (h > (int32_t)kMaxShardBits) return VF_EINVAL;
   if (o.tmax < 1 || o.tmax > 255) return VF_EINVAL;
+  if (!ring_cols_ok(o.ring_cols)) return VF_EINVAL;
   if ((o.c_num == 0) != (o.c_den == 0)) return VF_EINVAL;
   if (o.c_num && o.c_num < o.c_den) return VF_EINVAL;  // c >= 1
   if (o.sigma > 20) return VF_EINVAL;
@@ -405,6 +412,7 @@ int make_batch_layout(uint64_t count, const uint64_t *n, const int32_t *b, const
                       int ncu, BatchLayout *L) {
   if (!count || !n || !b || count > 0xFFFFFFFFull) return VF_EINVAL;
   if (o.tmax < 1 || o.tmax > 255) return VF_EINVAL;
+  if (!ring_cols_ok(o.ring_cols)) return VF_EINVAL;
   if ((o.c_num == 0) != (o.c_den == 0)) return VF_EINVAL;
   if (o.c_num && o.c_num < o.c_den) return VF_EINVAL;
   if (o.sigma > 20) return VF_EINVAL;
@@ -552,6 +560,7 @@ void vf_default_opts(vf_opts *o) {
   o->max_window = 0;
   o->packed = 0;
   o->small = 0;
+  o->ring_cols = 0;
 }
 
 int vf_plan(uint64_t n, int32_t b, double eps, int32_t is_filter, const vf_opts *o,
@@ -720,6 +729,7 @@ static int build_common(const uint64_t *keys, const uint64_t *values, uint64_t n
   A.fail_cap = L.fail_cap;
   A.M = M;
   A.tmax = op.tmax;
+  A.ring_cols = op.ring_cols;
   const BuildShape shape = build_shape(g.sigma, L.cell_bytes);
   A.lds_bytes = shape.lds_bytes;
   A.wmax = shape.wmax;
@@ -909,6 +919,7 @@ static int build_prepare(uint64_t n, uint32_t max_shard, int32_t b, double eps, 
   A.fail_cap = L.fail_cap;
   A.M = M;
   A.tmax = op.tmax;
+  A.ring_cols = op.ring_cols;
   const BuildShape shape = build_shape(g.sigma, L.cell_bytes);
   A.lds_bytes = shape.lds_bytes;
   A.wmax = shape.wmax;
@@ -1433,6 +1444,7 @@ static int batch_setup(BatchRun &R, uint64_t count, const uint64_t *n, const int
   A.fail_cap = L.fail_cap;
   A.M = L.maxM;
   A.tmax = R.op.tmax;
+  A.ring_cols = R.op.ring_cols;
   A.logcap = L.logcap;
   // the build reads the workspace descriptors (byte cells); queries read
   // the structure's (packed offsets when packed)

@@ -1628,27 +1628,30 @@ __device__ __forceinline__ uint64_t wave_or64_total(uint64_t x) {
 // 64 entries per step, each step's entries loading while the step before
 // is combined (the first step's from before the end of the previous batch).
 //
-// With ring (LDS, kRing cells), the values of the columns up to kRing below
-// the batch are kept there too: most of a record's vertices lie within
-// three segments below its column, so with 3 s + 64 <= kRing nearly every
+// With ring (LDS, rl cells: a power of two up to kRing, kRing but for test
+// builds), the values of the columns up to rl below the batch are kept
+// there too: most of a record's vertices lie within three segments below
+// its column, so with 3 s + 64 <= rl nearly every
 // gather is an LDS read and a batch waits for no global store of the batch
 // before it.  A vertex farther down (records grown by elimination) is read
 // from the cells after the wavefront's stores have completed.  The columns
 // between consecutive pivots (free or outside the 2-core) are cleared in
 // the ring as the sweep passes them.  While a batch that spans fewer than
-// kRing / 2 columns gathers, the slots of its own columns hold the lane of
+// rl / 2 columns gathers, the slots of its own columns hold the lane of
 // each of its pivots, so a dependency takes two LDS reads (the lane, then
 // its column to confirm) instead of a binary search over the batch.
-constexpr uint32_t kRing = 2048;
+constexpr uint32_t kRing = kRingCols;
 // LDS of the ring for cells of T (none for 8-byte cells, whose ring would
 // cost the window too many slots).
 template <typename T>
 __host__ __device__ constexpr uint32_t ring_bytes() {
   return sizeof(T) <= 4 ? kRing * (uint32_t)sizeof(T) : 0u;
 }
-template <typename T>
+template <typename T, bool kTestRing>
 __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np, T *wl,
-                                                uint32_t *bcol, T *ring) {
+                                                uint32_t *bcol, T *ring, uint32_t ring_cols) {
+  // a compile-time ring length but for test builds
+  const uint32_t rl = kTestRing ? ring_cols : kRing;
   constexpr uint32_t kPre = kBackPre;
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t lane = lane_id();
@@ -1707,7 +1710,7 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
   Head cur = load_head(load_off(0));
   uint32_t off_next = load_off(64);
   if (ring) {
-    for (uint32_t i = lane; i < kRing; i += 64) ring[i] = (T)0;
+    for (uint32_t i = lane; i < rl; i += 64) ring[i] = (T)0;
     wave_sync();
   }
   Step st = first_step(cur);
@@ -1717,30 +1720,30 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
     const uint32_t bmin = readlane(cur.col, 0);
     const uint32_t last = readlane(cur.col, (int)min(63u, np - 1 - bs));
     bcol[lane] = cur.col;
-    const bool tags = ring && last - bmin < kRing / 2;
+    const bool tags = ring && last - bmin < rl / 2;
     if (ring) {
       // the columns between the previous batch and this one, which this
       // batch's records may reference, are cleared before they are read
       if (bs) {
-        const uint32_t gap = min(bmin - prev_last - 1u, kRing);
-        for (uint32_t g = lane; g < gap; g += 64) ring[(bmin - 1u - g) & (kRing - 1)] = (T)0;
+        const uint32_t gap = min(bmin - prev_last - 1u, rl);
+        for (uint32_t g = lane; g < gap; g += 64) ring[(bmin - 1u - g) & (rl - 1)] = (T)0;
       }
       wave_sync();
-      if (tags && valid) ring[cur.col & (kRing - 1)] = (T)lane;
+      if (tags && valid) ring[cur.col & (rl - 1)] = (T)lane;
     }
     wave_sync();
-    // the ring holds the values of columns [rtop - kRing, bmin)
+    // the ring holds the values of columns [rtop - rl, bmin)
     const uint32_t rtop = tags ? last + 1u : bmin;
-    auto in_ring = [&](uint32_t v) { return ring && rtop - v <= kRing; };
+    auto in_ring = [&](uint32_t v) { return ring && rtop - v <= rl; };
     auto cell = [&](uint32_t v) -> uint64_t {
-      return in_ring(v) ? (uint64_t)ring[v & (kRing - 1)] : (uint64_t)wl[v];
+      return in_ring(v) ? (uint64_t)ring[v & (rl - 1)] : (uint64_t)wl[v];
     };
     // dependency bit of vertex v of this batch's range (bcol increases
     // with the lane; a pivot only depends on lower lanes)
     auto depbit = [&](uint32_t v, uint32_t below) -> uint64_t {
       uint32_t i;
       if (tags) {
-        i = (uint32_t)ring[v & (kRing - 1)] & 63u;
+        i = (uint32_t)ring[v & (rl - 1)] & 63u;
       } else {
         uint32_t lo = 0, hi = below;
         while (lo < hi) {
@@ -1825,14 +1828,14 @@ __device__ __forceinline__ void back_substitute(const ShardBufs &sc, uint32_t np
     if (ring) {
       // this batch's pivots into the ring, the columns between them
       // cleared (below the first, at the start of the next batch).  Only
-      // the kRing columns up to the batch's highest pivot are written, so
+      // the ring's rl columns up to the batch's highest pivot are written, so
       // no two lanes write one slot (the batch may span more columns).
       const uint32_t below = __shfl_up(cur.col, 1);
       const uint32_t pc = lane == 0 ? cur.col - 1u : below;
-      if (valid && last - cur.col < kRing) {
-        const uint32_t gap = min(cur.col - pc - 1u, kRing - 1u - (last - cur.col));
-        for (uint32_t g = 0; g < gap; g++) ring[(cur.col - 1u - g) & (kRing - 1)] = (T)0;
-        ring[cur.col & (kRing - 1)] = (T)x;
+      if (valid && last - cur.col < rl) {
+        const uint32_t gap = min(cur.col - pc - 1u, rl - 1u - (last - cur.col));
+        for (uint32_t g = 0; g < gap; g++) ring[(cur.col - 1u - g) & (rl - 1)] = (T)0;
+        ring[cur.col & (rl - 1)] = (T)x;
       }
       prev_last = last;
       wave_sync();
@@ -1889,7 +1892,10 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
 // instructions) shares its SIMD with the two that mostly wait on memory,
 // or with one emitter and one of those (a build 2.5% faster than with the
 // assignment on wavefront 3).
-template <typename T, int QM>
+// TR: a test build whose back-substitution ring holds A.ring_cols columns
+// (launched only when that option is set, so that the kernel of every
+// other build keeps a ring length known at compile time).
+template <typename T, int QM, bool TR>
 __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
   extern __shared__ __align__(16) uint8_t lds[];
   if (A.abort && *A.abort) return;  // same value for every thread
@@ -2532,8 +2538,9 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
       for (uint64_t v = lane; v < V; v += 64) wg[v] = (T)0;
       wave_sync_global();
       VF_CLK(c0a);
-      const bool use_ring = ring && 3u * (1u << uniform(rec[s].sigma)) + 64u <= kRing;
-      if (np) back_substitute<T>(sb, np, wg, bcol, use_ring ? ring : nullptr);
+      // (a test build's ring, of ring_cols columns, for every segment size)
+      const bool use_ring = ring && (TR || 3u * (1u << uniform(rec[s].sigma)) + 64u <= kRing);
+      if (np) back_substitute<T, TR>(sb, np, wg, bcol, use_ring ? ring : nullptr, A.ring_cols);
       VF_CLK_ADD(kClkBackSub, wall_clock64() - c0a);
       for (int r = (int)nrounds - 1; r >= 0; r--) {
         const uint32_t e0 = sb.rst[r], e1 = sb.rst[r + 1];
@@ -3284,7 +3291,7 @@ hipError_t launch_scatter(const uint64_t *keys, const uint64_t *vals, uint64_t n
   return hipGetLastError();
 }
 
-template <typename T, int QM>
+template <typename T, int QM, bool TR = false>
 static hipError_t set_build_lds(uint32_t lds_bytes) {
   // largest dynamic LDS set so far, per device: a launch within it makes no
   // attribute call (none is made while a stream is being captured then)
@@ -3294,7 +3301,7 @@ static hipError_t set_build_lds(uint32_t lds_bytes) {
   if (hipGetDevice(&dev) != hipSuccess) dev = -1;
   const bool cached = dev >= 0 && dev < kDevs;
   if (cached && done[dev].load(std::memory_order_relaxed) >= lds_bytes) return hipSuccess;
-  const hipError_t e = hipFuncSetAttribute((const void *)k_build<T, QM>,
+  const hipError_t e = hipFuncSetAttribute((const void *)k_build<T, QM, TR>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes);
   if (e == hipSuccess && cached) {
@@ -3305,11 +3312,11 @@ static hipError_t set_build_lds(uint32_t lds_bytes) {
   return e;
 }
 
-template <typename T, int QM>
+template <typename T, int QM, bool TR = false>
 static hipError_t launch_build_q(const BuildArgs &a, int nwg, hipStream_t s) {
-  const hipError_t e = set_build_lds<T, QM>(a.lds_bytes);
+  const hipError_t e = set_build_lds<T, QM, TR>(a.lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_build<T, QM>), dim3(nwg), dim3(kBuildThreads), a.lds_bytes, s, a);
+  hipLaunchKernelGGL((k_build<T, QM, TR>), dim3(nwg), dim3(kBuildThreads), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 
@@ -3317,6 +3324,7 @@ static hipError_t launch_build_q(const BuildArgs &a, int nwg, hipStream_t s) {
 // registers; fewer groups mean fewer instructions per column.
 template <typename T>
 static hipError_t launch_build_t(const BuildArgs &a, int nwg, hipStream_t s) {
+  if (a.ring_cols) return launch_build_q<T, 8, true>(a, nwg, s);  // test builds
   return a.wmax <= 256   ? launch_build_q<T, 4>(a, nwg, s)
          : a.wmax <= 384 ? launch_build_q<T, 6>(a, nwg, s)
                          : launch_build_q<T, 8>(a, nwg, s);
@@ -3326,7 +3334,7 @@ template <typename T, int QM>
 static int build_occ_q(uint32_t lds_bytes) {
   int nb = 0;
   if (set_build_lds<T, QM>(lds_bytes) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_build<T, QM>,
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_build<T, QM, false>,
                                                   (int)kBuildThreads, lds_bytes) != hipSuccess)
     return 0;
   return nb;
@@ -3350,6 +3358,7 @@ int build_blocks_per_cu(uint32_t cell_bytes, uint32_t wmax, uint32_t lds_bytes) 
 
 template <typename T>
 static hipError_t prepare_build_t(const BuildArgs &a) {
+  if (a.ring_cols) return set_build_lds<T, 8, true>(a.lds_bytes);
   return a.wmax <= 256   ? set_build_lds<T, 4>(a.lds_bytes)
          : a.wmax <= 384 ? set_build_lds<T, 6>(a.lds_bytes)
                          : set_build_lds<T, 8>(a.lds_bytes);

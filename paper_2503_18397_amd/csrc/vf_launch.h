@@ -89,6 +89,8 @@ struct BuildArgs {
   // Largest cells and segment count over all items (scratch layout).
   uint64_t scr_V;
   uint32_t scr_l;
+  // Test builds: columns of the back-substitution's ring (0: kRingCols).
+  uint32_t ring_cols;
   // If set and nonzero when the kernel starts (a failed value check earlier
   // on the stream), the kernel returns without writing anything.
   const uint32_t *abort;
@@ -98,6 +100,8 @@ constexpr uint32_t kLdsBudget = 160 * 1024;  // LDS of one CU
 // Bytes at the end of a build workgroup's dynamic LDS that hold the control
 // blocks shared by its wavefronts and the back-substitution columns.
 constexpr uint32_t kLdsTail = 2048;
+// Columns of the back-substitution's LDS ring (cells of at most 4 bytes).
+constexpr uint32_t kRingCols = 2048;
 // Threads of a build workgroup: three wavefronts eliminate (one searches
 // the pivots, two emit the pivot rows), one peels the next item and one
 // assigns the cells of solved items.

@@ -70,6 +70,13 @@ def test_plan_rejects_bad_arguments():
         vf.vf_plan(1000, 8, 0.01, True, vf.vf_default_opts(tmax=0))
     with pytest.raises(vf.VFError):
         vf.vf_plan(1000, 8, 0.01, True, vf.vf_default_opts(h=25))
+    # the ring test option: a power of two from 64 to 2048, or 0
+    for bad in (32, 100, 4096):
+        with pytest.raises(vf.VFError) as e:
+            vf.vf_plan(1 << 16, 8, 0.0175, True, vf.vf_default_opts(h=2, ring_cols=bad))
+        assert e.value.code == vf.VF_EINVAL
+    for good in (0, 64, 2048):
+        vf.vf_plan(1 << 16, 8, 0.0175, True, vf.vf_default_opts(h=2, ring_cols=good))
 
 
 def test_host_allocation_failure_is_vf_enomem():

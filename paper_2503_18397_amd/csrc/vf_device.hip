@@ -1969,6 +1969,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
     const uint32_t w0t = tid - lane;  // this wavefront's first thread
     const FrontBufs fb{f_st, f_pe, f_F0, f_F1, f_cc};
     uint32_t nrounds = 0;
+    // The workgroup's first item (all wavefronts, nothing in the window's
+    // LDS yet) counts the vertex state in LDS, kLdsChunk vertices per pass
+    // over the edges, and stores it whole: every workgroup peels its first
+    // item at the same time, when global atomics are the scarce resource.
+    const uint32_t kLdsChunk = (A.lds_bytes - kLdsTail - ring_bytes<T>()) / 8u;
+    const bool lds_inc = nthr == kBuildThreads && V <= 8ull * kLdsChunk;
     VF_CLK(pf0);
     if (tid == 0)
       for (int i = 0; i < 7; i++) fcnt[i] = 0;
@@ -1993,13 +1999,41 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         }
       }
     }
-    for (uint64_t v = tid; v < V; v += nthr) {
-      fb.st[v] = 0;
-    }
+    if (!lds_inc)
+      for (uint64_t v = tid; v < V; v += nthr) fb.st[v] = 0;
     sync();
     VF_CLK(pf1);
     // incidence: degree and xor of incident edges
-    for (uint32_t i0 = tid; i0 < m; i0 += nthr * kPU) {
+    for (uint64_t c0 = 0; lds_inc && c0 < V; c0 += kLdsChunk) {
+      uint64_t *const lst = (uint64_t *)lds;
+      const uint32_t cn = (uint32_t)min((uint64_t)kLdsChunk, V - c0);
+      for (uint32_t j = tid; j < cn; j += nthr) lst[j] = 0;
+      sync();
+      for (uint32_t i0 = tid; i0 < m; i0 += nthr * kPU) {
+        uint64_t e[kPU];
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) {
+          const uint32_t i = i0 + u * nthr;
+          e[u] = i < m ? E[i] : 0ull;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kPU; u++) {
+          const uint32_t i = i0 + u * nthr;
+          if (i < m) {
+            uint32_t v[3];
+            unpack3(e[u], v);
+            for (int k = 0; k < 3; k++) {
+              const uint64_t d = (uint64_t)v[k] - c0;
+              if (d < cn) atomicAdd((unsigned long long *)&lst[d], kDegOne + i);
+            }
+          }
+        }
+      }
+      sync();
+      for (uint32_t j = tid; j < cn; j += nthr) fb.st[c0 + j] = lst[j];
+      sync();
+    }
+    for (uint32_t i0 = tid; !lds_inc && i0 < m; i0 += nthr * kPU) {
       uint64_t e[kPU];
 #pragma unroll
       for (uint32_t u = 0; u < kPU; u++) {

@@ -2030,7 +2030,15 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
         }
       }
       sync();
-      for (uint32_t j = tid; j < cn; j += nthr) fb.st[c0 + j] = lst[j];
+      // stored whole, with the first frontier (the vertices of degree one)
+      for (uint32_t j0 = w0t; j0 < cn; j0 += nthr) {
+        const uint32_t j = j0 + lane;
+        const uint64_t sv = j < cn ? lst[j] : 0ull;
+        if (j < cn) fb.st[c0 + j] = sv;
+        const bool one = j < cn && (sv >> 32) == 1;
+        const uint32_t at = wave_append(one, &fcnt[0]);
+        if (one) fb.F0[at] = (uint32_t)(c0 + j);
+      }
       sync();
     }
     for (uint32_t i0 = tid; !lds_inc && i0 < m; i0 += nthr * kPU) {
@@ -2053,8 +2061,8 @@ __global__ void __launch_bounds__(kBuildThreads) k_build(BuildArgs A) {
     }
     sync();
     VF_CLK(pf2);
-    // round-synchronous peeling
-    for (uint64_t v0 = w0t; v0 < V; v0 += (uint64_t)nthr * kPU) {
+    // round-synchronous peeling (the first frontier, unless found above)
+    for (uint64_t v0 = w0t; !lds_inc && v0 < V; v0 += (uint64_t)nthr * kPU) {
       uint64_t sv[kPU];
 #pragma unroll
       for (uint32_t u = 0; u < kPU; u++) {

@@ -27,8 +27,8 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy); see
 # profiles/vfilter_b8_n2p27_hbm_traffic_pmc.md.  They hold for the kernel
 # source with this SHA-256 prefix only and are reported as null otherwise.
-PMC_SOURCE_SHA = "11f57a2db84a1fb5"
-PMC_TRAFFIC_BYTES = {"k_build": 95.99e9, "k_query": 410.88e9, "query_grouped": 58.36e9,
+PMC_SOURCE_SHA = "f28f41b75e3f6698"
+PMC_TRAFFIC_BYTES = {"k_build": 94.04e9, "k_query": 410.88e9, "query_grouped": 58.16e9,
                      "k_scatter": 2.97e9, "k_count+k_scan": 1.09e9}
 
 
